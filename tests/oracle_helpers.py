@@ -1,0 +1,64 @@
+"""Helpers shared by the oracle pin tests and the GPU parity tests."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import dense
+from oracle.frame import OracleFrame
+
+AMP_RTOL = 1e-10
+AMP_ATOL = 1e-13
+
+
+def tableau_bits(tab_words: np.ndarray, n: int) -> np.ndarray:
+    """[n, 2W] uint64 words -> [n, 2n] 0/1 matrix [x | z]."""
+    W = (n + 63) // 64
+    out = np.zeros((n, 2 * n), dtype=np.uint8)
+    for i in range(n):
+        for q in range(n):
+            out[i, q] = (int(tab_words[i, q >> 6]) >> (q & 63)) & 1
+            out[i, n + q] = (int(tab_words[i, W + (q >> 6)]) >> (q & 63)) & 1
+    return out
+
+
+def sigma_ints(sig_words: np.ndarray) -> list[int]:
+    out = []
+    for row in sig_words:
+        v = 0
+        for w, word in enumerate(row):
+            v |= int(word) << (64 * w)
+        out.append(v)
+    return out
+
+
+def assert_frames_equal(sig_a, amp_a, sig_b, amp_b, what=""):
+    """sigma lists bit-exact (same canonical order), amplitudes within the
+    1e-10 relative bound."""
+    assert list(sig_a) == list(sig_b), f"{what}: phase-vector sets differ ({len(sig_a)} vs {len(sig_b)})"
+    a = np.asarray(amp_a, dtype=complex)
+    b = np.asarray(amp_b, dtype=complex)
+    err = np.abs(a - b)
+    bound = AMP_RTOL * np.abs(b) + AMP_ATOL
+    assert np.all(err <= bound), f"{what}: amplitude mismatch, worst {np.max(err / bound)} x bound"
+
+
+def oracle_vs_dense(circ, seed: int = 0, every_gate: bool = True):
+    """Run the C oracle gate by gate and the dense checker; compare tableau,
+    frame and outcomes after every gate (or only at the end)."""
+    n = circ.n
+    gates = circ.gates
+    psi, M, outs, hist = dense.simulate(n, gates, circ.init_bits, seed=seed, trace=True)
+    f = OracleFrame(n, circ.init_bits, seed)
+    for gi, g in enumerate(gates):
+        f.apply(*g)
+        if not every_gate and gi != len(gates) - 1:
+            continue
+        psi_g, M_g = hist[gi]
+        tab, sig, amp = f.read()
+        assert np.array_equal(tableau_bits(tab, n), M_g), f"gate {gi}: tableau differs"
+        exp = dense.frame_expansion_fast(M_g, psi_g, n)
+        assert_frames_equal(sigma_ints(sig), amp, [s for s, _ in exp], [a for _, a in exp],
+                            what=f"gate {gi} {g}")
+    assert f.outcomes() == outs
+    assert not f.fragile
+    return f
