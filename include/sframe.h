@@ -1,0 +1,145 @@
+/*
+ * sframe -- stabilizer-frame simulation on AMD MI355X (gfx950).
+ *
+ * C ABI of libsframe.so.  The library simulates a quantum circuit of Clifford
+ * gates, non-Clifford phase gates and Z-basis measurements on one stabilizer
+ * frame (Garcia & Markov, "Simulation of Quantum Circuits via Stabilizer
+ * Frames", Definition 1): a stabilizer matrix shared by a set of phase vectors,
+ * each with a complex amplitude, such that the state is
+ *   Psi = sum_j a_j psi(M, sigma_j).
+ * The calls follow the paper's problem statement (section 2.3: initialise a
+ * basis state, apply the gates one at a time, measure) and its frame
+ * operations (section 3: ROTATE, COFACTOR; section 4: measuring a frame).
+ *
+ * Conventions
+ *  - Qubit q of a packed bit vector is word q>>6, bit q&63; W = ceil(n/64).
+ *  - Tableau rows are returned as W words of x bits followed by W words of z
+ *    bits; literal (x,z) = 00 I, 01 Z, 10 X, 11 Y (section 2.2).  The returned
+ *    tableau is the fully reduced row echelon form over the columns
+ *    x_0..x_{n-1}, z_0..z_{n-1}, rows sorted by pivot (X-block first, as in
+ *    Figure 2b); it carries no signs.
+ *  - Phase vector bit i (1 = sign -1) belongs to row i of that tableau.
+ *  - The amplitude a_j refers to psi(M, sigma_j) normalised with a real
+ *    positive amplitude at the smallest basis string of its support, where
+ *    qubit 0 is the most significant bit of a basis index.
+ *  - Frame elements are returned in ascending order of sum_i sigma_i 2^i, with
+ *    |a| > 1e-12 (smaller amplitudes are dropped after every merge).
+ *  - A measurement of qubit q gives outcome 1 exactly when
+ *    u = (splitmix64 output k of the stream seeded with `seed`) >> 11, * 2^-53
+ *    is below p(1); k counts the measurements of the state from 0.
+ *
+ * Ownership and errors: every call returns an sf_status; no exception or abort
+ * crosses the ABI.  The caller owns every host buffer it passes.  The library
+ * owns device memory (allocated through the sf_allocator hook, or hipMalloc
+ * when the hook is NULL) and frees it in the matching *_destroy.  Work is
+ * queued on the context's HIP stream; calls that return host data
+ * synchronise that stream.  A context must be used by one host thread at a
+ * time.  sf_last_error returns the message of the last failed call.
+ */
+#ifndef SFRAME_H
+#define SFRAME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SF_OK = 0,
+  SF_E_INVALID = 1,   /* malformed argument or circuit */
+  SF_E_OOM = 2,       /* device allocation failed */
+  SF_E_DEVICE = 3,    /* HIP runtime error */
+  SF_E_TOO_LARGE = 4, /* frame bound exceeds the limit or the memory budget */
+  SF_E_STATE = 5,     /* call not valid in the current state */
+  SF_E_BUFSIZE = 6,   /* output buffer too small; size returned */
+  SF_E_CANCELLED = 7
+} sf_status;
+
+/* Gate codes.  theta = pi * theta_num / theta_den for SF_PHASE / SF_CPHASE. */
+typedef enum {
+  SF_H = 0, SF_S = 1, SF_SDG = 2, SF_X = 3, SF_Y = 4, SF_Z = 5,
+  SF_CNOT = 6,    /* q0 control, q1 target */
+  SF_CZ = 7,
+  SF_T = 8, SF_TDG = 9,
+  SF_PHASE = 10,  /* diag(1, e^{i theta}) on q0 */
+  SF_CPHASE = 11, /* diag(1,1,1,e^{i theta}) on (q0,q1); expanded at load into
+                     three phase gates and two CNOTs */
+  SF_TOF = 12,    /* Toffoli (q0,q1 controls, q2 target); expanded at load into
+                     the 7-T Clifford+T network */
+  SF_MEASURE = 13 /* Z-basis measurement of q0 */
+} sf_op;
+
+typedef struct {
+  uint32_t op, q0, q1, q2;
+  int64_t theta_num, theta_den;
+} sf_gate;
+
+/* Device allocator hook.  alloc returns device memory of `bytes` usable on
+ * `stream` (NULL on failure); free releases it. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, size_t bytes, void* stream, void* user);
+  void* user;
+} sf_allocator;
+
+typedef struct sf_ctx sf_ctx;
+typedef struct sf_circuit sf_circuit;
+typedef struct sf_state sf_state;
+
+/* Create a context on HIP device `device` that queues work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  `alloc` may be NULL.
+ * hbm_budget_bytes bounds the device memory of all states (0 = no bound). */
+sf_status sf_ctx_create(int device, void* hip_stream, const sf_allocator* alloc,
+                        uint64_t hbm_budget_bytes, sf_ctx** out);
+sf_status sf_ctx_destroy(sf_ctx* ctx);
+const char* sf_last_error(const sf_ctx* ctx);
+
+/* Validate and load a circuit on n_qubits (1..256).  Qubit indices must be
+ * < n_qubits and distinct within a gate; theta_den != 0 for phase gates.
+ * Loading rewrites phase gates whose angle is a multiple of pi/2 into
+ * I/S/Z/S-dagger, expands SF_CPHASE and SF_TOF, and runs the tableau track
+ * once to bound the frame: every frame of the run has at most 2^bound
+ * elements (the dimension of the affine hull of its phase vectors).
+ * Returns SF_E_TOO_LARGE when the bound exceeds 29. */
+sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n_qubits, const sf_gate* gates, size_t n_gates,
+                          sf_circuit** out);
+/* Frame bound (log2) and the device bytes a state of this circuit needs. */
+sf_status sf_circuit_info(const sf_circuit* c, uint64_t* max_frame_bound_log2, uint64_t* projected_bytes);
+sf_status sf_circuit_destroy(sf_circuit* c);
+
+/* Allocate a state and set it to the basis state |b>: basis_bits holds W
+ * words, bit q = b_q (NULL = all zeros).  `seed` seeds the measurement coin. */
+sf_status sf_state_init(sf_ctx* ctx, const sf_circuit* c, const uint64_t* basis_bits, uint64_t seed,
+                        sf_state** out);
+sf_status sf_state_destroy(sf_state* s);
+
+/* Queue up to max_gates further gates of the circuit (counted as given to
+ * sf_circuit_load); stops after each measurement.  *gates_applied receives
+ * the number queued (0 at the end of the circuit).  Asynchronous. */
+sf_status sf_step(sf_state* s, size_t max_gates, size_t* gates_applied);
+/* Queue every remaining gate.  Asynchronous. */
+sf_status sf_run(sf_state* s);
+/* Wait for queued work; reports device-side failures of the queued steps. */
+sf_status sf_sync(sf_state* s);
+
+/* Measurement outcomes so far (synchronises).  *count receives their number;
+ * at most cap are written. */
+sf_status sf_outcomes(sf_state* s, uint8_t* out, size_t cap, size_t* count);
+/* Number of frame elements |F| (synchronises). */
+sf_status sf_frame_size(sf_state* s, uint64_t* K);
+/* Read the frame in canonical form (synchronises): tableau (n rows of 2W
+ * words), sigma (K rows of W words), amp (K interleaved re,im).  With
+ * cap_K < K nothing is written, *K_out = K and SF_E_BUFSIZE is returned.
+ * Any output pointer may be NULL. */
+sf_status sf_read_frame(sf_state* s, uint64_t* tableau, uint64_t* sigma, double* amp, size_t cap_K,
+                        size_t* K_out);
+/* Gates of the circuit applied so far and whether a measurement result was
+ * fragile (|u - p(1)| < 1e-12 or p(outcome) = 0). */
+sf_status sf_state_info(sf_state* s, size_t* gates_done, int* fragile);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFRAME_H */

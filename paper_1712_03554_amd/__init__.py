@@ -1,0 +1,246 @@
+"""Python binding of libsframe.so (stabilizer-frame simulation on MI355X).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of the library.  Device memory comes from PyTorch's caching allocator
+through the library's allocator hook, and work is queued on PyTorch's current
+HIP stream.  Importing works without a GPU; creating an Engine needs the built
+library and a HIP device and raises otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import workloads
+from .workloads import GATE_DTYPE
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsframe.so")
+
+SF_OK, SF_E_INVALID, SF_E_OOM, SF_E_DEVICE, SF_E_TOO_LARGE, SF_E_STATE, SF_E_BUFSIZE, SF_E_CANCELLED = range(8)
+STATUS_NAMES = ["SF_OK", "SF_E_INVALID", "SF_E_OOM", "SF_E_DEVICE", "SF_E_TOO_LARGE", "SF_E_STATE",
+                "SF_E_BUFSIZE", "SF_E_CANCELLED"]
+
+EXPORTS = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_circuit_load", "sf_circuit_info",
+           "sf_circuit_destroy", "sf_state_init", "sf_state_destroy", "sf_step", "sf_run", "sf_sync",
+           "sf_outcomes", "sf_frame_size", "sf_read_frame", "sf_state_info"]
+
+
+class SFrameError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 8 else status}: {msg}")
+        self.status = status
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsframe.so; raises if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libsframe.so not built ({path}); run __graft_entry__.build()")
+    L = ctypes.CDLL(path)
+    vp, u64, sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "sf_ctx_create": [ctypes.c_int, vp, vp, u64, P(vp)],
+        "sf_ctx_destroy": [vp],
+        "sf_circuit_load": [vp, ctypes.c_uint32, vp, sz, P(vp)],
+        "sf_circuit_info": [vp, P(u64), P(u64)],
+        "sf_circuit_destroy": [vp],
+        "sf_state_init": [vp, vp, vp, u64, P(vp)],
+        "sf_state_destroy": [vp],
+        "sf_step": [vp, sz, P(sz)],
+        "sf_run": [vp],
+        "sf_sync": [vp],
+        "sf_outcomes": [vp, vp, sz, P(sz)],
+        "sf_frame_size": [vp, P(u64)],
+        "sf_read_frame": [vp, vp, vp, vp, sz, P(sz)],
+        "sf_state_info": [vp, P(sz), P(ctypes.c_int)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.sf_last_error.argtypes = [vp]
+    L.sf_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+class Engine:
+    """A library context bound to one HIP device and stream."""
+
+    def __init__(self, device: int = 0, stream=None, budget_bytes: int = 0, torch_allocator: bool = True):
+        self._L = load_library()
+        self._keep = []
+        stream_ptr = None
+        alloc_ptr = None
+        try:
+            import torch
+        except ImportError:  # pragma: no cover
+            torch = None
+        if torch is not None and torch.cuda.is_available():
+            torch.cuda.set_device(device)
+            s = stream if stream is not None else torch.cuda.current_stream(device)
+            stream_ptr = ctypes.c_void_p(s.cuda_stream)
+            self._torch_stream = s
+            if torch_allocator:
+                dev = device
+
+                def _alloc(nbytes, stream, user):
+                    try:
+                        return torch.cuda.caching_allocator_alloc(int(nbytes), dev, s)
+                    except Exception:
+                        return None
+
+                def _free(ptr, nbytes, stream, user):
+                    try:
+                        torch.cuda.caching_allocator_delete(ptr)
+                    except Exception:
+                        pass
+
+                self._alloc_struct = _Allocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
+                alloc_ptr = ctypes.cast(ctypes.pointer(self._alloc_struct), ctypes.c_void_p)
+        h = ctypes.c_void_p()
+        st = self._L.sf_ctx_create(device, stream_ptr, alloc_ptr, budget_bytes, ctypes.byref(h))
+        if st != SF_OK:
+            raise SFrameError(st, "sf_ctx_create failed (no HIP device?)")
+        self._h = h
+
+    def _check(self, st):
+        if st != SF_OK:
+            raise SFrameError(st, self._L.sf_last_error(self._h).decode())
+
+    def load(self, n: int, gates) -> "Circuit":
+        arr = gates.array() if hasattr(gates, "array") else np.ascontiguousarray(gates, dtype=GATE_DTYPE)
+        arr = np.ascontiguousarray(arr, dtype=GATE_DTYPE)
+        h = ctypes.c_void_p()
+        self._check(self._L.sf_circuit_load(self._h, n, _ptr(arr), len(arr), ctypes.byref(h)))
+        return Circuit(self, h, n)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.sf_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Circuit:
+    def __init__(self, eng: Engine, h, n: int):
+        self.eng, self._h, self.n = eng, h, n
+
+    def info(self):
+        b, p = ctypes.c_uint64(), ctypes.c_uint64()
+        self.eng._check(self.eng._L.sf_circuit_info(self._h, ctypes.byref(b), ctypes.byref(p)))
+        return int(b.value), int(p.value)
+
+    def state(self, basis_bits=None, seed: int = 0) -> "State":
+        W = (self.n + 63) // 64
+        words = None
+        if basis_bits is not None:
+            words = np.zeros(W, dtype=np.uint64)
+            for q, b in enumerate(basis_bits):
+                if int(b) & 1:
+                    words[q >> 6] |= np.uint64(1 << (q & 63))
+        h = ctypes.c_void_p()
+        self.eng._check(self.eng._L.sf_state_init(self.eng._h, self._h, _ptr(words),
+                                                  ctypes.c_uint64(seed & ((1 << 64) - 1)), ctypes.byref(h)))
+        return State(self, h)
+
+    def close(self):
+        if getattr(self, "_h", None) and self.eng._h:
+            self.eng._L.sf_circuit_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class State:
+    def __init__(self, circ: Circuit, h):
+        self.circ, self._h = circ, h
+        self.n = circ.n
+        self.W = (circ.n + 63) // 64
+        self._L = circ.eng._L
+
+    def _check(self, st):
+        self.circ.eng._check(st)
+
+    def step(self, max_gates: int) -> int:
+        k = ctypes.c_size_t()
+        self._check(self._L.sf_step(self._h, max_gates, ctypes.byref(k)))
+        return int(k.value)
+
+    def run(self):
+        self._check(self._L.sf_run(self._h))
+
+    def sync(self):
+        self._check(self._L.sf_sync(self._h))
+
+    def outcomes(self) -> list[int]:
+        cnt = ctypes.c_size_t()
+        self._check(self._L.sf_outcomes(self._h, None, 0, ctypes.byref(cnt)))
+        out = np.zeros(max(1, cnt.value), dtype=np.uint8)
+        self._check(self._L.sf_outcomes(self._h, _ptr(out), cnt.value, ctypes.byref(cnt)))
+        return out[: cnt.value].tolist()
+
+    def frame_size(self) -> int:
+        k = ctypes.c_uint64()
+        self._check(self._L.sf_frame_size(self._h, ctypes.byref(k)))
+        return int(k.value)
+
+    def info(self):
+        done, frag = ctypes.c_size_t(), ctypes.c_int()
+        self._check(self._L.sf_state_info(self._h, ctypes.byref(done), ctypes.byref(frag)))
+        return int(done.value), bool(frag.value)
+
+    def read_frame(self):
+        """(tableau[n, 2W] uint64, sigma[K, W] uint64, amp[K] complex128), canonical order."""
+        K = ctypes.c_size_t()
+        tab = np.zeros((self.n, 2 * self.W), dtype=np.uint64)
+        st = self._L.sf_read_frame(self._h, _ptr(tab), None, None, 0, ctypes.byref(K))
+        if st not in (SF_OK, SF_E_BUFSIZE):
+            self._check(st)
+        k = K.value
+        sig = np.zeros((max(k, 1), self.W), dtype=np.uint64)
+        amp = np.zeros(2 * max(k, 1), dtype=np.float64)
+        self._check(self._L.sf_read_frame(self._h, _ptr(tab), _ptr(sig), _ptr(amp), k, ctypes.byref(K)))
+        return tab, sig[:k], (amp[0::2] + 1j * amp[1::2])[:k]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.sf_state_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def simulate(eng: Engine, circ: "workloads.Circuit", seed: int = 0) -> State:
+    """Load, initialise and run a whole circuit; returns the (synchronised) state."""
+    c = eng.load(circ.n, circ)
+    s = c.state(circ.init_bits, seed)
+    s.run()
+    s.sync()
+    s._circ_ref = c
+    return s

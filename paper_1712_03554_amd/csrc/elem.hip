@@ -1,0 +1,358 @@
+// Element kernels: stream the dense amplitude array of a frame.
+//
+// Slot Y of the array holds the element (sigma(Y), amp[Y]) of the frame; the
+// phase vectors themselves are implicit in the hull (sf_dev.h).  A segment
+// kernel applies, per element, the global-phase factors of a run of Clifford
+// gates (ROTATE with global-phase maintenance, section 3) and then the
+// segment's terminal step: a deterministic phase, or COFACTOR with the
+// non-Clifford phase on the |1> cofactor.  Cofactor children of partner
+// elements (phase vectors differing by the rows that anticommute with Z_q)
+// land on the same slot pair and are merged in place by a butterfly, so no
+// sort is needed.  Measurement (section 4) reduces p(1) with a fixed-shape
+// tree, draws a counter-based uniform and filters the consistent elements.
+#include <hip/hip_runtime.h>
+
+#include "sf_dev.h"
+
+#define EB 256
+
+__device__ __forceinline__ int evalZ4(const Z4Q* __restrict__ t, uint32_t Y) {
+  int e = (int)t->c + __popc(t->L1 & Y) + 2 * __popc(t->L2 & Y);
+  uint32_t m = Y & t->qnz;
+  while (m) {
+    int j = __builtin_ctz(m);
+    m &= m - 1;
+    e += 2 * (__popc(t->Q[j] & Y) & 1);
+  }
+  return e & 3;
+}
+
+__device__ __forceinline__ int evalGF2(const GF2Q* __restrict__ t, uint32_t Y) {
+  int e = (int)t->c ^ (__popc(t->L & Y) & 1);
+  uint32_t m = Y & t->qnz;
+  while (m) {
+    int j = __builtin_ctz(m);
+    m &= m - 1;
+    e ^= __popc(t->Q[j] & Y) & 1;
+  }
+  return e;
+}
+
+// a * exp(i pi m / 4)
+__device__ __forceinline__ double2 rot8(double2 a, int m) {
+  m &= 7;
+  double r, i;
+  switch (m >> 1) {
+    case 0: r = a.x; i = a.y; break;
+    case 1: r = -a.y; i = a.x; break;
+    case 2: r = -a.x; i = -a.y; break;
+    default: r = a.y; i = -a.x; break;
+  }
+  if (m & 1) {
+    const double s = 0.70710678118654752440;
+    double nr = __dmul_rn(__dsub_rn(r, i), s);
+    double ni = __dmul_rn(__dadd_rn(r, i), s);
+    r = nr; i = ni;
+  }
+  return make_double2(r, i);
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double re, double im) {
+  return make_double2(__dsub_rn(__dmul_rn(a.x, re), __dmul_rn(a.y, im)),
+                      __dadd_rn(__dmul_rn(a.x, im), __dmul_rn(a.y, re)));
+}
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+  return make_double2(__dadd_rn(a.x, b.x), __dadd_rn(a.y, b.y));
+}
+
+__device__ __forceinline__ double norm2(double2 a) {
+  return __dadd_rn(__dmul_rn(a.x, a.x), __dmul_rn(a.y, a.y));
+}
+
+__device__ __forceinline__ double2 prune(double2 a) {
+  return norm2(a) <= 1e-24 ? make_double2(0.0, 0.0) : a;
+}
+
+// accumulated global-phase exponent (units of pi/4) of the segment's Cliffords
+__device__ __forceinline__ int seg_phase(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had, uint32_t Y) {
+  int m = 2 * evalZ4(&sp->E, Y) + sp->nhad;
+  const int nh = sp->nhad;
+  for (int h = 0; h < nh; ++h) m -= 2 * evalGF2(&had[h], Y);
+  return m & 7;
+}
+
+// cofactor child x: a * 2^{-1/2} i^{B_x(Y)}
+__device__ __forceinline__ double2 child(double2 a, const Z4Q* __restrict__ B, uint32_t Y) {
+  double2 r = rot8(a, 2 * evalZ4(B, Y));
+  const double s = 0.70710678118654752440;
+  return make_double2(__dmul_rn(r.x, s), __dmul_rn(r.y, s));
+}
+
+__device__ __forceinline__ uint32_t insert_zero(uint64_t r, int j) {
+  uint64_t lo = r & ((1ull << j) - 1ull);
+  return (uint32_t)(lo | ((r >> j) << (j + 1)));
+}
+
+extern "C" __global__ void __launch_bounds__(EB)
+sf_seg_kernel(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all, double2* __restrict__ amp) {
+  const int kind = sp->kind;
+  const int d = sp->d;
+  const GF2Q* had = had_all + sp->had_off;
+  const uint64_t N = 1ull << d;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double pre = sp->ph_re, pim = sp->ph_im;
+  if (kind == SEG_PAIR) {
+    const int j0 = sp->j0;
+    const uint32_t delta = sp->delta;
+    for (uint64_t r = tid; r < (N >> 1); r += stride) {
+      uint32_t Y = insert_zero(r, j0);
+      uint32_t Yd = Y ^ delta;
+      double2 a = amp[Y], b = amp[Yd];
+      a = rot8(a, seg_phase(sp, had, Y));
+      b = rot8(b, seg_phase(sp, had, Yd));
+      double2 c0 = cadd(child(a, &sp->B0, Y), child(b, &sp->B0, Yd));
+      double2 c1 = cadd(child(a, &sp->B1, Y), child(b, &sp->B1, Yd));
+      c1 = cmul(c1, pre, pim);
+      amp[Y] = prune(c0);
+      amp[Yd] = prune(c1);
+    }
+  } else if (kind == SEG_GROW) {
+    for (uint64_t Y = tid; Y < N; Y += stride) {
+      double2 a = amp[Y];
+      a = rot8(a, seg_phase(sp, had, (uint32_t)Y));
+      double2 c0 = child(a, &sp->B0, (uint32_t)Y);
+      double2 c1 = cmul(child(a, &sp->B1, (uint32_t)Y), pre, pim);
+      amp[Y] = prune(c0);
+      amp[Y + N] = prune(c1);
+    }
+  } else {
+    const uint32_t dc = sp->det_c, dr = sp->det_r;
+    const bool det = kind == SEG_DET;
+    for (uint64_t Y = tid; Y < N; Y += stride) {
+      double2 a = amp[Y];
+      if (a.x == 0.0 && a.y == 0.0) continue;
+      a = rot8(a, seg_phase(sp, had, (uint32_t)Y));
+      if (det && ((dc ^ (uint32_t)__popc(dr & (uint32_t)Y)) & 1u)) a = cmul(a, pre, pim);
+      amp[Y] = a;
+    }
+  }
+}
+
+// Measurement: block partial sums of |a|^2 split by the qubit value.
+extern "C" __global__ void __launch_bounds__(EB)
+sf_meas_reduce(const SegProg* __restrict__ sp, const double2* __restrict__ amp, double2* __restrict__ partials) {
+  __shared__ double s0[EB], s1[EB];
+  const uint64_t N = 1ull << sp->d_out;
+  const uint32_t c0 = sp->m_c0, r = sp->m_r;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  double p0 = 0.0, p1 = 0.0;
+  for (uint64_t Y = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; Y < N; Y += stride) {
+    double v = norm2(amp[Y]);
+    if ((c0 ^ (uint32_t)__popc(r & (uint32_t)Y)) & 1u) p1 = __dadd_rn(p1, v);
+    else p0 = __dadd_rn(p0, v);
+  }
+  s0[threadIdx.x] = p0;
+  s1[threadIdx.x] = p1;
+  __syncthreads();
+  for (int h = EB / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      s0[threadIdx.x] = __dadd_rn(s0[threadIdx.x], s0[threadIdx.x + h]);
+      s1[threadIdx.x] = __dadd_rn(s1[threadIdx.x], s1[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = make_double2(s0[0], s1[0]);
+}
+
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t state, uint64_t index) {
+  // output `index` of the SplitMix64 generator started at `state`
+  uint64_t z = state + (index + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// One block: fixed-order sum of the partials, seeded biased coin, outcome.
+extern "C" __global__ void __launch_bounds__(EB)
+sf_meas_final(const SegProg* __restrict__ sp, const double2* __restrict__ partials, int G, uint64_t seed,
+              uint8_t* __restrict__ outcomes, double* __restrict__ pvals, double* __restrict__ scale,
+              int* __restrict__ flags) {
+  __shared__ double s0[EB], s1[EB];
+  double p0 = 0.0, p1 = 0.0;
+  for (int i = threadIdx.x; i < G; i += EB) {
+    p0 = __dadd_rn(p0, partials[i].x);
+    p1 = __dadd_rn(p1, partials[i].y);
+  }
+  s0[threadIdx.x] = p0;
+  s1[threadIdx.x] = p1;
+  __syncthreads();
+  for (int h = EB / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      s0[threadIdx.x] = __dadd_rn(s0[threadIdx.x], s0[threadIdx.x + h]);
+      s1[threadIdx.x] = __dadd_rn(s1[threadIdx.x], s1[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int mi = sp->meas_index;
+    double P0 = s0[0], P1 = s1[0];
+    double u = (double)(splitmix64_at(seed, (uint64_t)mi) >> 11) * (1.0 / 9007199254740992.0);
+    int o = u < P1 ? 1 : 0;
+    outcomes[mi] = (uint8_t)o;
+    pvals[mi] = P1;
+    double po = o ? P1 : P0;
+    scale[0] = po > 0.0 ? 1.0 / sqrt(po) : 0.0;
+    if (fabs(u - P1) < 1e-12 || po <= 0.0) atomicOr(flags, 1);
+  }
+}
+
+// Keep the elements consistent with the outcome and renormalise (new buffer).
+extern "C" __global__ void __launch_bounds__(EB)
+sf_meas_filter(const SegProg* __restrict__ sp, const double2* __restrict__ src, double2* __restrict__ dst,
+               const uint8_t* __restrict__ outcomes, const double* __restrict__ scale) {
+  const int mi = sp->meas_index;
+  const uint32_t o = outcomes[mi];
+  const double s = scale[0];
+  const uint32_t c0 = sp->m_c0, r = sp->m_r;
+  const int j0 = sp->m_j0;
+  const int dout = sp->d_out;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r == 0) {
+    const uint64_t N = 1ull << dout;
+    for (uint64_t Y = tid; Y < N; Y += stride) {
+      double2 a = src[Y];
+      dst[Y] = make_double2(__dmul_rn(a.x, s), __dmul_rn(a.y, s));
+    }
+  } else {
+    const uint64_t N = 1ull << (dout - 1);
+    for (uint64_t Yp = tid; Yp < N; Yp += stride) {
+      uint32_t rest = insert_zero(Yp, j0);
+      uint32_t bit = (o ^ c0 ^ (uint32_t)__popc(r & rest)) & 1u;
+      double2 a = src[rest | (bit << j0)];
+      dst[Yp] = make_double2(__dmul_rn(a.x, s), __dmul_rn(a.y, s));
+    }
+  }
+}
+
+// Number of non-zero amplitudes (frame size |F|).
+extern "C" __global__ void __launch_bounds__(EB)
+sf_count_kernel(const TrackState* __restrict__ st, const double2* __restrict__ amp, unsigned long long* out) {
+  __shared__ unsigned long long sc[EB];
+  // a measurement's filter is already applied to the array, not yet to the hull
+  const int d = st->d - ((st->pend && st->pend_r) ? 1 : 0);
+  const uint64_t N = 1ull << d;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  unsigned long long c = 0;
+  for (uint64_t Y = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; Y < N; Y += stride) {
+    double2 a = amp[Y];
+    c += (a.x != 0.0 || a.y != 0.0) ? 1ull : 0ull;
+  }
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = EB / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) sc[threadIdx.x] += sc[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && sc[0]) atomicAdd(out, sc[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Readout in canonical order
+// ---------------------------------------------------------------------------
+// Scatter every slot to its rank key: the phase-vector bits at the echelon
+// pivots of the hull, which orders slots exactly as ascending sigma.
+extern "C" __global__ void __launch_bounds__(EB)
+sf_readout_scatter(const ReadoutInfo* __restrict__ ri, const double2* __restrict__ amp,
+                   uint64_t* __restrict__ tsig, double2* __restrict__ tamp, uint8_t* __restrict__ flag) {
+  const int d = ri->d, W = ri->W;
+  const uint64_t N = 1ull << d;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t Y = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; Y < N; Y += stride) {
+    uint64_t s[SF_WMAX];
+    for (int w = 0; w < SF_WMAX; ++w) s[w] = ri->s0[w];
+    uint32_t y = (uint32_t)Y;
+    while (y) {
+      int j = __builtin_ctz(y);
+      y &= y - 1;
+      for (int w = 0; w < SF_WMAX; ++w) s[w] ^= ri->V[j][w];
+    }
+    uint64_t key = 0;
+    for (int i = 0; i < d; ++i) {
+      int pv = ri->piv[i];
+      key = (key << 1) | ((s[pv >> 6] >> (pv & 63)) & 1ull);
+    }
+    double2 a = amp[Y];
+    for (int w = 0; w < W; ++w) tsig[key * W + w] = s[w];
+    tamp[key] = a;
+    flag[key] = (a.x != 0.0 || a.y != 0.0) ? 1 : 0;
+  }
+}
+
+#define CH_ITEMS 16
+#define CH (EB * CH_ITEMS)
+
+extern "C" __global__ void __launch_bounds__(EB)
+sf_compact_count(const uint8_t* __restrict__ flag, uint64_t N, unsigned int* __restrict__ counts) {
+  __shared__ unsigned int sc[EB];
+  uint64_t base = (uint64_t)blockIdx.x * CH + (uint64_t)threadIdx.x * CH_ITEMS;
+  unsigned int c = 0;
+  for (int k = 0; k < CH_ITEMS; ++k) c += (base + k < N) ? flag[base + k] : 0u;
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = EB / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) sc[threadIdx.x] += sc[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counts[blockIdx.x] = sc[0];
+}
+
+// single block: exclusive scan of the block counts, total at counts[nb]
+extern "C" __global__ void __launch_bounds__(EB)
+sf_compact_scan(unsigned int* __restrict__ counts, int nb, unsigned long long* __restrict__ total) {
+  __shared__ unsigned long long part[EB];
+  const int per = (nb + EB - 1) / EB;
+  const int b0 = threadIdx.x * per;
+  unsigned long long s = 0;
+  for (int i = 0; i < per; ++i) if (b0 + i < nb) s += counts[b0 + i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long run = 0;
+    for (int t = 0; t < EB; ++t) { unsigned long long v = part[t]; part[t] = run; run += v; }
+    *total = run;
+  }
+  __syncthreads();
+  unsigned long long run = part[threadIdx.x];
+  for (int i = 0; i < per; ++i) {
+    if (b0 + i < nb) { unsigned int v = counts[b0 + i]; counts[b0 + i] = (unsigned int)run; run += v; }
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(EB)
+sf_compact_write(const uint8_t* __restrict__ flag, const uint64_t* __restrict__ tsig, const double2* __restrict__ tamp,
+                 uint64_t N, int W, const unsigned int* __restrict__ offs, uint64_t* __restrict__ osig,
+                 double2* __restrict__ oamp) {
+  __shared__ unsigned int sc[EB];
+  uint64_t base = (uint64_t)blockIdx.x * CH + (uint64_t)threadIdx.x * CH_ITEMS;
+  unsigned int c = 0;
+  for (int k = 0; k < CH_ITEMS; ++k) c += (base + k < N) ? flag[base + k] : 0u;
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int run = 0;
+    for (int t = 0; t < EB; ++t) { unsigned int v = sc[t]; sc[t] = run; run += v; }
+  }
+  __syncthreads();
+  uint64_t pos = (uint64_t)offs[blockIdx.x] + sc[threadIdx.x];
+  for (int k = 0; k < CH_ITEMS; ++k) {
+    uint64_t i = base + k;
+    if (i < N && flag[i]) {
+      for (int w = 0; w < W; ++w) osig[pos * W + w] = tsig[i * W + w];
+      oamp[pos] = tamp[i];
+      ++pos;
+    }
+  }
+}

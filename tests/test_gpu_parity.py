@@ -1,0 +1,230 @@
+"""Parity of the HIP library with the CPU oracle (needs an MI355X).
+
+Tableau and canonically ordered phase vectors bit-exact, seeded outcomes
+bit-exact, complex128 amplitudes within |a - a_ref| <= 1e-10 |a_ref| + 1e-13.
+"""
+import numpy as np
+import pytest
+
+from oracle.frame import OracleFrame
+from paper_1712_03554_amd import workloads as wl
+from tests.oracle_helpers import assert_frames_equal, sigma_ints
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1712_03554_amd as sf
+    return sf.Engine(0)
+
+
+def _compare(st, ref, what):
+    tab, sig, amp = st.read_frame()
+    rtab, rsig, ramp = ref.read()
+    assert np.array_equal(tab, rtab), f"{what}: tableau differs"
+    assert_frames_equal(sigma_ints(sig), amp, sigma_ints(rsig), ramp, what=what)
+
+
+def run_pair(eng, circ, seed, boundaries=()):
+    """Run the circuit on the GPU and the oracle; compare at the listed gate
+    counts (in the circuit's own gate units) and at the end."""
+    print(f"case {circ.name} n={circ.n} gates={len(circ)} seed={seed}", flush=True)
+    c = eng.load(circ.n, circ)
+    st = c.state(circ.init_bits, seed)
+    ref = OracleFrame(circ.n, circ.init_bits, seed)
+    done = 0
+    for b in sorted(set(boundaries)) + [len(circ)]:
+        while done < b:
+            k = st.step(b - done)
+            assert k > 0
+            for g in circ.gates[done:done + k]:
+                ref.apply(*g)
+            done += k
+        _compare(st, ref, f"{circ.name} after {done} gates")
+    assert st.outcomes() == ref.outcomes(), f"{circ.name}: outcomes differ"
+    assert not ref.fragile
+    _, frag = st.info()
+    assert not frag
+    return st, ref
+
+
+def _mixed_circuit(seed, n, n_cliff=60, n_t=5, meas=True):
+    rng = np.random.default_rng(seed)
+    c = wl.random_clifford_t(n, n_cliff, n_t, 7000 + seed,
+                             measure_qubits=rng.permutation(n)[: int(rng.integers(0, n + 1))] if meas else ())
+    extra = [(wl.SDG, 0, 0, 0, 0, 1), (wl.X, n - 1, 0, 0, 0, 1), (wl.Y, 0, 0, 0, 0, 1), (wl.Z, 1, 0, 0, 0, 1),
+             (wl.CZ, 0, 1, 0, 0, 1), (wl.TDG, 0, 0, 0, 0, 1), (wl.PHASE, 1, 0, 0, 1, 8),
+             (wl.PHASE, 0, 0, 0, 3, 2), (wl.PHASE, 1, 0, 0, -5, 12), (wl.H, 1, 0, 0, 0, 1)]
+    if meas:
+        extra.append((wl.MEASURE, 1, 0, 0, 0, 1))
+    for g in extra:
+        c.gates.insert(int(rng.integers(0, len(c.gates))), g)
+    c.name = f"mixed{seed}-n{n}"
+    return c
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_small_circuits(eng, seed):
+    n = 2 + seed % 9
+    run_pair(eng, _mixed_circuit(seed, n), seed, boundaries=(5, 20, 41))
+
+
+def test_gate_by_gate(eng):
+    circ = _mixed_circuit(99, 5, n_cliff=40, n_t=4)
+    run_pair(eng, circ, 3, boundaries=range(1, len(circ)))
+
+
+@pytest.mark.parametrize("job", range(10))
+def test_config1_all_seeds(eng, job):
+    circ = wl.config1(job)
+    run_pair(eng, circ, wl.derive_seed(1, job), boundaries=(100, 204))
+
+
+def test_config1_matches_dense_vector(eng):
+    from oracle import dense
+    circ = wl.config1(0)
+    seed = wl.derive_seed(1, 0)
+    c = eng.load(circ.n, circ)
+    st = c.state(circ.init_bits, seed)
+    st.step(204)
+    tab, sig, amp = st.read_frame()
+    psi, M, _ = dense.simulate(8, circ.gates[:204])
+    from tests.oracle_helpers import tableau_bits
+    assert np.array_equal(tableau_bits(tab, 8), M)
+    exp = dense.frame_expansion_fast(M, psi, 8)
+    assert_frames_equal(sigma_ints(sig), amp, [s for s, _ in exp], [a for _, a in exp], what="cfg1 vs dense")
+
+
+@pytest.mark.parametrize("trial", range(12))
+def test_config3_steane_trials(eng, trial):
+    run_pair(eng, wl.config3(trial), trial)
+
+
+@pytest.mark.parametrize("n", [3, 6, 9])
+def test_qft(eng, n):
+    rng = np.random.default_rng(n)
+    x = rng.integers(0, 2, size=n).tolist()
+    run_pair(eng, wl.qft(n, x, max_k=6), 0)
+
+
+def test_cuccaro_small(eng):
+    run_pair(eng, wl.cuccaro_adder(2), 0)
+
+
+def test_library_expands_tof_and_cphase(eng):
+    base = wl.random_clifford_t(5, 20, 2, 11)
+    base.add(wl.TOF, 0, 2, 4)
+    base.add(wl.CPHASE, 1, 3, 0, 1, 4)
+    base.add(wl.CPHASE, 4, 0, 0, -3, 8)
+    base.add(wl.CPHASE, 2, 1, 0, 1, 1)
+    base.name = "tof-cphase"
+    run_pair(eng, base, 5)
+
+
+@pytest.mark.parametrize("n", [63, 64, 65, 128, 200, 256])
+def test_word_boundaries_and_max_qubits(eng, n):
+    circ = wl.random_clifford_t(n, 4 * n, 6, 500 + n, measure_qubits=(0, n - 1, n // 2))
+    circ.add(wl.CNOT, n - 1, 0).add(wl.H, n - 1).add(wl.T, n - 1).add(wl.CZ, 63 % n, n - 1)
+    circ.name = f"wide{n}"
+    run_pair(eng, circ, n)
+
+
+@pytest.mark.parametrize("job", [0, 3, 5])
+def test_config4_circuits(eng, job):
+    circ = wl.config4(job)
+    if circ.count([wl.T]) > 9:
+        circ = wl.random_clifford_t(circ.n, 10 * circ.n, 9, wl.derive_seed(4, job), name=circ.name + "t9")
+    run_pair(eng, circ, job)
+
+
+def test_config2_full_size(eng):
+    circ = wl.config2(0)
+    run_pair(eng, circ, wl.derive_seed(2, 0), boundaries=(1000,))
+
+
+def test_edge_cases(eng):
+    # no gates, n = 1
+    c1 = wl.Circuit(1, name="empty")
+    run_pair(eng, c1, 0)
+    # only measurements on a basis state
+    c2 = wl.Circuit(3, init_bits=[1, 0, 1], name="measure-only")
+    for q in range(3):
+        c2.measure(q)
+    st, _ = run_pair(eng, c2, 0)
+    assert st.outcomes() == [1, 0, 1]
+    # Clifford angles of the phase gate and identity phases
+    c3 = wl.Circuit(2, name="clifford-phases")
+    c3.h(0).h(1).phase(0, 1, 2).phase(1, 2, 2).phase(0, -1, 2).phase(1, 4, 1).phase(0, 3, 2).t(1)
+    run_pair(eng, c3, 0)
+    # repeated measurement of the same qubit is deterministic
+    c4 = wl.random_clifford_t(4, 20, 3, 77)
+    c4.measure(2).measure(2).measure(2)
+    c4.name = "remeasure"
+    st, _ = run_pair(eng, c4, 9)
+    o = st.outcomes()
+    assert o[0] == o[1] == o[2]
+
+
+def test_invalid_circuits_rejected(eng):
+    import paper_1712_03554_amd as sf
+    bad = [
+        [(wl.H, 5, 0, 0, 0, 1)],
+        [(wl.CNOT, 1, 1, 0, 0, 1)],
+        [(wl.PHASE, 0, 0, 0, 1, 0)],
+        [(99, 0, 0, 0, 0, 1)],
+        [(wl.TOF, 0, 1, 1, 0, 1)],
+    ]
+    for gates in bad:
+        c = wl.Circuit(3)
+        c.gates = gates
+        with pytest.raises(sf.SFrameError) as ei:
+            eng.load(3, c)
+        assert ei.value.status == sf.SF_E_INVALID
+    with pytest.raises(sf.SFrameError):
+        eng.load(0, wl.Circuit(1))
+    with pytest.raises(sf.SFrameError):
+        eng.load(257, wl.Circuit(1))
+
+
+def test_too_large_frame_rejected(eng):
+    import paper_1712_03554_amd as sf
+    c = wl.Circuit(40)
+    for q in range(40):
+        c.h(q)
+    for q in range(32):
+        c.t(q)
+    with pytest.raises(sf.SFrameError) as ei:
+        eng.load(40, c)
+    assert ei.value.status == sf.SF_E_TOO_LARGE
+
+
+def test_budget_rejects_state(eng):
+    import paper_1712_03554_amd as sf
+    small = sf.Engine(0, budget_bytes=1 << 16)
+    c = wl.Circuit(20)
+    for q in range(20):
+        c.h(q)
+    for q in range(14):
+        c.t(q)
+    circ = small.load(20, c)
+    bound, need = circ.info()
+    assert bound == 14 and need > (1 << 16)
+    with pytest.raises(sf.SFrameError) as ei:
+        circ.state()
+    assert ei.value.status == sf.SF_E_TOO_LARGE
+
+
+def test_frame_size_and_determinism(eng):
+    circ = _mixed_circuit(5, 7, n_cliff=80, n_t=6)
+    a, ref = run_pair(eng, circ, 42)
+    assert a.frame_size() == ref.size
+    c = eng.load(circ.n, circ)
+    b = c.state(circ.init_bits, 42)
+    b.run()
+    ta, sa, aa = a.read_frame()
+    tb, sb, ab = b.read_frame()
+    assert np.array_equal(sa, sb) and np.array_equal(aa.view(np.uint64), ab.view(np.uint64))

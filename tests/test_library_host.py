@@ -1,0 +1,61 @@
+"""Host-side checks of the C-ABI library (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1712_03554_amd as sf
+from paper_1712_03554_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sframe.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:sf_status|const char\*)\s+(sf_\w+)\(", text, re.M)))
+
+
+def test_header_declares_binding_exports():
+    assert _declared() == sorted(sf.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(sf.LIB_PATH):
+        pytest.skip("library not built")
+    lib = ctypes.CDLL(sf.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_enums_match_header():
+    text = open(HEADER).read()
+    for i, name in enumerate(wl.OP_NAMES):
+        assert re.search(rf"SF_{name}\s*=\s*{i}\b", text), name
+    for i, name in enumerate(sf.STATUS_NAMES):
+        assert re.search(rf"{name}\s*=\s*{i}\b", text), name
+
+
+def test_gate_record_layout():
+    assert wl.GATE_DTYPE.itemsize == 32
+    assert [wl.GATE_DTYPE.fields[k][1] for k in ("op", "q0", "q1", "q2", "num", "den")] == [0, 4, 8, 12, 16, 24]
+
+
+def test_context_without_device_fails_cleanly():
+    """With no HIP device the library reports SF_E_DEVICE instead of crashing."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    if not os.path.exists(sf.LIB_PATH):
+        pytest.skip("library not built")
+    L = sf.load_library()
+    h = ctypes.c_void_p()
+    st = L.sf_ctx_create(0, None, None, 0, ctypes.byref(h))
+    assert st == sf.SF_E_DEVICE and not h.value
+
+
+def test_engine_requires_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(sf, "_lib", None)
+    with pytest.raises(ImportError):
+        sf.load_library(str(tmp_path / "missing.so"))
