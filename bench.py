@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Frame-element gate updates per second on one MI355X.
+
+Workload (default): the n=128 random Clifford+T circuits (2000 H/S/CNOT drawn
+uniformly, 16 T at uniform slots, then 16 Z measurements), three seeded
+circuits per step, run through the plain path (one tableau-track launch per
+measurement-delimited range and one element launch per segment).  U counts,
+for every gate applied, the frame size just before it; value = U / wall time
+of the timed steps, with states already resident in HBM (a step resets each
+state on the device and runs its circuit).
+
+Prints one JSON line (see the design doc for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+TERMINAL_OPS = None
+
+
+def terminal_indices(circ, wl):
+    """Indices of the gates that end a segment: non-Clifford phase gates and
+    measurements (T, T-dagger, PHASE with an angle off the pi/2 grid, MEASURE)."""
+    out = []
+    for i, g in enumerate(circ.gates):
+        op, num, den = g[0], g[4], g[5]
+        if op in (wl.T, wl.TDG, wl.MEASURE):
+            out.append(i)
+        elif op == wl.PHASE and (2 * num) % den != 0:
+            out.append(i)
+        elif op in (wl.CPHASE, wl.TOF):
+            raise ValueError("bench workloads use expanded gates only")
+    return out
+
+
+def accounting(state, circ, seed, wl):
+    """Untimed pass: U (sum over gates of |F| before the gate) and the hull
+    dimension on entry to every segment launch."""
+    state.reset(circ.init_bits, seed)
+    terms = terminal_indices(circ, wl)
+    U, K, d, pos = 0, 1, 0, 0
+    seg_dims = []
+    ends = terms + ([len(circ.gates) - 1] if (not terms or terms[-1] != len(circ.gates) - 1) else [])
+    for t in ends:
+        seg_dims.append(d)
+        U += K * (t - pos + 1)
+        k = state.step(t + 1 - pos)
+        assert k == t + 1 - pos, (k, t, pos)
+        K = state.frame_size()
+        d = state.dim()
+        pos = t + 1
+    return U, seg_dims
+
+
+def cpu_baseline(circ, seed):
+    from oracle.frame import OracleFrame
+    f = OracleFrame(circ.n, circ.init_bits, seed)
+    arr = circ.array()
+    t0 = time.perf_counter()
+    sizes = f.run(arr)
+    dt = time.perf_counter() - t0
+    U = int(sizes.sum())
+    return {"value": U / dt, "unit": "frame-element gate updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{circ.name}: one full circuit ({len(arr)} gates, U={U}) on one host thread, {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--jobs", type=int, default=3)
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg2L"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--path", default="batched", choices=["batched", "plain"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_1712_03554_amd as sf
+    from paper_1712_03554_amd import workloads as wl
+
+    eng = sf.Engine(0)
+    if args.workload == "cfg2":
+        circs = [wl.config2(j) for j in range(args.jobs)]
+        seeds = [wl.derive_seed(2, j) for j in range(args.jobs)]
+        wname = "random Clifford+T, n=128, 2000 H/S/CNOT + 16 T, measure 16 qubits"
+    else:
+        circs = [wl.config2(j, n_t=24) for j in range(args.jobs)]
+        seeds = [wl.derive_seed(22, j) for j in range(args.jobs)]
+        wname = "random Clifford+T, n=128, 2000 H/S/CNOT + 24 T, measure 16 qubits (HBM probe)"
+    loaded = [eng.load(c.n, c) for c in circs]
+    states = [l.state(c.init_bits, s) for l, c, s in zip(loaded, circs, seeds)]
+    bounds = [l.info()[0] for l in loaded]
+
+    U_total, seg_dims = 0, []
+    for st, c, s in zip(states, circs, seeds):
+        U, dims = accounting(st, c, s, wl)
+        U_total += U
+        seg_dims.append(dims)
+
+    def plain_step():
+        for st, c, s in zip(states, circs, seeds):
+            st.reset(c.init_bits, s)
+            st.run()
+
+    def batched_step():
+        for st, c, s in zip(states, circs, seeds):
+            st.reset(c.init_bits, s)
+        eng.batch_run(states)
+
+    # plain form (one frame at a time), timed for the record
+    for _ in range(args.warmup):
+        plain_step()
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for _ in range(args.steps):
+        plain_step()
+    torch.cuda.synchronize()
+    plain_value = args.steps * U_total / (time.perf_counter() - tp0)
+
+    one_step = batched_step if args.path == "batched" else plain_step
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    eng.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = eng.profile_read()
+    eng.profile(False)
+    cyc = {}
+    for st in states:
+        for k, v in st.track_cycles().items():
+            cyc[k] = cyc.get(k, 0) + v
+    elapsed = t1 - t0
+    value = args.steps * U_total / elapsed
+
+    # roofline of the dominant kernel
+    kinds = {k: v for k, v in prof.items() if v[1] > 0}
+    dom = max(kinds, key=lambda k: kinds[k][0])
+    seg_bytes_per_step = sum(32.0 * (1 << d) for dims in seg_dims for d in dims)
+    seg_ms, seg_n = prof["segment"]
+    roof = None
+    if dom == "segment":
+        avg_s = seg_ms / 1e3 / seg_n
+        bytes_per_launch = seg_bytes_per_step * args.steps / seg_n
+        ach = bytes_per_launch / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": "sf_seg_kernel", "achieved": ach, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": None}
+    else:
+        tr_ms, tr_n = prof["track"]
+        seg_avg = seg_ms / max(seg_n, 1) / 1e3
+        ach = (seg_bytes_per_step * args.steps / max(seg_n, 1)) / seg_avg / 1e9 if seg_n else 0.0
+        roof = {"bound": "latency", "kernel": "sf_track_kernel",
+                "note": "one wavefront per circuit walks the gate sequence; element kernels: "
+                        f"{ach:.1f} GB/s algorithmic",
+                "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                "traffic": None}
+    line = {
+        "metric": "frame-element gate updates/s",
+        "value": value,
+        "unit": "frame-element gate updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": wname, "circuits_per_step": args.jobs, "path": args.path,
+                   "U_per_step": U_total, "frame_bound_log2": bounds},
+        "plain_value": plain_value,
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kinds.items()},
+        "kernel_launches_per_step": {k: v[1] / args.steps for k, v in kinds.items()},
+        "roofline": roof,
+        "track_cycles_last_step": cyc,
+    }
+    if not args.no_cpu and args.workload == "cfg2":
+        line["cpu_baseline"] = cpu_baseline(circs[0], seeds[0])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -114,6 +114,12 @@ sf_status sf_circuit_destroy(sf_circuit* c);
 sf_status sf_state_init(sf_ctx* ctx, const sf_circuit* c, const uint64_t* basis_bits, uint64_t seed,
                         sf_state** out);
 sf_status sf_state_destroy(sf_state* s);
+/* Set an existing state back to |b> with a new seed, without allocating;
+ * the circuit restarts from its first gate.  Asynchronous. */
+sf_status sf_state_reset(sf_state* s, const uint64_t* basis_bits, uint64_t seed);
+/* Dimension of the affine hull of the current phase vectors (|F| <= 2^d);
+ * synchronises. */
+sf_status sf_state_dim(sf_state* s, uint32_t* d);
 
 /* Queue up to max_gates further gates of the circuit (counted as given to
  * sf_circuit_load); stops after each measurement.  *gates_applied receives
@@ -121,6 +127,11 @@ sf_status sf_state_destroy(sf_state* s);
 sf_status sf_step(sf_state* s, size_t max_gates, size_t* gates_applied);
 /* Queue every remaining gate.  Asynchronous. */
 sf_status sf_run(sf_state* s);
+/* Run every remaining gate of n_states states (all of this context) as one
+ * batch: per round, the tableau tracks of all frames share one launch (one
+ * wavefront each) and the element kernels of all frames share one launch per
+ * segment.  Results are identical to running each state alone.  Synchronises. */
+sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t n_states);
 /* Wait for queued work; reports device-side failures of the queued steps. */
 sf_status sf_sync(sf_state* s);
 
@@ -138,6 +149,21 @@ sf_status sf_read_frame(sf_state* s, uint64_t* tableau, uint64_t* sigma, double*
 /* Gates of the circuit applied so far and whether a measurement result was
  * fragile (|u - p(1)| < 1e-12 or p(outcome) = 0). */
 sf_status sf_state_info(sf_state* s, size_t* gates_done, int* fragile);
+
+/* Per-kernel device time, measured with HIP events on the context stream.
+ * sf_profile(ctx, 1) starts collecting (and clears the totals), 0 stops.
+ * sf_profile_read returns total milliseconds and launch counts per kernel
+ * kind: 0 tableau track, 1 segment (phase + cofactor), 2 measurement
+ * reduction, 3 measurement coin, 4 measurement filter, 5 readout, 6 state
+ * initialisation.  Both synchronise. */
+sf_status sf_profile(sf_ctx* ctx, int enable);
+sf_status sf_profile_read(sf_ctx* ctx, double* ms, uint64_t* launches, int n_kinds);
+/* Shader clocks the tableau track of this state spent per phase since the
+ * last init/reset: 0 saving the pre-gate tableau, 1 column updates, 2 echelon
+ * repair, 3 index and b* images, 4 phase sampling, 5 fitting of Hadamard
+ * terms, 6 cofactor/measurement steps, 7 total, 8-10 parts of the repair (checks,
+ * row products, replay on the hull), 11 spare.  Synchronises. */
+sf_status sf_state_cycles(sf_state* s, uint64_t* cycles, int n);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,10 @@ STATUS_NAMES = ["SF_OK", "SF_E_INVALID", "SF_E_OOM", "SF_E_DEVICE", "SF_E_TOO_LA
 
 EXPORTS = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_circuit_load", "sf_circuit_info",
            "sf_circuit_destroy", "sf_state_init", "sf_state_destroy", "sf_step", "sf_run", "sf_sync",
-           "sf_outcomes", "sf_frame_size", "sf_read_frame", "sf_state_info"]
+           "sf_outcomes", "sf_frame_size", "sf_read_frame", "sf_state_info", "sf_state_reset",
+           "sf_state_dim", "sf_profile", "sf_profile_read", "sf_state_cycles", "sf_batch_run"]
+
+KERNEL_KINDS = ["track", "segment", "meas_reduce", "meas_coin", "meas_filter", "readout", "init"]
 
 
 class SFrameError(RuntimeError):
@@ -70,6 +73,12 @@ def load_library(path: str = LIB_PATH):
         "sf_frame_size": [vp, P(u64)],
         "sf_read_frame": [vp, vp, vp, vp, sz, P(sz)],
         "sf_state_info": [vp, P(sz), P(ctypes.c_int)],
+        "sf_state_reset": [vp, vp, u64],
+        "sf_state_dim": [vp, P(ctypes.c_uint32)],
+        "sf_profile": [vp, ctypes.c_int],
+        "sf_profile_read": [vp, vp, vp, ctypes.c_int],
+        "sf_state_cycles": [vp, vp, ctypes.c_int],
+        "sf_batch_run": [vp, vp, sz],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -136,6 +145,21 @@ class Engine:
         self._check(self._L.sf_circuit_load(self._h, n, _ptr(arr), len(arr), ctypes.byref(h)))
         return Circuit(self, h, n)
 
+    def batch_run(self, states):
+        """Run every remaining gate of the given states as one batch (synchronises)."""
+        arr = (ctypes.c_void_p * max(1, len(states)))(*[s._h.value for s in states])
+        self._check(self._L.sf_batch_run(self._h, ctypes.cast(arr, ctypes.c_void_p), len(states)))
+
+    def profile(self, enable: bool):
+        self._check(self._L.sf_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        k = len(KERNEL_KINDS)
+        ms = np.zeros(k, dtype=np.float64)
+        cnt = np.zeros(k, dtype=np.uint64)
+        self._check(self._L.sf_profile_read(self._h, _ptr(ms), _ptr(cnt), k))
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(KERNEL_KINDS)}
+
     def close(self):
         if getattr(self, "_h", None):
             self._L.sf_ctx_destroy(self._h)
@@ -185,6 +209,28 @@ class State:
 
     def _check(self, st):
         self.circ.eng._check(st)
+
+    def reset(self, basis_bits=None, seed: int = 0):
+        words = None
+        if basis_bits is not None:
+            words = np.zeros(self.W, dtype=np.uint64)
+            for q, b in enumerate(basis_bits):
+                if int(b) & 1:
+                    words[q >> 6] |= np.uint64(1 << (q & 63))
+        self._check(self._L.sf_state_reset(self._h, _ptr(words), ctypes.c_uint64(seed & ((1 << 64) - 1))))
+
+    TRACK_PHASES = ["save", "columns", "repair", "index", "sampling", "fit", "cofactor", "total",
+                    "repair_check", "repair_rowmul", "repair_replay", "spare"]
+
+    def track_cycles(self) -> dict:
+        c = np.zeros(12, dtype=np.uint64)
+        self._check(self._L.sf_state_cycles(self._h, _ptr(c), 12))
+        return {k: int(c[i]) for i, k in enumerate(self.TRACK_PHASES)}
+
+    def dim(self) -> int:
+        d = ctypes.c_uint32()
+        self._check(self._L.sf_state_dim(self._h, ctypes.byref(d)))
+        return int(d.value)
 
     def step(self, max_gates: int) -> int:
         k = ctypes.c_size_t()

@@ -19,6 +19,8 @@
 #include "sf_dev.h"
 #include "track.hip"
 
+enum { PK_TRACK = 0, PK_SEG, PK_MREDUCE, PK_MFINAL, PK_MFILTER, PK_READOUT, PK_INIT, PK_N };
+
 struct sf_ctx {
   int device;
   hipStream_t stream;
@@ -26,7 +28,45 @@ struct sf_ctx {
   int has_alloc;
   uint64_t budget, in_use;
   char err[512];
+  // per-kernel timing with HIP events on the context stream
+  int prof;
+  std::vector<hipEvent_t> ev;   // pairs (start, end)
+  std::vector<int> ev_kind;
+  size_t ev_used;
+  double prof_ms[PK_N];
+  uint64_t prof_n[PK_N];
 };
+
+static void prof_begin(sf_ctx* ctx, int kind) {
+  if (!ctx->prof) return;
+  size_t i = ctx->ev_used;
+  if (2 * i + 2 > ctx->ev.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+    ctx->ev.push_back(a);
+    ctx->ev.push_back(b);
+    ctx->ev_kind.push_back(kind);
+  }
+  ctx->ev_kind[i] = kind;
+  (void)hipEventRecord(ctx->ev[2 * i], ctx->stream);
+}
+
+static void prof_end(sf_ctx* ctx) {
+  if (!ctx->prof || 2 * ctx->ev_used + 2 > ctx->ev.size()) return;
+  (void)hipEventRecord(ctx->ev[2 * ctx->ev_used + 1], ctx->stream);
+  ctx->ev_used++;
+}
+
+static void prof_collect(sf_ctx* ctx) {
+  for (size_t i = 0; i < ctx->ev_used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[2 * i], ctx->ev[2 * i + 1]) == hipSuccess) {
+      ctx->prof_ms[ctx->ev_kind[i]] += ms;
+      ctx->prof_n[ctx->ev_kind[i]] += 1;
+    }
+  }
+  ctx->ev_used = 0;
+}
 
 struct DevBuf {
   void* p = nullptr;
@@ -103,6 +143,12 @@ extern "C" sf_status sf_ctx_create(int device, void* hip_stream, const sf_alloca
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return SF_E_DEVICE;
   if (device < 0 || device >= ndev) return SF_E_INVALID;
   if (hipSetDevice(device) != hipSuccess) return SF_E_DEVICE;
+  // the tableau track keeps the tableau, its column-major copy and the hull
+  // in LDS: it needs a device with more than 64 KiB per workgroup (gfx950)
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess ||
+      lds < (int)(sizeof(TrackLdsProbe) + 1024))
+    return SF_E_DEVICE;
   sf_ctx* c = new (std::nothrow) sf_ctx();
   if (!c) return SF_E_OOM;
   c->device = device;
@@ -112,12 +158,37 @@ extern "C" sf_status sf_ctx_create(int device, void* hip_stream, const sf_alloca
   c->budget = hbm_budget_bytes;
   c->in_use = 0;
   c->err[0] = 0;
+  c->prof = 0;
+  c->ev_used = 0;
+  for (int k = 0; k < PK_N; ++k) { c->prof_ms[k] = 0; c->prof_n[k] = 0; }
   *out = c;
   return SF_OK;
 }
 
 extern "C" sf_status sf_ctx_destroy(sf_ctx* ctx) {
+  if (!ctx) return SF_OK;
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   delete ctx;
+  return SF_OK;
+}
+
+extern "C" sf_status sf_profile(sf_ctx* ctx, int enable) {
+  if (!ctx) return SF_E_INVALID;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  prof_collect(ctx);
+  ctx->prof = enable ? 1 : 0;
+  for (int k = 0; k < PK_N; ++k) { ctx->prof_ms[k] = 0; ctx->prof_n[k] = 0; }
+  return SF_OK;
+}
+
+extern "C" sf_status sf_profile_read(sf_ctx* ctx, double* ms, uint64_t* launches, int nk) {
+  if (!ctx) return SF_E_INVALID;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  prof_collect(ctx);
+  for (int k = 0; k < nk && k < PK_N; ++k) {
+    if (ms) ms[k] = ctx->prof_ms[k];
+    if (launches) launches[k] = ctx->prof_n[k];
+  }
   return SF_OK;
 }
 
@@ -328,6 +399,50 @@ static int grid_for(int d) {
   return (int)blocks;
 }
 
+static sf_status queue_init(sf_state* s, const uint64_t* basis, uint64_t seed) {
+  sf_ctx* ctx = s->ctx;
+  uint64_t b[4] = {0, 0, 0, 0};
+  const int W = (int)((s->c->n + 63) / 64);
+  if (basis)
+    for (int w = 0; w < W; ++w) b[w] = basis[w];
+  s->cur = 0;
+  s->orig_done = s->dev_done = s->nmeas = 0;
+  s->seed = seed;
+  prof_begin(ctx, PK_INIT);
+  hipLaunchKernelGGL(sf_init_state, dim3(1), dim3(EB), 0, ctx->stream, (TrackState*)s->st.p, (int)s->c->n, b[0],
+                     b[1], b[2], b[3], (double2*)s->amp[0].p, (int*)s->flags.p);
+  prof_end(ctx);
+  HIPCHK(ctx, hipGetLastError());
+  return SF_OK;
+}
+
+extern "C" sf_status sf_state_reset(sf_state* s, const uint64_t* basis, uint64_t seed) {
+  if (!s) return SF_E_INVALID;
+  return queue_init(s, basis, seed);
+}
+
+extern "C" sf_status sf_state_cycles(sf_state* s, uint64_t* cycles, int n) {
+  if (!s || !cycles) return SF_E_INVALID;
+  sf_ctx* ctx = s->ctx;
+  uint64_t c[12];
+  HIPCHK(ctx, hipMemcpyAsync(c, (char*)s->st.p + offsetof(TrackState, cycles), sizeof c, hipMemcpyDeviceToHost,
+                             ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < n && k < 12; ++k) cycles[k] = c[k];
+  return SF_OK;
+}
+
+extern "C" sf_status sf_state_dim(sf_state* s, uint32_t* d) {
+  if (!s || !d) return SF_E_INVALID;
+  sf_ctx* ctx = s->ctx;
+  int hdr[16];
+  HIPCHK(ctx, hipMemcpyAsync(hdr, s->st.p, sizeof hdr, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  // d, pend, pend_r: a measurement's filter is applied to the hull lazily
+  *d = (uint32_t)(hdr[2] - ((hdr[4] && hdr[8]) ? 1 : 0));
+  return SF_OK;
+}
+
 extern "C" sf_status sf_state_init(sf_ctx* ctx, const sf_circuit* c, const uint64_t* basis, uint64_t seed,
                                    sf_state** out) {
   if (!ctx || !c || !out) return SF_E_INVALID;
@@ -355,24 +470,16 @@ extern "C" sf_status sf_state_init(sf_ctx* ctx, const sf_circuit* c, const uint6
     delete s;
     return rc;
   }
-  TrackState* h = (TrackState*)calloc(1, sizeof(TrackState));
-  h->n = (int)c->n;
-  h->W = (int)((c->n + 63) / 64);
-  for (uint32_t q = 0; q < c->n; ++q) h->rz[q * SF_WMAX + (q >> 6)] = 1ull << (q & 63);  // row q = Z_q
-  if (basis)
-    for (int w = 0; w < h->W; ++w) h->s0[w] = basis[w];
-  if (c->n % 64) h->s0[h->W - 1] &= (1ull << (c->n % 64)) - 1ull;
-  double one[2] = {1.0, 0.0};
-  hipError_t e = hipMemcpyAsync(s->st.p, h, sizeof(TrackState), hipMemcpyHostToDevice, ctx->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(s->amp[0].p, one, 16, hipMemcpyHostToDevice, ctx->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(s->flags.p, 0, 8, ctx->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(s->outcomes.p, 0, std::max<size_t>(1, c->n_meas), ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);  // host buffers are on the stack
-  free(h);
-  if (e != hipSuccess) {
+  sf_status r2 = queue_init(s, basis, seed);
+  if (r2 == SF_OK) {
+    hipError_t e = hipMemsetAsync(s->outcomes.p, 0, std::max<size_t>(1, c->n_meas), ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) r2 = fail(ctx, SF_E_DEVICE, "state init: %s", hipGetErrorString(e));
+  }
+  if (r2 != SF_OK) {
     state_free(s);
     delete s;
-    return fail(ctx, SF_E_DEVICE, "state init: %s", hipGetErrorString(e));
+    return r2;
   }
   *out = s;
   return SF_OK;
@@ -401,7 +508,9 @@ static sf_status run_range(sf_state* s, size_t a, size_t b) {
   job.had = (GF2Q*)s->had.p;
   job.outcomes = (const uint8_t*)s->outcomes.p;
   job.dry = 0;
+  prof_begin(ctx, PK_TRACK);
   hipLaunchKernelGGL(sf_track_kernel, dim3(1), dim3(TL), 0, ctx->stream, job, (const TrackJob*)nullptr);
+  prof_end(ctx);
   HIPCHK(ctx, hipGetLastError());
   // segments: one per non-Clifford phase gate or measurement, plus a final one
   int nseg = 0;
@@ -415,18 +524,26 @@ static sf_status run_range(sf_state* s, size_t a, size_t b) {
   const int grid = grid_for(c->dmax);
   const SegProg* prog = (const SegProg*)s->prog.p;
   for (int k = 0; k < nseg; ++k) {
+    prof_begin(ctx, PK_SEG);
     hipLaunchKernelGGL(sf_seg_kernel, dim3(grid), dim3(EB), 0, ctx->stream, prog + k, (const GF2Q*)s->had.p,
                        (double2*)s->amp[s->cur].p);
+    prof_end(ctx);
   }
   if (meas_last) {
     const SegProg* sp = prog + (nseg - 1);
+    prof_begin(ctx, PK_MREDUCE);
     hipLaunchKernelGGL(sf_meas_reduce, dim3(s->G), dim3(EB), 0, ctx->stream, sp, (const double2*)s->amp[s->cur].p,
                        (double2*)s->partials.p);
+    prof_end(ctx);
+    prof_begin(ctx, PK_MFINAL);
     hipLaunchKernelGGL(sf_meas_final, dim3(1), dim3(EB), 0, ctx->stream, sp, (const double2*)s->partials.p, s->G,
                        s->seed, (uint8_t*)s->outcomes.p, (double*)s->pvals.p, (double*)s->scale.p,
                        (int*)s->flags.p);
+    prof_end(ctx);
+    prof_begin(ctx, PK_MFILTER);
     hipLaunchKernelGGL(sf_meas_filter, dim3(grid), dim3(EB), 0, ctx->stream, sp, (const double2*)s->amp[s->cur].p,
                        (double2*)s->amp[s->cur ^ 1].p, (const uint8_t*)s->outcomes.p, (const double*)s->scale.p);
+    prof_end(ctx);
     s->cur ^= 1;
     s->nmeas++;
   }
@@ -579,5 +696,159 @@ extern "C" sf_status sf_read_frame(sf_state* s, uint64_t* tableau, uint64_t* sig
   dfree(ctx, &osig); dfree(ctx, &oamp);
   dfree(ctx, &tsig); dfree(ctx, &flag); dfree(ctx, &counts); dfree(ctx, &total);
   if (e != hipSuccess) return fail(ctx, SF_E_DEVICE, "readout: %s", hipGetErrorString(e));
+  return SF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched execution: every round runs, for each unfinished frame, the gates up
+// to and including its next measurement.  The tableau tracks of all frames
+// share one launch (one wavefront each); the element kernels of segment k of
+// every frame share one launch (grid y = frame).
+// ---------------------------------------------------------------------------
+static void plan_range(const sf_state* s, size_t* a, size_t* b, size_t* orig_after, int* nseg, int* meas_last) {
+  const sf_circuit* c = s->c;
+  size_t o = s->orig_done, e = s->dev_done;
+  *a = s->dev_done;
+  while (o < c->orig_end.size()) {
+    size_t end = c->orig_end[o];
+    bool meas = end > e && c->g[end - 1].op == DG_MEASURE;
+    e = end;
+    ++o;
+    if (meas) break;
+  }
+  *b = e;
+  *orig_after = o;
+  int ns = 0;
+  bool open = false, ml = false;
+  for (size_t i = *a; i < *b; ++i) {
+    int op = c->g[i].op;
+    if (op == DG_NCPHASE || op == DG_MEASURE) { ++ns; open = false; ml = op == DG_MEASURE; }
+    else { open = true; ml = false; }
+  }
+  if (open) ++ns;
+  *nseg = ns;
+  *meas_last = ml ? 1 : 0;
+}
+
+static ElemDesc elem_desc(const sf_state* s, const SegProg* prog) {
+  ElemDesc e;
+  memset(&e, 0, sizeof e);
+  e.prog = prog;
+  e.had = (const GF2Q*)s->had.p;
+  e.amp = (double2*)s->amp[s->cur].p;
+  e.amp_other = (double2*)s->amp[s->cur ^ 1].p;
+  e.partials = (double2*)s->partials.p;
+  e.outcomes = (uint8_t*)s->outcomes.p;
+  e.pvals = (double*)s->pvals.p;
+  e.scale = (double*)s->scale.p;
+  e.flags = (int*)s->flags.p;
+  e.seed = s->seed;
+  e.G = s->G;
+  return e;
+}
+
+extern "C" sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t ns) {
+  if (!ctx || (ns && !states)) return SF_E_INVALID;
+  int maxseg = 1;
+  for (size_t i = 0; i < ns; ++i) {
+    if (!states[i] || states[i]->ctx != ctx) return fail(ctx, SF_E_INVALID, "state %zu is not of this context", i);
+    maxseg = std::max(maxseg, states[i]->c->max_segs);
+  }
+  if (ns == 0) return SF_OK;
+  DevBuf djobs, ddesc;
+  sf_status rc;
+  if ((rc = dalloc(ctx, &djobs, ns * sizeof(TrackJob))) ||
+      (rc = dalloc(ctx, &ddesc, (size_t)(maxseg + 1) * ns * sizeof(ElemDesc)))) {
+    dfree(ctx, &djobs);
+    return rc;
+  }
+  std::vector<std::vector<TrackJob>> keep_jobs;
+  std::vector<std::vector<ElemDesc>> keep_desc;
+  hipError_t e = hipSuccess;
+  for (;;) {
+    std::vector<int> act;
+    std::vector<size_t> A(ns), B(ns), O(ns);
+    std::vector<int> NS(ns), ML(ns);
+    for (size_t i = 0; i < ns; ++i) {
+      sf_state* s = states[i];
+      if (s->orig_done >= s->c->orig_end.size()) continue;
+      plan_range(s, &A[i], &B[i], &O[i], &NS[i], &ML[i]);
+      act.push_back((int)i);
+    }
+    if (act.empty()) break;
+    const int na = (int)act.size();
+    keep_jobs.emplace_back(na);
+    std::vector<TrackJob>& jobs = keep_jobs.back();
+    int kmax = 0, gx = 1, gm = 1;
+    for (int j = 0; j < na; ++j) {
+      sf_state* s = states[act[j]];
+      TrackJob& jb = jobs[j];
+      memset(&jb, 0, sizeof jb);
+      jb.st = (TrackState*)s->st.p;
+      jb.gates = (const DGate*)s->c->dgates.p;
+      jb.g0 = (int)A[act[j]];
+      jb.g1 = (int)B[act[j]];
+      jb.prog = (SegProg*)s->prog.p;
+      jb.had = (GF2Q*)s->had.p;
+      jb.outcomes = (const uint8_t*)s->outcomes.p;
+      kmax = std::max(kmax, NS[act[j]]);
+      gx = std::max(gx, grid_for(s->c->dmax));
+      gm = std::max(gm, s->G);
+    }
+    e = hipMemcpyAsync(djobs.p, jobs.data(), na * sizeof(TrackJob), hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) break;
+    prof_begin(ctx, PK_TRACK);
+    hipLaunchKernelGGL(sf_track_kernel, dim3(na), dim3(TL), 0, ctx->stream, TrackJob{}, (const TrackJob*)djobs.p);
+    prof_end(ctx);
+    keep_desc.emplace_back((size_t)(kmax + 1) * na);
+    std::vector<ElemDesc>& D = keep_desc.back();
+    for (int k = 0; k <= kmax; ++k)
+      for (int j = 0; j < na; ++j) {
+        sf_state* s = states[act[j]];
+        const SegProg* base = (const SegProg*)s->prog.p;
+        const SegProg* p = nullptr;
+        if (k < kmax) p = k < NS[act[j]] ? base + k : nullptr;
+        else p = ML[act[j]] ? base + (NS[act[j]] - 1) : nullptr;  // measurement descriptors
+        D[(size_t)k * na + j] = elem_desc(s, p);
+      }
+    e = hipMemcpyAsync(ddesc.p, D.data(), D.size() * sizeof(ElemDesc), hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) break;
+    const ElemDesc* dd = (const ElemDesc*)ddesc.p;
+    for (int k = 0; k < kmax; ++k) {
+      prof_begin(ctx, PK_SEG);
+      hipLaunchKernelGGL(sf_seg_batch, dim3(gx, na), dim3(EB), 0, ctx->stream, dd + (size_t)k * na);
+      prof_end(ctx);
+    }
+    bool anym = false;
+    for (int j = 0; j < na; ++j) anym |= ML[act[j]] != 0;
+    if (anym) {
+      const ElemDesc* dm = dd + (size_t)kmax * na;
+      prof_begin(ctx, PK_MREDUCE);
+      hipLaunchKernelGGL(sf_meas_reduce_batch, dim3(gm, na), dim3(EB), 0, ctx->stream, dm);
+      prof_end(ctx);
+      prof_begin(ctx, PK_MFINAL);
+      hipLaunchKernelGGL(sf_meas_final_batch, dim3(1, na), dim3(EB), 0, ctx->stream, dm);
+      prof_end(ctx);
+      prof_begin(ctx, PK_MFILTER);
+      hipLaunchKernelGGL(sf_meas_filter_batch, dim3(gx, na), dim3(EB), 0, ctx->stream, dm);
+      prof_end(ctx);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) break;
+    for (int j = 0; j < na; ++j) {
+      sf_state* s = states[act[j]];
+      s->dev_done = B[act[j]];
+      s->orig_done = O[act[j]];
+      if (ML[act[j]]) { s->cur ^= 1; s->nmeas++; }
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  dfree(ctx, &djobs);
+  dfree(ctx, &ddesc);
+  if (e != hipSuccess) return fail(ctx, SF_E_DEVICE, "batch run: %s", hipGetErrorString(e));
+  for (size_t i = 0; i < ns; ++i) {
+    rc = check_track(states[i]);
+    if (rc != SF_OK) return rc;
+  }
   return SF_OK;
 }

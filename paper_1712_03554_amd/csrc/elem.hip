@@ -94,14 +94,15 @@ __device__ __forceinline__ uint32_t insert_zero(uint64_t r, int j) {
   return (uint32_t)(lo | ((r >> j) << (j + 1)));
 }
 
-extern "C" __global__ void __launch_bounds__(EB)
-sf_seg_kernel(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all, double2* __restrict__ amp) {
+// ---------------------------------------------------------------------------
+// Segment: Clifford phases, then the terminal step of the segment
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void seg_body(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all,
+                                         double2* __restrict__ amp, uint64_t tid, uint64_t stride) {
   const int kind = sp->kind;
   const int d = sp->d;
   const GF2Q* had = had_all + sp->had_off;
   const uint64_t N = 1ull << d;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const double pre = sp->ph_re, pim = sp->ph_im;
   if (kind == SEG_PAIR) {
     const int j0 = sp->j0;
@@ -140,15 +141,16 @@ sf_seg_kernel(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all, 
   }
 }
 
-// Measurement: block partial sums of |a|^2 split by the qubit value.
-extern "C" __global__ void __launch_bounds__(EB)
-sf_meas_reduce(const SegProg* __restrict__ sp, const double2* __restrict__ amp, double2* __restrict__ partials) {
+// Measurement: block partial sums of |a|^2 split by the qubit value; block b
+// of G covers slots b*EB + t, stepping by G*EB (a fixed reduction shape).
+__device__ __forceinline__ void meas_reduce_body(const SegProg* __restrict__ sp, const double2* __restrict__ amp,
+                                                 double2* __restrict__ partials, int block, int G) {
   __shared__ double s0[EB], s1[EB];
   const uint64_t N = 1ull << sp->d_out;
   const uint32_t c0 = sp->m_c0, r = sp->m_r;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t stride = (uint64_t)G * EB;
   double p0 = 0.0, p1 = 0.0;
-  for (uint64_t Y = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; Y < N; Y += stride) {
+  for (uint64_t Y = (uint64_t)block * EB + threadIdx.x; Y < N; Y += stride) {
     double v = norm2(amp[Y]);
     if ((c0 ^ (uint32_t)__popc(r & (uint32_t)Y)) & 1u) p1 = __dadd_rn(p1, v);
     else p0 = __dadd_rn(p0, v);
@@ -163,7 +165,7 @@ sf_meas_reduce(const SegProg* __restrict__ sp, const double2* __restrict__ amp, 
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) partials[blockIdx.x] = make_double2(s0[0], s1[0]);
+  if (threadIdx.x == 0) partials[block] = make_double2(s0[0], s1[0]);
 }
 
 __device__ __forceinline__ uint64_t splitmix64_at(uint64_t state, uint64_t index) {
@@ -175,10 +177,10 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t state, uint64_t index
 }
 
 // One block: fixed-order sum of the partials, seeded biased coin, outcome.
-extern "C" __global__ void __launch_bounds__(EB)
-sf_meas_final(const SegProg* __restrict__ sp, const double2* __restrict__ partials, int G, uint64_t seed,
-              uint8_t* __restrict__ outcomes, double* __restrict__ pvals, double* __restrict__ scale,
-              int* __restrict__ flags) {
+__device__ __forceinline__ void meas_final_body(const SegProg* __restrict__ sp, const double2* __restrict__ partials,
+                                                int G, uint64_t seed, uint8_t* __restrict__ outcomes,
+                                                double* __restrict__ pvals, double* __restrict__ scale,
+                                                int* __restrict__ flags) {
   __shared__ double s0[EB], s1[EB];
   double p0 = 0.0, p1 = 0.0;
   for (int i = threadIdx.x; i < G; i += EB) {
@@ -209,17 +211,15 @@ sf_meas_final(const SegProg* __restrict__ sp, const double2* __restrict__ partia
 }
 
 // Keep the elements consistent with the outcome and renormalise (new buffer).
-extern "C" __global__ void __launch_bounds__(EB)
-sf_meas_filter(const SegProg* __restrict__ sp, const double2* __restrict__ src, double2* __restrict__ dst,
-               const uint8_t* __restrict__ outcomes, const double* __restrict__ scale) {
+__device__ __forceinline__ void meas_filter_body(const SegProg* __restrict__ sp, const double2* __restrict__ src,
+                                                 double2* __restrict__ dst, const uint8_t* __restrict__ outcomes,
+                                                 const double* __restrict__ scale, uint64_t tid, uint64_t stride) {
   const int mi = sp->meas_index;
   const uint32_t o = outcomes[mi];
   const double s = scale[0];
   const uint32_t c0 = sp->m_c0, r = sp->m_r;
   const int j0 = sp->m_j0;
   const int dout = sp->d_out;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r == 0) {
     const uint64_t N = 1ull << dout;
     for (uint64_t Y = tid; Y < N; Y += stride) {
@@ -235,6 +235,63 @@ sf_meas_filter(const SegProg* __restrict__ sp, const double2* __restrict__ src, 
       dst[Yp] = make_double2(__dmul_rn(a.x, s), __dmul_rn(a.y, s));
     }
   }
+}
+
+#define TID ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x)
+#define STRIDE ((uint64_t)gridDim.x * blockDim.x)
+
+extern "C" __global__ void __launch_bounds__(EB)
+sf_seg_kernel(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all, double2* __restrict__ amp) {
+  seg_body(sp, had_all, amp, TID, STRIDE);
+}
+
+extern "C" __global__ void __launch_bounds__(EB)
+sf_meas_reduce(const SegProg* __restrict__ sp, const double2* __restrict__ amp, double2* __restrict__ partials) {
+  meas_reduce_body(sp, amp, partials, blockIdx.x, gridDim.x);
+}
+
+extern "C" __global__ void __launch_bounds__(EB)
+sf_meas_final(const SegProg* __restrict__ sp, const double2* __restrict__ partials, int G, uint64_t seed,
+              uint8_t* __restrict__ outcomes, double* __restrict__ pvals, double* __restrict__ scale,
+              int* __restrict__ flags) {
+  meas_final_body(sp, partials, G, seed, outcomes, pvals, scale, flags);
+}
+
+extern "C" __global__ void __launch_bounds__(EB)
+sf_meas_filter(const SegProg* __restrict__ sp, const double2* __restrict__ src, double2* __restrict__ dst,
+               const uint8_t* __restrict__ outcomes, const double* __restrict__ scale) {
+  meas_filter_body(sp, src, dst, outcomes, scale, TID, STRIDE);
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms: blockIdx.y selects the frame (ElemDesc), blockIdx.x and the
+// block's threads stride over that frame's slots.
+// ---------------------------------------------------------------------------
+#define BTID ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x)
+#define BSTRIDE ((uint64_t)gridDim.x * blockDim.x)
+
+extern "C" __global__ void __launch_bounds__(EB) sf_seg_batch(const ElemDesc* __restrict__ D) {
+  const ElemDesc& e = D[blockIdx.y];
+  if (!e.prog) return;
+  seg_body(e.prog, e.had, e.amp, BTID, BSTRIDE);
+}
+
+extern "C" __global__ void __launch_bounds__(EB) sf_meas_reduce_batch(const ElemDesc* __restrict__ D) {
+  const ElemDesc& e = D[blockIdx.y];
+  if (!e.prog || (int)blockIdx.x >= e.G) return;
+  meas_reduce_body(e.prog, e.amp, e.partials, blockIdx.x, e.G);
+}
+
+extern "C" __global__ void __launch_bounds__(EB) sf_meas_final_batch(const ElemDesc* __restrict__ D) {
+  const ElemDesc& e = D[blockIdx.y];
+  if (!e.prog) return;
+  meas_final_body(e.prog, e.partials, e.G, e.seed, e.outcomes, e.pvals, e.scale, e.flags);
+}
+
+extern "C" __global__ void __launch_bounds__(EB) sf_meas_filter_batch(const ElemDesc* __restrict__ D) {
+  const ElemDesc& e = D[blockIdx.y];
+  if (!e.prog) return;
+  meas_filter_body(e.prog, e.amp, e.amp_other, e.outcomes, e.scale, BTID, BSTRIDE);
 }
 
 // Number of non-zero amplitudes (frame size |F|).
@@ -354,5 +411,32 @@ sf_compact_write(const uint8_t* __restrict__ flag, const uint64_t* __restrict__ 
       oamp[pos] = tamp[i];
       ++pos;
     }
+  }
+}
+
+// Basis state |b>: stabilizer matrix in basis form (row q = Z_q, Figure 2a),
+// phase vector sigma = b, one element of amplitude 1.
+extern "C" __global__ void __launch_bounds__(EB)
+sf_init_state(TrackState* __restrict__ st, int n, uint64_t b0, uint64_t b1, uint64_t b2, uint64_t b3,
+              double2* __restrict__ amp, int* __restrict__ flags) {
+  const int W = (n + 63) / 64;
+  for (int i = threadIdx.x; i < SF_NMAX * SF_WMAX; i += blockDim.x) {
+    int q = i / SF_WMAX, w = i % SF_WMAX;
+    st->rx[i] = 0ull;
+    st->rz[i] = (q < n && w == (q >> 6)) ? (1ull << (q & 63)) : 0ull;
+  }
+  if (threadIdx.x == 0) {
+    st->n = n; st->W = W; st->d = 0; st->nmeas = 0;
+    st->pend = 0; st->pend_j0 = -1; st->pend_c0 = 0; st->pend_meas = -1; st->pend_r = 0;
+    st->dmax = 0; st->error = 0; st->pad = 0;
+    for (int k = 0; k < 12; ++k) st->cycles[k] = 0;
+    uint64_t b[4] = {b0, b1, b2, b3};
+    for (int w = 0; w < SF_WMAX; ++w) {
+      uint64_t m = w < W ? ~0ull : 0ull;
+      if (w == W - 1 && (n & 63)) m = (1ull << (n & 63)) - 1ull;
+      st->s0[w] = b[w] & m;
+    }
+    amp[0] = make_double2(1.0, 0.0);
+    *flags = 0;
   }
 }

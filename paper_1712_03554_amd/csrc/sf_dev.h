@@ -75,6 +75,7 @@ struct TrackState {
   uint64_t rz[SF_NMAX * SF_WMAX];
   uint64_t s0[SF_WMAX];
   uint64_t V[SF_DMAX][SF_WMAX];
+  uint64_t cycles[12];     // shader clocks spent per phase of the track (profiling)
 };
 
 // One circuit range for the tableau-track kernel.
@@ -101,4 +102,19 @@ struct ReadoutInfo {
   uint64_t s0[SF_WMAX];
   uint64_t V[SF_DMAX][SF_WMAX];
   uint64_t tab[SF_NMAX * 2 * SF_WMAX];
+};
+
+// One frame's element-kernel arguments in a batched launch.
+struct ElemDesc {
+  const SegProg* prog;     // program of this launch's segment (nullptr: idle)
+  const GF2Q* had;
+  double2* amp;            // current amplitude buffer
+  double2* amp_other;      // measurement filter target
+  double2* partials;
+  uint8_t* outcomes;
+  double* pvals;
+  double* scale;
+  int* flags;
+  uint64_t seed;
+  int32_t G, pad;
 };

@@ -229,3 +229,30 @@ def test_frame_size_and_determinism(eng):
     ta, sa, aa = a.read_frame()
     tb, sb, ab = b.read_frame()
     assert np.array_equal(sa, sb) and np.array_equal(aa.view(np.uint64), ab.view(np.uint64))
+
+
+def test_batch_matches_alone(eng):
+    """Each frame's result in a batched run equals its result run alone (bit
+    for bit: same kernels, same reduction shapes), and matches the oracle."""
+    circs = [wl.config1(j) for j in range(4)] + [wl.config3(t) for t in range(6)] + \
+            [_mixed_circuit(s, 3 + s) for s in range(4)] + [wl.config4(1)]
+    seeds = list(range(100, 100 + len(circs)))
+    alone = []
+    for c, s in zip(circs, seeds):
+        st = eng.load(c.n, c).state(c.init_bits, s)
+        st.run()
+        alone.append((st.read_frame(), st.outcomes()))
+    loaded = [eng.load(c.n, c) for c in circs]
+    states = [l.state(c.init_bits, s) for l, c, s in zip(loaded, circs, seeds)]
+    eng.batch_run(states)
+    for c, s, st, (fa, oa) in zip(circs, seeds, states, alone):
+        tab, sig, amp = st.read_frame()
+        assert np.array_equal(tab, fa[0]) and np.array_equal(sig, fa[1]), c.name
+        assert np.array_equal(amp.view(np.uint64), fa[2].view(np.uint64)), c.name
+        assert st.outcomes() == oa, c.name
+        ref = OracleFrame(c.n, c.init_bits, s)
+        ref.run(c.array())
+        rtab, rsig, ramp = ref.read()
+        assert np.array_equal(tab, rtab), c.name
+        assert_frames_equal(sigma_ints(sig), amp, sigma_ints(rsig), ramp, what=c.name)
+        assert st.outcomes() == ref.outcomes(), c.name
