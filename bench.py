@@ -23,6 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz 32-bit ops; a 64-bit bitwise word op is two
+PEAK_WORD_GOPS = 256 * 4 * 16 * 2.4 / 2
 TERMINAL_OPS = None
 
 
@@ -154,22 +156,23 @@ def main():
     dom = max(kinds, key=lambda k: kinds[k][0])
     seg_bytes_per_step = sum(32.0 * (1 << d) for dims in seg_dims for d in dims)
     seg_ms, seg_n = prof["segment"]
-    roof = None
+    seg_ach = (seg_bytes_per_step * args.steps / max(seg_n, 1)) / (seg_ms / 1e3 / max(seg_n, 1)) / 1e9 \
+        if seg_n else 0.0
+    elem_roof = {"bound": "hbm", "kernel": "sf_seg_batch" if args.path == "batched" else "sf_seg_kernel",
+                 "achieved": seg_ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": seg_ach / PEAK_HBM_GBS,
+                 "traffic": None,
+                 "note": "32 B per slot (read + write of 16 B) over 2^d slots per segment launch"}
     if dom == "segment":
-        avg_s = seg_ms / 1e3 / seg_n
-        bytes_per_launch = seg_bytes_per_step * args.steps / seg_n
-        ach = bytes_per_launch / avg_s / 1e9
-        roof = {"bound": "hbm", "kernel": "sf_seg_kernel", "achieved": ach, "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": None}
+        roof = dict(elem_roof)
     else:
+        # tableau track: one pass over the n rows per gate (4 n W 64-bit words)
         tr_ms, tr_n = prof["track"]
-        seg_avg = seg_ms / max(seg_n, 1) / 1e3
-        ach = (seg_bytes_per_step * args.steps / max(seg_n, 1)) / seg_avg / 1e9 if seg_n else 0.0
-        roof = {"bound": "latency", "kernel": "sf_track_kernel",
-                "note": "one wavefront per circuit walks the gate sequence; element kernels: "
-                        f"{ach:.1f} GB/s algorithmic",
-                "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-                "traffic": None}
+        words_per_step = sum(len(c.gates) * 4 * c.n * ((c.n + 63) // 64) for c in circs)
+        ach = (words_per_step * args.steps / tr_n) / (tr_ms / 1e3 / tr_n) / 1e9
+        roof = {"bound": "alu", "kernel": "sf_track_kernel", "achieved": ach, "peak": PEAK_WORD_GOPS,
+                "unit": "G 64-bit word-ops/s", "frac": ach / PEAK_WORD_GOPS, "traffic": None,
+                "note": "one wavefront per circuit walks the gates; bound by the dependent LDS/VALU latency of "
+                        "that wavefront, not by throughput"}
     line = {
         "metric": "frame-element gate updates/s",
         "value": value,
@@ -189,6 +192,7 @@ def main():
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kinds.items()},
         "kernel_launches_per_step": {k: v[1] / args.steps for k, v in kinds.items()},
         "roofline": roof,
+        "element_roofline": elem_roof,
         "track_cycles_last_step": cyc,
     }
     if not args.no_cpu and args.workload == "cfg2":

@@ -47,8 +47,17 @@ typedef Lds TrackLdsProbe;
 // phases: 0 save, 1 column update, 2 repair, 3 index+b* images, 4 sampling,
 // 5 fitting, 6 cofactor, 7 total, 8 repair checks, 9 repair row products,
 // 10 repair replay on the hull
+// (compiled in with -DSF_TRACK_TIMERS; each reading waits for outstanding LDS
+// traffic, so the counters are off in normal builds)
+#ifdef SF_TRACK_TIMERS
 #define TIC(k) do { if (lane_id() == 0) L.tc[k] -= clock64(); } while (0)
 #define TOC(k) do { if (lane_id() == 0) L.tc[k] += clock64(); } while (0)
+#define TCLOCK() clock64()
+#else
+#define TIC(k) do { } while (0)
+#define TOC(k) do { } while (0)
+#define TCLOCK() 0ull
+#endif
 
 __device__ __forceinline__ int getb(const uint64_t* v, int q) { return (int)((v[q >> 6] >> (q & 63)) & 1ull); }
 __device__ __forceinline__ void flipb(uint64_t* v, int q) { v[q >> 6] ^= 1ull << (q & 63); }
@@ -985,7 +994,7 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
     st->pend_r = pend_r; st->pend_c0 = pend_c0; st->pend_j0 = pend_j0; st->pend_meas = pend_meas;
     st->dmax = dmax;
     if (err && !st->error) st->error = err;
-    L.tc[7] += clock64();
+    L.tc[7] += TCLOCK();
     for (int k = 0; k < 12; ++k) st->cycles[k] += L.tc[k];
   }
 }
