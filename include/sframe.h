@@ -87,6 +87,7 @@ typedef struct {
 typedef struct sf_ctx sf_ctx;
 typedef struct sf_circuit sf_circuit;
 typedef struct sf_state sf_state;
+typedef struct sf_server sf_server;
 
 /* Create a context on HIP device `device` that queues work on `hip_stream`
  * (a hipStream_t; NULL = the null stream).  `alloc` may be NULL.
@@ -149,6 +150,27 @@ sf_status sf_read_frame(sf_state* s, uint64_t* tableau, uint64_t* sigma, double*
 /* Gates of the circuit applied so far and whether a measurement result was
  * fragile (|u - p(1)| < 1e-12 or p(outcome) = 0). */
 sf_status sf_state_info(sf_state* s, size_t* gates_done, int* fragile);
+
+/* Serving with continuous batching.  Jobs are admitted in arrival order while
+ * their projected device bytes (sf_circuit_info) fit budget_bytes (0 = no
+ * bound) and fewer than max_resident jobs are resident.  Each sf_serve_tick
+ * admits what fits, runs one batched round over all resident frames (each
+ * advances to its next measurement or to its end), synchronises and retires
+ * finished jobs, whose memory stays reserved until sf_serve_release.  A job's
+ * result does not depend on what else is resident.  Job status: 0 queued,
+ * 1 resident, 2 done, 3 cancelled, 4 failed.  sf_serve_submit returns
+ * SF_E_TOO_LARGE for a job that can never fit. */
+sf_status sf_serve_create(sf_ctx* ctx, uint64_t budget_bytes, uint32_t max_resident, sf_server** out);
+sf_status sf_serve_submit(sf_server* sv, const sf_circuit* c, const uint64_t* basis_bits, uint64_t seed,
+                          uint64_t* job_id);
+sf_status sf_serve_tick(sf_server* sv, uint32_t* n_resident, uint32_t* n_queued);
+/* *state receives the finished state (owned by the server) when status is 2. */
+sf_status sf_serve_poll(sf_server* sv, uint64_t job_id, int* status, sf_state** state);
+sf_status sf_serve_release(sf_server* sv, uint64_t job_id);
+sf_status sf_serve_cancel(sf_server* sv, uint64_t job_id);
+sf_status sf_serve_stats(sf_server* sv, uint64_t* ticks, uint64_t* admitted, uint64_t* rejected,
+                         uint64_t* used_bytes);
+sf_status sf_serve_destroy(sf_server* sv);
 
 /* Per-kernel device time, measured with HIP events on the context stream.
  * sf_profile(ctx, 1) starts collecting (and clears the totals), 0 stops.

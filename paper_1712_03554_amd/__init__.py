@@ -26,7 +26,9 @@ STATUS_NAMES = ["SF_OK", "SF_E_INVALID", "SF_E_OOM", "SF_E_DEVICE", "SF_E_TOO_LA
 EXPORTS = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_circuit_load", "sf_circuit_info",
            "sf_circuit_destroy", "sf_state_init", "sf_state_destroy", "sf_step", "sf_run", "sf_sync",
            "sf_outcomes", "sf_frame_size", "sf_read_frame", "sf_state_info", "sf_state_reset",
-           "sf_state_dim", "sf_profile", "sf_profile_read", "sf_state_cycles", "sf_batch_run"]
+           "sf_state_dim", "sf_profile", "sf_profile_read", "sf_state_cycles", "sf_batch_run",
+           "sf_serve_create", "sf_serve_submit", "sf_serve_tick", "sf_serve_poll", "sf_serve_release",
+           "sf_serve_cancel", "sf_serve_stats", "sf_serve_destroy"]
 
 KERNEL_KINDS = ["track", "segment", "meas_reduce", "meas_coin", "meas_filter", "readout", "init"]
 
@@ -79,6 +81,14 @@ def load_library(path: str = LIB_PATH):
         "sf_profile_read": [vp, vp, vp, ctypes.c_int],
         "sf_state_cycles": [vp, vp, ctypes.c_int],
         "sf_batch_run": [vp, vp, sz],
+        "sf_serve_create": [vp, u64, ctypes.c_uint32, P(vp)],
+        "sf_serve_submit": [vp, vp, vp, u64, P(u64)],
+        "sf_serve_tick": [vp, P(ctypes.c_uint32), P(ctypes.c_uint32)],
+        "sf_serve_poll": [vp, u64, P(ctypes.c_int), P(vp)],
+        "sf_serve_release": [vp, u64],
+        "sf_serve_cancel": [vp, u64],
+        "sf_serve_stats": [vp, P(u64), P(u64), P(u64), P(u64)],
+        "sf_serve_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -201,8 +211,8 @@ class Circuit:
 
 
 class State:
-    def __init__(self, circ: Circuit, h):
-        self.circ, self._h = circ, h
+    def __init__(self, circ: Circuit, h, owned: bool = True):
+        self.circ, self._h, self._owned = circ, h, owned
         self.n = circ.n
         self.W = (circ.n + 63) // 64
         self._L = circ.eng._L
@@ -274,8 +284,69 @@ class State:
         return tab, sig[:k], (amp[0::2] + 1j * amp[1::2])[:k]
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and getattr(self, "_owned", True):
             self._L.sf_state_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Server:
+    """Continuous-batching request loop over one Engine (see sf_serve_* in sframe.h)."""
+
+    QUEUED, RESIDENT, DONE, CANCELLED, FAILED = range(5)
+
+    def __init__(self, eng: Engine, budget_bytes: int = 0, max_resident: int = 64):
+        self.eng = eng
+        self._L = eng._L
+        h = ctypes.c_void_p()
+        eng._check(self._L.sf_serve_create(eng._h, budget_bytes, max_resident, ctypes.byref(h)))
+        self._h = h
+        self._circuits = {}
+
+    def submit(self, circ: Circuit, basis_bits=None, seed: int = 0) -> int:
+        words = None
+        if basis_bits is not None:
+            words = np.zeros((circ.n + 63) // 64, dtype=np.uint64)
+            for q, b in enumerate(basis_bits):
+                if int(b) & 1:
+                    words[q >> 6] |= np.uint64(1 << (q & 63))
+        jid = ctypes.c_uint64()
+        self.eng._check(self._L.sf_serve_submit(self._h, circ._h, _ptr(words),
+                                                ctypes.c_uint64(seed & ((1 << 64) - 1)), ctypes.byref(jid)))
+        self._circuits[int(jid.value)] = circ
+        return int(jid.value)
+
+    def tick(self):
+        r, q = ctypes.c_uint32(), ctypes.c_uint32()
+        self.eng._check(self._L.sf_serve_tick(self._h, ctypes.byref(r), ctypes.byref(q)))
+        return int(r.value), int(q.value)
+
+    def poll(self, job_id: int):
+        """(status, State or None); the State belongs to the server."""
+        stt, sh = ctypes.c_int(), ctypes.c_void_p()
+        self.eng._check(self._L.sf_serve_poll(self._h, job_id, ctypes.byref(stt), ctypes.byref(sh)))
+        st = None
+        if stt.value == self.DONE and sh.value:
+            st = State(self._circuits[job_id], sh, owned=False)
+        return int(stt.value), st
+
+    def release(self, job_id: int):
+        self.eng._check(self._L.sf_serve_release(self._h, job_id))
+        self._circuits.pop(job_id, None)
+
+    def cancel(self, job_id: int):
+        self.eng._check(self._L.sf_serve_cancel(self._h, job_id))
+
+    def stats(self):
+        v = [ctypes.c_uint64() for _ in range(4)]
+        self.eng._check(self._L.sf_serve_stats(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(["ticks", "admitted", "rejected", "used_bytes"], [int(x.value) for x in v]))
+
+    def close(self):
+        if getattr(self, "_h", None) and self.eng._h:
+            self._L.sf_serve_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -747,6 +747,117 @@ static ElemDesc elem_desc(const sf_state* s, const SegProg* prog) {
   return e;
 }
 
+// Device descriptor buffers of batched rounds and the host copies they were
+// filled from (kept alive until the stream is synchronised).
+struct BatchScratch {
+  DevBuf djobs, ddesc;
+  std::vector<std::vector<TrackJob>> keep_jobs;
+  std::vector<std::vector<ElemDesc>> keep_desc;
+};
+
+static sf_status scratch_reserve(sf_ctx* ctx, BatchScratch* bs, size_t ns, int maxseg) {
+  size_t need_j = std::max<size_t>(1, ns) * sizeof(TrackJob);
+  size_t need_d = (size_t)(maxseg + 1) * std::max<size_t>(1, ns) * sizeof(ElemDesc);
+  sf_status rc;
+  if (bs->djobs.bytes < need_j) {
+    dfree(ctx, &bs->djobs);
+    if ((rc = dalloc(ctx, &bs->djobs, need_j))) return rc;
+  }
+  if (bs->ddesc.bytes < need_d) {
+    dfree(ctx, &bs->ddesc);
+    if ((rc = dalloc(ctx, &bs->ddesc, need_d))) return rc;
+  }
+  return SF_OK;
+}
+
+static void scratch_free(sf_ctx* ctx, BatchScratch* bs) {
+  dfree(ctx, &bs->djobs);
+  dfree(ctx, &bs->ddesc);
+  bs->keep_jobs.clear();
+  bs->keep_desc.clear();
+}
+
+// Queue one round for the given states: each unfinished state runs its gates
+// up to and including its next measurement.  *active = number of states that
+// had work.  Asynchronous; the scratch must be large enough.
+static sf_status batch_round(sf_ctx* ctx, sf_state* const* states, size_t ns, BatchScratch* bs, int* active) {
+  std::vector<int> act;
+  std::vector<size_t> A(ns), B(ns), O(ns);
+  std::vector<int> NS(ns), ML(ns);
+  for (size_t i = 0; i < ns; ++i) {
+    sf_state* s = states[i];
+    if (s->orig_done >= s->c->orig_end.size()) continue;
+    plan_range(s, &A[i], &B[i], &O[i], &NS[i], &ML[i]);
+    act.push_back((int)i);
+  }
+  *active = (int)act.size();
+  if (act.empty()) return SF_OK;
+  const int na = (int)act.size();
+  bs->keep_jobs.emplace_back(na);
+  std::vector<TrackJob>& jobs = bs->keep_jobs.back();
+  int kmax = 0, gx = 1, gm = 1;
+  for (int j = 0; j < na; ++j) {
+    sf_state* s = states[act[j]];
+    TrackJob& jb = jobs[j];
+    memset(&jb, 0, sizeof jb);
+    jb.st = (TrackState*)s->st.p;
+    jb.gates = (const DGate*)s->c->dgates.p;
+    jb.g0 = (int)A[act[j]];
+    jb.g1 = (int)B[act[j]];
+    jb.prog = (SegProg*)s->prog.p;
+    jb.had = (GF2Q*)s->had.p;
+    jb.outcomes = (const uint8_t*)s->outcomes.p;
+    kmax = std::max(kmax, NS[act[j]]);
+    gx = std::max(gx, grid_for(s->c->dmax));
+    gm = std::max(gm, s->G);
+  }
+  HIPCHK(ctx, hipMemcpyAsync(bs->djobs.p, jobs.data(), na * sizeof(TrackJob), hipMemcpyHostToDevice, ctx->stream));
+  prof_begin(ctx, PK_TRACK);
+  hipLaunchKernelGGL(sf_track_kernel, dim3(na), dim3(TL), 0, ctx->stream, TrackJob{}, (const TrackJob*)bs->djobs.p);
+  prof_end(ctx);
+  bs->keep_desc.emplace_back((size_t)(kmax + 1) * na);
+  std::vector<ElemDesc>& D = bs->keep_desc.back();
+  for (int k = 0; k <= kmax; ++k)
+    for (int j = 0; j < na; ++j) {
+      sf_state* s = states[act[j]];
+      const SegProg* base = (const SegProg*)s->prog.p;
+      const SegProg* p = nullptr;
+      if (k < kmax) p = k < NS[act[j]] ? base + k : nullptr;
+      else p = ML[act[j]] ? base + (NS[act[j]] - 1) : nullptr;  // measurement descriptors
+      D[(size_t)k * na + j] = elem_desc(s, p);
+    }
+  HIPCHK(ctx, hipMemcpyAsync(bs->ddesc.p, D.data(), D.size() * sizeof(ElemDesc), hipMemcpyHostToDevice,
+                             ctx->stream));
+  const ElemDesc* dd = (const ElemDesc*)bs->ddesc.p;
+  for (int k = 0; k < kmax; ++k) {
+    prof_begin(ctx, PK_SEG);
+    hipLaunchKernelGGL(sf_seg_batch, dim3(gx, na), dim3(EB), 0, ctx->stream, dd + (size_t)k * na);
+    prof_end(ctx);
+  }
+  bool anym = false;
+  for (int j = 0; j < na; ++j) anym |= ML[act[j]] != 0;
+  if (anym) {
+    const ElemDesc* dm = dd + (size_t)kmax * na;
+    prof_begin(ctx, PK_MREDUCE);
+    hipLaunchKernelGGL(sf_meas_reduce_batch, dim3(gm, na), dim3(EB), 0, ctx->stream, dm);
+    prof_end(ctx);
+    prof_begin(ctx, PK_MFINAL);
+    hipLaunchKernelGGL(sf_meas_final_batch, dim3(1, na), dim3(EB), 0, ctx->stream, dm);
+    prof_end(ctx);
+    prof_begin(ctx, PK_MFILTER);
+    hipLaunchKernelGGL(sf_meas_filter_batch, dim3(gx, na), dim3(EB), 0, ctx->stream, dm);
+    prof_end(ctx);
+  }
+  HIPCHK(ctx, hipGetLastError());
+  for (int j = 0; j < na; ++j) {
+    sf_state* s = states[act[j]];
+    s->dev_done = B[act[j]];
+    s->orig_done = O[act[j]];
+    if (ML[act[j]]) { s->cur ^= 1; s->nmeas++; }
+  }
+  return SF_OK;
+}
+
 extern "C" sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t ns) {
   if (!ctx || (ns && !states)) return SF_E_INVALID;
   int maxseg = 1;
@@ -755,100 +866,205 @@ extern "C" sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t n
     maxseg = std::max(maxseg, states[i]->c->max_segs);
   }
   if (ns == 0) return SF_OK;
-  DevBuf djobs, ddesc;
-  sf_status rc;
-  if ((rc = dalloc(ctx, &djobs, ns * sizeof(TrackJob))) ||
-      (rc = dalloc(ctx, &ddesc, (size_t)(maxseg + 1) * ns * sizeof(ElemDesc)))) {
-    dfree(ctx, &djobs);
-    return rc;
-  }
-  std::vector<std::vector<TrackJob>> keep_jobs;
-  std::vector<std::vector<ElemDesc>> keep_desc;
-  hipError_t e = hipSuccess;
-  for (;;) {
-    std::vector<int> act;
-    std::vector<size_t> A(ns), B(ns), O(ns);
-    std::vector<int> NS(ns), ML(ns);
-    for (size_t i = 0; i < ns; ++i) {
-      sf_state* s = states[i];
-      if (s->orig_done >= s->c->orig_end.size()) continue;
-      plan_range(s, &A[i], &B[i], &O[i], &NS[i], &ML[i]);
-      act.push_back((int)i);
-    }
-    if (act.empty()) break;
-    const int na = (int)act.size();
-    keep_jobs.emplace_back(na);
-    std::vector<TrackJob>& jobs = keep_jobs.back();
-    int kmax = 0, gx = 1, gm = 1;
-    for (int j = 0; j < na; ++j) {
-      sf_state* s = states[act[j]];
-      TrackJob& jb = jobs[j];
-      memset(&jb, 0, sizeof jb);
-      jb.st = (TrackState*)s->st.p;
-      jb.gates = (const DGate*)s->c->dgates.p;
-      jb.g0 = (int)A[act[j]];
-      jb.g1 = (int)B[act[j]];
-      jb.prog = (SegProg*)s->prog.p;
-      jb.had = (GF2Q*)s->had.p;
-      jb.outcomes = (const uint8_t*)s->outcomes.p;
-      kmax = std::max(kmax, NS[act[j]]);
-      gx = std::max(gx, grid_for(s->c->dmax));
-      gm = std::max(gm, s->G);
-    }
-    e = hipMemcpyAsync(djobs.p, jobs.data(), na * sizeof(TrackJob), hipMemcpyHostToDevice, ctx->stream);
-    if (e != hipSuccess) break;
-    prof_begin(ctx, PK_TRACK);
-    hipLaunchKernelGGL(sf_track_kernel, dim3(na), dim3(TL), 0, ctx->stream, TrackJob{}, (const TrackJob*)djobs.p);
-    prof_end(ctx);
-    keep_desc.emplace_back((size_t)(kmax + 1) * na);
-    std::vector<ElemDesc>& D = keep_desc.back();
-    for (int k = 0; k <= kmax; ++k)
-      for (int j = 0; j < na; ++j) {
-        sf_state* s = states[act[j]];
-        const SegProg* base = (const SegProg*)s->prog.p;
-        const SegProg* p = nullptr;
-        if (k < kmax) p = k < NS[act[j]] ? base + k : nullptr;
-        else p = ML[act[j]] ? base + (NS[act[j]] - 1) : nullptr;  // measurement descriptors
-        D[(size_t)k * na + j] = elem_desc(s, p);
-      }
-    e = hipMemcpyAsync(ddesc.p, D.data(), D.size() * sizeof(ElemDesc), hipMemcpyHostToDevice, ctx->stream);
-    if (e != hipSuccess) break;
-    const ElemDesc* dd = (const ElemDesc*)ddesc.p;
-    for (int k = 0; k < kmax; ++k) {
-      prof_begin(ctx, PK_SEG);
-      hipLaunchKernelGGL(sf_seg_batch, dim3(gx, na), dim3(EB), 0, ctx->stream, dd + (size_t)k * na);
-      prof_end(ctx);
-    }
-    bool anym = false;
-    for (int j = 0; j < na; ++j) anym |= ML[act[j]] != 0;
-    if (anym) {
-      const ElemDesc* dm = dd + (size_t)kmax * na;
-      prof_begin(ctx, PK_MREDUCE);
-      hipLaunchKernelGGL(sf_meas_reduce_batch, dim3(gm, na), dim3(EB), 0, ctx->stream, dm);
-      prof_end(ctx);
-      prof_begin(ctx, PK_MFINAL);
-      hipLaunchKernelGGL(sf_meas_final_batch, dim3(1, na), dim3(EB), 0, ctx->stream, dm);
-      prof_end(ctx);
-      prof_begin(ctx, PK_MFILTER);
-      hipLaunchKernelGGL(sf_meas_filter_batch, dim3(gx, na), dim3(EB), 0, ctx->stream, dm);
-      prof_end(ctx);
-    }
-    e = hipGetLastError();
-    if (e != hipSuccess) break;
-    for (int j = 0; j < na; ++j) {
-      sf_state* s = states[act[j]];
-      s->dev_done = B[act[j]];
-      s->orig_done = O[act[j]];
-      if (ML[act[j]]) { s->cur ^= 1; s->nmeas++; }
-    }
-  }
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  dfree(ctx, &djobs);
-  dfree(ctx, &ddesc);
+  BatchScratch bs;
+  sf_status rc = scratch_reserve(ctx, &bs, ns, maxseg);
+  int active = 1;
+  while (rc == SF_OK && active) rc = batch_round(ctx, states, ns, &bs, &active);
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  scratch_free(ctx, &bs);
+  if (rc != SF_OK) return rc;
   if (e != hipSuccess) return fail(ctx, SF_E_DEVICE, "batch run: %s", hipGetErrorString(e));
   for (size_t i = 0; i < ns; ++i) {
     rc = check_track(states[i]);
     if (rc != SF_OK) return rc;
   }
+  return SF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Serving: a request loop with continuous batching.  Jobs are admitted in
+// arrival order while their projected device bytes fit the budget and a slot
+// is free; every tick runs one batched round (each resident frame advances to
+// its next measurement or to its end), then finished jobs are reported.  A job
+// that arrives while others run joins at the next tick.
+// ---------------------------------------------------------------------------
+struct ServeJob {
+  uint64_t id;
+  const sf_circuit* c;
+  std::vector<uint64_t> basis;
+  uint64_t seed;
+  sf_state* st;
+  int status;  // 0 queued, 1 resident, 2 done, 3 cancelled, 4 failed
+};
+
+struct sf_server {
+  sf_ctx* ctx;
+  uint64_t budget, used;
+  uint32_t max_resident;
+  uint64_t next_id;
+  std::vector<ServeJob*> queue;     // waiting, arrival order
+  std::vector<ServeJob*> resident;  // admitted, running
+  std::vector<ServeJob*> all;
+  BatchScratch bs;
+  uint64_t ticks, admitted, rejected;
+};
+
+extern "C" sf_status sf_serve_create(sf_ctx* ctx, uint64_t budget_bytes, uint32_t max_resident, sf_server** out) {
+  if (!ctx || !out || max_resident == 0) return SF_E_INVALID;
+  sf_server* sv = new (std::nothrow) sf_server();
+  if (!sv) return fail(ctx, SF_E_OOM, "host allocation failed");
+  sv->ctx = ctx;
+  sv->budget = budget_bytes;
+  sv->used = 0;
+  sv->max_resident = max_resident;
+  sv->next_id = 1;
+  sv->ticks = sv->admitted = sv->rejected = 0;
+  *out = sv;
+  return SF_OK;
+}
+
+static ServeJob* find_job(sf_server* sv, uint64_t id) {
+  for (ServeJob* j : sv->all)
+    if (j->id == id) return j;
+  return nullptr;
+}
+
+extern "C" sf_status sf_serve_submit(sf_server* sv, const sf_circuit* c, const uint64_t* basis, uint64_t seed,
+                                     uint64_t* job_id) {
+  if (!sv || !c || !job_id) return SF_E_INVALID;
+  if (sv->budget && c->projected > sv->budget) {
+    sv->rejected++;
+    return fail(sv->ctx, SF_E_TOO_LARGE, "job needs %llu bytes, budget is %llu",
+                (unsigned long long)c->projected, (unsigned long long)sv->budget);
+  }
+  ServeJob* j = new (std::nothrow) ServeJob();
+  if (!j) return fail(sv->ctx, SF_E_OOM, "host allocation failed");
+  j->id = sv->next_id++;
+  j->c = c;
+  const int W = (int)((c->n + 63) / 64);
+  j->basis.assign(W, 0);
+  if (basis)
+    for (int w = 0; w < W; ++w) j->basis[w] = basis[w];
+  j->seed = seed;
+  j->st = nullptr;
+  j->status = 0;
+  sv->queue.push_back(j);
+  sv->all.push_back(j);
+  *job_id = j->id;
+  return SF_OK;
+}
+
+extern "C" sf_status sf_serve_tick(sf_server* sv, uint32_t* n_resident, uint32_t* n_queued) {
+  if (!sv) return SF_E_INVALID;
+  sf_ctx* ctx = sv->ctx;
+  // admission in arrival order
+  size_t qi = 0;
+  while (qi < sv->queue.size() && sv->resident.size() < sv->max_resident) {
+    ServeJob* j = sv->queue[qi];
+    if (sv->budget && sv->used + j->c->projected > sv->budget) break;
+    sf_status rc = sf_state_init(ctx, j->c, j->basis.data(), j->seed, &j->st);
+    if (rc == SF_E_OOM || rc == SF_E_TOO_LARGE) break;  // retry when memory frees
+    if (rc != SF_OK) { j->status = 4; sv->queue.erase(sv->queue.begin() + qi); continue; }
+    j->status = 1;
+    sv->used += j->c->projected;
+    sv->admitted++;
+    sv->resident.push_back(j);
+    sv->queue.erase(sv->queue.begin() + qi);
+  }
+  if (!sv->resident.empty()) {
+    std::vector<sf_state*> sts;
+    int maxseg = 1;
+    for (ServeJob* j : sv->resident) { sts.push_back(j->st); maxseg = std::max(maxseg, j->c->max_segs); }
+    sf_status rc = scratch_reserve(ctx, &sv->bs, sts.size(), maxseg);
+    int active = 0;
+    if (rc == SF_OK) rc = batch_round(ctx, sts.data(), sts.size(), &sv->bs, &active);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    sv->bs.keep_jobs.clear();
+    sv->bs.keep_desc.clear();
+    if (rc != SF_OK) return rc;
+    if (e != hipSuccess) return fail(ctx, SF_E_DEVICE, "serve tick: %s", hipGetErrorString(e));
+    std::vector<ServeJob*> still;
+    for (ServeJob* j : sv->resident) {
+      if (j->st->orig_done >= j->c->orig_end.size()) {
+        j->status = check_track(j->st) == SF_OK ? 2 : 4;
+      } else {
+        still.push_back(j);
+      }
+    }
+    sv->resident.swap(still);
+  }
+  sv->ticks++;
+  if (n_resident) *n_resident = (uint32_t)sv->resident.size();
+  if (n_queued) *n_queued = (uint32_t)sv->queue.size();
+  return SF_OK;
+}
+
+extern "C" sf_status sf_serve_poll(sf_server* sv, uint64_t job_id, int* status, sf_state** state) {
+  if (!sv || !status) return SF_E_INVALID;
+  ServeJob* j = find_job(sv, job_id);
+  if (!j) return fail(sv->ctx, SF_E_INVALID, "unknown job %llu", (unsigned long long)job_id);
+  *status = j->status;
+  if (state) *state = j->status == 2 ? j->st : nullptr;
+  return SF_OK;
+}
+
+// Free a finished, failed or queued job's state and its budget share.
+extern "C" sf_status sf_serve_release(sf_server* sv, uint64_t job_id) {
+  if (!sv) return SF_E_INVALID;
+  ServeJob* j = find_job(sv, job_id);
+  if (!j) return fail(sv->ctx, SF_E_INVALID, "unknown job %llu", (unsigned long long)job_id);
+  if (j->status == 1) return fail(sv->ctx, SF_E_STATE, "job %llu is running", (unsigned long long)job_id);
+  if (j->st) {
+    sf_state_destroy(j->st);
+    j->st = nullptr;
+    if (j->status == 2 || j->status == 4) sv->used -= j->c->projected;
+  }
+  for (size_t i = 0; i < sv->queue.size(); ++i)
+    if (sv->queue[i] == j) { sv->queue.erase(sv->queue.begin() + i); break; }
+  for (size_t i = 0; i < sv->all.size(); ++i)
+    if (sv->all[i] == j) { sv->all.erase(sv->all.begin() + i); break; }
+  delete j;
+  return SF_OK;
+}
+
+// Cancel a queued or resident job; its slot and budget share free at once.
+extern "C" sf_status sf_serve_cancel(sf_server* sv, uint64_t job_id) {
+  if (!sv) return SF_E_INVALID;
+  ServeJob* j = find_job(sv, job_id);
+  if (!j) return fail(sv->ctx, SF_E_INVALID, "unknown job %llu", (unsigned long long)job_id);
+  if (j->status == 0) {
+    for (size_t i = 0; i < sv->queue.size(); ++i)
+      if (sv->queue[i] == j) { sv->queue.erase(sv->queue.begin() + i); break; }
+  } else if (j->status == 1) {
+    for (size_t i = 0; i < sv->resident.size(); ++i)
+      if (sv->resident[i] == j) { sv->resident.erase(sv->resident.begin() + i); break; }
+    sf_state_destroy(j->st);
+    j->st = nullptr;
+    sv->used -= j->c->projected;
+  } else {
+    return SF_OK;
+  }
+  j->status = 3;
+  return SF_OK;
+}
+
+extern "C" sf_status sf_serve_stats(sf_server* sv, uint64_t* ticks, uint64_t* admitted, uint64_t* rejected,
+                                    uint64_t* used_bytes) {
+  if (!sv) return SF_E_INVALID;
+  if (ticks) *ticks = sv->ticks;
+  if (admitted) *admitted = sv->admitted;
+  if (rejected) *rejected = sv->rejected;
+  if (used_bytes) *used_bytes = sv->used;
+  return SF_OK;
+}
+
+extern "C" sf_status sf_serve_destroy(sf_server* sv) {
+  if (!sv) return SF_OK;
+  for (ServeJob* j : sv->all) {
+    if (j->st) sf_state_destroy(j->st);
+    delete j;
+  }
+  scratch_free(sv->ctx, &sv->bs);
+  delete sv;
   return SF_OK;
 }

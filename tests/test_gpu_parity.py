@@ -256,3 +256,93 @@ def test_batch_matches_alone(eng):
         assert np.array_equal(tab, rtab), c.name
         assert_frames_equal(sigma_ints(sig), amp, sigma_ints(rsig), ramp, what=c.name)
         assert st.outcomes() == ref.outcomes(), c.name
+
+
+def _run_alone(eng, circ, seed):
+    st = eng.load(circ.n, circ).state(circ.init_bits, seed)
+    st.run()
+    return st.read_frame(), st.outcomes()
+
+
+def test_serve_mix_matches_alone(eng):
+    """Jobs that arrive while others run join the batch; each result equals
+    the job run alone (bit for bit) and the oracle."""
+    import paper_1712_03554_amd as sf
+    circs = [wl.config1(j) for j in range(3)] + [wl.config3(t) for t in range(3)] + \
+            [_mixed_circuit(s, 4 + s) for s in range(3)] + [wl.qft(5, [1, 0, 1, 1, 0], max_k=6)]
+    seeds = list(range(300, 300 + len(circs)))
+    alone = [_run_alone(eng, c, s) for c, s in zip(circs, seeds)]
+    loaded = [eng.load(c.n, c) for c in circs]
+    srv = sf.Server(eng, budget_bytes=0, max_resident=4)
+    ids, pending = {}, list(range(len(circs)))
+    done = {}
+    ticks = 0
+    while len(done) < len(circs):
+        for _ in range(2):  # two arrivals per tick
+            if pending:
+                i = pending.pop(0)
+                ids[srv.submit(loaded[i], circs[i].init_bits, seeds[i])] = i
+        srv.tick()
+        ticks += 1
+        for jid, i in list(ids.items()):
+            stt, st = srv.poll(jid)
+            if stt == sf.Server.DONE and i not in done:
+                done[i] = (st.read_frame(), st.outcomes())
+                srv.release(jid)
+                del ids[jid]
+        assert ticks < 500
+    for i, (c, s) in enumerate(zip(circs, seeds)):
+        (tab, sig, amp), out = done[i]
+        (ta, sa, aa), oa = alone[i]
+        assert np.array_equal(tab, ta) and np.array_equal(sig, sa), c.name
+        assert np.array_equal(amp.view(np.uint64), aa.view(np.uint64)), c.name
+        assert out == oa, c.name
+        ref = OracleFrame(c.n, c.init_bits, s)
+        ref.run(c.array())
+        rtab, rsig, ramp = ref.read()
+        assert_frames_equal(sigma_ints(sig), amp, sigma_ints(rsig), ramp, what=c.name)
+    st = srv.stats()
+    assert st["admitted"] == len(circs) and st["used_bytes"] == 0
+
+
+def test_serve_budget_cancel_and_rejection(eng):
+    import paper_1712_03554_amd as sf
+    c = wl.config1(0)
+    lc = eng.load(c.n, c)
+    need = lc.info()[1]
+    srv = sf.Server(eng, budget_bytes=int(need * 1.5), max_resident=8)
+    j1 = srv.submit(lc, c.init_bits, 1)
+    j2 = srv.submit(lc, c.init_bits, 2)
+    j3 = srv.submit(lc, c.init_bits, 3)
+    r, q = srv.tick()
+    assert (r, q) in ((1, 2), (0, 2))            # only one fits the budget
+    srv.cancel(j2)                                # cancel a queued job
+    assert srv.poll(j2)[0] == sf.Server.CANCELLED
+    for _ in range(200):
+        if srv.poll(j1)[0] == sf.Server.DONE:
+            break
+        srv.tick()
+    assert srv.poll(j1)[0] == sf.Server.DONE
+    assert srv.poll(j3)[0] == sf.Server.QUEUED    # still waiting: j1 holds the budget
+    srv.release(j1)
+    for _ in range(200):
+        if srv.poll(j3)[0] == sf.Server.DONE:
+            break
+        srv.tick()
+    assert srv.poll(j3)[0] == sf.Server.DONE
+    (tab, sig, amp), out = _run_alone(eng, c, 3)
+    stt, st = srv.poll(j3)
+    assert np.array_equal(st.read_frame()[1], sig) and st.outcomes() == out
+    srv.release(j3)
+    # a job larger than the whole budget is refused at submission
+    big = wl.Circuit(20)
+    for q_ in range(20):
+        big.h(q_)
+    for q_ in range(14):
+        big.t(q_)
+    lb = eng.load(20, big)
+    small = sf.Server(eng, budget_bytes=1 << 20, max_resident=2)
+    with pytest.raises(sf.SFrameError) as ei:
+        small.submit(lb)
+    assert ei.value.status == sf.SF_E_TOO_LARGE
+    assert small.stats()["rejected"] == 1
