@@ -963,7 +963,9 @@ extern "C" sf_status sf_serve_tick(sf_server* sv, uint32_t* n_resident, uint32_t
     ServeJob* j = sv->queue[qi];
     if (sv->budget && sv->used + j->c->projected > sv->budget) break;
     sf_status rc = sf_state_init(ctx, j->c, j->basis.data(), j->seed, &j->st);
-    if (rc == SF_E_OOM || rc == SF_E_TOO_LARGE) break;  // retry when memory frees
+    // out of device memory: wait for resident jobs to free some; with none
+    // resident, waiting cannot help and the job fails
+    if ((rc == SF_E_OOM || rc == SF_E_TOO_LARGE) && !sv->resident.empty()) break;
     if (rc != SF_OK) { j->status = 4; sv->queue.erase(sv->queue.begin() + qi); continue; }
     j->status = 1;
     sv->used += j->c->projected;

@@ -338,8 +338,8 @@ def test_serve_budget_cancel_and_rejection(eng):
     big = wl.Circuit(20)
     for q_ in range(20):
         big.h(q_)
-    for q_ in range(14):
-        big.t(q_)
+    for q_ in range(20):
+        big.t(q_)                                 # frame bound 2^20: 32 MiB of amplitudes
     lb = eng.load(20, big)
     small = sf.Server(eng, budget_bytes=1 << 20, max_resident=2)
     with pytest.raises(sf.SFrameError) as ei:
