@@ -74,6 +74,80 @@ def cpu_baseline(circ, seed):
             "sample": f"{circ.name}: one full circuit ({len(arr)} gates, U={U}) on one host thread, {dt:.2f} s"}
 
 
+def serve_bench(eng, sf, wl, n_jobs, tick_segments, max_resident, budget_bytes, load_frac=0.7):
+    """Serving on the mixed request stream (AQFT 40%, Cuccaro adder 40%,
+    random Clifford+T 20%).  First a saturation run (every job submitted at
+    t=0) gives the batched capacity in jobs/s; then jobs arrive as a Poisson
+    stream at load_frac of that capacity.  Latency = time from a job's arrival
+    to its outcomes and frame size being on the host."""
+    import numpy as np
+    import torch
+    jobs = [wl.config5_job(j) for j in range(n_jobs)]
+    seeds = [wl.derive_seed(5, j) for j in range(n_jobs)]
+    loaded, rejected_load = {}, 0
+    tl0 = time.perf_counter()
+    for j, c in enumerate(jobs):
+        try:
+            loaded[j] = eng.load(c.n, c)
+        except sf.SFrameError as e:
+            if e.status != sf.SF_E_TOO_LARGE:
+                raise
+            rejected_load += 1
+    load_s = time.perf_counter() - tl0
+    ok = sorted(loaded)
+    print(f"serve: {len(ok)} of {n_jobs} jobs loadable ({load_s:.2f} s)", file=sys.stderr, flush=True)
+
+    def run(arrivals):
+        srv = sf.Server(eng, budget_bytes=budget_bytes, max_resident=max_resident, tick_segments=tick_segments)
+        lat, rejected, pending, live = [], 0, list(range(len(ok))), {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while pending or live:
+            now = time.perf_counter() - t0
+            while pending and arrivals[pending[0]] <= now:
+                i = pending.pop(0)
+                j = ok[i]
+                try:
+                    live[srv.submit(loaded[j], jobs[j].init_bits, seeds[j])] = i
+                except sf.SFrameError as e:
+                    if e.status != sf.SF_E_TOO_LARGE:
+                        raise
+                    rejected += 1
+            if not live:
+                time.sleep(max(0.0, arrivals[pending[0]] - (time.perf_counter() - t0)))
+                continue
+            srv.tick()
+            for jid, i in list(live.items()):
+                stt, st = srv.poll(jid)
+                if stt == srv.QUEUED or stt == srv.RESIDENT:
+                    continue
+                if stt != srv.DONE:
+                    raise RuntimeError(f"served job {ok[i]} ended with status {stt}")
+                st.outcomes()
+                st.frame_size()
+                lat.append(time.perf_counter() - t0 - arrivals[i])
+                srv.release(jid)
+                del live[jid]
+        wall = time.perf_counter() - t0
+        ticks = srv.stats()["ticks"]
+        srv.close()
+        return np.array(lat), wall, rejected, ticks
+
+    lat_sat, wall_sat, rej_sat, ticks_sat = run([0.0] * len(ok))
+    capacity = len(lat_sat) / wall_sat
+    lam = load_frac * capacity
+    rng = np.random.default_rng(wl.derive_seed(5, 1 << 20))
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(ok))).tolist()
+    lat, wall, rej, ticks = run(arrivals)
+    return {"jobs": n_jobs, "served": int(len(lat)), "rejected_too_large": rejected_load + rej,
+            "capacity_jobs_per_s": capacity, "lambda_jobs_per_s": lam, "offered_load": load_frac,
+            "throughput_jobs_per_s": len(lat) / wall, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "max_ms": float(lat.max() * 1e3),
+            "saturated_p50_ms": float(np.percentile(lat_sat, 50) * 1e3), "ticks": ticks,
+            "tick_segments": tick_segments, "max_resident": max_resident, "budget_bytes": budget_bytes,
+            "circuit_load_ms_mean": load_s / n_jobs * 1e3}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +157,10 @@ def main():
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg2L"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--path", default="batched", choices=["batched", "plain"])
+    ap.add_argument("--serve-jobs", type=int, default=48, help="0 skips the serving run")
+    ap.add_argument("--tick-segments", type=int, default=8)
+    ap.add_argument("--max-resident", type=int, default=32)
+    ap.add_argument("--serve-budget-gib", type=float, default=128.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -195,6 +273,9 @@ def main():
         "element_roofline": elem_roof,
         "track_cycles_last_step": cyc,
     }
+    if args.serve_jobs > 0:
+        line["serve"] = serve_bench(eng, sf, wl, args.serve_jobs, args.tick_segments, args.max_resident,
+                                    int(args.serve_budget_gib * (1 << 30)))
     if not args.no_cpu and args.workload == "cfg2":
         line["cpu_baseline"] = cpu_baseline(circs[0], seeds[0])
     print(json.dumps(line), flush=True)

@@ -155,12 +155,16 @@ sf_status sf_state_info(sf_state* s, size_t* gates_done, int* fragile);
  * their projected device bytes (sf_circuit_info) fit budget_bytes (0 = no
  * bound) and fewer than max_resident jobs are resident.  Each sf_serve_tick
  * admits what fits, runs one batched round over all resident frames (each
- * advances to its next measurement or to its end), synchronises and retires
- * finished jobs, whose memory stays reserved until sf_serve_release.  A job's
- * result does not depend on what else is resident.  Job status: 0 queued,
- * 1 resident, 2 done, 3 cancelled, 4 failed.  sf_serve_submit returns
- * SF_E_TOO_LARGE for a job that can never fit. */
-sf_status sf_serve_create(sf_ctx* ctx, uint64_t budget_bytes, uint32_t max_resident, sf_server** out);
+ * advances to its next measurement or to its end, or, with tick_segments > 0,
+ * stops earlier right after its tick_segments-th non-Clifford phase gate, so
+ * that long measurement-free jobs yield to new arrivals), synchronises and
+ * retires finished jobs, whose memory stays reserved until sf_serve_release.
+ * A job's result does not depend on what else is resident or on
+ * tick_segments.  Job status: 0 queued, 1 resident, 2 done, 3 cancelled,
+ * 4 failed.  sf_serve_submit returns SF_E_TOO_LARGE for a job that can never
+ * fit. */
+sf_status sf_serve_create(sf_ctx* ctx, uint64_t budget_bytes, uint32_t max_resident, uint32_t tick_segments,
+                          sf_server** out);
 sf_status sf_serve_submit(sf_server* sv, const sf_circuit* c, const uint64_t* basis_bits, uint64_t seed,
                           uint64_t* job_id);
 sf_status sf_serve_tick(sf_server* sv, uint32_t* n_resident, uint32_t* n_queued);

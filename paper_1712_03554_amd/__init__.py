@@ -81,7 +81,7 @@ def load_library(path: str = LIB_PATH):
         "sf_profile_read": [vp, vp, vp, ctypes.c_int],
         "sf_state_cycles": [vp, vp, ctypes.c_int],
         "sf_batch_run": [vp, vp, sz],
-        "sf_serve_create": [vp, u64, ctypes.c_uint32, P(vp)],
+        "sf_serve_create": [vp, u64, ctypes.c_uint32, ctypes.c_uint32, P(vp)],
         "sf_serve_submit": [vp, vp, vp, u64, P(u64)],
         "sf_serve_tick": [vp, P(ctypes.c_uint32), P(ctypes.c_uint32)],
         "sf_serve_poll": [vp, u64, P(ctypes.c_int), P(vp)],
@@ -297,11 +297,11 @@ class Server:
 
     QUEUED, RESIDENT, DONE, CANCELLED, FAILED = range(5)
 
-    def __init__(self, eng: Engine, budget_bytes: int = 0, max_resident: int = 64):
+    def __init__(self, eng: Engine, budget_bytes: int = 0, max_resident: int = 64, tick_segments: int = 0):
         self.eng = eng
         self._L = eng._L
         h = ctypes.c_void_p()
-        eng._check(self._L.sf_serve_create(eng._h, budget_bytes, max_resident, ctypes.byref(h)))
+        eng._check(self._L.sf_serve_create(eng._h, budget_bytes, max_resident, tick_segments, ctypes.byref(h)))
         self._h = h
         self._circuits = {}
 

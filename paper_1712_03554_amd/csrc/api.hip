@@ -705,16 +705,24 @@ extern "C" sf_status sf_read_frame(sf_state* s, uint64_t* tableau, uint64_t* sig
 // share one launch (one wavefront each); the element kernels of segment k of
 // every frame share one launch (grid y = frame).
 // ---------------------------------------------------------------------------
-static void plan_range(const sf_state* s, size_t* a, size_t* b, size_t* orig_after, int* nseg, int* meas_last) {
+// The range runs to the next measurement; with cap > 0 it may also stop right
+// after its cap-th non-Clifford phase gate when that gate ends a circuit gate
+// (a segment boundary either way, so the segments and their arithmetic are
+// those of the uncapped run).
+static void plan_range(const sf_state* s, size_t* a, size_t* b, size_t* orig_after, int* nseg, int* meas_last,
+                       int cap = 0) {
   const sf_circuit* c = s->c;
   size_t o = s->orig_done, e = s->dev_done;
   *a = s->dev_done;
+  int terms = 0;
   while (o < c->orig_end.size()) {
     size_t end = c->orig_end[o];
+    for (size_t i = e; i < end; ++i) terms += c->g[i].op == DG_NCPHASE;
     bool meas = end > e && c->g[end - 1].op == DG_MEASURE;
+    bool cut = cap > 0 && terms >= cap && end > e && c->g[end - 1].op == DG_NCPHASE;
     e = end;
     ++o;
-    if (meas) break;
+    if (meas || cut) break;
   }
   *b = e;
   *orig_after = o;
@@ -780,14 +788,15 @@ static void scratch_free(sf_ctx* ctx, BatchScratch* bs) {
 // Queue one round for the given states: each unfinished state runs its gates
 // up to and including its next measurement.  *active = number of states that
 // had work.  Asynchronous; the scratch must be large enough.
-static sf_status batch_round(sf_ctx* ctx, sf_state* const* states, size_t ns, BatchScratch* bs, int* active) {
+static sf_status batch_round(sf_ctx* ctx, sf_state* const* states, size_t ns, BatchScratch* bs, int* active,
+                             int cap = 0) {
   std::vector<int> act;
   std::vector<size_t> A(ns), B(ns), O(ns);
   std::vector<int> NS(ns), ML(ns);
   for (size_t i = 0; i < ns; ++i) {
     sf_state* s = states[i];
     if (s->orig_done >= s->c->orig_end.size()) continue;
-    plan_range(s, &A[i], &B[i], &O[i], &NS[i], &ML[i]);
+    plan_range(s, &A[i], &B[i], &O[i], &NS[i], &ML[i], cap);
     act.push_back((int)i);
   }
   *active = (int)act.size();
@@ -901,6 +910,7 @@ struct sf_server {
   sf_ctx* ctx;
   uint64_t budget, used;
   uint32_t max_resident;
+  int tick_segments;
   uint64_t next_id;
   std::vector<ServeJob*> queue;     // waiting, arrival order
   std::vector<ServeJob*> resident;  // admitted, running
@@ -909,14 +919,16 @@ struct sf_server {
   uint64_t ticks, admitted, rejected;
 };
 
-extern "C" sf_status sf_serve_create(sf_ctx* ctx, uint64_t budget_bytes, uint32_t max_resident, sf_server** out) {
-  if (!ctx || !out || max_resident == 0) return SF_E_INVALID;
+extern "C" sf_status sf_serve_create(sf_ctx* ctx, uint64_t budget_bytes, uint32_t max_resident,
+                                     uint32_t tick_segments, sf_server** out) {
+  if (!ctx || !out || max_resident == 0 || tick_segments > (1u << 30)) return SF_E_INVALID;
   sf_server* sv = new (std::nothrow) sf_server();
   if (!sv) return fail(ctx, SF_E_OOM, "host allocation failed");
   sv->ctx = ctx;
   sv->budget = budget_bytes;
   sv->used = 0;
   sv->max_resident = max_resident;
+  sv->tick_segments = (int)tick_segments;
   sv->next_id = 1;
   sv->ticks = sv->admitted = sv->rejected = 0;
   *out = sv;
@@ -979,7 +991,7 @@ extern "C" sf_status sf_serve_tick(sf_server* sv, uint32_t* n_resident, uint32_t
     for (ServeJob* j : sv->resident) { sts.push_back(j->st); maxseg = std::max(maxseg, j->c->max_segs); }
     sf_status rc = scratch_reserve(ctx, &sv->bs, sts.size(), maxseg);
     int active = 0;
-    if (rc == SF_OK) rc = batch_round(ctx, sts.data(), sts.size(), &sv->bs, &active);
+    if (rc == SF_OK) rc = batch_round(ctx, sts.data(), sts.size(), &sv->bs, &active, sv->tick_segments);
     hipError_t e = hipStreamSynchronize(ctx->stream);
     sv->bs.keep_jobs.clear();
     sv->bs.keep_desc.clear();

@@ -264,16 +264,18 @@ def _run_alone(eng, circ, seed):
     return st.read_frame(), st.outcomes()
 
 
-def test_serve_mix_matches_alone(eng):
+@pytest.mark.parametrize("tick_segments", [0, 1, 3])
+def test_serve_mix_matches_alone(eng, tick_segments):
     """Jobs that arrive while others run join the batch; each result equals
-    the job run alone (bit for bit) and the oracle."""
+    the job run alone (bit for bit) and the oracle, whatever the tick slice."""
     import paper_1712_03554_amd as sf
     circs = [wl.config1(j) for j in range(3)] + [wl.config3(t) for t in range(3)] + \
-            [_mixed_circuit(s, 4 + s) for s in range(3)] + [wl.qft(5, [1, 0, 1, 1, 0], max_k=6)]
+            [_mixed_circuit(s, 4 + s) for s in range(3)] + [wl.qft(5, [1, 0, 1, 1, 0], max_k=6)] + \
+            [wl.cuccaro_adder(3), wl.config5_job(4)]
     seeds = list(range(300, 300 + len(circs)))
     alone = [_run_alone(eng, c, s) for c, s in zip(circs, seeds)]
     loaded = [eng.load(c.n, c) for c in circs]
-    srv = sf.Server(eng, budget_bytes=0, max_resident=4)
+    srv = sf.Server(eng, budget_bytes=0, max_resident=4, tick_segments=tick_segments)
     ids, pending = {}, list(range(len(circs)))
     done = {}
     ticks = 0
@@ -290,7 +292,7 @@ def test_serve_mix_matches_alone(eng):
                 done[i] = (st.read_frame(), st.outcomes())
                 srv.release(jid)
                 del ids[jid]
-        assert ticks < 500
+        assert ticks < 2000
     for i, (c, s) in enumerate(zip(circs, seeds)):
         (tab, sig, amp), out = done[i]
         (ta, sa, aa), oa = alone[i]
