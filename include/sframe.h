@@ -133,6 +133,15 @@ sf_status sf_run(sf_state* s);
  * wavefront each) and the element kernels of all frames share one launch per
  * segment.  Results are identical to running each state alone.  Synchronises. */
 sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t n_states);
+/* Measure qubit q in the Z basis now, between circuit gates (the state must
+ * be at a gate boundary, as after sf_step).  Same rule and random stream as
+ * a MEASURE gate at this point of the circuit (section 3, measurement of a
+ * stabilizer frame): the outcome takes the next measurement index, so later
+ * circuit measurements draw the following ones.  *outcome receives 0 or 1.
+ * Synchronises.  SF_E_INVALID for q >= n; SF_E_TOO_LARGE (state unchanged)
+ * if after this measurement the rest of the circuit would need more frame
+ * elements than the state was sized for. */
+sf_status sf_measure(sf_state* s, uint32_t q, int* outcome);
 /* Wait for queued work; reports device-side failures of the queued steps. */
 sf_status sf_sync(sf_state* s);
 

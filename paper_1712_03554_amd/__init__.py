@@ -8,6 +8,7 @@ library and a HIP device and raises otherwise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -23,7 +24,7 @@ SF_OK, SF_E_INVALID, SF_E_OOM, SF_E_DEVICE, SF_E_TOO_LARGE, SF_E_STATE, SF_E_BUF
 STATUS_NAMES = ["SF_OK", "SF_E_INVALID", "SF_E_OOM", "SF_E_DEVICE", "SF_E_TOO_LARGE", "SF_E_STATE",
                 "SF_E_BUFSIZE", "SF_E_CANCELLED"]
 
-EXPORTS = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_circuit_load", "sf_circuit_info",
+EXPORTS = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_measure", "sf_circuit_load", "sf_circuit_info",
            "sf_circuit_destroy", "sf_state_init", "sf_state_destroy", "sf_step", "sf_run", "sf_sync",
            "sf_outcomes", "sf_frame_size", "sf_read_frame", "sf_state_info", "sf_state_reset",
            "sf_state_dim", "sf_profile", "sf_profile_read", "sf_state_cycles", "sf_batch_run",
@@ -70,6 +71,7 @@ def load_library(path: str = LIB_PATH):
         "sf_state_destroy": [vp],
         "sf_step": [vp, sz, P(sz)],
         "sf_run": [vp],
+        "sf_measure": [vp, ctypes.c_uint32, P(ctypes.c_int)],
         "sf_sync": [vp],
         "sf_outcomes": [vp, vp, sz, P(sz)],
         "sf_frame_size": [vp, P(u64)],
@@ -98,6 +100,20 @@ def load_library(path: str = LIB_PATH):
     L.sf_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
+
+
+_exiting = False
+
+
+def _mark_exit():
+    # At interpreter exit objects are finalised in no particular order (an
+    # Engine may go before its states) and torch's allocator may already be
+    # gone; the process is ending, so the library is not called any more.
+    global _exiting
+    _exiting = True
+
+
+atexit.register(_mark_exit)
 
 
 def _ptr(a):
@@ -171,9 +187,9 @@ class Engine:
         return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(KERNEL_KINDS)}
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and not _exiting:
             self._L.sf_ctx_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.close()
@@ -202,9 +218,9 @@ class Circuit:
         return State(self, h)
 
     def close(self):
-        if getattr(self, "_h", None) and self.eng._h:
+        if getattr(self, "_h", None) and self.eng._h and not _exiting:
             self.eng._L.sf_circuit_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.close()
@@ -250,6 +266,12 @@ class State:
     def run(self):
         self._check(self._L.sf_run(self._h))
 
+    def measure(self, qubit: int) -> int:
+        """Measure a qubit now (between circuit gates); returns the outcome."""
+        o = ctypes.c_int()
+        self._check(self._L.sf_measure(self._h, qubit, ctypes.byref(o)))
+        return int(o.value)
+
     def sync(self):
         self._check(self._L.sf_sync(self._h))
 
@@ -284,7 +306,7 @@ class State:
         return tab, sig[:k], (amp[0::2] + 1j * amp[1::2])[:k]
 
     def close(self):
-        if getattr(self, "_h", None) and getattr(self, "_owned", True):
+        if getattr(self, "_h", None) and getattr(self, "_owned", True) and self.circ.eng._h and not _exiting:
             self._L.sf_state_destroy(self._h)
         self._h = None
 
@@ -345,9 +367,9 @@ class Server:
         return dict(zip(["ticks", "admitted", "rejected", "used_bytes"], [int(x.value) for x in v]))
 
     def close(self):
-        if getattr(self, "_h", None) and self.eng._h:
+        if getattr(self, "_h", None) and self.eng._h and not _exiting:
             self._L.sf_serve_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.close()

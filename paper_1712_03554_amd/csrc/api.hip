@@ -88,9 +88,10 @@ struct sf_circuit {
 struct sf_state {
   sf_ctx* ctx;
   const sf_circuit* c;
-  DevBuf st, prog, had, amp[2], outcomes, pvals, scale, flags, partials, ri, count;
+  DevBuf st, prog, had, amp[2], outcomes, pvals, scale, flags, partials, ri, count, adhoc;
   int cur;
   size_t orig_done, dev_done, nmeas;
+  size_t meas_cap;  // capacity of outcomes / pvals (circuit measurements, grown by sf_measure)
   uint64_t seed;
   int G;  // measurement reduction grid (fixed per state)
 };
@@ -388,7 +389,7 @@ extern "C" sf_status sf_circuit_destroy(sf_circuit* c) {
 static void state_free(sf_state* s) {
   sf_ctx* ctx = s->ctx;
   DevBuf* all[] = {&s->st, &s->prog, &s->had, &s->amp[0], &s->amp[1], &s->outcomes, &s->pvals,
-                   &s->scale, &s->flags, &s->partials, &s->ri, &s->count};
+                   &s->scale, &s->flags, &s->partials, &s->ri, &s->count, &s->adhoc};
   for (DevBuf* b : all) dfree(ctx, b);
 }
 
@@ -455,6 +456,7 @@ extern "C" sf_status sf_state_init(sf_ctx* ctx, const sf_circuit* c, const uint6
   s->orig_done = s->dev_done = s->nmeas = 0;
   s->seed = seed;
   s->G = grid_for(c->dmax) > 1024 ? 1024 : grid_for(c->dmax);
+  s->meas_cap = std::max<size_t>(1, c->n_meas);
   sf_status rc = SF_OK;
   size_t ampb = (size_t)16 << c->dmax;
   if ((rc = dalloc(ctx, &s->st, sizeof(TrackState))) ||
@@ -493,15 +495,20 @@ extern "C" sf_status sf_state_destroy(sf_state* s) {
   return SF_OK;
 }
 
-// Queue the device gates [a, b) (b ends at most right after a measurement).
-static sf_status run_range(sf_state* s, size_t a, size_t b) {
+// Queue the device gates [a, b) of dgates (device copy) / hg (host copy); b
+// ends at most right after a measurement.
+static sf_status run_gates(sf_state* s, const DGate* dgates, const DGate* hg, size_t a, size_t b) {
   sf_ctx* ctx = s->ctx;
   const sf_circuit* c = s->c;
   if (a >= b) return SF_OK;
+  size_t nm = 0;
+  for (size_t i = a; i < b; ++i) nm += hg[i].op == DG_MEASURE;
+  if (s->nmeas + nm > s->meas_cap)
+    return fail(ctx, SF_E_STATE, "outcome buffer holds %zu measurements, %zu needed", s->meas_cap, s->nmeas + nm);
   TrackJob job;
   memset(&job, 0, sizeof job);
   job.st = (TrackState*)s->st.p;
-  job.gates = (const DGate*)c->dgates.p;
+  job.gates = dgates;
   job.g0 = (int)a;
   job.g1 = (int)b;
   job.prog = (SegProg*)s->prog.p;
@@ -516,7 +523,7 @@ static sf_status run_range(sf_state* s, size_t a, size_t b) {
   int nseg = 0;
   bool open = false, meas_last = false;
   for (size_t i = a; i < b; ++i) {
-    int op = c->g[i].op;
+    int op = hg[i].op;
     if (op == DG_NCPHASE || op == DG_MEASURE) { ++nseg; open = false; meas_last = op == DG_MEASURE; }
     else { open = true; meas_last = false; }
   }
@@ -551,6 +558,10 @@ static sf_status run_range(sf_state* s, size_t a, size_t b) {
   return SF_OK;
 }
 
+static sf_status run_range(sf_state* s, size_t a, size_t b) {
+  return run_gates(s, (const DGate*)s->c->dgates.p, s->c->g.data(), a, b);
+}
+
 extern "C" sf_status sf_step(sf_state* s, size_t max_gates, size_t* applied) {
   if (!s) return SF_E_INVALID;
   const sf_circuit* c = s->c;
@@ -579,6 +590,84 @@ extern "C" sf_status sf_run(sf_state* s) {
     sf_status rc = sf_step(s, (size_t)-1, &k);
     if (rc != SF_OK) return rc;
   }
+  return SF_OK;
+}
+
+static sf_status check_track(sf_state* s);
+
+// Ad-hoc measurement of qubit q between circuit gates.  The frame bound of
+// the rest of the circuit is re-derived first (the tableau track does not
+// depend on outcomes, so a dry pass from the current tableau gives it); a
+// measurement that would let a later gate outgrow the state's buffers is
+// refused and leaves the state as it was.
+extern "C" sf_status sf_measure(sf_state* s, uint32_t q, int* outcome) {
+  if (!s) return SF_E_INVALID;
+  sf_ctx* ctx = s->ctx;
+  const sf_circuit* c = s->c;
+  if (q >= c->n) return fail(ctx, SF_E_INVALID, "qubit %u out of range (n = %u)", q, c->n);
+  sf_status rc = check_track(s);
+  if (rc != SF_OK) return rc;
+  if (!s->adhoc.p && (rc = dalloc(ctx, &s->adhoc, sizeof(DGate)))) return rc;
+  DGate g;
+  memset(&g, 0, sizeof g);
+  g.op = DG_MEASURE;
+  g.q0 = (int)q;
+  HIPCHK(ctx, hipMemcpyAsync(s->adhoc.p, &g, sizeof g, hipMemcpyHostToDevice, ctx->stream));
+  // dry pass: this measurement, then the rest of the circuit
+  DevBuf tmp;
+  if ((rc = dalloc(ctx, &tmp, sizeof(TrackState)))) return rc;
+  hipError_t e = hipMemcpyAsync(tmp.p, s->st.p, sizeof(TrackState), hipMemcpyDeviceToDevice, ctx->stream);
+  for (int part = 0; part < 2 && e == hipSuccess; ++part) {
+    TrackJob job;
+    memset(&job, 0, sizeof job);
+    job.st = (TrackState*)tmp.p;
+    job.gates = part == 0 ? (const DGate*)s->adhoc.p : (const DGate*)c->dgates.p;
+    job.g0 = part == 0 ? 0 : (int)s->dev_done;
+    job.g1 = part == 0 ? 1 : (int)c->g.size();
+    job.dry = 1;
+    if (job.g0 >= job.g1) break;
+    hipLaunchKernelGGL(sf_track_kernel, dim3(1), dim3(TL), 0, ctx->stream, job, (const TrackJob*)nullptr);
+    e = hipGetLastError();
+  }
+  int hdr[16];
+  if (e == hipSuccess) e = hipMemcpyAsync(hdr, tmp.p, sizeof hdr, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  dfree(ctx, &tmp);
+  if (e != hipSuccess) return fail(ctx, SF_E_DEVICE, "measure: %s", hipGetErrorString(e));
+  static_assert(offsetof(TrackState, dmax) == 9 * 4 && offsetof(TrackState, error) == 10 * 4, "header layout");
+  const int dmax_after = hdr[9], terr = hdr[10];
+  if (terr == TRK_E_DIM || dmax_after > c->dmax)
+    return fail(ctx, SF_E_TOO_LARGE, "after measuring qubit %u the rest of the circuit needs 2^%d elements, "
+                "the state holds 2^%d", q, dmax_after, c->dmax);
+  if (terr) return fail(ctx, SF_E_DEVICE, "tableau track reported internal error %d", terr);
+  // room for this outcome and for those of the circuit's remaining
+  // measurements, whose indices it shifts by one
+  size_t rem = 0;
+  for (size_t i = s->dev_done; i < c->g.size(); ++i) rem += c->g[i].op == DG_MEASURE;
+  const size_t need = s->nmeas + 1 + rem;
+  if (need > s->meas_cap) {
+    size_t cap = std::max<size_t>(2 * s->meas_cap, need);
+    DevBuf no, np;
+    if ((rc = dalloc(ctx, &no, cap))) return rc;
+    if ((rc = dalloc(ctx, &np, 8 * cap))) { dfree(ctx, &no); return rc; }
+    e = hipMemsetAsync(no.p, 0, cap, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(no.p, s->outcomes.p, s->meas_cap, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(np.p, s->pvals.p, 8 * s->meas_cap, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) { dfree(ctx, &no); dfree(ctx, &np); return fail(ctx, SF_E_DEVICE, "measure: %s", hipGetErrorString(e)); }
+    dfree(ctx, &s->outcomes);
+    dfree(ctx, &s->pvals);
+    s->outcomes = no;
+    s->pvals = np;
+    s->meas_cap = cap;
+  }
+  const size_t idx = s->nmeas;
+  if ((rc = run_gates(s, (const DGate*)s->adhoc.p, &g, 0, 1))) return rc;
+  uint8_t o = 0;
+  HIPCHK(ctx, hipMemcpyAsync(&o, (const uint8_t*)s->outcomes.p + idx, 1, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if ((rc = check_track(s))) return rc;
+  if (outcome) *outcome = o;
   return SF_OK;
 }
 
@@ -797,6 +886,8 @@ static sf_status batch_round(sf_ctx* ctx, sf_state* const* states, size_t ns, Ba
     sf_state* s = states[i];
     if (s->orig_done >= s->c->orig_end.size()) continue;
     plan_range(s, &A[i], &B[i], &O[i], &NS[i], &ML[i], cap);
+    if (ML[i] && s->nmeas + 1 > s->meas_cap)
+      return fail(ctx, SF_E_STATE, "state %zu: outcome buffer holds %zu measurements", i, s->meas_cap);
     act.push_back((int)i);
   }
   *active = (int)act.size();

@@ -348,3 +348,37 @@ def test_serve_budget_cancel_and_rejection(eng):
         small.submit(lb)
     assert ei.value.status == sf.SF_E_TOO_LARGE
     assert small.stats()["rejected"] == 1
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_adhoc_measurement(eng, case):
+    """sf_measure between gates equals a MEASURE gate inserted at that point
+    (same outcome index, same frame) in the oracle."""
+    import paper_1712_03554_amd as sf
+    circ = [wl.config1(case), _mixed_circuit(40 + case, 5 + case), wl.config3(case),
+            wl.qft(6, [1, 1, 0, 1, 0, 1], max_k=6), wl.config1(7), _mixed_circuit(50, 9)][case]
+    rng = np.random.default_rng(900 + case)
+    seed = 77 + case
+    print(f"case adhoc {circ.name} n={circ.n} seed={seed}", flush=True)
+    c = eng.load(circ.n, circ)
+    st = c.state(circ.init_bits, seed)
+    ref = OracleFrame(circ.n, circ.init_bits, seed)
+    cuts = sorted(set(int(x) for x in rng.integers(0, len(circ) + 1, size=3)))
+    done = 0
+    for cut in cuts + [len(circ)]:
+        while done < cut:
+            k = st.step(cut - done)
+            for g in circ.gates[done:done + k]:
+                ref.apply(*g)
+            done += k
+        if cut < len(circ) or case % 2:
+            for q in rng.permutation(circ.n)[:2]:
+                o = st.measure(int(q))
+                ref.apply(wl.MEASURE, int(q), 0, 0, 0, 1)
+                assert o == ref.outcomes()[-1]
+            _compare(st, ref, f"{circ.name} after ad-hoc measurements at {done}")
+    assert st.outcomes() == ref.outcomes()
+    _compare(st, ref, f"{circ.name} end")
+    with pytest.raises(sf.SFrameError) as ei:
+        st.measure(circ.n)
+    assert ei.value.status == sf.SF_E_INVALID
