@@ -277,94 +277,152 @@ static __device__ void cols_rowsum(Lds& L, int m, int n) {
   }
 }
 
-// Smallest column that breaks the echelon form: the lead column of some row
-// on which at least two rows have a bit (counting, on z columns, only the
-// Z-block rows unless full).  Returns -1 if the form holds.
-static __device__ int find_problem(const Lds& L, int n, int full) {
-  const int lane = lane_id();
-  const int R = (n + 63) / 64;
-  uint64_t zs[W];
-  for (int w = 0; w < W; ++w) zs[w] = 0;
-  for (int it = 0; it < R; ++it) {
-    const int i = it * 64 + lane;
-    bool zr = false;
-    if (i < n) {
-      uint64_t xa = 0;
-      for (int w = 0; w < W; ++w) xa |= L.rx[i * SF_WMAX + w];
-      zr = xa == 0;
-    }
-    const uint64_t b = __ballot(zr);
-    zs[it] = full ? ~0ull : b;
-  }
-  int best = 0x7fffffff;
-  for (int it = 0; it < R; ++it) {
-    const int i = it * 64 + lane;
-    if (i >= n) continue;
-    const int c = L.lead[i];
-    if (c < 0) continue;
-    int cnt = 0;
-    if (c < n) {
-      for (int w = 0; w < W; ++w) cnt += __popcll(L.cx[c * SF_WMAX + w]);
-    } else {
-      for (int w = 0; w < W; ++w) cnt += __popcll(L.cz[(c - n) * SF_WMAX + w] & zs[w]);
-    }
-    if (cnt >= 2 && c < best) best = c;
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    const int t = __shfl_xor(best, o);
-    best = t < best ? t : best;
-  }
-  return best == 0x7fffffff ? -1 : best;
-}
-
 // Gaussian elimination restricted to the columns that break the echelon
-// form.  full = 0 keeps the form of Figure 2b (X-block reduced on x-leads,
-// Z-block reduced on z-leads); full = 1 also clears X-block bits on z-leads.
-// Every row multiplication is replayed on the tracked phase vectors.
+// form: a column breaks it when it is the lead of some row and at least two
+// rows have a bit there (on z columns only Z-block rows count, unless full).
+// full = 0 keeps the form of Figure 2b (X-block reduced on x-leads, Z-block
+// reduced on z-leads); full = 1 also clears X-block bits on z-leads.  Each
+// step takes the smallest such column, multiplies its first leading row into
+// every other row with a bit there, and replays the row multiplication on the
+// tracked phase vectors.
+// Rows, their leads, the column-major copy and the tracked phase vectors are
+// held in registers for the whole loop: lane l owns
+// row slots and columns 64k + l (k < W) and hull vector l (V[l], then s0 at
+// lane d, u at lane d + 1).  The pivot row travels by readlane, the row masks
+// of each step by ballot; LDS is read on entry and written on exit only.
 static __device__ void repair(Lds& L, int n, int d, bool with_u, int full) {
   const int lane = lane_id();
-  const int R = (n + 63) / 64;
+  uint64_t x[W][W], z[W][W], cxr[W][W], czr[W][W];
+  int ld[W];
+  bool valid[W];
+  for (int k = 0; k < W; ++k) {
+    const int i = 64 * k + lane;
+    valid[k] = i < n;
+    for (int w = 0; w < W; ++w) {
+      x[k][w] = valid[k] ? L.rx[i * SF_WMAX + w] : 0ull;
+      z[k][w] = valid[k] ? L.rz[i * SF_WMAX + w] : 0ull;
+      cxr[k][w] = valid[k] ? L.cx[i * SF_WMAX + w] : 0ull;
+      czr[k][w] = valid[k] ? L.cz[i * SF_WMAX + w] : 0ull;
+    }
+    ld[k] = valid[k] ? (int)L.lead[i] : -1;
+  }
+  const bool has_vec = lane < d || lane == d || (lane == d + 1 && with_u);
+  const bool affine = lane == d;
+  uint64_t hv[W];
+  for (int w = 0; w < W; ++w)
+    hv[w] = lane < d ? L.V[lane][w] : lane == d ? L.s0[w] : (lane == d + 1 && with_u) ? L.u[w] : 0ull;
   for (int guard = 0; guard < 4 * SF_NMAX + 8; ++guard) {
     TIC(8);
-    const int col = find_problem(L, n, full);
-    TOC(8);
-    if (col < 0) break;
-    TIC(9);
-    int m = -1;
-    for (int it = 0; it < R && m < 0; ++it) {
-      int i = it * 64 + lane;
-      uint64_t b = __ballot(i < n && L.lead[i] == col);
-      if (b) m = it * 64 + __builtin_ctzll(b);
+    // Z-block rows (no x bits)
+    uint64_t zs[W];
+    for (int k = 0; k < W; ++k) {
+      uint64_t xa = 0;
+      for (int w = 0; w < W; ++w) xa |= x[k][w];
+      const uint64_t b = __ballot(valid[k] && xa == 0ull);
+      zs[k] = full ? ~0ull : b;
     }
-    const uint64_t* xm = &L.rx[m * SF_WMAX];
-    const uint64_t* zm = &L.rz[m * SF_WMAX];
-    for (int it = 0; it < R; ++it) {
-      const int i = it * 64 + lane;
-      bool hit = false;
-      int c = 0;
-      if (i < n && i != m) {
-        bool zrow = true;
-        for (int w = 0; w < W; ++w) zrow &= L.rx[i * SF_WMAX + w] == 0ull;
-        hit = (col < n || full || zrow) && colbit(L, i, col, n);
-        if (hit) {
-          c = rowprod_sign(&L.rx[i * SF_WMAX], &L.rz[i * SF_WMAX], xm, zm);
-          for (int w = 0; w < W; ++w) {
-            L.rx[i * SF_WMAX + w] ^= xm[w];
-            L.rz[i * SF_WMAX + w] ^= zm[w];
-          }
-          L.lead[i] = (int16_t)row_lead(&L.rx[i * SF_WMAX], &L.rz[i * SF_WMAX], n);
-        }
+    // bit counts of my columns (z columns: Z-block rows only unless full)
+    int cntx[W], cntz[W];
+    for (int k = 0; k < W; ++k) {
+      int a = 0, b = 0;
+      for (int w = 0; w < W; ++w) { a += __popcll(cxr[k][w]); b += __popcll(czr[k][w] & zs[w]); }
+      cntx[k] = a;
+      cntz[k] = b;
+    }
+    // smallest lead column shared by two rows
+    int best = 0x7fffffff;
+    for (int k = 0; k < W; ++k) {
+      const int c = ld[k];
+      const bool isx = c >= 0 && c < n;
+      const int cc = c < 0 ? 0 : (isx ? c : c - n);
+      int cnt = 0;
+      for (int kk = 0; kk < W; ++kk) {
+        const int vx = __shfl(cntx[kk], cc & 63);
+        const int vz = __shfl(cntz[kk], cc & 63);
+        if ((cc >> 6) == kk) cnt = isx ? vx : vz;
       }
-      const uint64_t rb = __ballot(hit), cb = __ballot(hit && c);
-      if (lane == 0) { L.rmask[it] = rb; L.cmask[it] = cb; }
+      if (c >= 0 && cnt >= 2 && c < best) best = c;
     }
-    __syncthreads();
-    cols_rowsum(L, m, n);
+    for (int o = 32; o > 0; o >>= 1) {
+      const int t = __shfl_xor(best, o);
+      best = t < best ? t : best;
+    }
+    TOC(8);
+    if (best == 0x7fffffff) break;
+    TIC(9);
+    const int col = __builtin_amdgcn_readfirstlane(best);
+    // pivot: the first slot leading at col
+    int m = -1;
+    for (int k = 0; k < W && m < 0; ++k) {
+      const uint64_t b = __ballot(valid[k] && ld[k] == col);
+      if (b) m = 64 * k + __builtin_ctzll(b);
+    }
+    const int km = m >> 6, lm = m & 63;
+    uint64_t xm[W], zm[W];
+    for (int w = 0; w < W; ++w) {
+      uint64_t sx = 0, sz = 0;
+      for (int kk = 0; kk < W; ++kk)
+        if (kk == km) { sx = x[kk][w]; sz = z[kk][w]; }
+      xm[w] = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sx >> 32), lm) << 32) |
+              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sx, lm);
+      zm[w] = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sz >> 32), lm) << 32) |
+              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sz, lm);
+    }
+    const bool xcol = col < n;
+    const int cb = xcol ? col : col - n;
+    uint64_t rm[W], cm[W];
+    for (int k = 0; k < W; ++k) {
+      const int i = 64 * k + lane;
+      uint64_t xa = 0, wsel = 0;
+      for (int w = 0; w < W; ++w) {
+        xa |= x[k][w];
+        if ((cb >> 6) == w) wsel = xcol ? x[k][w] : z[k][w];
+      }
+      const bool hit = valid[k] && i != m && (xcol || full || xa == 0ull) && ((wsel >> (cb & 63)) & 1ull);
+      int c = 0;
+      if (hit) {
+        c = rowprod_sign(x[k], z[k], xm, zm);
+        for (int w = 0; w < W; ++w) { x[k][w] ^= xm[w]; z[k][w] ^= zm[w]; }
+        ld[k] = row_lead(x[k], z[k], n);
+      }
+      rm[k] = __ballot(hit);
+      cm[k] = __ballot(hit && c);
+    }
+    // the column-major copy: columns where row m has a bit get the hit rows
+    for (int k = 0; k < W; ++k) {
+      if (!valid[k]) continue;
+      const bool bx = (xm[k] >> lane) & 1ull, bz = (zm[k] >> lane) & 1ull;
+      for (int w = 0; w < W; ++w) {
+        if (bx) cxr[k][w] ^= rm[w];
+        if (bz) czr[k][w] ^= rm[w];
+      }
+    }
     TOC(9);
     TIC(10);
-    apply_rowsum_batch(L, m, d, with_u);
+    // replay on the tracked phase vectors: sigma_i ^= sigma_m (^ c_i on s0)
+    if (has_vec) {
+      uint64_t wm = 0;
+      for (int w = 0; w < W; ++w) if ((m >> 6) == w) wm = hv[w];
+      const bool bm = (wm >> (m & 63)) & 1ull;
+      for (int w = 0; w < W; ++w) hv[w] ^= (bm ? rm[w] : 0ull) ^ (affine ? cm[w] : 0ull);
+    }
     TOC(10);
   }
+  for (int k = 0; k < W; ++k) {
+    const int i = 64 * k + lane;
+    if (!valid[k]) continue;
+    for (int w = 0; w < W; ++w) {
+      L.rx[i * SF_WMAX + w] = x[k][w];
+      L.rz[i * SF_WMAX + w] = z[k][w];
+      L.cx[i * SF_WMAX + w] = cxr[k][w];
+      L.cz[i * SF_WMAX + w] = czr[k][w];
+    }
+    L.lead[i] = (int16_t)ld[k];
+  }
+  if (lane < d) for (int w = 0; w < W; ++w) L.V[lane][w] = hv[w];
+  else if (lane == d) for (int w = 0; w < W; ++w) L.s0[w] = hv[w];
+  else if (lane == d + 1 && with_u) for (int w = 0; w < W; ++w) L.u[w] = hv[w];
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
