@@ -74,6 +74,48 @@ def cpu_baseline(circ, seed):
             "sample": f"{circ.name}: one full circuit ({len(arr)} gates, U={U}) on one host thread, {dt:.2f} s"}
 
 
+def batched_extra(eng, wl, name, circs, seeds, plain_sample):
+    """Batched vs plain U/s on a many-frame workload: the batched form runs
+    every frame of the workload per step; the plain form runs the first
+    plain_sample frames one at a time (a rate, so the two compare)."""
+    import torch
+    loaded = [eng.load(c.n, c) for c in circs]
+    states = [l.state(c.init_bits, s) for l, c, s in zip(loaded, circs, seeds)]
+    Us = [accounting(st, c, s, wl)[0] for st, c, s in zip(states, circs, seeds)]
+
+    def reset(idx):
+        for i in idx:
+            states[i].reset(circs[i].init_bits, seeds[i])
+
+    allidx = range(len(states))
+    reset(allidx)
+    eng.batch_run(states)  # warm-up
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        reset(allidx)
+        eng.batch_run(states)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    sub = range(min(plain_sample, len(states)))
+    reset(sub)
+    for i in sub:
+        states[i].run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reset(sub)
+    for i in sub:
+        states[i].run()
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    for st in states:
+        st.close()
+    return {"workload": name, "frames": len(states), "U_per_step": int(sum(Us)),
+            "batched_value": sum(Us) / tb, "batched_ms_per_step": tb * 1e3,
+            "plain_value": sum(Us[i] for i in sub) / tp, "plain_sample_frames": len(sub)}
+
+
 def serve_bench(eng, sf, wl, n_jobs, tick_segments, max_resident, budget_bytes, load_frac=0.7):
     """Serving on the mixed request stream (AQFT 40%, Cuccaro adder 40%,
     random Clifford+T 20%).  First a saturation run (every job submitted at
@@ -158,6 +200,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--path", default="batched", choices=["batched", "plain"])
     ap.add_argument("--serve-jobs", type=int, default=48, help="0 skips the serving run")
+    ap.add_argument("--no-extra", action="store_true", help="skip the many-frame batched workloads")
     ap.add_argument("--tick-segments", type=int, default=8)
     ap.add_argument("--max-resident", type=int, default=32)
     ap.add_argument("--serve-budget-gib", type=float, default=128.0)
@@ -273,6 +316,15 @@ def main():
         "element_roofline": elem_roof,
         "track_cycles_last_step": cyc,
     }
+    if not args.no_extra:
+        c3 = [wl.config3(t) for t in range(4096)]
+        c4 = [wl.config4(j) for j in range(1024)]
+        line["batched_workloads"] = [
+            batched_extra(eng, wl, "Steane fault-injection trials, 4096 x 13 qubits", c3,
+                          [wl.derive_seed(3, t) for t in range(4096)], 256),
+            batched_extra(eng, wl, "uneven random Clifford+T, 1024 circuits, n in 16..256", c4,
+                          [wl.derive_seed(4, j) for j in range(1024)], 16),
+        ]
     if args.serve_jobs > 0:
         line["serve"] = serve_bench(eng, sf, wl, args.serve_jobs, args.tick_segments, args.max_resident,
                                     int(args.serve_budget_gib * (1 << 30)))

@@ -88,6 +88,7 @@ typedef struct sf_ctx sf_ctx;
 typedef struct sf_circuit sf_circuit;
 typedef struct sf_state sf_state;
 typedef struct sf_server sf_server;
+typedef struct sf_graph sf_graph;
 
 /* Create a context on HIP device `device` that queues work on `hip_stream`
  * (a hipStream_t; NULL = the null stream).  `alloc` may be NULL.
@@ -142,6 +143,25 @@ sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t n_states);
  * if after this measurement the rest of the circuit would need more frame
  * elements than the state was sized for. */
 sf_status sf_measure(sf_state* s, uint32_t q, int* outcome);
+/* Graph form of sf_batch_run for frames that are run again and again (the
+ * batched execution of section 3's frame updates over many independent
+ * frames, recorded once).  Plans every round of a run of the given states
+ * from their initial basis states and records the initialisation and all
+ * launches as one hipGraph of kernel nodes; basis[i] (W words, or NULL for
+ * |0...0>) and seeds[i] are the inputs of frame i (basis and seeds may be
+ * NULL).  The states stay bound to the graph until sf_graph_destroy:
+ * sf_state_destroy on them returns SF_E_STATE, and so does an sf_measure that
+ * would have to grow their outcome buffers.  Synchronises. */
+sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t n_states, const uint64_t* const* basis,
+                         const uint64_t* seeds, sf_graph** out);
+/* Change the inputs of frame i for the next launch. */
+sf_status sf_graph_set_input(sf_graph* g, size_t i, const uint64_t* basis_bits, uint64_t seed);
+/* Re-initialise every frame of the graph from its inputs and run all its
+ * gates (asynchronous, one graph launch on the context's stream).  Results
+ * are those of sf_state_reset + sf_batch_run with the same inputs. */
+sf_status sf_graph_launch(sf_graph* g);
+/* Synchronises, frees the graph and releases its states. */
+sf_status sf_graph_destroy(sf_graph* g);
 /* Wait for queued work; reports device-side failures of the queued steps. */
 sf_status sf_sync(sf_state* s);
 

@@ -24,7 +24,8 @@ SF_OK, SF_E_INVALID, SF_E_OOM, SF_E_DEVICE, SF_E_TOO_LARGE, SF_E_STATE, SF_E_BUF
 STATUS_NAMES = ["SF_OK", "SF_E_INVALID", "SF_E_OOM", "SF_E_DEVICE", "SF_E_TOO_LARGE", "SF_E_STATE",
                 "SF_E_BUFSIZE", "SF_E_CANCELLED"]
 
-EXPORTS = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_measure", "sf_circuit_load", "sf_circuit_info",
+EXPORTS = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_measure", "sf_batch_graph",
+           "sf_graph_set_input", "sf_graph_launch", "sf_graph_destroy", "sf_circuit_load", "sf_circuit_info",
            "sf_circuit_destroy", "sf_state_init", "sf_state_destroy", "sf_step", "sf_run", "sf_sync",
            "sf_outcomes", "sf_frame_size", "sf_read_frame", "sf_state_info", "sf_state_reset",
            "sf_state_dim", "sf_profile", "sf_profile_read", "sf_state_cycles", "sf_batch_run",
@@ -72,6 +73,10 @@ def load_library(path: str = LIB_PATH):
         "sf_step": [vp, sz, P(sz)],
         "sf_run": [vp],
         "sf_measure": [vp, ctypes.c_uint32, P(ctypes.c_int)],
+        "sf_batch_graph": [vp, vp, sz, vp, vp, P(vp)],
+        "sf_graph_set_input": [vp, sz, vp, u64],
+        "sf_graph_launch": [vp],
+        "sf_graph_destroy": [vp],
         "sf_sync": [vp],
         "sf_outcomes": [vp, vp, sz, P(sz)],
         "sf_frame_size": [vp, P(u64)],
@@ -175,6 +180,10 @@ class Engine:
         """Run every remaining gate of the given states as one batch (synchronises)."""
         arr = (ctypes.c_void_p * max(1, len(states)))(*[s._h.value for s in states])
         self._check(self._L.sf_batch_run(self._h, ctypes.cast(arr, ctypes.c_void_p), len(states)))
+
+    def batch_graph(self, states, bases=None, seeds=None) -> "Graph":
+        """Record a whole batched run of these states (see sf_batch_graph)."""
+        return Graph(self, states, bases, seeds)
 
     def profile(self, enable: bool):
         self._check(self._L.sf_profile(self._h, 1 if enable else 0))
@@ -369,6 +378,48 @@ class Server:
     def close(self):
         if getattr(self, "_h", None) and self.eng._h and not _exiting:
             self._L.sf_serve_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def _basis_words(n: int, bits):
+    words = np.zeros(4, dtype=np.uint64)
+    if bits is not None:
+        for q, b in enumerate(bits):
+            if int(b) & 1:
+                words[q >> 6] |= np.uint64(1 << (q & 63))
+    return words
+
+
+class Graph:
+    """A recorded batched run; launch() replays it (asynchronously)."""
+
+    def __init__(self, eng: Engine, states, bases=None, seeds=None):
+        self.eng, self._L, self.states = eng, eng._L, list(states)
+        ns = len(self.states)
+        words = [_basis_words(s.n, None if bases is None else bases[i]) for i, s in enumerate(self.states)]
+        self._words = words
+        ptrs = (ctypes.c_void_p * max(1, ns))(*[w.ctypes.data for w in words])
+        sd = np.array([0 if seeds is None else int(seeds[i]) & ((1 << 64) - 1) for i in range(ns)] or [0],
+                      dtype=np.uint64)
+        arr = (ctypes.c_void_p * max(1, ns))(*[s._h.value for s in self.states])
+        h = ctypes.c_void_p()
+        eng._check(self._L.sf_batch_graph(eng._h, ctypes.cast(arr, ctypes.c_void_p), ns,
+                                          ctypes.cast(ptrs, ctypes.c_void_p), _ptr(sd), ctypes.byref(h)))
+        self._h = h
+
+    def set_input(self, i: int, basis_bits=None, seed: int = 0):
+        w = _basis_words(self.states[i].n, basis_bits)
+        self.eng._check(self._L.sf_graph_set_input(self._h, i, _ptr(w), ctypes.c_uint64(seed & ((1 << 64) - 1))))
+
+    def launch(self):
+        self.eng._check(self._L.sf_graph_launch(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) and self.eng._h and not _exiting:
+            self._L.sf_graph_destroy(self._h)
         self._h = None
 
     def __del__(self):

@@ -92,6 +92,7 @@ struct sf_state {
   int cur;
   size_t orig_done, dev_done, nmeas;
   size_t meas_cap;  // capacity of outcomes / pvals (circuit measurements, grown by sf_measure)
+  int graph_refs;   // graphs that hold this state's buffers
   uint64_t seed;
   int G;  // measurement reduction grid (fixed per state)
 };
@@ -457,6 +458,7 @@ extern "C" sf_status sf_state_init(sf_ctx* ctx, const sf_circuit* c, const uint6
   s->seed = seed;
   s->G = grid_for(c->dmax) > 1024 ? 1024 : grid_for(c->dmax);
   s->meas_cap = std::max<size_t>(1, c->n_meas);
+  s->graph_refs = 0;
   sf_status rc = SF_OK;
   size_t ampb = (size_t)16 << c->dmax;
   if ((rc = dalloc(ctx, &s->st, sizeof(TrackState))) ||
@@ -489,6 +491,7 @@ extern "C" sf_status sf_state_init(sf_ctx* ctx, const sf_circuit* c, const uint6
 
 extern "C" sf_status sf_state_destroy(sf_state* s) {
   if (!s) return SF_OK;
+  if (s->graph_refs) return fail(s->ctx, SF_E_STATE, "state is part of a graph; destroy the graph first");
   hipStreamSynchronize(s->ctx->stream);
   state_free(s);
   delete s;
@@ -646,6 +649,7 @@ extern "C" sf_status sf_measure(sf_state* s, uint32_t q, int* outcome) {
   for (size_t i = s->dev_done; i < c->g.size(); ++i) rem += c->g[i].op == DG_MEASURE;
   const size_t need = s->nmeas + 1 + rem;
   if (need > s->meas_cap) {
+    if (s->graph_refs) return fail(ctx, SF_E_STATE, "measurement buffers of a state in a graph cannot grow");
     size_t cap = std::max<size_t>(2 * s->meas_cap, need);
     DevBuf no, np;
     if ((rc = dalloc(ctx, &no, cap))) return rc;
@@ -794,15 +798,29 @@ extern "C" sf_status sf_read_frame(sf_state* s, uint64_t* tableau, uint64_t* sig
 // share one launch (one wavefront each); the element kernels of segment k of
 // every frame share one launch (grid y = frame).
 // ---------------------------------------------------------------------------
+// Host bookkeeping of a frame's progress through its circuit.
+struct Progress {
+  size_t orig_done, dev_done, nmeas;
+  int cur;
+};
+
+static Progress progress_of(const sf_state* s) { return Progress{s->orig_done, s->dev_done, s->nmeas, s->cur}; }
+
+static void set_progress(sf_state* s, const Progress& p) {
+  s->orig_done = p.orig_done;
+  s->dev_done = p.dev_done;
+  s->nmeas = p.nmeas;
+  s->cur = p.cur;
+}
+
 // The range runs to the next measurement; with cap > 0 it may also stop right
 // after its cap-th non-Clifford phase gate when that gate ends a circuit gate
 // (a segment boundary either way, so the segments and their arithmetic are
 // those of the uncapped run).
-static void plan_range(const sf_state* s, size_t* a, size_t* b, size_t* orig_after, int* nseg, int* meas_last,
-                       int cap = 0) {
-  const sf_circuit* c = s->c;
-  size_t o = s->orig_done, e = s->dev_done;
-  *a = s->dev_done;
+static void plan_range(const sf_circuit* c, const Progress& pr, size_t* a, size_t* b, size_t* orig_after, int* nseg,
+                       int* meas_last, int cap = 0) {
+  size_t o = pr.orig_done, e = pr.dev_done;
+  *a = pr.dev_done;
   int terms = 0;
   while (o < c->orig_end.size()) {
     size_t end = c->orig_end[o];
@@ -827,21 +845,96 @@ static void plan_range(const sf_state* s, size_t* a, size_t* b, size_t* orig_aft
   *meas_last = ml ? 1 : 0;
 }
 
-static ElemDesc elem_desc(const sf_state* s, const SegProg* prog) {
+static ElemDesc elem_desc(const sf_state* s, int cur, const SegProg* prog, const uint64_t* seedp) {
   ElemDesc e;
   memset(&e, 0, sizeof e);
   e.prog = prog;
   e.had = (const GF2Q*)s->had.p;
-  e.amp = (double2*)s->amp[s->cur].p;
-  e.amp_other = (double2*)s->amp[s->cur ^ 1].p;
+  e.amp = (double2*)s->amp[cur].p;
+  e.amp_other = (double2*)s->amp[cur ^ 1].p;
   e.partials = (double2*)s->partials.p;
   e.outcomes = (uint8_t*)s->outcomes.p;
   e.pvals = (double*)s->pvals.p;
   e.scale = (double*)s->scale.p;
   e.flags = (int*)s->flags.p;
   e.seed = s->seed;
+  e.seedp = seedp;
   e.G = s->G;
   return e;
+}
+
+// One batched round: the track job of every frame with work left and the
+// element descriptors of its segments (row k of desc = segment k of every
+// frame; row kmax = the measurement of frames whose range ends in one).
+struct RoundPlan {
+  std::vector<TrackJob> jobs;
+  std::vector<ElemDesc> desc;
+  int na = 0, kmax = 0, gx = 1, gm = 1;
+  bool anym = false;
+};
+
+// Plans the next round from the progress pr[] and advances it; false when no
+// frame has work left.  seedp[i] (optional) is where frame i's seed is read.
+static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap, const uint64_t* const* seedp,
+                       RoundPlan* rp, sf_status* err) {
+  std::vector<int> act;
+  std::vector<size_t> A(ns), B(ns), O(ns);
+  std::vector<int> NS(ns), ML(ns);
+  *err = SF_OK;
+  for (size_t i = 0; i < ns; ++i) {
+    const sf_circuit* c = states[i]->c;
+    if (pr[i].orig_done >= c->orig_end.size()) continue;
+    plan_range(c, pr[i], &A[i], &B[i], &O[i], &NS[i], &ML[i], cap);
+    if (ML[i] && pr[i].nmeas + 1 > states[i]->meas_cap) {
+      *err = fail(states[i]->ctx, SF_E_STATE, "state %zu: outcome buffer holds %zu measurements", i,
+                  states[i]->meas_cap);
+      return false;
+    }
+    act.push_back((int)i);
+  }
+  if (act.empty()) return false;
+  const int na = (int)act.size();
+  rp->na = na;
+  rp->jobs.assign(na, TrackJob{});
+  rp->kmax = 0;
+  rp->gx = rp->gm = 1;
+  rp->anym = false;
+  for (int j = 0; j < na; ++j) {
+    const int i = act[j];
+    sf_state* s = states[i];
+    TrackJob& jb = rp->jobs[j];
+    memset(&jb, 0, sizeof jb);
+    jb.st = (TrackState*)s->st.p;
+    jb.gates = (const DGate*)s->c->dgates.p;
+    jb.g0 = (int)A[i];
+    jb.g1 = (int)B[i];
+    jb.prog = (SegProg*)s->prog.p;
+    jb.had = (GF2Q*)s->had.p;
+    jb.outcomes = (const uint8_t*)s->outcomes.p;
+    rp->kmax = std::max(rp->kmax, NS[i]);
+    rp->gx = std::max(rp->gx, grid_for(s->c->dmax));
+    rp->gm = std::max(rp->gm, s->G);
+    rp->anym |= ML[i] != 0;
+  }
+  const int kmax = rp->kmax;
+  rp->desc.assign((size_t)(kmax + 1) * na, ElemDesc{});
+  for (int k = 0; k <= kmax; ++k)
+    for (int j = 0; j < na; ++j) {
+      const int i = act[j];
+      sf_state* s = states[i];
+      const SegProg* base = (const SegProg*)s->prog.p;
+      const SegProg* p = nullptr;
+      if (k < kmax) p = k < NS[i] ? base + k : nullptr;
+      else p = ML[i] ? base + (NS[i] - 1) : nullptr;  // measurement descriptors
+      rp->desc[(size_t)k * na + j] = elem_desc(s, pr[i].cur, p, seedp ? seedp[i] : nullptr);
+    }
+  for (int j = 0; j < na; ++j) {
+    const int i = act[j];
+    pr[i].dev_done = B[i];
+    pr[i].orig_done = O[i];
+    if (ML[i]) { pr[i].cur ^= 1; pr[i].nmeas++; }
+  }
+  return true;
 }
 
 // Device descriptor buffers of batched rounds and the host copies they were
@@ -874,87 +967,53 @@ static void scratch_free(sf_ctx* ctx, BatchScratch* bs) {
   bs->keep_desc.clear();
 }
 
-// Queue one round for the given states: each unfinished state runs its gates
-// up to and including its next measurement.  *active = number of states that
-// had work.  Asynchronous; the scratch must be large enough.
-static sf_status batch_round(sf_ctx* ctx, sf_state* const* states, size_t ns, BatchScratch* bs, int* active,
-                             int cap = 0) {
-  std::vector<int> act;
-  std::vector<size_t> A(ns), B(ns), O(ns);
-  std::vector<int> NS(ns), ML(ns);
-  for (size_t i = 0; i < ns; ++i) {
-    sf_state* s = states[i];
-    if (s->orig_done >= s->c->orig_end.size()) continue;
-    plan_range(s, &A[i], &B[i], &O[i], &NS[i], &ML[i], cap);
-    if (ML[i] && s->nmeas + 1 > s->meas_cap)
-      return fail(ctx, SF_E_STATE, "state %zu: outcome buffer holds %zu measurements", i, s->meas_cap);
-    act.push_back((int)i);
-  }
-  *active = (int)act.size();
-  if (act.empty()) return SF_OK;
-  const int na = (int)act.size();
-  bs->keep_jobs.emplace_back(na);
-  std::vector<TrackJob>& jobs = bs->keep_jobs.back();
-  int kmax = 0, gx = 1, gm = 1;
-  for (int j = 0; j < na; ++j) {
-    sf_state* s = states[act[j]];
-    TrackJob& jb = jobs[j];
-    memset(&jb, 0, sizeof jb);
-    jb.st = (TrackState*)s->st.p;
-    jb.gates = (const DGate*)s->c->dgates.p;
-    jb.g0 = (int)A[act[j]];
-    jb.g1 = (int)B[act[j]];
-    jb.prog = (SegProg*)s->prog.p;
-    jb.had = (GF2Q*)s->had.p;
-    jb.outcomes = (const uint8_t*)s->outcomes.p;
-    kmax = std::max(kmax, NS[act[j]]);
-    gx = std::max(gx, grid_for(s->c->dmax));
-    gm = std::max(gm, s->G);
-  }
-  HIPCHK(ctx, hipMemcpyAsync(bs->djobs.p, jobs.data(), na * sizeof(TrackJob), hipMemcpyHostToDevice, ctx->stream));
+// Kernel launches of one planned round, with its descriptors at djobs/ddesc.
+static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs, const ElemDesc* dd) {
+  const int na = rp.na;
   prof_begin(ctx, PK_TRACK);
-  hipLaunchKernelGGL(sf_track_kernel, dim3(na), dim3(TL), 0, ctx->stream, TrackJob{}, (const TrackJob*)bs->djobs.p);
+  hipLaunchKernelGGL(sf_track_kernel, dim3(na), dim3(TL), 0, ctx->stream, TrackJob{}, djobs);
   prof_end(ctx);
-  bs->keep_desc.emplace_back((size_t)(kmax + 1) * na);
-  std::vector<ElemDesc>& D = bs->keep_desc.back();
-  for (int k = 0; k <= kmax; ++k)
-    for (int j = 0; j < na; ++j) {
-      sf_state* s = states[act[j]];
-      const SegProg* base = (const SegProg*)s->prog.p;
-      const SegProg* p = nullptr;
-      if (k < kmax) p = k < NS[act[j]] ? base + k : nullptr;
-      else p = ML[act[j]] ? base + (NS[act[j]] - 1) : nullptr;  // measurement descriptors
-      D[(size_t)k * na + j] = elem_desc(s, p);
-    }
-  HIPCHK(ctx, hipMemcpyAsync(bs->ddesc.p, D.data(), D.size() * sizeof(ElemDesc), hipMemcpyHostToDevice,
-                             ctx->stream));
-  const ElemDesc* dd = (const ElemDesc*)bs->ddesc.p;
-  for (int k = 0; k < kmax; ++k) {
+  for (int k = 0; k < rp.kmax; ++k) {
     prof_begin(ctx, PK_SEG);
-    hipLaunchKernelGGL(sf_seg_batch, dim3(gx, na), dim3(EB), 0, ctx->stream, dd + (size_t)k * na);
+    hipLaunchKernelGGL(sf_seg_batch, dim3(rp.gx, na), dim3(EB), 0, ctx->stream, dd + (size_t)k * na);
     prof_end(ctx);
   }
-  bool anym = false;
-  for (int j = 0; j < na; ++j) anym |= ML[act[j]] != 0;
-  if (anym) {
-    const ElemDesc* dm = dd + (size_t)kmax * na;
+  if (rp.anym) {
+    const ElemDesc* dm = dd + (size_t)rp.kmax * na;
     prof_begin(ctx, PK_MREDUCE);
-    hipLaunchKernelGGL(sf_meas_reduce_batch, dim3(gm, na), dim3(EB), 0, ctx->stream, dm);
+    hipLaunchKernelGGL(sf_meas_reduce_batch, dim3(rp.gm, na), dim3(EB), 0, ctx->stream, dm);
     prof_end(ctx);
     prof_begin(ctx, PK_MFINAL);
     hipLaunchKernelGGL(sf_meas_final_batch, dim3(1, na), dim3(EB), 0, ctx->stream, dm);
     prof_end(ctx);
     prof_begin(ctx, PK_MFILTER);
-    hipLaunchKernelGGL(sf_meas_filter_batch, dim3(gx, na), dim3(EB), 0, ctx->stream, dm);
+    hipLaunchKernelGGL(sf_meas_filter_batch, dim3(rp.gx, na), dim3(EB), 0, ctx->stream, dm);
     prof_end(ctx);
   }
+}
+
+// Queue one round for the given states: each unfinished state runs its gates
+// up to and including its next measurement (or its cap-th non-Clifford phase
+// gate).  *active = number of states that had work.  Asynchronous; the
+// scratch must be large enough.
+static sf_status batch_round(sf_ctx* ctx, sf_state* const* states, size_t ns, BatchScratch* bs, int* active,
+                             int cap = 0) {
+  std::vector<Progress> pr(ns);
+  for (size_t i = 0; i < ns; ++i) pr[i] = progress_of(states[i]);
+  RoundPlan rp;
+  sf_status err;
+  *active = 0;
+  if (!plan_round(states, ns, pr.data(), cap, nullptr, &rp, &err)) return err;
+  *active = rp.na;
+  bs->keep_jobs.push_back(rp.jobs);
+  bs->keep_desc.push_back(rp.desc);
+  HIPCHK(ctx, hipMemcpyAsync(bs->djobs.p, bs->keep_jobs.back().data(), rp.na * sizeof(TrackJob),
+                             hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(bs->ddesc.p, bs->keep_desc.back().data(), rp.desc.size() * sizeof(ElemDesc),
+                             hipMemcpyHostToDevice, ctx->stream));
+  launch_round(ctx, rp, (const TrackJob*)bs->djobs.p, (const ElemDesc*)bs->ddesc.p);
   HIPCHK(ctx, hipGetLastError());
-  for (int j = 0; j < na; ++j) {
-    sf_state* s = states[act[j]];
-    s->dev_done = B[act[j]];
-    s->orig_done = O[act[j]];
-    if (ML[act[j]]) { s->cur ^= 1; s->nmeas++; }
-  }
+  for (size_t i = 0; i < ns; ++i) set_progress(states[i], pr[i]);
   return SF_OK;
 }
 
@@ -978,6 +1037,190 @@ extern "C" sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t n
     rc = check_track(states[i]);
     if (rc != SF_OK) return rc;
   }
+  return SF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Graph form of a batched run: the launches of a whole run of a fixed set of
+// frames (initialisation included) recorded once as a hipGraph of kernel
+// nodes and replayed with one launch.  The rounds depend on the circuits
+// only, so their descriptors are planned and uploaded when the graph is
+// built; basis states and seeds sit in a device table that each replay reads.
+// ---------------------------------------------------------------------------
+struct sf_graph {
+  sf_ctx* ctx;
+  std::vector<sf_state*> states;
+  std::vector<Progress> final_pr;
+  std::vector<uint64_t> params;  // 8 words per frame: basis[4], seed, unused
+  DevBuf dparams, ddesc;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static hipError_t add_kernel_node(hipGraph_t g, hipGraphNode_t* last, const void* func, dim3 grid, dim3 block,
+                                  void** args) {
+  hipKernelNodeParams p;
+  memset(&p, 0, sizeof p);
+  p.func = const_cast<void*>(func);
+  p.gridDim = grid;
+  p.blockDim = block;
+  p.sharedMemBytes = 0;
+  p.kernelParams = args;
+  p.extra = nullptr;
+  hipGraphNode_t node;
+  hipError_t e = hipGraphAddKernelNode(&node, g, *last ? last : nullptr, *last ? 1 : 0, &p);
+  if (e == hipSuccess) *last = node;
+  return e;
+}
+
+static void graph_free(sf_graph* g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  dfree(g->ctx, &g->dparams);
+  dfree(g->ctx, &g->ddesc);
+  for (sf_state* s : g->states) s->graph_refs--;
+}
+
+extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t ns, const uint64_t* const* basis,
+                                    const uint64_t* seeds, sf_graph** out) {
+  if (!ctx || !out || (ns && !states)) return SF_E_INVALID;
+  *out = nullptr;
+  for (size_t i = 0; i < ns; ++i)
+    if (!states[i] || states[i]->ctx != ctx) return fail(ctx, SF_E_INVALID, "state %zu is not of this context", i);
+  {
+    std::vector<sf_state*> srt(states, states + ns);
+    std::sort(srt.begin(), srt.end());
+    if (std::adjacent_find(srt.begin(), srt.end()) != srt.end())
+      return fail(ctx, SF_E_INVALID, "a state appears twice in the batch");
+  }
+  sf_graph* g = new (std::nothrow) sf_graph();
+  if (!g) return fail(ctx, SF_E_OOM, "host allocation failed");
+  g->ctx = ctx;
+  g->states.assign(states, states + ns);
+  for (sf_state* s : g->states) s->graph_refs++;
+  g->params.assign(8 * std::max<size_t>(1, ns), 0);
+  for (size_t i = 0; i < ns; ++i) {
+    const int W = (int)((states[i]->c->n + 63) / 64);
+    if (basis && basis[i])
+      for (int w = 0; w < W; ++w) g->params[8 * i + w] = basis[i][w];
+    g->params[8 * i + 4] = seeds ? seeds[i] : 0;
+  }
+  sf_status rc = dalloc(ctx, &g->dparams, g->params.size() * 8);
+  if (rc) { graph_free(g); delete g; return rc; }
+  // plan every round from the initial state
+  std::vector<Progress> pr(ns, Progress{0, 0, 0, 0});
+  std::vector<const uint64_t*> seedp(ns);
+  for (size_t i = 0; i < ns; ++i) seedp[i] = (const uint64_t*)g->dparams.p + 8 * i + 4;
+  std::vector<RoundPlan> rounds;
+  for (;;) {
+    RoundPlan rp;
+    sf_status err;
+    if (!plan_round(states, ns, pr.data(), 0, seedp.data(), &rp, &err)) {
+      if (err != SF_OK) { graph_free(g); delete g; return err; }
+      break;
+    }
+    rounds.push_back(std::move(rp));
+  }
+  g->final_pr = pr;
+  // one descriptor table: init descriptors, then each round's jobs and descs
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t off_init = 0, total = al(std::max<size_t>(1, ns) * sizeof(InitDesc));
+  std::vector<size_t> off_j(rounds.size()), off_d(rounds.size());
+  for (size_t r = 0; r < rounds.size(); ++r) {
+    off_j[r] = total;
+    total += al(rounds[r].jobs.size() * sizeof(TrackJob));
+    off_d[r] = total;
+    total += al(rounds[r].desc.size() * sizeof(ElemDesc));
+  }
+  if ((rc = dalloc(ctx, &g->ddesc, total))) { graph_free(g); delete g; return rc; }
+  std::vector<char> host(total, 0);
+  for (size_t i = 0; i < ns; ++i) {
+    InitDesc d;
+    memset(&d, 0, sizeof d);
+    d.st = (TrackState*)states[i]->st.p;
+    d.amp = (double2*)states[i]->amp[0].p;
+    d.flags = (int*)states[i]->flags.p;
+    d.params = (const uint64_t*)g->dparams.p + 8 * i;
+    d.n = (int)states[i]->c->n;
+    memcpy(host.data() + off_init + i * sizeof(InitDesc), &d, sizeof d);
+  }
+  for (size_t r = 0; r < rounds.size(); ++r) {
+    memcpy(host.data() + off_j[r], rounds[r].jobs.data(), rounds[r].jobs.size() * sizeof(TrackJob));
+    memcpy(host.data() + off_d[r], rounds[r].desc.data(), rounds[r].desc.size() * sizeof(ElemDesc));
+  }
+  hipError_t e = hipMemcpyAsync(g->ddesc.p, host.data(), total, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = hipGraphCreate(&g->graph, 0);
+  hipGraphNode_t last = nullptr;
+  char* base = (char*)g->ddesc.p;
+  if (e == hipSuccess && ns) {
+    const InitDesc* di = (const InitDesc*)(base + off_init);
+    void* args[] = {(void*)&di};
+    e = add_kernel_node(g->graph, &last, (const void*)sf_init_batch, dim3((unsigned)ns), dim3(EB), args);
+  }
+  for (size_t r = 0; r < rounds.size() && e == hipSuccess; ++r) {
+    const RoundPlan& rp = rounds[r];
+    const int na = rp.na;
+    TrackJob zero;
+    memset(&zero, 0, sizeof zero);
+    const TrackJob* dj = (const TrackJob*)(base + off_j[r]);
+    const ElemDesc* dd = (const ElemDesc*)(base + off_d[r]);
+    {
+      void* args[] = {(void*)&zero, (void*)&dj};
+      e = add_kernel_node(g->graph, &last, (const void*)sf_track_kernel, dim3(na), dim3(TL), args);
+    }
+    for (int k = 0; k < rp.kmax && e == hipSuccess; ++k) {
+      const ElemDesc* dk = dd + (size_t)k * na;
+      void* args[] = {(void*)&dk};
+      e = add_kernel_node(g->graph, &last, (const void*)sf_seg_batch, dim3(rp.gx, na), dim3(EB), args);
+    }
+    if (rp.anym && e == hipSuccess) {
+      const ElemDesc* dm = dd + (size_t)rp.kmax * na;
+      void* args[] = {(void*)&dm};
+      e = add_kernel_node(g->graph, &last, (const void*)sf_meas_reduce_batch, dim3(rp.gm, na), dim3(EB), args);
+      if (e == hipSuccess)
+        e = add_kernel_node(g->graph, &last, (const void*)sf_meas_final_batch, dim3(1, na), dim3(EB), args);
+      if (e == hipSuccess)
+        e = add_kernel_node(g->graph, &last, (const void*)sf_meas_filter_batch, dim3(rp.gx, na), dim3(EB), args);
+    }
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    graph_free(g);
+    delete g;
+    return fail(ctx, SF_E_DEVICE, "graph build: %s", hipGetErrorString(e));
+  }
+  *out = g;
+  return SF_OK;
+}
+
+extern "C" sf_status sf_graph_set_input(sf_graph* g, size_t i, const uint64_t* basis, uint64_t seed) {
+  if (!g) return SF_E_INVALID;
+  if (i >= g->states.size()) return fail(g->ctx, SF_E_INVALID, "frame %zu of %zu", i, g->states.size());
+  const int W = (int)((g->states[i]->c->n + 63) / 64);
+  for (int w = 0; w < 4; ++w) g->params[8 * i + w] = (basis && w < W) ? basis[w] : 0;
+  g->params[8 * i + 4] = seed;
+  return SF_OK;
+}
+
+extern "C" sf_status sf_graph_launch(sf_graph* g) {
+  if (!g) return SF_E_INVALID;
+  sf_ctx* ctx = g->ctx;
+  HIPCHK(ctx, hipMemcpyAsync(g->dparams.p, g->params.data(), g->params.size() * 8, hipMemcpyHostToDevice,
+                             ctx->stream));
+  HIPCHK(ctx, hipGraphLaunch(g->exec, ctx->stream));
+  for (size_t i = 0; i < g->states.size(); ++i) {
+    set_progress(g->states[i], g->final_pr[i]);
+    g->states[i]->seed = g->params[8 * i + 4];
+  }
+  return SF_OK;
+}
+
+extern "C" sf_status sf_graph_destroy(sf_graph* g) {
+  if (!g) return SF_OK;
+  (void)hipStreamSynchronize(g->ctx->stream);
+  graph_free(g);
+  delete g;
   return SF_OK;
 }
 

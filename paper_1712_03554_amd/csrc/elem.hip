@@ -285,7 +285,7 @@ extern "C" __global__ void __launch_bounds__(EB) sf_meas_reduce_batch(const Elem
 extern "C" __global__ void __launch_bounds__(EB) sf_meas_final_batch(const ElemDesc* __restrict__ D) {
   const ElemDesc& e = D[blockIdx.y];
   if (!e.prog) return;
-  meas_final_body(e.prog, e.partials, e.G, e.seed, e.outcomes, e.pvals, e.scale, e.flags);
+  meas_final_body(e.prog, e.partials, e.G, e.seedp ? *e.seedp : e.seed, e.outcomes, e.pvals, e.scale, e.flags);
 }
 
 extern "C" __global__ void __launch_bounds__(EB) sf_meas_filter_batch(const ElemDesc* __restrict__ D) {
@@ -416,9 +416,8 @@ sf_compact_write(const uint8_t* __restrict__ flag, const uint64_t* __restrict__ 
 
 // Basis state |b>: stabilizer matrix in basis form (row q = Z_q, Figure 2a),
 // phase vector sigma = b, one element of amplitude 1.
-extern "C" __global__ void __launch_bounds__(EB)
-sf_init_state(TrackState* __restrict__ st, int n, uint64_t b0, uint64_t b1, uint64_t b2, uint64_t b3,
-              double2* __restrict__ amp, int* __restrict__ flags) {
+__device__ void init_body(TrackState* __restrict__ st, int n, uint64_t b0, uint64_t b1, uint64_t b2, uint64_t b3,
+                          double2* __restrict__ amp, int* __restrict__ flags) {
   const int W = (n + 63) / 64;
   for (int i = threadIdx.x; i < SF_NMAX * SF_WMAX; i += blockDim.x) {
     int q = i / SF_WMAX, w = i % SF_WMAX;
@@ -439,4 +438,17 @@ sf_init_state(TrackState* __restrict__ st, int n, uint64_t b0, uint64_t b1, uint
     amp[0] = make_double2(1.0, 0.0);
     *flags = 0;
   }
+}
+
+extern "C" __global__ void __launch_bounds__(EB)
+sf_init_state(TrackState* __restrict__ st, int n, uint64_t b0, uint64_t b1, uint64_t b2, uint64_t b3,
+              double2* __restrict__ amp, int* __restrict__ flags) {
+  init_body(st, n, b0, b1, b2, b3, amp, flags);
+}
+
+// One block per frame (blockIdx.x selects the InitDesc).
+extern "C" __global__ void __launch_bounds__(EB) sf_init_batch(const InitDesc* __restrict__ D) {
+  const InitDesc& e = D[blockIdx.x];
+  const uint64_t* b = e.params;
+  init_body(e.st, e.n, b[0], b[1], b[2], b[3], e.amp, e.flags);
 }

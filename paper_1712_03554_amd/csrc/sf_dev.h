@@ -116,5 +116,16 @@ struct ElemDesc {
   double* scale;
   int* flags;
   uint64_t seed;
+  const uint64_t* seedp;   // if set, the seed is read here (graph replays)
   int32_t G, pad;
+};
+
+// Initialisation of one frame in a batched launch: basis words and seed are
+// read from device memory (params[0..3] = basis, params[4] = seed).
+struct InitDesc {
+  TrackState* st;
+  double2* amp;
+  int* flags;
+  const uint64_t* params;
+  int32_t n, pad;
 };

@@ -382,3 +382,40 @@ def test_adhoc_measurement(eng, case):
     with pytest.raises(sf.SFrameError) as ei:
         st.measure(circ.n)
     assert ei.value.status == sf.SF_E_INVALID
+
+
+def test_graph_replays_match_eager(eng):
+    """A recorded batched run, replayed with new basis states and seeds, gives
+    each frame the result of an eager run alone with the same inputs (bit for
+    bit), replay after replay, with eager work between the replays."""
+    import paper_1712_03554_amd as sf
+    circs = [wl.config1(j) for j in range(3)] + [wl.config3(t) for t in range(3)] + \
+            [_mixed_circuit(s, 4 + s) for s in range(3)] + [wl.config4(1), wl.qft(5, [0] * 5, max_k=6)]
+    loaded = [eng.load(c.n, c) for c in circs]
+    states = [l.state(c.init_bits, 0) for l, c in zip(loaded, circs)]
+    g = eng.batch_graph(states, [c.init_bits for c in circs], [5] * len(circs))
+    assert eng._L.sf_state_destroy(states[0]._h) == sf.SF_E_STATE
+    rng = np.random.default_rng(4242)
+    for rep in range(3):
+        print(f"case graph replay {rep}", flush=True)
+        bases = [c.init_bits if rep == 0 else rng.integers(0, 2, size=c.n).tolist() for c in circs]
+        seeds = [int(rng.integers(0, 1 << 62)) for _ in circs]
+        for i in range(len(circs)):
+            g.set_input(i, bases[i], seeds[i])
+        g.launch()
+        for i, (c, st) in enumerate(zip(circs, states)):
+            alone = loaded[i].state(bases[i], seeds[i])
+            alone.run()
+            ta, sa, aa = alone.read_frame()
+            tb, sb, ab = st.read_frame()
+            assert np.array_equal(ta, tb) and np.array_equal(sa, sb), (rep, c.name)
+            assert np.array_equal(aa.view(np.uint64), ab.view(np.uint64)), (rep, c.name)
+            assert alone.outcomes() == st.outcomes(), (rep, c.name)
+            alone.close()
+        ref = OracleFrame(circs[0].n, bases[0], seeds[0])
+        ref.run(circs[0].array())
+        _compare(states[0], ref, f"graph replay {rep}")
+        assert states[0].outcomes() == ref.outcomes()
+    g.close()
+    for st in states:
+        st.close()
