@@ -98,6 +98,15 @@ def batched_extra(eng, wl, name, circs, seeds, plain_sample):
         eng.batch_run(states)
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / reps
+    g = eng.batch_graph(states, [c.init_bits for c in circs], seeds)
+    g.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.launch()
+    torch.cuda.synchronize()
+    tg = (time.perf_counter() - t0) / reps
+    g.close()
     sub = range(min(plain_sample, len(states)))
     reset(sub)
     for i in sub:
@@ -112,6 +121,7 @@ def batched_extra(eng, wl, name, circs, seeds, plain_sample):
     for st in states:
         st.close()
     return {"workload": name, "frames": len(states), "U_per_step": int(sum(Us)),
+            "graph_value": sum(Us) / tg, "graph_ms_per_step": tg * 1e3,
             "batched_value": sum(Us) / tb, "batched_ms_per_step": tb * 1e3,
             "plain_value": sum(Us[i] for i in sub) / tp, "plain_sample_frames": len(sub)}
 
@@ -198,7 +208,7 @@ def main():
     ap.add_argument("--jobs", type=int, default=3)
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg2L"])
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--path", default="batched", choices=["batched", "plain"])
+    ap.add_argument("--path", default="batched", choices=["graph", "batched", "plain"])
     ap.add_argument("--serve-jobs", type=int, default=48, help="0 skips the serving run")
     ap.add_argument("--no-extra", action="store_true", help="skip the many-frame batched workloads")
     ap.add_argument("--tick-segments", type=int, default=8)
@@ -242,17 +252,28 @@ def main():
             st.reset(c.init_bits, s)
         eng.batch_run(states)
 
-    # plain form (one frame at a time), timed for the record
-    for _ in range(args.warmup):
-        plain_step()
-    torch.cuda.synchronize()
-    tp0 = time.perf_counter()
-    for _ in range(args.steps):
-        plain_step()
-    torch.cuda.synchronize()
-    plain_value = args.steps * U_total / (time.perf_counter() - tp0)
+    graph = None
 
-    one_step = batched_step if args.path == "batched" else plain_step
+    def graph_step():
+        graph.launch()
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return args.steps * U_total / (time.perf_counter() - t)
+
+    # the other forms, timed for the record
+    plain_value = timed(plain_step)
+    batched_value = timed(batched_step)
+    graph = eng.batch_graph(states, [c.init_bits for c in circs], seeds)
+    graph_value = timed(graph_step)
+
+    one_step = {"graph": graph_step, "batched": batched_step, "plain": plain_step}[args.path]
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
@@ -279,7 +300,7 @@ def main():
     seg_ms, seg_n = prof["segment"]
     seg_ach = (seg_bytes_per_step * args.steps / max(seg_n, 1)) / (seg_ms / 1e3 / max(seg_n, 1)) / 1e9 \
         if seg_n else 0.0
-    elem_roof = {"bound": "hbm", "kernel": "sf_seg_batch" if args.path == "batched" else "sf_seg_kernel",
+    elem_roof = {"bound": "hbm", "kernel": "sf_seg_kernel" if args.path == "plain" else "sf_seg_batch",
                  "achieved": seg_ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": seg_ach / PEAK_HBM_GBS,
                  "traffic": None,
                  "note": "32 B per slot (read + write of 16 B) over 2^d slots per segment launch"}
@@ -310,6 +331,8 @@ def main():
         "config": {"workload": wname, "circuits_per_step": args.jobs, "path": args.path,
                    "U_per_step": U_total, "frame_bound_log2": bounds},
         "plain_value": plain_value,
+        "batched_value": batched_value,
+        "graph_value": graph_value,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kinds.items()},
         "kernel_launches_per_step": {k: v[1] / args.steps for k, v in kinds.items()},
         "roofline": roof,
