@@ -162,6 +162,16 @@ sf_status sf_graph_set_input(sf_graph* g, size_t i, const uint64_t* basis_bits, 
 sf_status sf_graph_launch(sf_graph* g);
 /* Synchronises, frees the graph and releases its states. */
 sf_status sf_graph_destroy(sf_graph* g);
+/* Autotuner of the elementwise frame kernels (segment update and measurement
+ * filter; implementation choice, not from the paper): for every hull
+ * dimension d in [d_lo, d_hi] (0 <= d_lo <= d_hi <= 29) it times the segment
+ * kernel over 2^d slots at each candidate shape (64/128/256 threads per
+ * block x 1..32 slots per thread) and keeps the fastest for later launches of
+ * this context.  Results do not depend on the shape.  blocks, grids and ms
+ * (optional, d_hi - d_lo + 1 entries) receive the choice and its time per
+ * launch.  Allocates 16 * 2^d_hi bytes of scratch while it runs.
+ * Synchronises. */
+sf_status sf_autotune(sf_ctx* ctx, int d_lo, int d_hi, int* blocks, int* grids, float* ms);
 /* Wait for queued work; reports device-side failures of the queued steps. */
 sf_status sf_sync(sf_state* s);
 

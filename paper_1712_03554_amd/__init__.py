@@ -24,7 +24,7 @@ SF_OK, SF_E_INVALID, SF_E_OOM, SF_E_DEVICE, SF_E_TOO_LARGE, SF_E_STATE, SF_E_BUF
 STATUS_NAMES = ["SF_OK", "SF_E_INVALID", "SF_E_OOM", "SF_E_DEVICE", "SF_E_TOO_LARGE", "SF_E_STATE",
                 "SF_E_BUFSIZE", "SF_E_CANCELLED"]
 
-EXPORTS = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_measure", "sf_batch_graph",
+EXPORTS = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_measure", "sf_batch_graph", "sf_autotune",
            "sf_graph_set_input", "sf_graph_launch", "sf_graph_destroy", "sf_circuit_load", "sf_circuit_info",
            "sf_circuit_destroy", "sf_state_init", "sf_state_destroy", "sf_step", "sf_run", "sf_sync",
            "sf_outcomes", "sf_frame_size", "sf_read_frame", "sf_state_info", "sf_state_reset",
@@ -77,6 +77,7 @@ def load_library(path: str = LIB_PATH):
         "sf_graph_set_input": [vp, sz, vp, u64],
         "sf_graph_launch": [vp],
         "sf_graph_destroy": [vp],
+        "sf_autotune": [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp],
         "sf_sync": [vp],
         "sf_outcomes": [vp, vp, sz, P(sz)],
         "sf_frame_size": [vp, P(u64)],
@@ -184,6 +185,15 @@ class Engine:
     def batch_graph(self, states, bases=None, seeds=None) -> "Graph":
         """Record a whole batched run of these states (see sf_batch_graph)."""
         return Graph(self, states, bases, seeds)
+
+    def autotune(self, d_lo: int = 12, d_hi: int = 24) -> dict:
+        """Pick launch shapes of the elementwise frame kernels; {d: (block, grid, ms)}."""
+        k = d_hi - d_lo + 1
+        b = np.zeros(k, dtype=np.int32)
+        g = np.zeros(k, dtype=np.int32)
+        t = np.zeros(k, dtype=np.float32)
+        self._check(self._L.sf_autotune(self._h, d_lo, d_hi, _ptr(b), _ptr(g), _ptr(t)))
+        return {d_lo + i: (int(b[i]), int(g[i]), float(t[i])) for i in range(k)}
 
     def profile(self, enable: bool):
         self._check(self._L.sf_profile(self._h, 1 if enable else 0))

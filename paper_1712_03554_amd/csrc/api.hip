@@ -35,7 +35,24 @@ struct sf_ctx {
   size_t ev_used;
   double prof_ms[PK_N];
   uint64_t prof_n[PK_N];
+  // launch shape of the elementwise frame kernels (segment, measurement
+  // filter) per hull dimension d: threads per block and blocks (grid-stride)
+  int tune_block[SF_DMAX + 1], tune_grid[SF_DMAX + 1];
 };
+
+static int grid_for(int d) {
+  uint64_t blocks = ((1ull << d) + EB - 1) / EB;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  return (int)blocks;
+}
+
+static void elem_shape(const sf_ctx* ctx, int d, int* block, int* grid) {
+  if (d < 0) d = 0;
+  if (d > SF_DMAX) d = SF_DMAX;
+  *block = ctx->tune_block[d];
+  *grid = ctx->tune_grid[d];
+}
 
 static void prof_begin(sf_ctx* ctx, int kind) {
   if (!ctx->prof) return;
@@ -163,6 +180,7 @@ extern "C" sf_status sf_ctx_create(int device, void* hip_stream, const sf_alloca
   c->prof = 0;
   c->ev_used = 0;
   for (int k = 0; k < PK_N; ++k) { c->prof_ms[k] = 0; c->prof_n[k] = 0; }
+  for (int d = 0; d <= SF_DMAX; ++d) { c->tune_block[d] = EB; c->tune_grid[d] = grid_for(d); }
   *out = c;
   return SF_OK;
 }
@@ -394,13 +412,6 @@ static void state_free(sf_state* s) {
   for (DevBuf* b : all) dfree(ctx, b);
 }
 
-static int grid_for(int d) {
-  uint64_t blocks = ((1ull << d) + EB - 1) / EB;
-  if (blocks > 8192) blocks = 8192;
-  if (blocks < 1) blocks = 1;
-  return (int)blocks;
-}
-
 static sf_status queue_init(sf_state* s, const uint64_t* basis, uint64_t seed) {
   sf_ctx* ctx = s->ctx;
   uint64_t b[4] = {0, 0, 0, 0};
@@ -531,11 +542,12 @@ static sf_status run_gates(sf_state* s, const DGate* dgates, const DGate* hg, si
     else { open = true; meas_last = false; }
   }
   if (open) ++nseg;
-  const int grid = grid_for(c->dmax);
+  int eb, grid;
+  elem_shape(ctx, c->dmax, &eb, &grid);
   const SegProg* prog = (const SegProg*)s->prog.p;
   for (int k = 0; k < nseg; ++k) {
     prof_begin(ctx, PK_SEG);
-    hipLaunchKernelGGL(sf_seg_kernel, dim3(grid), dim3(EB), 0, ctx->stream, prog + k, (const GF2Q*)s->had.p,
+    hipLaunchKernelGGL(sf_seg_kernel, dim3(grid), dim3(eb), 0, ctx->stream, prog + k, (const GF2Q*)s->had.p,
                        (double2*)s->amp[s->cur].p);
     prof_end(ctx);
   }
@@ -551,7 +563,7 @@ static sf_status run_gates(sf_state* s, const DGate* dgates, const DGate* hg, si
                        (int*)s->flags.p);
     prof_end(ctx);
     prof_begin(ctx, PK_MFILTER);
-    hipLaunchKernelGGL(sf_meas_filter, dim3(grid), dim3(EB), 0, ctx->stream, sp, (const double2*)s->amp[s->cur].p,
+    hipLaunchKernelGGL(sf_meas_filter, dim3(grid), dim3(eb), 0, ctx->stream, sp, (const double2*)s->amp[s->cur].p,
                        (double2*)s->amp[s->cur ^ 1].p, (const uint8_t*)s->outcomes.p, (const double*)s->scale.p);
     prof_end(ctx);
     s->cur ^= 1;
@@ -869,7 +881,7 @@ static ElemDesc elem_desc(const sf_state* s, int cur, const SegProg* prog, const
 struct RoundPlan {
   std::vector<TrackJob> jobs;
   std::vector<ElemDesc> desc;
-  int na = 0, kmax = 0, gx = 1, gm = 1;
+  int na = 0, kmax = 0, gx = 1, bx = EB, gm = 1;
   bool anym = false;
 };
 
@@ -899,6 +911,7 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
   rp->kmax = 0;
   rp->gx = rp->gm = 1;
   rp->anym = false;
+  int dm = 0;
   for (int j = 0; j < na; ++j) {
     const int i = act[j];
     sf_state* s = states[i];
@@ -912,10 +925,11 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
     jb.had = (GF2Q*)s->had.p;
     jb.outcomes = (const uint8_t*)s->outcomes.p;
     rp->kmax = std::max(rp->kmax, NS[i]);
-    rp->gx = std::max(rp->gx, grid_for(s->c->dmax));
+    dm = std::max(dm, s->c->dmax);
     rp->gm = std::max(rp->gm, s->G);
     rp->anym |= ML[i] != 0;
   }
+  elem_shape(states[act[0]]->ctx, dm, &rp->bx, &rp->gx);
   const int kmax = rp->kmax;
   rp->desc.assign((size_t)(kmax + 1) * na, ElemDesc{});
   for (int k = 0; k <= kmax; ++k)
@@ -975,7 +989,7 @@ static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs
   prof_end(ctx);
   for (int k = 0; k < rp.kmax; ++k) {
     prof_begin(ctx, PK_SEG);
-    hipLaunchKernelGGL(sf_seg_batch, dim3(rp.gx, na), dim3(EB), 0, ctx->stream, dd + (size_t)k * na);
+    hipLaunchKernelGGL(sf_seg_batch, dim3(rp.gx, na), dim3(rp.bx), 0, ctx->stream, dd + (size_t)k * na);
     prof_end(ctx);
   }
   if (rp.anym) {
@@ -987,7 +1001,7 @@ static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs
     hipLaunchKernelGGL(sf_meas_final_batch, dim3(1, na), dim3(EB), 0, ctx->stream, dm);
     prof_end(ctx);
     prof_begin(ctx, PK_MFILTER);
-    hipLaunchKernelGGL(sf_meas_filter_batch, dim3(rp.gx, na), dim3(EB), 0, ctx->stream, dm);
+    hipLaunchKernelGGL(sf_meas_filter_batch, dim3(rp.gx, na), dim3(rp.bx), 0, ctx->stream, dm);
     prof_end(ctx);
   }
 }
@@ -1037,6 +1051,84 @@ extern "C" sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t n
     rc = check_track(states[i]);
     if (rc != SF_OK) return rc;
   }
+  return SF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: for each hull dimension d in [d_lo, d_hi], times the segment
+// kernel over 2^d slots at every candidate launch shape (threads per block x
+// slots per thread) and keeps the fastest for the elementwise frame kernels.
+// The kernels are elementwise, so every shape gives bit-identical results;
+// the measurement reductions keep their fixed shape.
+// ---------------------------------------------------------------------------
+extern "C" sf_status sf_autotune(sf_ctx* ctx, int d_lo, int d_hi, int* blocks, int* grids, float* ms) {
+  if (!ctx || d_lo < 0 || d_hi > SF_DMAX - 1 || d_lo > d_hi) return SF_E_INVALID;
+  DevBuf amp, sp, had;
+  sf_status rc;
+  if ((rc = dalloc(ctx, &amp, (size_t)16 << d_hi))) return rc;
+  if ((rc = dalloc(ctx, &sp, sizeof(SegProg))) || (rc = dalloc(ctx, &had, sizeof(GF2Q)))) {
+    dfree(ctx, &amp);
+    dfree(ctx, &sp);
+    return rc;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(sf_fill_unit, dim3(grid_for(d_hi)), dim3(EB), 0, ctx->stream, (double2*)amp.p,
+                       (uint64_t)1 << d_hi);
+    e = hipGetLastError();
+  }
+  static const int cand_block[] = {64, 128, 256};
+  static const int cand_items[] = {1, 2, 4, 8, 16, 32};
+  for (int d = d_lo; d <= d_hi && e == hipSuccess; ++d) {
+    // a phase-only segment program whose form touches every coordinate
+    SegProg h;
+    memset(&h, 0, sizeof h);
+    h.kind = SEG_NONE;
+    h.d = h.d_out = d;
+    h.j0 = h.m_j0 = h.meas_index = -1;
+    h.ph_re = 1.0;
+    h.E.L1 = d ? (uint32_t)((1ull << d) - 1) & 0x55555555u : 0u;
+    h.E.L2 = d ? (uint32_t)((1ull << d) - 1) & 0x33333333u : 0u;
+    e = hipMemcpyAsync(sp.p, &h, sizeof h, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    const uint64_t N = 1ull << d;
+    float best = 1e30f;
+    int bb = EB, bg = grid_for(d);
+    for (int b : cand_block)
+      for (int it : cand_items) {
+        if (e != hipSuccess) break;
+        uint64_t gq = (N + (uint64_t)b * it - 1) / ((uint64_t)b * it);
+        const int g = (int)std::max<uint64_t>(1, std::min<uint64_t>(gq, 65535));
+        const int reps = 5;
+        hipLaunchKernelGGL(sf_seg_kernel, dim3(g), dim3(b), 0, ctx->stream, (const SegProg*)sp.p,
+                           (const GF2Q*)had.p, (double2*)amp.p);
+        e = hipEventRecord(e0, ctx->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+          hipLaunchKernelGGL(sf_seg_kernel, dim3(g), dim3(b), 0, ctx->stream, (const SegProg*)sp.p,
+                             (const GF2Q*)had.p, (double2*)amp.p);
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        t /= reps;
+        if (e == hipSuccess && t < best) { best = t; bb = b; bg = g; }
+      }
+    if (e != hipSuccess) break;
+    ctx->tune_block[d] = bb;
+    ctx->tune_grid[d] = bg;
+    if (blocks) blocks[d - d_lo] = bb;
+    if (grids) grids[d - d_lo] = bg;
+    if (ms) ms[d - d_lo] = best;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  dfree(ctx, &amp);
+  dfree(ctx, &sp);
+  dfree(ctx, &had);
+  if (e != hipSuccess) return fail(ctx, SF_E_DEVICE, "autotune: %s", hipGetErrorString(e));
   return SF_OK;
 }
 
@@ -1172,7 +1264,7 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
     for (int k = 0; k < rp.kmax && e == hipSuccess; ++k) {
       const ElemDesc* dk = dd + (size_t)k * na;
       void* args[] = {(void*)&dk};
-      e = add_kernel_node(g->graph, &last, (const void*)sf_seg_batch, dim3(rp.gx, na), dim3(EB), args);
+      e = add_kernel_node(g->graph, &last, (const void*)sf_seg_batch, dim3(rp.gx, na), dim3(rp.bx), args);
     }
     if (rp.anym && e == hipSuccess) {
       const ElemDesc* dm = dd + (size_t)rp.kmax * na;
@@ -1181,7 +1273,7 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
       if (e == hipSuccess)
         e = add_kernel_node(g->graph, &last, (const void*)sf_meas_final_batch, dim3(1, na), dim3(EB), args);
       if (e == hipSuccess)
-        e = add_kernel_node(g->graph, &last, (const void*)sf_meas_filter_batch, dim3(rp.gx, na), dim3(EB), args);
+        e = add_kernel_node(g->graph, &last, (const void*)sf_meas_filter_batch, dim3(rp.gx, na), dim3(rp.bx), args);
     }
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);

@@ -452,3 +452,8 @@ extern "C" __global__ void __launch_bounds__(EB) sf_init_batch(const InitDesc* _
   const uint64_t* b = e.params;
   init_body(e.st, e.n, b[0], b[1], b[2], b[3], e.amp, e.flags);
 }
+
+// Unit amplitudes over N slots (scratch input of the autotuner).
+extern "C" __global__ void __launch_bounds__(EB) sf_fill_unit(double2* __restrict__ amp, uint64_t N) {
+  for (uint64_t i = TID; i < N; i += STRIDE) amp[i] = make_double2(1.0, 0.0);
+}

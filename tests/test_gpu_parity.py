@@ -419,3 +419,24 @@ def test_graph_replays_match_eager(eng):
     g.close()
     for st in states:
         st.close()
+
+
+def test_autotune_keeps_results(eng):
+    """Launch shapes picked by the autotuner change no result bit."""
+    circs = [wl.config1(2), _mixed_circuit(60, 8), wl.config2(0, n_t=10), wl.qft(9, [1, 0] * 4 + [1], max_k=6)]
+    before = [_run_alone(eng, c, 31) for c in circs]
+    choice = eng.autotune(0, 14)
+    assert set(choice) == set(range(15))
+    for d, (b, g, ms) in choice.items():
+        assert b in (64, 128, 256) and 1 <= g <= 65535 and ms > 0
+    after = [_run_alone(eng, c, 31) for c in circs]
+    for c, ((ta, sa, aa), oa), ((tb, sb, ab), ob) in zip(circs, before, after):
+        assert np.array_equal(ta, tb) and np.array_equal(sa, sb), c.name
+        assert np.array_equal(aa.view(np.uint64), ab.view(np.uint64)), c.name
+        assert oa == ob, c.name
+    loaded = [eng.load(c.n, c) for c in circs]
+    states = [l.state(c.init_bits, 31) for l, c in zip(loaded, circs)]
+    eng.batch_run(states)
+    for c, st, ((ta, sa, aa), oa) in zip(circs, states, before):
+        tb, sb, ab = st.read_frame()
+        assert np.array_equal(sa, sb) and np.array_equal(aa.view(np.uint64), ab.view(np.uint64)), c.name
