@@ -211,6 +211,8 @@ def main():
     ap.add_argument("--path", default="batched", choices=["graph", "batched", "plain"])
     ap.add_argument("--serve-jobs", type=int, default=48, help="0 skips the serving run")
     ap.add_argument("--no-extra", action="store_true", help="skip the many-frame batched workloads")
+    ap.add_argument("--tune-lo", type=int, default=8)
+    ap.add_argument("--tune-hi", type=int, default=24, help="below --tune-lo: no autotuning")
     ap.add_argument("--tick-segments", type=int, default=8)
     ap.add_argument("--max-resident", type=int, default=32)
     ap.add_argument("--serve-budget-gib", type=float, default=128.0)
@@ -224,6 +226,7 @@ def main():
     from paper_1712_03554_amd import workloads as wl
 
     eng = sf.Engine(0)
+    tuned = eng.autotune(args.tune_lo, args.tune_hi) if args.tune_hi >= args.tune_lo else {}
     if args.workload == "cfg2":
         circs = [wl.config2(j) for j in range(args.jobs)]
         seeds = [wl.derive_seed(2, j) for j in range(args.jobs)]
@@ -338,6 +341,7 @@ def main():
         "roofline": roof,
         "element_roofline": elem_roof,
         "track_cycles_last_step": cyc,
+        "autotune": {str(d): {"block": b, "grid": g, "ms": round(t, 4)} for d, (b, g, t) in tuned.items()},
     }
     if not args.no_extra:
         c3 = [wl.config3(t) for t in range(4096)]
