@@ -265,11 +265,12 @@ class State:
         self._check(self._L.sf_state_reset(self._h, _ptr(words), ctypes.c_uint64(seed & ((1 << 64) - 1))))
 
     TRACK_PHASES = ["save", "columns", "repair", "index", "sampling", "fit", "cofactor", "total",
-                    "repair_check", "repair_rowmul", "repair_replay", "spare"]
+                    "repair_check", "repair_rowmul", "repair_replay", "repair_passes",
+                    "index_pivots", "index_beta", "index_images", "sampling_points"]
 
     def track_cycles(self) -> dict:
-        c = np.zeros(12, dtype=np.uint64)
-        self._check(self._L.sf_state_cycles(self._h, _ptr(c), 12))
+        c = np.zeros(16, dtype=np.uint64)
+        self._check(self._L.sf_state_cycles(self._h, _ptr(c), 16))
         return {k: int(c[i]) for i, k in enumerate(self.TRACK_PHASES)}
 
     def dim(self) -> int:

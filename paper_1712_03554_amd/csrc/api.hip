@@ -437,11 +437,11 @@ extern "C" sf_status sf_state_reset(sf_state* s, const uint64_t* basis, uint64_t
 extern "C" sf_status sf_state_cycles(sf_state* s, uint64_t* cycles, int n) {
   if (!s || !cycles) return SF_E_INVALID;
   sf_ctx* ctx = s->ctx;
-  uint64_t c[12];
+  uint64_t c[16];
   HIPCHK(ctx, hipMemcpyAsync(c, (char*)s->st.p + offsetof(TrackState, cycles), sizeof c, hipMemcpyDeviceToHost,
                              ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  for (int k = 0; k < n && k < 12; ++k) cycles[k] = c[k];
+  for (int k = 0; k < n && k < 16; ++k) cycles[k] = c[k];
   return SF_OK;
 }
 

@@ -428,7 +428,7 @@ __device__ void init_body(TrackState* __restrict__ st, int n, uint64_t b0, uint6
     st->n = n; st->W = W; st->d = 0; st->nmeas = 0;
     st->pend = 0; st->pend_j0 = -1; st->pend_c0 = 0; st->pend_meas = -1; st->pend_r = 0;
     st->dmax = 0; st->error = 0; st->pad = 0;
-    for (int k = 0; k < 12; ++k) st->cycles[k] = 0;
+    for (int k = 0; k < 16; ++k) st->cycles[k] = 0;
     uint64_t b[4] = {b0, b1, b2, b3};
     for (int w = 0; w < SF_WMAX; ++w) {
       uint64_t m = w < W ? ~0ull : 0ull;

@@ -75,7 +75,7 @@ struct TrackState {
   uint64_t rz[SF_NMAX * SF_WMAX];
   uint64_t s0[SF_WMAX];
   uint64_t V[SF_DMAX][SF_WMAX];
-  uint64_t cycles[12];     // shader clocks spent per phase of the track (profiling)
+  uint64_t cycles[16];     // shader clocks spent per phase of the track (profiling)
 };
 
 // One circuit range for the tableau-track kernel.

@@ -38,15 +38,17 @@ struct Lds {
   int16_t lead[SF_NMAX], xpiv[SF_NMAX], zpiv[SF_NMAX], oxpiv[SF_NMAX];
   uint8_t ow[SF_NMAX];
   uint32_t ech[SF_DMAX];          // scratch for span tests
-  int misc[8];
-  uint64_t tc[12];                // per-phase shader clocks
+  uint32_t lst[2 * SF_NMAX];      // lead stamps of the elimination passes
+  int misc[8];                    // [0] X-block size, [1] last lead stamp
+  uint64_t tc[16];                // per-phase shader clocks
 };
 
 typedef Lds TrackLdsProbe;
 
 // phases: 0 save, 1 column update, 2 repair, 3 index+b* images, 4 sampling,
 // 5 fitting, 6 cofactor, 7 total, 8 repair checks, 9 repair row products,
-// 10 repair replay on the hull
+// 10 repair replay on the hull, 11 elimination passes (a count), 12 pivot
+// index, 13 b* basis, 14 hull images, 15 sample points evaluated (a count)
 // (compiled in with -DSF_TRACK_TIMERS; each reading waits for outstanding LDS
 // traffic, so the counters are off in normal builds)
 #ifdef SF_TRACK_TIMERS
@@ -173,6 +175,59 @@ __device__ void apply_pending(Lds& L, const TrackState* st, const uint8_t* outco
 
 template <int W>
 struct Trk {
+// The tableau as the Clifford loop keeps it: lane l holds row slots and
+// columns 64k + l (k < W); rows x/z (W words each), the column-major copy
+// cx/cz (slot masks of rows with an x / z bit at that qubit) and each row's
+// lead column.  LDS holds write-only snapshots of it for random access.
+struct Regs {
+  uint64_t x[W][W], z[W][W], cx[W][W], cz[W][W];
+  int ld[W];
+};
+
+static __device__ __forceinline__ uint64_t pick(const uint64_t (&v)[W], int w) {
+  uint64_t r = 0;
+  for (int t = 0; t < W; ++t) if (t == w) r = v[t];
+  return r;
+}
+
+static __device__ __forceinline__ uint64_t bcast64(uint64_t v, int l) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+}
+
+static __device__ __forceinline__ void regs_load(const Lds& L, Regs& R, int n) {
+  const int lane = lane_id();
+  for (int k = 0; k < W; ++k) {
+    const int i = 64 * k + lane;
+    const bool ok = i < n;
+    for (int w = 0; w < W; ++w) {
+      R.x[k][w] = ok ? L.rx[i * SF_WMAX + w] : 0ull;
+      R.z[k][w] = ok ? L.rz[i * SF_WMAX + w] : 0ull;
+      R.cx[k][w] = ok ? L.cx[i * SF_WMAX + w] : 0ull;
+      R.cz[k][w] = ok ? L.cz[i * SF_WMAX + w] : 0ull;
+    }
+    R.ld[k] = ok ? (int)L.lead[i] : -1;
+  }
+}
+
+// rows, leads and (cols) the column-major copy into LDS; no barrier
+static __device__ __forceinline__ void regs_store(Lds& L, const Regs& R, int n, bool cols) {
+  const int lane = lane_id();
+  for (int k = 0; k < W; ++k) {
+    const int i = 64 * k + lane;
+    if (i >= n) continue;
+    for (int w = 0; w < W; ++w) {
+      L.rx[i * SF_WMAX + w] = R.x[k][w];
+      L.rz[i * SF_WMAX + w] = R.z[k][w];
+      if (cols) {
+        L.cx[i * SF_WMAX + w] = R.cx[k][w];
+        L.cz[i * SF_WMAX + w] = R.cz[k][w];
+      }
+    }
+    L.lead[i] = (int16_t)R.ld[k];
+  }
+}
+
 static __device__ int row_lead(const uint64_t* x, const uint64_t* z, int n) {
   for (int w = 0; w < W; ++w) if (x[w]) return 64 * w + __builtin_ctzll(x[w]);
   for (int w = 0; w < W; ++w) if (z[w]) return n + 64 * w + __builtin_ctzll(z[w]);
@@ -290,28 +345,25 @@ static __device__ void cols_rowsum(Lds& L, int m, int n) {
 // row slots and columns 64k + l (k < W) and hull vector l (V[l], then s0 at
 // lane d, u at lane d + 1).  The pivot row travels by readlane, the row masks
 // of each step by ballot; LDS is read on entry and written on exit only.
-static __device__ void repair(Lds& L, int n, int d, bool with_u, int full) {
+static __device__ __forceinline__ void repair_core(Lds& L, Regs& R, int n, int d, bool with_u, int full) {
   const int lane = lane_id();
-  uint64_t x[W][W], z[W][W], cxr[W][W], czr[W][W];
-  int ld[W];
+  uint64_t (&x)[W][W] = R.x;
+  uint64_t (&z)[W][W] = R.z;
+  uint64_t (&cxr)[W][W] = R.cx;
+  uint64_t (&czr)[W][W] = R.cz;
+  int (&ld)[W] = R.ld;
   bool valid[W];
-  for (int k = 0; k < W; ++k) {
-    const int i = 64 * k + lane;
-    valid[k] = i < n;
-    for (int w = 0; w < W; ++w) {
-      x[k][w] = valid[k] ? L.rx[i * SF_WMAX + w] : 0ull;
-      z[k][w] = valid[k] ? L.rz[i * SF_WMAX + w] : 0ull;
-      cxr[k][w] = valid[k] ? L.cx[i * SF_WMAX + w] : 0ull;
-      czr[k][w] = valid[k] ? L.cz[i * SF_WMAX + w] : 0ull;
-    }
-    ld[k] = valid[k] ? (int)L.lead[i] : -1;
-  }
+  for (int k = 0; k < W; ++k) valid[k] = 64 * k + lane < n;
   const bool has_vec = lane < d || lane == d || (lane == d + 1 && with_u);
   const bool affine = lane == d;
   uint64_t hv[W];
   for (int w = 0; w < W; ++w)
     hv[w] = lane < d ? L.V[lane][w] : lane == d ? L.s0[w] : (lane == d + 1 && with_u) ? L.u[w] : 0ull;
+  uint32_t gen = (uint32_t)L.misc[1];
   for (int guard = 0; guard < 4 * SF_NMAX + 8; ++guard) {
+#ifdef SF_TRACK_TIMERS
+    if (lane == 0) L.tc[11] += 1;  // elimination passes
+#endif
     TIC(8);
     // Z-block rows (no x bits)
     uint64_t zs[W];
@@ -321,36 +373,28 @@ static __device__ void repair(Lds& L, int n, int d, bool with_u, int full) {
       const uint64_t b = __ballot(valid[k] && xa == 0ull);
       zs[k] = full ? ~0ull : b;
     }
-    // bit counts of my columns (z columns: Z-block rows only unless full)
-    int cntx[W], cntz[W];
+    // every row stamps its lead column; a column breaks the form if it holds
+    // this pass's stamp and at least two bits (z columns: Z-block rows only
+    // unless full).  The smallest such column, x columns before z columns.
+    ++gen;
+    for (int k = 0; k < W; ++k)
+      if (valid[k] && ld[k] >= 0) L.lst[ld[k]] = gen;
+    __syncthreads();
+    uint64_t px[W], pz[W];
     for (int k = 0; k < W; ++k) {
+      const int q = 64 * k + lane;
       int a = 0, b = 0;
       for (int w = 0; w < W; ++w) { a += __popcll(cxr[k][w]); b += __popcll(czr[k][w] & zs[w]); }
-      cntx[k] = a;
-      cntz[k] = b;
+      const bool ok = q < n;
+      px[k] = __ballot(ok && a >= 2 && L.lst[q] == gen);
+      pz[k] = __ballot(ok && b >= 2 && L.lst[n + q] == gen);
     }
-    // smallest lead column shared by two rows
-    int best = 0x7fffffff;
-    for (int k = 0; k < W; ++k) {
-      const int c = ld[k];
-      const bool isx = c >= 0 && c < n;
-      const int cc = c < 0 ? 0 : (isx ? c : c - n);
-      int cnt = 0;
-      for (int kk = 0; kk < W; ++kk) {
-        const int vx = __shfl(cntx[kk], cc & 63);
-        const int vz = __shfl(cntz[kk], cc & 63);
-        if ((cc >> 6) == kk) cnt = isx ? vx : vz;
-      }
-      if (c >= 0 && cnt >= 2 && c < best) best = c;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      const int t = __shfl_xor(best, o);
-      best = t < best ? t : best;
-    }
+    int col = -1;
+    for (int k = 0; k < W; ++k) if (col < 0 && px[k]) col = 64 * k + __builtin_ctzll(px[k]);
+    for (int k = 0; k < W; ++k) if (col < 0 && pz[k]) col = n + 64 * k + __builtin_ctzll(pz[k]);
     TOC(8);
-    if (best == 0x7fffffff) break;
+    if (col < 0) break;
     TIC(9);
-    const int col = __builtin_amdgcn_readfirstlane(best);
     // pivot: the first slot leading at col
     int m = -1;
     for (int k = 0; k < W && m < 0; ++k) {
@@ -368,6 +412,8 @@ static __device__ void repair(Lds& L, int n, int d, bool with_u, int full) {
       zm[w] = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sz >> 32), lm) << 32) |
               (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sz, lm);
     }
+    int wm = 0;
+    for (int w = 0; w < W; ++w) wm += __popcll(xm[w] & zm[w]);
     const bool xcol = col < n;
     const int cb = xcol ? col : col - n;
     uint64_t rm[W], cm[W];
@@ -381,8 +427,17 @@ static __device__ void repair(Lds& L, int n, int d, bool with_u, int full) {
       const bool hit = valid[k] && i != m && (xcol || full || xa == 0ull) && ((wsel >> (cb & 63)) & 1ull);
       int c = 0;
       if (hit) {
-        c = rowprod_sign(x[k], z[k], xm, zm);
-        for (int w = 0; w < W; ++w) { x[k][w] ^= xm[w]; z[k][w] ^= zm[w]; }
+        // P(x1,z1) P(x2,z2) = i^e P(x1^x2, z1^z2) with
+        // e = |x1 z1| + |x2 z2| + 2 |z1 x2| - |(x1^x2)(z1^z2)|  (Y = iXZ);
+        // for commuting rows e is even and the sign is (-1)^(e/2)
+        int e = wm;
+        for (int w = 0; w < W; ++w) {
+          const uint64_t nx = x[k][w] ^ xm[w], nz = z[k][w] ^ zm[w];
+          e += __popcll(x[k][w] & z[k][w]) + 2 * __popcll(z[k][w] & xm[w]) - __popcll(nx & nz);
+          x[k][w] = nx;
+          z[k][w] = nz;
+        }
+        c = (e & 3) >> 1;
         ld[k] = row_lead(x[k], z[k], n);
       }
       rm[k] = __ballot(hit);
@@ -408,20 +463,20 @@ static __device__ void repair(Lds& L, int n, int d, bool with_u, int full) {
     }
     TOC(10);
   }
-  for (int k = 0; k < W; ++k) {
-    const int i = 64 * k + lane;
-    if (!valid[k]) continue;
-    for (int w = 0; w < W; ++w) {
-      L.rx[i * SF_WMAX + w] = x[k][w];
-      L.rz[i * SF_WMAX + w] = z[k][w];
-      L.cx[i * SF_WMAX + w] = cxr[k][w];
-      L.cz[i * SF_WMAX + w] = czr[k][w];
-    }
-    L.lead[i] = (int16_t)ld[k];
-  }
   if (lane < d) for (int w = 0; w < W; ++w) L.V[lane][w] = hv[w];
   else if (lane == d) for (int w = 0; w < W; ++w) L.s0[w] = hv[w];
   else if (lane == d + 1 && with_u) for (int w = 0; w < W; ++w) L.u[w] = hv[w];
+  __syncthreads();
+  if (lane == 0) L.misc[1] = (int)gen;
+  __syncthreads();
+}
+
+// The same on the LDS copy of the tableau (terminal steps and readout).
+static __device__ void repair(Lds& L, int n, int d, bool with_u, int full) {
+  Regs R;
+  regs_load(L, R, n);
+  repair_core(L, R, n, d, with_u, full);
+  regs_store(L, R, n, true);
   __syncthreads();
 }
 
@@ -449,6 +504,28 @@ static __device__ void build_beta(Lds& L, int n) {
   __syncthreads();
 }
 
+// The same from the register tableau (rows already in LDS, xpiv current).
+static __device__ __forceinline__ void build_beta_regs(Lds& L, const Regs& R, int n) {
+  const int lane = lane_id();
+  for (int k = 0; k < W; ++k) {
+    const int h = 64 * k + lane;
+    const int ld = R.ld[k];
+    if (h >= n) continue;
+    uint64_t b[W];
+    for (int w = 0; w < W; ++w) b[w] = 0;
+    if (ld >= n) {
+      const int q = ld - n;
+      const int l = L.xpiv[q];
+      for (int w = 0; w < W; ++w) {
+        if (w == (q >> 6)) b[w] = 1ull << (q & 63);
+        if (l >= 0) b[w] ^= L.rx[l * SF_WMAX + w];
+      }
+    }
+    for (int w = 0; w < W; ++w) L.beta[h * SF_WMAX + w] = b[w];
+  }
+  __syncthreads();
+}
+
 static __device__ void bimage(const Lds& L, const uint64_t* vec, uint64_t* out) {
   uint64_t acc[SF_WMAX] = {0, 0, 0, 0};
   for (int w = 0; w < W; ++w) {
@@ -472,7 +549,8 @@ static __device__ void hull_images(Lds& L, uint64_t (*hb)[SF_WMAX], int d, bool 
 }
 
 // exponent e with psi(M_old, sigma)(b) = 2^{-k/2} i^e, or -1 if b is outside
-// the support.  psi ~ prod_l (I + g_l)/2 |b*>: the amplitude at b* ^ x_S is the
+// the support.  The old X-block rows are stored by pivot column (ox/oz/ow at
+// q hold the row whose x-lead is q; oxpiv[q] is its slot, for its sign).  psi ~ prod_l (I + g_l)/2 |b*>: the amplitude at b* ^ x_S is the
 // phase of applying the X-block generators in S to |b*>.
 static __device__ int uexp(const Lds& L, const uint64_t* sig, const uint64_t* bO, const uint64_t* b) {
   uint64_t v[SF_WMAX];
@@ -483,11 +561,11 @@ static __device__ int uexp(const Lds& L, const uint64_t* sig, const uint64_t* bO
     while (D) {
       int q = 64 * w + __builtin_ctzll(D);
       D &= D - 1;
-      int l = L.oxpiv[q];
+      const int l = L.oxpiv[q];
       uint64_t zv = 0;
-      for (int t = 0; t < W; ++t) zv ^= L.oz[l * SF_WMAX + t] & v[t];
-      e += 2 * (getb(sig, l) ^ par64(zv)) + L.ow[l];
-      for (int t = 0; t < W; ++t) v[t] ^= L.ox[l * SF_WMAX + t];
+      for (int t = 0; t < W; ++t) zv ^= L.oz[q * SF_WMAX + t] & v[t];
+      e += 2 * (getb(sig, l) ^ par64(zv)) + L.ow[q];
+      for (int t = 0; t < W; ++t) v[t] ^= L.ox[q * SF_WMAX + t];
     }
   }
   for (int w = 0; w < W; ++w) if (v[w] != b[w]) return -1;
@@ -503,16 +581,17 @@ static __device__ int uexp(const Lds& L, const uint64_t* sig, const uint64_t* bO
 static __device__ void save_old(Lds& L, int n, int d) {
   const int lane = lane_id();
   for (int i = lane; i < n; i += TL) {
-    uint64_t wz = 0;
-    for (int w = 0; w < SF_WMAX; ++w) {
-      L.ox[i * SF_WMAX + w] = L.rx[i * SF_WMAX + w];
-      L.oz[i * SF_WMAX + w] = L.rz[i * SF_WMAX + w];
+    const int ld = L.lead[i];
+    if (ld >= 0 && ld < n) {
+      int c = 0;
+      for (int w = 0; w < W; ++w) {
+        L.ox[ld * SF_WMAX + w] = L.rx[i * SF_WMAX + w];
+        L.oz[ld * SF_WMAX + w] = L.rz[i * SF_WMAX + w];
+        c += __popcll(L.rx[i * SF_WMAX + w] & L.rz[i * SF_WMAX + w]);
+      }
+      L.ow[ld] = (uint8_t)(c & 3);
     }
-    int c = 0;
-    for (int w = 0; w < W; ++w) c += __popcll(L.rx[i * SF_WMAX + w] & L.rz[i * SF_WMAX + w]);
-    L.ow[i] = (uint8_t)(c & 3);
     L.oxpiv[i] = L.xpiv[i];
-    (void)wz;
   }
   for (int i = n + lane; i < SF_NMAX; i += TL) L.oxpiv[i] = -1;
   if (lane < d) for (int w = 0; w < SF_WMAX; ++w) L.oV[lane][w] = L.V[lane][w];
@@ -541,45 +620,144 @@ static __device__ __forceinline__ void point_vec(const uint64_t* base, const uin
 // ---------------------------------------------------------------------------
 // Clifford gate
 // ---------------------------------------------------------------------------
-static __device__ void clifford_gate(Lds& L, int op, int a, int b, int n, int d, int dry, GF2Q* had_out,
-                              int* nhad, int* err) {
+// Table 2 on the register tableau: conjugate every row by the gate, collect
+// the sign flips f (applied to every phase vector through s0 ^= f) and keep
+// the column-major copy in step.  No barrier.
+static __device__ __forceinline__ void conj_regs(Lds& L, Regs& R, int op, int a, int b, int n) {
   const int lane = lane_id();
-  const int R = (n + 63) / 64;
+  const int wa = a >> 6, ba = a & 63, wb = b >> 6, bb = b & 63;
+  const bool two = op == DG_CNOT || op == DG_CZ;
+  uint64_t fm[W];
+  for (int k = 0; k < W; ++k) {
+    const int xa = (int)((pick(R.x[k], wa) >> ba) & 1ull), za = (int)((pick(R.z[k], wa) >> ba) & 1ull);
+    const int xb = two ? (int)((pick(R.x[k], wb) >> bb) & 1ull) : 0;
+    const int zb = two ? (int)((pick(R.z[k], wb) >> bb) & 1ull) : 0;
+    int fl = 0, fxa = 0, fza = 0, fxb = 0, fzb = 0;
+    switch (op) {
+      case DG_H: fl = xa & za; fxa = fza = xa ^ za; break;
+      case DG_S: fl = xa & za; fza = xa; break;
+      case DG_SDG: fl = xa & (za ^ 1); fza = xa; break;
+      case DG_X: fl = za; break;
+      case DG_Z: fl = xa; break;
+      case DG_Y: fl = xa ^ za; break;
+      case DG_CNOT: fl = xa & zb & (xb ^ za ^ 1); fxb = xa; fza = zb; break;
+      case DG_CZ: fl = xa & xb & (za ^ zb); fza = xb; fzb = xa; break;
+    }
+    for (int w = 0; w < W; ++w) {
+      R.x[k][w] ^= ((w == wa ? (uint64_t)fxa << ba : 0ull) | (w == wb ? (uint64_t)fxb << bb : 0ull));
+      R.z[k][w] ^= ((w == wa ? (uint64_t)fza << ba : 0ull) ^ (w == wb ? (uint64_t)fzb << bb : 0ull));
+    }
+    if (fxa | fza | fxb | fzb) R.ld[k] = row_lead(R.x[k], R.z[k], n);
+    fm[k] = __ballot(fl);
+  }
+  // column-major copy
+  if (op == DG_H) {
+    if (lane == ba)
+      for (int k = 0; k < W; ++k)
+        if (k == wa)
+          for (int w = 0; w < W; ++w) { const uint64_t t = R.cx[k][w]; R.cx[k][w] = R.cz[k][w]; R.cz[k][w] = t; }
+  } else if (op == DG_S || op == DG_SDG) {
+    if (lane == ba)
+      for (int k = 0; k < W; ++k)
+        if (k == wa)
+          for (int w = 0; w < W; ++w) R.cz[k][w] ^= R.cx[k][w];
+  } else if (op == DG_CNOT) {
+    // column b of x gets the rows with x at a; column a of z the rows with z at b
+    uint64_t cxa[W], czb[W];
+    for (int w = 0; w < W; ++w) {
+      uint64_t u = 0, v = 0;
+      for (int k = 0; k < W; ++k) { if (k == wa) u = R.cx[k][w]; if (k == wb) v = R.cz[k][w]; }
+      cxa[w] = bcast64(u, ba);
+      czb[w] = bcast64(v, bb);
+    }
+    for (int k = 0; k < W; ++k)
+      for (int w = 0; w < W; ++w) {
+        if (k == wb && lane == bb) R.cx[k][w] ^= cxa[w];
+        if (k == wa && lane == ba) R.cz[k][w] ^= czb[w];
+      }
+  } else if (op == DG_CZ) {
+    uint64_t cxa[W], cxb[W];
+    for (int w = 0; w < W; ++w) {
+      uint64_t u = 0, v = 0;
+      for (int k = 0; k < W; ++k) { if (k == wa) u = R.cx[k][w]; if (k == wb) v = R.cx[k][w]; }
+      cxa[w] = bcast64(u, ba);
+      cxb[w] = bcast64(v, bb);
+    }
+    for (int k = 0; k < W; ++k)
+      for (int w = 0; w < W; ++w) {
+        if (k == wa && lane == ba) R.cz[k][w] ^= cxb[w];
+        if (k == wb && lane == bb) R.cz[k][w] ^= cxa[w];
+      }
+  }
+  if (lane == 0)
+    for (int w = 0; w < W; ++w) L.s0[w] ^= fm[w];
+}
+
+// Pivot index from the register tableau (xpiv / zpiv / zsm / X-block size)
+// and the LDS snapshot of the rows and leads.  Ends with a barrier.
+static __device__ __forceinline__ void index_regs(Lds& L, const Regs& R, int n) {
+  const int lane = lane_id();
+  for (int i = lane; i < SF_NMAX; i += TL) { L.xpiv[i] = -1; L.zpiv[i] = -1; }
+  regs_store(L, R, n, false);
+  __syncthreads();
+  int kx = 0;
+  for (int k = 0; k < W; ++k) {
+    const int i = 64 * k + lane;
+    const int c = R.ld[k];
+    const bool ok = i < n;
+    if (ok && c >= 0 && c < n) L.xpiv[c] = (int16_t)i;
+    else if (ok && c >= n) L.zpiv[c - n] = (int16_t)i;
+    const uint64_t bx = __ballot(ok && c >= 0 && c < n), bz = __ballot(ok && c >= n);
+    kx += __popcll(bx);
+    if (lane == 0) L.zsm[k] = bz;
+  }
+  if (lane == 0) {
+    for (int k = W; k < SF_WMAX; ++k) L.zsm[k] = 0;
+    L.misc[0] = kx;
+  }
+  __syncthreads();
+}
+
+// Pre-gate snapshot for the phase evaluation: rows, their Y counts, the
+// x-pivot index and mask, the hull and its b* images.
+static __device__ __forceinline__ void save_old_regs(Lds& L, const Regs& R, int n, int d) {
+  const int lane = lane_id();
+  for (int k = 0; k < W; ++k) {
+    const int i = 64 * k + lane;
+    const int ld = R.ld[k];
+    if (i >= n || ld < 0 || ld >= n) continue;
+    int c = 0;
+    for (int w = 0; w < W; ++w) {
+      L.ox[ld * SF_WMAX + w] = R.x[k][w];
+      L.oz[ld * SF_WMAX + w] = R.z[k][w];
+      c += __popcll(R.x[k][w] & R.z[k][w]);
+    }
+    L.ow[ld] = (uint8_t)(c & 3);
+  }
+  for (int i = lane; i < SF_NMAX; i += TL) L.oxpiv[i] = i < n ? L.xpiv[i] : (int16_t)-1;
+  if (lane < d) for (int w = 0; w < SF_WMAX; ++w) L.oV[lane][w] = L.V[lane][w];
+  if (lane == d) for (int w = 0; w < SF_WMAX; ++w) L.os0[w] = L.s0[w];
+  if (lane <= d + 1) for (int w = 0; w < SF_WMAX; ++w) L.hbO[lane][w] = L.hbN[lane][w];
+  for (int it = 0; it < SF_WMAX; ++it) {
+    const int q = it * 64 + lane;
+    const uint64_t m = __ballot(q < n && L.xpiv[q] >= 0);
+    if (lane == 0) L.oxpm[it] = m;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Clifford gate on the register tableau
+// ---------------------------------------------------------------------------
+static __device__ __forceinline__ void clifford_gate(Lds& L, Regs& R, int op, int a, int b, int n, int d, int dry, GF2Q* had_out,
+                                     int* nhad, int* err) {
+  const int lane = lane_id();
   if (op == DG_S || op == DG_SDG || op == DG_Z || op == DG_CZ) {
     // Diagonal gates change only z bits of X-block rows and flip only X-block
     // signs: the echelon form, the support and b*(sigma) stay as they are, and
     // U|b*> = mu(b*) |b*>, so omega(Y) = mu(b*(sigma(Y))).
     TIC(1);
-    if (lane == 0)
-      for (int w = 0; w < SF_WMAX; ++w) L.fmask[w] = 0;
-    __syncthreads();
-    for (int it = 0; it < R; ++it) {
-      int i = it * 64 + lane;
-      if (i >= n) continue;
-      uint64_t* x = &L.rx[i * SF_WMAX];
-      uint64_t* z = &L.rz[i * SF_WMAX];
-      int xa = getb(x, a), za = getb(z, a), fl = 0;
-      if (op == DG_S) { fl = xa & za; if (xa) flipb(z, a); }
-      else if (op == DG_SDG) { fl = xa & (za ^ 1); if (xa) flipb(z, a); }
-      else if (op == DG_Z) fl = xa;
-      else {
-        int xb = getb(x, b), zb = getb(z, b);
-        fl = xa & xb & (za ^ zb);
-        if (xb) flipb(z, a);
-        if (xa) flipb(z, b);
-      }
-      if (fl) atomicOr((unsigned long long*)&L.fmask[i >> 6], 1ull << (i & 63));
-    }
-    if (lane < W) {
-      const int w = lane;
-      if (op == DG_S || op == DG_SDG) L.cz[a * SF_WMAX + w] ^= L.cx[a * SF_WMAX + w];
-      else if (op == DG_CZ) {
-        L.cz[a * SF_WMAX + w] ^= L.cx[b * SF_WMAX + w];
-        L.cz[b * SF_WMAX + w] ^= L.cx[a * SF_WMAX + w];
-      }
-    }
-    __syncthreads();
-    if (lane < SF_WMAX) L.s0[lane] ^= L.fmask[lane];
+    conj_regs(L, R, op, a, b, n);
     __syncthreads();
     TOC(1);
     if (dry) return;
@@ -602,72 +780,32 @@ static __device__ void clifford_gate(Lds& L, int op, int a, int b, int n, int d,
     return;
   }
   TIC(0);
-  if (!dry) save_old(L, n, d);
+  if (!dry) save_old_regs(L, R, n, d);
   TOC(0);
   const int kold = L.misc[0];
-  if (lane == 0)
-    for (int w = 0; w < SF_WMAX; ++w) L.fmask[w] = 0;
-  __syncthreads();
   TIC(1);
-  // column update (Table 2) and sign flips
-  for (int it = 0; it < R; ++it) {
-    int i = it * 64 + lane;
-    if (i >= n) continue;
-    uint64_t* x = &L.rx[i * SF_WMAX];
-    uint64_t* z = &L.rz[i * SF_WMAX];
-    int xa = getb(x, a), za = getb(z, a), fl = 0;
-    switch (op) {
-      case DG_H: fl = xa & za; if (xa != za) { flipb(x, a); flipb(z, a); } break;
-      case DG_S: fl = xa & za; if (xa) flipb(z, a); break;
-      case DG_SDG: fl = xa & (za ^ 1); if (xa) flipb(z, a); break;
-      case DG_X: fl = za; break;
-      case DG_Z: fl = xa; break;
-      case DG_Y: fl = xa ^ za; break;
-      case DG_CNOT: {
-        int xb = getb(x, b), zb = getb(z, b);
-        fl = xa & zb & (xb ^ za ^ 1);
-        if (xa) flipb(x, b);
-        if (zb) flipb(z, a);
-        break;
-      }
-      case DG_CZ: {
-        int xb = getb(x, b), zb = getb(z, b);
-        fl = xa & xb & (za ^ zb);
-        if (xb) flipb(z, a);
-        if (xa) flipb(z, b);
-        break;
-      }
-    }
-    if (fl) atomicOr((unsigned long long*)&L.fmask[i >> 6], 1ull << (i & 63));
-    L.lead[i] = (int16_t)row_lead(x, z, n);
-  }
-  // the same column operations on the column-major copy
-  if (lane < W) {
-    const int w = lane;
-    uint64_t* cxa = &L.cx[a * SF_WMAX];
-    uint64_t* cza = &L.cz[a * SF_WMAX];
-    if (op == DG_H) {
-      uint64_t t = cxa[w]; cxa[w] = cza[w]; cza[w] = t;
-    } else if (op == DG_CNOT) {
-      L.cx[b * SF_WMAX + w] ^= cxa[w];
-      cza[w] ^= L.cz[b * SF_WMAX + w];
-    }
-  }
-  __syncthreads();
-  // sign flips broadcast to every phase vector: s0 ^= f
-  if (lane < SF_WMAX) L.s0[lane] ^= L.fmask[lane];
+  conj_regs(L, R, op, a, b, n);
   __syncthreads();
   TOC(1);
   TIC(2);
-  repair(L, n, d, false, 0);
+  repair_core(L, R, n, d, false, 0);
   TOC(2);
   TIC(3);
-  rebuild_index(L, n);
+  TIC(12);
+  index_regs(L, R, n);
+  TOC(12);
   if (dry) { TOC(3); return; }
   const int knew = L.misc[0];
-  build_beta(L, n);
+  TIC(13);
+  build_beta_regs(L, R, n);
+  TOC(13);
+  TIC(14);
   hull_images(L, L.hbN, d, false);
+  TOC(14);
   TOC(3);
+#ifdef SF_TRACK_TIMERS
+  if (lane == 0) L.tc[15] += npoints(d);
+#endif
   // per-element phase factor omega(Y), sampled at the fitting points
   const int dk = knew - kold;
   const bool hsplit = op == DG_H && dk == 0;
@@ -807,7 +945,9 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
   const int n = st->n;
   int d = st->d;
   int err = 0;
-  if (lane_id() < 12) L.tc[lane_id()] = 0;
+  if (lane_id() < 16) L.tc[lane_id()] = 0;
+  for (int i = lane; i < 2 * SF_NMAX; i += TL) L.lst[i] = 0u;
+  if (lane == 0) L.misc[1] = 0;
   __syncthreads();
   TIC(7);
   // load state
@@ -829,6 +969,8 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
   }
   for (int p = lane; p < SF_PMAX; p += TL) L.acc[p] = 0;
   __syncthreads();
+  Regs TB;
+  regs_load(L, TB, n);
   int seg = 0, nhad = 0, had_base = 0, nmeas = st->nmeas, dmax = st->dmax;
   int pend = 0, pend_j0 = -1, pend_c0 = 0, pend_meas = -1;
   uint32_t pend_r = 0;
@@ -836,13 +978,15 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
   for (int g = job.g0; g < job.g1 && !err; ++g) {
     const DGate gt = job.gates[g];
     if (gt.op < DG_NCPHASE) {
-      clifford_gate(L, gt.op, gt.q0, gt.q1, n, d, job.dry, job.had + had_base, &nhad, &err);
+      clifford_gate(L, TB, gt.op, gt.q0, gt.q1, n, d, job.dry, job.had + had_base, &nhad, &err);
       err = wave_max(err);
       open = true;
       continue;
     }
     TIC(6);
-    // terminal gate of the segment
+    // terminal gate of the segment: works on the LDS copy of the tableau
+    regs_store(L, TB, n, true);
+    __syncthreads();
     const int q = gt.q0;
     const bool is_meas = gt.op == DG_MEASURE;
     SegProg* sp = job.dry ? nullptr : job.prog + seg;
@@ -997,6 +1141,8 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
     if (d > SF_DMAX - 1) err = TRK_E_DIM;
     err = wave_max(err);
     (void)d_entry;
+    __syncthreads();
+    regs_load(L, TB, n);
     TOC(6);
     // new segment
     had_base += nhad;
@@ -1040,6 +1186,7 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
     zero_z4(&sp->B1);
     ++seg;
   }
+  regs_store(L, TB, n, false);
   __syncthreads();
   // write back
   for (int i = lane; i < n * SF_WMAX; i += TL) { st->rx[i] = L.rx[i]; st->rz[i] = L.rz[i]; }
@@ -1053,7 +1200,7 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
     st->dmax = dmax;
     if (err && !st->error) st->error = err;
     L.tc[7] += TCLOCK();
-    for (int k = 0; k < 12; ++k) st->cycles[k] += L.tc[k];
+    for (int k = 0; k < 16; ++k) st->cycles[k] += L.tc[k];
   }
 }
 
@@ -1061,6 +1208,8 @@ static __device__ void readout_body(Lds& L, int16_t* rank, const TrackState* st,
   const int lane = lane_id();
   const int n = st->n;
   int d = st->d;
+  for (int i = lane; i < 2 * SF_NMAX; i += TL) L.lst[i] = 0u;
+  if (lane == 0) L.misc[1] = 0;
   for (int i = lane; i < SF_NMAX * SF_WMAX; i += TL) {
     L.rx[i] = i < n * SF_WMAX ? st->rx[i] : 0ull;
     L.rz[i] = i < n * SF_WMAX ? st->rz[i] : 0ull;
