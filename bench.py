@@ -28,6 +28,31 @@ PEAK_WORD_GOPS = 256 * 4 * 16 * 2.4 / 2
 TERMINAL_OPS = None
 
 
+def kernel_source_hash():
+    """Hash of the device sources; HBM traffic figures measured with counters
+    are reported only while the kernels are the ones they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("track.hip", "elem.hip", "sf_dev.h"):
+        with open(os.path.join(ROOT, "paper_1712_03554_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter summary, or None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            tab = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    rec = tab.get(kernel, {}).get(workload)
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def terminal_indices(circ, wl):
     """Indices of the gates that end a segment: non-Clifford phase gates and
     measurements (T, T-dagger, PHASE with an angle off the pi/2 grid, MEASURE)."""
@@ -211,6 +236,8 @@ def main():
     ap.add_argument("--path", default="batched", choices=["graph", "batched", "plain"])
     ap.add_argument("--serve-jobs", type=int, default=48, help="0 skips the serving run")
     ap.add_argument("--no-extra", action="store_true", help="skip the many-frame batched workloads")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, one device-to-device copy of this size (counter calibration)")
     ap.add_argument("--tune-lo", type=int, default=8)
     ap.add_argument("--tune-hi", type=int, default=24, help="below --tune-lo: no autotuning")
     ap.add_argument("--tick-segments", type=int, default=8)
@@ -305,7 +332,8 @@ def main():
         if seg_n else 0.0
     elem_roof = {"bound": "hbm", "kernel": "sf_seg_kernel" if args.path == "plain" else "sf_seg_batch",
                  "achieved": seg_ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": seg_ach / PEAK_HBM_GBS,
-                 "traffic": None,
+                 "traffic": measured_traffic("sf_seg_kernel" if args.path == "plain" else "sf_seg_batch",
+                                             args.workload),
                  "note": "32 B per slot (read + write of 16 B) over 2^d slots per segment launch"}
     if dom == "segment":
         roof = dict(elem_roof)
@@ -314,8 +342,11 @@ def main():
         tr_ms, tr_n = prof["track"]
         words_per_step = sum(len(c.gates) * 4 * c.n * ((c.n + 63) // 64) for c in circs)
         ach = (words_per_step * args.steps / tr_n) / (tr_ms / 1e3 / tr_n) / 1e9
-        roof = {"bound": "alu", "kernel": "sf_track_kernel", "achieved": ach, "peak": PEAK_WORD_GOPS,
-                "unit": "G 64-bit word-ops/s", "frac": ach / PEAK_WORD_GOPS, "traffic": None,
+        kname = "sf_track_kernel" if args.path == "plain" else "sf_track_batch"
+        roof = {"bound": "alu", "kernel": kname,
+                "achieved": ach, "peak": PEAK_WORD_GOPS,
+                "unit": "G 64-bit word-ops/s", "frac": ach / PEAK_WORD_GOPS,
+                "traffic": measured_traffic(kname, args.workload),
                 "note": "one wavefront per circuit walks the gates; bound by the dependent LDS/VALU latency of "
                         "that wavefront, not by throughput"}
     line = {
@@ -357,6 +388,11 @@ def main():
                                     int(args.serve_budget_gib * (1 << 30)))
     if not args.no_cpu and args.workload == "cfg2":
         line["cpu_baseline"] = cpu_baseline(circs[0], seeds[0])
+    if args.calib_copy_mib > 0:
+        src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     print(json.dumps(line), flush=True)
 
 

@@ -357,7 +357,7 @@ extern "C" sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n, const sf_gate* gat
     job.g0 = 0;
     job.g1 = (int)c->g.size();
     job.dry = 1;
-    hipLaunchKernelGGL(sf_track_kernel, dim3(1), dim3(TL), 0, ctx->stream, job, (const TrackJob*)nullptr);
+    hipLaunchKernelGGL(sf_track_kernel, dim3(1), dim3(TL), 0, ctx->stream, job);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpyAsync(h, dst.p, 64, hipMemcpyDeviceToHost, ctx->stream);
@@ -530,7 +530,7 @@ static sf_status run_gates(sf_state* s, const DGate* dgates, const DGate* hg, si
   job.outcomes = (const uint8_t*)s->outcomes.p;
   job.dry = 0;
   prof_begin(ctx, PK_TRACK);
-  hipLaunchKernelGGL(sf_track_kernel, dim3(1), dim3(TL), 0, ctx->stream, job, (const TrackJob*)nullptr);
+  hipLaunchKernelGGL(sf_track_kernel, dim3(1), dim3(TL), 0, ctx->stream, job);
   prof_end(ctx);
   HIPCHK(ctx, hipGetLastError());
   // segments: one per non-Clifford phase gate or measurement, plus a final one
@@ -641,7 +641,7 @@ extern "C" sf_status sf_measure(sf_state* s, uint32_t q, int* outcome) {
     job.g1 = part == 0 ? 1 : (int)c->g.size();
     job.dry = 1;
     if (job.g0 >= job.g1) break;
-    hipLaunchKernelGGL(sf_track_kernel, dim3(1), dim3(TL), 0, ctx->stream, job, (const TrackJob*)nullptr);
+    hipLaunchKernelGGL(sf_track_kernel, dim3(1), dim3(TL), 0, ctx->stream, job);
     e = hipGetLastError();
   }
   int hdr[16];
@@ -985,7 +985,7 @@ static void scratch_free(sf_ctx* ctx, BatchScratch* bs) {
 static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs, const ElemDesc* dd) {
   const int na = rp.na;
   prof_begin(ctx, PK_TRACK);
-  hipLaunchKernelGGL(sf_track_kernel, dim3(na), dim3(TL), 0, ctx->stream, TrackJob{}, djobs);
+  hipLaunchKernelGGL(sf_track_batch, dim3(na), dim3(TL), 0, ctx->stream, djobs);
   prof_end(ctx);
   for (int k = 0; k < rp.kmax; ++k) {
     prof_begin(ctx, PK_SEG);
@@ -1253,13 +1253,11 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
   for (size_t r = 0; r < rounds.size() && e == hipSuccess; ++r) {
     const RoundPlan& rp = rounds[r];
     const int na = rp.na;
-    TrackJob zero;
-    memset(&zero, 0, sizeof zero);
     const TrackJob* dj = (const TrackJob*)(base + off_j[r]);
     const ElemDesc* dd = (const ElemDesc*)(base + off_d[r]);
     {
-      void* args[] = {(void*)&zero, (void*)&dj};
-      e = add_kernel_node(g->graph, &last, (const void*)sf_track_kernel, dim3(na), dim3(TL), args);
+      void* args[] = {(void*)&dj};
+      e = add_kernel_node(g->graph, &last, (const void*)sf_track_batch, dim3(na), dim3(TL), args);
     }
     for (int k = 0; k < rp.kmax && e == hipSuccess; ++k) {
       const ElemDesc* dk = dd + (size_t)k * na;

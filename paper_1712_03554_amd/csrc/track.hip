@@ -1264,15 +1264,26 @@ static __device__ void readout_body(Lds& L, int16_t* rank, const TrackState* st,
 }
 };
 
-extern "C" __global__ void __launch_bounds__(TL) sf_track_kernel(TrackJob one, const TrackJob* jobs) {
-  __shared__ Lds L;
-  const TrackJob job = jobs ? jobs[blockIdx.x] : one;
+static __device__ __forceinline__ void track_dispatch(Lds& L, const TrackJob& job) {
   switch (job.st->W) {
     case 1: Trk<1>::track_body(L, job); break;
     case 2: Trk<2>::track_body(L, job); break;
     case 3: Trk<3>::track_body(L, job); break;
     default: Trk<4>::track_body(L, job); break;
   }
+}
+
+// One frame: the range given by value.
+extern "C" __global__ void __launch_bounds__(TL) sf_track_kernel(TrackJob one) {
+  __shared__ Lds L;
+  track_dispatch(L, one);
+}
+
+// Many frames: workgroup b runs jobs[b].
+extern "C" __global__ void __launch_bounds__(TL) sf_track_batch(const TrackJob* __restrict__ jobs) {
+  __shared__ Lds L;
+  const TrackJob job = jobs[blockIdx.x];
+  track_dispatch(L, job);
 }
 
 // Readout: canonical (fully reduced, pivot-sorted) tableau, the hull in that
