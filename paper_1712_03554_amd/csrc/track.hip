@@ -507,21 +507,22 @@ static __device__ void build_beta(Lds& L, int n) {
 // The same from the register tableau (rows already in LDS, xpiv current).
 static __device__ __forceinline__ void build_beta_regs(Lds& L, const Regs& R, int n) {
   const int lane = lane_id();
+  // all pivot lookups first, then all row reads: two LDS round trips in all
+  int l[W];
+  for (int k = 0; k < W; ++k) {
+    const int ld = R.ld[k];
+    l[k] = (64 * k + lane < n && ld >= n) ? (int)L.xpiv[ld - n] : -1;
+  }
   for (int k = 0; k < W; ++k) {
     const int h = 64 * k + lane;
     const int ld = R.ld[k];
     if (h >= n) continue;
-    uint64_t b[W];
-    for (int w = 0; w < W; ++w) b[w] = 0;
-    if (ld >= n) {
-      const int q = ld - n;
-      const int l = L.xpiv[q];
-      for (int w = 0; w < W; ++w) {
-        if (w == (q >> 6)) b[w] = 1ull << (q & 63);
-        if (l >= 0) b[w] ^= L.rx[l * SF_WMAX + w];
-      }
+    const int q = ld - n;
+    for (int w = 0; w < W; ++w) {
+      uint64_t b = (ld >= n && w == (q >> 6)) ? 1ull << (q & 63) : 0ull;
+      if (l[k] >= 0) b ^= L.rx[l[k] * SF_WMAX + w];
+      L.beta[h * SF_WMAX + w] = b;
     }
-    for (int w = 0; w < W; ++w) L.beta[h * SF_WMAX + w] = b[w];
   }
   __syncthreads();
 }
@@ -975,11 +976,17 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
   int pend = 0, pend_j0 = -1, pend_c0 = 0, pend_meas = -1;
   uint32_t pend_r = 0;
   bool open = false;
-  for (int g = job.g0; g < job.g1 && !err; ++g) {
-    const DGate gt = job.gates[g];
+  // errors of Clifford steps are per lane until the next terminal step or
+  // the end of the range; errw is the wave-uniform copy that stops the loop
+  int errw = 0;
+  DGate nxt;
+  memset(&nxt, 0, sizeof nxt);
+  if (job.g0 < job.g1) nxt = job.gates[job.g0];
+  for (int g = job.g0; g < job.g1 && !errw; ++g) {
+    const DGate gt = nxt;
+    if (g + 1 < job.g1) nxt = job.gates[g + 1];  // next gate's load overlaps this one
     if (gt.op < DG_NCPHASE) {
       clifford_gate(L, TB, gt.op, gt.q0, gt.q1, n, d, job.dry, job.had + had_base, &nhad, &err);
-      err = wave_max(err);
       open = true;
       continue;
     }
@@ -1140,6 +1147,7 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
     if (d > dmax) dmax = d;
     if (d > SF_DMAX - 1) err = TRK_E_DIM;
     err = wave_max(err);
+    errw = err;
     (void)d_entry;
     __syncthreads();
     regs_load(L, TB, n);
@@ -1178,6 +1186,7 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
     }
     __syncthreads();
   }
+  err = wave_max(err);
   if (open && !job.dry && !err) {
     SegProg* sp = job.prog + seg;
     if (lane == 0) emit_header(sp, SEG_NONE, 0, d, d, nhad, had_base);
