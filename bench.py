@@ -342,7 +342,8 @@ def main():
         tr_ms, tr_n = prof["track"]
         words_per_step = sum(len(c.gates) * 4 * c.n * ((c.n + 63) // 64) for c in circs)
         ach = (words_per_step * args.steps / tr_n) / (tr_ms / 1e3 / tr_n) / 1e9
-        kname = "sf_track_kernel" if args.path == "plain" else "sf_track_batch"
+        wset = sorted({(c.n + 63) // 64 for c in circs})
+        kname = ("sf_track_one<%d>" if args.path == "plain" else "sf_track_many<%d>") % wset[-1]
         roof = {"bound": "alu", "kernel": kname,
                 "achieved": ach, "peak": PEAK_WORD_GOPS,
                 "unit": "G 64-bit word-ops/s", "frac": ach / PEAK_WORD_GOPS,

@@ -47,6 +47,35 @@ static int grid_for(int d) {
   return (int)blocks;
 }
 
+static int words_of(uint32_t n) { return (int)((n + 63) / 64); }
+
+static const void* track_many_fn(int W) {
+  switch (W) {
+    case 1: return (const void*)sf_track_many<1>;
+    case 2: return (const void*)sf_track_many<2>;
+    case 3: return (const void*)sf_track_many<3>;
+    default: return (const void*)sf_track_many<4>;
+  }
+}
+
+static void launch_track_one(hipStream_t st, const TrackJob& job, int W) {
+  switch (W) {
+    case 1: hipLaunchKernelGGL(sf_track_one<1>, dim3(1), dim3(TL), 0, st, job); break;
+    case 2: hipLaunchKernelGGL(sf_track_one<2>, dim3(1), dim3(TL), 0, st, job); break;
+    case 3: hipLaunchKernelGGL(sf_track_one<3>, dim3(1), dim3(TL), 0, st, job); break;
+    default: hipLaunchKernelGGL(sf_track_one<4>, dim3(1), dim3(TL), 0, st, job); break;
+  }
+}
+
+static void launch_track_many(hipStream_t st, const TrackJob* jobs, int count, int W) {
+  switch (W) {
+    case 1: hipLaunchKernelGGL(sf_track_many<1>, dim3(count), dim3(TL), 0, st, jobs); break;
+    case 2: hipLaunchKernelGGL(sf_track_many<2>, dim3(count), dim3(TL), 0, st, jobs); break;
+    case 3: hipLaunchKernelGGL(sf_track_many<3>, dim3(count), dim3(TL), 0, st, jobs); break;
+    default: hipLaunchKernelGGL(sf_track_many<4>, dim3(count), dim3(TL), 0, st, jobs); break;
+  }
+}
+
 static void elem_shape(const sf_ctx* ctx, int d, int* block, int* grid) {
   if (d < 0) d = 0;
   if (d > SF_DMAX) d = SF_DMAX;
@@ -357,7 +386,7 @@ extern "C" sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n, const sf_gate* gat
     job.g0 = 0;
     job.g1 = (int)c->g.size();
     job.dry = 1;
-    hipLaunchKernelGGL(sf_track_kernel, dim3(1), dim3(TL), 0, ctx->stream, job);
+    launch_track_one(ctx->stream, job, words_of(n));
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpyAsync(h, dst.p, 64, hipMemcpyDeviceToHost, ctx->stream);
@@ -530,7 +559,7 @@ static sf_status run_gates(sf_state* s, const DGate* dgates, const DGate* hg, si
   job.outcomes = (const uint8_t*)s->outcomes.p;
   job.dry = 0;
   prof_begin(ctx, PK_TRACK);
-  hipLaunchKernelGGL(sf_track_kernel, dim3(1), dim3(TL), 0, ctx->stream, job);
+  launch_track_one(ctx->stream, job, words_of(c->n));
   prof_end(ctx);
   HIPCHK(ctx, hipGetLastError());
   // segments: one per non-Clifford phase gate or measurement, plus a final one
@@ -641,7 +670,7 @@ extern "C" sf_status sf_measure(sf_state* s, uint32_t q, int* outcome) {
     job.g1 = part == 0 ? 1 : (int)c->g.size();
     job.dry = 1;
     if (job.g0 >= job.g1) break;
-    hipLaunchKernelGGL(sf_track_kernel, dim3(1), dim3(TL), 0, ctx->stream, job);
+    launch_track_one(ctx->stream, job, words_of(c->n));
     e = hipGetLastError();
   }
   int hdr[16];
@@ -883,6 +912,7 @@ struct RoundPlan {
   std::vector<ElemDesc> desc;
   int na = 0, kmax = 0, gx = 1, bx = EB, gm = 1;
   bool anym = false;
+  int wcount[SF_WMAX + 1] = {0, 0, 0, 0, 0};  // frames per word count (jobs are ordered by it)
 };
 
 // Plans the next round from the progress pr[] and advances it; false when no
@@ -905,6 +935,12 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
     act.push_back((int)i);
   }
   if (act.empty()) return false;
+  // one track launch per word count: order the frames by it
+  std::stable_sort(act.begin(), act.end(), [&](int u, int v) {
+    return words_of(states[u]->c->n) < words_of(states[v]->c->n);
+  });
+  for (int w = 0; w <= SF_WMAX; ++w) rp->wcount[w] = 0;
+  for (int i : act) rp->wcount[words_of(states[i]->c->n)]++;
   const int na = (int)act.size();
   rp->na = na;
   rp->jobs.assign(na, TrackJob{});
@@ -984,9 +1020,14 @@ static void scratch_free(sf_ctx* ctx, BatchScratch* bs) {
 // Kernel launches of one planned round, with its descriptors at djobs/ddesc.
 static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs, const ElemDesc* dd) {
   const int na = rp.na;
-  prof_begin(ctx, PK_TRACK);
-  hipLaunchKernelGGL(sf_track_batch, dim3(na), dim3(TL), 0, ctx->stream, djobs);
-  prof_end(ctx);
+  int off = 0;
+  for (int w = 1; w <= SF_WMAX; ++w) {
+    if (!rp.wcount[w]) continue;
+    prof_begin(ctx, PK_TRACK);
+    launch_track_many(ctx->stream, djobs + off, rp.wcount[w], w);
+    prof_end(ctx);
+    off += rp.wcount[w];
+  }
   for (int k = 0; k < rp.kmax; ++k) {
     prof_begin(ctx, PK_SEG);
     hipLaunchKernelGGL(sf_seg_batch, dim3(rp.gx, na), dim3(rp.bx), 0, ctx->stream, dd + (size_t)k * na);
@@ -1255,9 +1296,13 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
     const int na = rp.na;
     const TrackJob* dj = (const TrackJob*)(base + off_j[r]);
     const ElemDesc* dd = (const ElemDesc*)(base + off_d[r]);
-    {
-      void* args[] = {(void*)&dj};
-      e = add_kernel_node(g->graph, &last, (const void*)sf_track_batch, dim3(na), dim3(TL), args);
+    int off = 0;
+    for (int w = 1; w <= SF_WMAX && e == hipSuccess; ++w) {
+      if (!rp.wcount[w]) continue;
+      const TrackJob* djw = dj + off;
+      void* args[] = {(void*)&djw};
+      e = add_kernel_node(g->graph, &last, track_many_fn(w), dim3(rp.wcount[w]), dim3(TL), args);
+      off += rp.wcount[w];
     }
     for (int k = 0; k < rp.kmax && e == hipSuccess; ++k) {
       const ElemDesc* dk = dd + (size_t)k * na;

@@ -1273,26 +1273,974 @@ static __device__ void readout_body(Lds& L, int16_t* rank, const TrackState* st,
 }
 };
 
-static __device__ __forceinline__ void track_dispatch(Lds& L, const TrackJob& job) {
-  switch (job.st->W) {
-    case 1: Trk<1>::track_body(L, job); break;
-    case 2: Trk<2>::track_body(L, job); break;
-    case 3: Trk<3>::track_body(L, job); break;
-    default: Trk<4>::track_body(L, job); break;
+// LDS-resident variant of the tableau track (rows in LDS, elimination in
+// registers per call), used for frames of more than 128 qubits: keeping the
+// whole tableau in registers there spills to scratch.
+template <int W>
+struct TrkL {
+static __device__ int row_lead(const uint64_t* x, const uint64_t* z, int n) {
+  for (int w = 0; w < W; ++w) if (x[w]) return 64 * w + __builtin_ctzll(x[w]);
+  for (int w = 0; w < W; ++w) if (z[w]) return n + 64 * w + __builtin_ctzll(z[w]);
+  return -1;
+}
+
+// Sign bit c of row1 * row2 = (-1)^c (row1 xor row2) for commuting rows,
+// from the literal products of Table 1 (XY=iZ, YZ=iX, ZX=iY; reversed -i).
+static __device__ int rowprod_sign(const uint64_t* x1, const uint64_t* z1, const uint64_t* x2,
+                            const uint64_t* z2) {
+  int pos = 0, neg = 0;
+  for (int w = 0; w < W; ++w) {
+    uint64_t a = x1[w], b = z1[w], c = x2[w], d = z2[w];
+    pos += __popcll((a & b & ~c & d) | (a & ~b & c & d) | (~a & b & c & ~d));
+    neg += __popcll((a & b & c & ~d) | (a & ~b & ~c & d) | (~a & b & c & d));
+  }
+  return ((pos - neg) & 3) >> 1;
+}
+
+// ---------------------------------------------------------------------------
+// Echelon bookkeeping
+// ---------------------------------------------------------------------------
+static __device__ void rebuild_index(Lds& L, int n) {
+  const int lane = lane_id();
+  for (int i = lane; i < SF_NMAX; i += TL) { L.xpiv[i] = -1; L.zpiv[i] = -1; }
+  __syncthreads();
+  for (int i = lane; i < n; i += TL) {
+    int ld = row_lead(&L.rx[i * SF_WMAX], &L.rz[i * SF_WMAX], n);
+    L.lead[i] = (int16_t)ld;
+    if (ld >= 0 && ld < n) L.xpiv[ld] = (int16_t)i;
+    else if (ld >= n) L.zpiv[ld - n] = (int16_t)i;
+  }
+  __syncthreads();
+  const int R = (n + 63) / 64;
+  int k = 0;
+  for (int it = 0; it < R; ++it) {
+    int i = it * 64 + lane;
+    bool isx = i < n && L.lead[i] >= 0 && L.lead[i] < n;
+    bool isz = i < n && L.lead[i] >= n;
+    uint64_t bx = __ballot(isx), bz = __ballot(isz);
+    k += __popcll(bx);
+    if (lane == 0) L.zsm[it] = bz;
+  }
+  if (lane == 0) {
+    for (int it = R; it < SF_WMAX; ++it) L.zsm[it] = 0;
+    L.misc[0] = k;
+  }
+  __syncthreads();
+}
+
+// Tracked phase-vector images: s0 (affine), V[0..d) and optionally u (linear).
+// Apply sigma_i ^= sigma_m ^ c_i for every i in rmask (c in cmask).
+static __device__ void apply_rowsum_batch(Lds& L, int m, int d, bool with_u) {
+  const int lane = lane_id();
+  uint64_t* vec = nullptr;
+  bool affine = false;
+  if (lane < d) vec = L.V[lane];
+  else if (lane == d) { vec = L.s0; affine = true; }
+  else if (lane == d + 1 && with_u) vec = L.u;
+  if (vec) {
+    int bm = getb(vec, m);
+    for (int w = 0; w < W; ++w) vec[w] ^= (bm ? L.rmask[w] : 0ull) ^ (affine ? L.cmask[w] : 0ull);
+  }
+  __syncthreads();
+}
+
+// Column-major copy of the tableau: L.cx[q] / L.cz[q] hold the slots whose
+// row has an x (z) bit at qubit q.  Built by one transpose per launch and kept
+// in step with every row change.
+static __device__ void build_cols(Lds& L, int n) {
+  const int lane = lane_id();
+  const int R = (n + 63) / 64;
+  for (int it = 0; it < R; ++it) {
+    const int q = it * 64 + lane;
+    uint64_t cxv[W], czv[W];
+    for (int w = 0; w < W; ++w) { cxv[w] = 0; czv[w] = 0; }
+    if (q < n) {
+      for (int i = 0; i < n; ++i) {
+        const uint64_t bx = (L.rx[i * SF_WMAX + (q >> 6)] >> (q & 63)) & 1ull;
+        const uint64_t bz = (L.rz[i * SF_WMAX + (q >> 6)] >> (q & 63)) & 1ull;
+        cxv[i >> 6] |= bx << (i & 63);
+        czv[i >> 6] |= bz << (i & 63);
+      }
+      for (int w = 0; w < W; ++w) { L.cx[q * SF_WMAX + w] = cxv[w]; L.cz[q * SF_WMAX + w] = czv[w]; }
+    }
+  }
+  __syncthreads();
+}
+
+// rows in L.rmask received row m: toggle those slots in every column where
+// row m has a bit
+static __device__ void cols_rowsum(Lds& L, int m, int n) {
+  const int lane = lane_id();
+  const int R = (n + 63) / 64;
+  for (int it = 0; it < R; ++it) {
+    const int q = it * 64 + lane;
+    if (q >= n) continue;
+    if (getb(&L.rx[m * SF_WMAX], q))
+      for (int w = 0; w < W; ++w) L.cx[q * SF_WMAX + w] ^= L.rmask[w];
+    if (getb(&L.rz[m * SF_WMAX], q))
+      for (int w = 0; w < W; ++w) L.cz[q * SF_WMAX + w] ^= L.rmask[w];
   }
 }
 
-// One frame: the range given by value.
-extern "C" __global__ void __launch_bounds__(TL) sf_track_kernel(TrackJob one) {
-  __shared__ Lds L;
-  track_dispatch(L, one);
+// Gaussian elimination restricted to the columns that break the echelon
+// form: a column breaks it when it is the lead of some row and at least two
+// rows have a bit there (on z columns only Z-block rows count, unless full).
+// full = 0 keeps the form of Figure 2b (X-block reduced on x-leads, Z-block
+// reduced on z-leads); full = 1 also clears X-block bits on z-leads.  Each
+// step takes the smallest such column, multiplies its first leading row into
+// every other row with a bit there, and replays the row multiplication on the
+// tracked phase vectors.
+// Rows, their leads, the column-major copy and the tracked phase vectors are
+// held in registers for the whole loop: lane l owns
+// row slots and columns 64k + l (k < W) and hull vector l (V[l], then s0 at
+// lane d, u at lane d + 1).  The pivot row travels by readlane, the row masks
+// of each step by ballot; LDS is read on entry and written on exit only.
+static __device__ void repair(Lds& L, int n, int d, bool with_u, int full) {
+  const int lane = lane_id();
+  uint64_t x[W][W], z[W][W], cxr[W][W], czr[W][W];
+  int ld[W];
+  bool valid[W];
+  for (int k = 0; k < W; ++k) {
+    const int i = 64 * k + lane;
+    valid[k] = i < n;
+    for (int w = 0; w < W; ++w) {
+      x[k][w] = valid[k] ? L.rx[i * SF_WMAX + w] : 0ull;
+      z[k][w] = valid[k] ? L.rz[i * SF_WMAX + w] : 0ull;
+      cxr[k][w] = valid[k] ? L.cx[i * SF_WMAX + w] : 0ull;
+      czr[k][w] = valid[k] ? L.cz[i * SF_WMAX + w] : 0ull;
+    }
+    ld[k] = valid[k] ? (int)L.lead[i] : -1;
+  }
+  const bool has_vec = lane < d || lane == d || (lane == d + 1 && with_u);
+  const bool affine = lane == d;
+  uint64_t hv[W];
+  for (int w = 0; w < W; ++w)
+    hv[w] = lane < d ? L.V[lane][w] : lane == d ? L.s0[w] : (lane == d + 1 && with_u) ? L.u[w] : 0ull;
+  for (int guard = 0; guard < 4 * SF_NMAX + 8; ++guard) {
+    TIC(8);
+    // Z-block rows (no x bits)
+    uint64_t zs[W];
+    for (int k = 0; k < W; ++k) {
+      uint64_t xa = 0;
+      for (int w = 0; w < W; ++w) xa |= x[k][w];
+      const uint64_t b = __ballot(valid[k] && xa == 0ull);
+      zs[k] = full ? ~0ull : b;
+    }
+    // bit counts of my columns (z columns: Z-block rows only unless full)
+    int cntx[W], cntz[W];
+    for (int k = 0; k < W; ++k) {
+      int a = 0, b = 0;
+      for (int w = 0; w < W; ++w) { a += __popcll(cxr[k][w]); b += __popcll(czr[k][w] & zs[w]); }
+      cntx[k] = a;
+      cntz[k] = b;
+    }
+    // smallest lead column shared by two rows
+    int best = 0x7fffffff;
+    for (int k = 0; k < W; ++k) {
+      const int c = ld[k];
+      const bool isx = c >= 0 && c < n;
+      const int cc = c < 0 ? 0 : (isx ? c : c - n);
+      int cnt = 0;
+      for (int kk = 0; kk < W; ++kk) {
+        const int vx = __shfl(cntx[kk], cc & 63);
+        const int vz = __shfl(cntz[kk], cc & 63);
+        if ((cc >> 6) == kk) cnt = isx ? vx : vz;
+      }
+      if (c >= 0 && cnt >= 2 && c < best) best = c;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const int t = __shfl_xor(best, o);
+      best = t < best ? t : best;
+    }
+    TOC(8);
+    if (best == 0x7fffffff) break;
+    TIC(9);
+    const int col = __builtin_amdgcn_readfirstlane(best);
+    // pivot: the first slot leading at col
+    int m = -1;
+    for (int k = 0; k < W && m < 0; ++k) {
+      const uint64_t b = __ballot(valid[k] && ld[k] == col);
+      if (b) m = 64 * k + __builtin_ctzll(b);
+    }
+    const int km = m >> 6, lm = m & 63;
+    uint64_t xm[W], zm[W];
+    for (int w = 0; w < W; ++w) {
+      uint64_t sx = 0, sz = 0;
+      for (int kk = 0; kk < W; ++kk)
+        if (kk == km) { sx = x[kk][w]; sz = z[kk][w]; }
+      xm[w] = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sx >> 32), lm) << 32) |
+              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sx, lm);
+      zm[w] = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sz >> 32), lm) << 32) |
+              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sz, lm);
+    }
+    const bool xcol = col < n;
+    const int cb = xcol ? col : col - n;
+    uint64_t rm[W], cm[W];
+    for (int k = 0; k < W; ++k) {
+      const int i = 64 * k + lane;
+      uint64_t xa = 0, wsel = 0;
+      for (int w = 0; w < W; ++w) {
+        xa |= x[k][w];
+        if ((cb >> 6) == w) wsel = xcol ? x[k][w] : z[k][w];
+      }
+      const bool hit = valid[k] && i != m && (xcol || full || xa == 0ull) && ((wsel >> (cb & 63)) & 1ull);
+      int c = 0;
+      if (hit) {
+        c = rowprod_sign(x[k], z[k], xm, zm);
+        for (int w = 0; w < W; ++w) { x[k][w] ^= xm[w]; z[k][w] ^= zm[w]; }
+        ld[k] = row_lead(x[k], z[k], n);
+      }
+      rm[k] = __ballot(hit);
+      cm[k] = __ballot(hit && c);
+    }
+    // the column-major copy: columns where row m has a bit get the hit rows
+    for (int k = 0; k < W; ++k) {
+      if (!valid[k]) continue;
+      const bool bx = (xm[k] >> lane) & 1ull, bz = (zm[k] >> lane) & 1ull;
+      for (int w = 0; w < W; ++w) {
+        if (bx) cxr[k][w] ^= rm[w];
+        if (bz) czr[k][w] ^= rm[w];
+      }
+    }
+    TOC(9);
+    TIC(10);
+    // replay on the tracked phase vectors: sigma_i ^= sigma_m (^ c_i on s0)
+    if (has_vec) {
+      uint64_t wm = 0;
+      for (int w = 0; w < W; ++w) if ((m >> 6) == w) wm = hv[w];
+      const bool bm = (wm >> (m & 63)) & 1ull;
+      for (int w = 0; w < W; ++w) hv[w] ^= (bm ? rm[w] : 0ull) ^ (affine ? cm[w] : 0ull);
+    }
+    TOC(10);
+  }
+  for (int k = 0; k < W; ++k) {
+    const int i = 64 * k + lane;
+    if (!valid[k]) continue;
+    for (int w = 0; w < W; ++w) {
+      L.rx[i * SF_WMAX + w] = x[k][w];
+      L.rz[i * SF_WMAX + w] = z[k][w];
+      L.cx[i * SF_WMAX + w] = cxr[k][w];
+      L.cz[i * SF_WMAX + w] = czr[k][w];
+    }
+    L.lead[i] = (int16_t)ld[k];
+  }
+  if (lane < d) for (int w = 0; w < W; ++w) L.V[lane][w] = hv[w];
+  else if (lane == d) for (int w = 0; w < W; ++w) L.s0[w] = hv[w];
+  else if (lane == d + 1 && with_u) for (int w = 0; w < W; ++w) L.u[w] = hv[w];
+  __syncthreads();
 }
 
-// Many frames: workgroup b runs jobs[b].
-extern "C" __global__ void __launch_bounds__(TL) sf_track_batch(const TrackJob* __restrict__ jobs) {
+// ---------------------------------------------------------------------------
+// b*(sigma): smallest basis string of the support of psi(M, sigma).
+// Flipping the sign of Z-block row h moves the support by e_{q_h} (X_{q_h}
+// anticommutes with that row only); the result is then reduced on the X-block
+// leads.  So b*(sigma) = XOR over Z-rows h with sigma_h = 1 of beta_h, with
+// beta_h = e_{q_h} ^ (x-part of the X-row leading at q_h, if any).
+// ---------------------------------------------------------------------------
+static __device__ void build_beta(Lds& L, int n) {
+  const int lane = lane_id();
+  for (int h = lane; h < n; h += TL) {
+    uint64_t* b = &L.beta[h * SF_WMAX];
+    for (int w = 0; w < SF_WMAX; ++w) b[w] = 0;
+    int ld = L.lead[h];
+    if (ld >= n) {
+      int q = ld - n;
+      flipb(b, q);
+      int l = L.xpiv[q];
+      if (l >= 0)
+        for (int w = 0; w < W; ++w) b[w] ^= L.rx[l * SF_WMAX + w];
+    }
+  }
+  __syncthreads();
+}
+
+static __device__ void bimage(const Lds& L, const uint64_t* vec, uint64_t* out) {
+  uint64_t acc[SF_WMAX] = {0, 0, 0, 0};
+  for (int w = 0; w < W; ++w) {
+    uint64_t bits = vec[w] & L.zsm[w];
+    while (bits) {
+      int h = 64 * w + __builtin_ctzll(bits);
+      bits &= bits - 1;
+      for (int v = 0; v < W; ++v) acc[v] ^= L.beta[h * SF_WMAX + v];
+    }
+  }
+  for (int w = 0; w < W; ++w) out[w] = acc[w];
+}
+
+// images of s0 (index 0), V[j] (1+j) and, if with_u, u (index d+1) into hb
+static __device__ void hull_images(Lds& L, uint64_t (*hb)[SF_WMAX], int d, bool with_u) {
+  const int lane = lane_id();
+  if (lane == 0) bimage(L, L.s0, hb[0]);
+  else if (lane <= d) bimage(L, L.V[lane - 1], hb[lane]);
+  else if (lane == d + 1 && with_u) bimage(L, L.u, hb[d + 1]);
+  __syncthreads();
+}
+
+// exponent e with psi(M_old, sigma)(b) = 2^{-k/2} i^e, or -1 if b is outside
+// the support.  psi ~ prod_l (I + g_l)/2 |b*>: the amplitude at b* ^ x_S is the
+// phase of applying the X-block generators in S to |b*>.
+static __device__ int uexp(const Lds& L, const uint64_t* sig, const uint64_t* bO, const uint64_t* b) {
+  uint64_t v[SF_WMAX];
+  for (int w = 0; w < W; ++w) v[w] = bO[w];
+  int e = 0;
+  for (int w = 0; w < W; ++w) {
+    uint64_t D = (b[w] ^ bO[w]) & L.oxpm[w];
+    while (D) {
+      int q = 64 * w + __builtin_ctzll(D);
+      D &= D - 1;
+      int l = L.oxpiv[q];
+      uint64_t zv = 0;
+      for (int t = 0; t < W; ++t) zv ^= L.oz[l * SF_WMAX + t] & v[t];
+      e += 2 * (getb(sig, l) ^ par64(zv)) + L.ow[l];
+      for (int t = 0; t < W; ++t) v[t] ^= L.ox[l * SF_WMAX + t];
+    }
+  }
+  for (int w = 0; w < W; ++w) if (v[w] != b[w]) return -1;
+  return e & 3;
+}
+
+// ---------------------------------------------------------------------------
+// Sample points and fitting of quadratic forms over the hull coordinates
+// ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Save the pre-gate tableau and hull (needed by the phase evaluation)
+// ---------------------------------------------------------------------------
+static __device__ void save_old(Lds& L, int n, int d) {
+  const int lane = lane_id();
+  for (int i = lane; i < n; i += TL) {
+    uint64_t wz = 0;
+    for (int w = 0; w < SF_WMAX; ++w) {
+      L.ox[i * SF_WMAX + w] = L.rx[i * SF_WMAX + w];
+      L.oz[i * SF_WMAX + w] = L.rz[i * SF_WMAX + w];
+    }
+    int c = 0;
+    for (int w = 0; w < W; ++w) c += __popcll(L.rx[i * SF_WMAX + w] & L.rz[i * SF_WMAX + w]);
+    L.ow[i] = (uint8_t)(c & 3);
+    L.oxpiv[i] = L.xpiv[i];
+    (void)wz;
+  }
+  for (int i = n + lane; i < SF_NMAX; i += TL) L.oxpiv[i] = -1;
+  if (lane < d) for (int w = 0; w < SF_WMAX; ++w) L.oV[lane][w] = L.V[lane][w];
+  if (lane == d) for (int w = 0; w < SF_WMAX; ++w) L.os0[w] = L.s0[w];
+  if (lane <= d + 1) for (int w = 0; w < SF_WMAX; ++w) L.hbO[lane][w] = L.hbN[lane][w];
+  __syncthreads();
+  for (int it = 0; it < SF_WMAX; ++it) {
+    const int q = it * 64 + lane;
+    const uint64_t m = __ballot(q < n && L.xpiv[q] >= 0);
+    if (lane == 0) L.oxpm[it] = m;
+  }
+  __syncthreads();
+}
+
+// gather the (<= 2) hull vectors of point Y into sigma/b images
+static __device__ __forceinline__ void point_vec(const uint64_t* base, const uint64_t (*vecs)[SF_WMAX], uint32_t Y,
+                                          int off, uint64_t* out) {
+  for (int w = 0; w < W; ++w) out[w] = base[w];
+  while (Y) {
+    int j = __builtin_ctz(Y);
+    Y &= Y - 1;
+    for (int w = 0; w < W; ++w) out[w] ^= vecs[j + off][w];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Clifford gate
+// ---------------------------------------------------------------------------
+static __device__ void clifford_gate(Lds& L, int op, int a, int b, int n, int d, int dry, GF2Q* had_out,
+                              int* nhad, int* err) {
+  const int lane = lane_id();
+  const int R = (n + 63) / 64;
+  if (op == DG_S || op == DG_SDG || op == DG_Z || op == DG_CZ) {
+    // Diagonal gates change only z bits of X-block rows and flip only X-block
+    // signs: the echelon form, the support and b*(sigma) stay as they are, and
+    // U|b*> = mu(b*) |b*>, so omega(Y) = mu(b*(sigma(Y))).
+    TIC(1);
+    if (lane == 0)
+      for (int w = 0; w < SF_WMAX; ++w) L.fmask[w] = 0;
+    __syncthreads();
+    for (int it = 0; it < R; ++it) {
+      int i = it * 64 + lane;
+      if (i >= n) continue;
+      uint64_t* x = &L.rx[i * SF_WMAX];
+      uint64_t* z = &L.rz[i * SF_WMAX];
+      int xa = getb(x, a), za = getb(z, a), fl = 0;
+      if (op == DG_S) { fl = xa & za; if (xa) flipb(z, a); }
+      else if (op == DG_SDG) { fl = xa & (za ^ 1); if (xa) flipb(z, a); }
+      else if (op == DG_Z) fl = xa;
+      else {
+        int xb = getb(x, b), zb = getb(z, b);
+        fl = xa & xb & (za ^ zb);
+        if (xb) flipb(z, a);
+        if (xa) flipb(z, b);
+      }
+      if (fl) atomicOr((unsigned long long*)&L.fmask[i >> 6], 1ull << (i & 63));
+    }
+    if (lane < W) {
+      const int w = lane;
+      if (op == DG_S || op == DG_SDG) L.cz[a * SF_WMAX + w] ^= L.cx[a * SF_WMAX + w];
+      else if (op == DG_CZ) {
+        L.cz[a * SF_WMAX + w] ^= L.cx[b * SF_WMAX + w];
+        L.cz[b * SF_WMAX + w] ^= L.cx[a * SF_WMAX + w];
+      }
+    }
+    __syncthreads();
+    if (lane < SF_WMAX) L.s0[lane] ^= L.fmask[lane];
+    __syncthreads();
+    TOC(1);
+    if (dry) return;
+    TIC(4);
+    const int P = npoints(d);
+    for (int p = lane; p < P; p += TL) {
+      uint32_t Y = L.Ys[p];
+      int ba = getb(L.hbN[0], a), bb = op == DG_CZ ? getb(L.hbN[0], b) : 0;
+      while (Y) {
+        const int j = __builtin_ctz(Y);
+        Y &= Y - 1;
+        ba ^= getb(L.hbN[1 + j], a);
+        if (op == DG_CZ) bb ^= getb(L.hbN[1 + j], b);
+      }
+      int mu = op == DG_S ? ba : op == DG_SDG ? 3 * ba : op == DG_Z ? 2 * ba : 2 * (ba & bb);
+      L.acc[p] = (uint8_t)((L.acc[p] + mu) & 3);
+    }
+    __syncthreads();
+    TOC(4);
+    return;
+  }
+  TIC(0);
+  if (!dry) save_old(L, n, d);
+  TOC(0);
+  const int kold = L.misc[0];
+  if (lane == 0)
+    for (int w = 0; w < SF_WMAX; ++w) L.fmask[w] = 0;
+  __syncthreads();
+  TIC(1);
+  // column update (Table 2) and sign flips
+  for (int it = 0; it < R; ++it) {
+    int i = it * 64 + lane;
+    if (i >= n) continue;
+    uint64_t* x = &L.rx[i * SF_WMAX];
+    uint64_t* z = &L.rz[i * SF_WMAX];
+    int xa = getb(x, a), za = getb(z, a), fl = 0;
+    switch (op) {
+      case DG_H: fl = xa & za; if (xa != za) { flipb(x, a); flipb(z, a); } break;
+      case DG_S: fl = xa & za; if (xa) flipb(z, a); break;
+      case DG_SDG: fl = xa & (za ^ 1); if (xa) flipb(z, a); break;
+      case DG_X: fl = za; break;
+      case DG_Z: fl = xa; break;
+      case DG_Y: fl = xa ^ za; break;
+      case DG_CNOT: {
+        int xb = getb(x, b), zb = getb(z, b);
+        fl = xa & zb & (xb ^ za ^ 1);
+        if (xa) flipb(x, b);
+        if (zb) flipb(z, a);
+        break;
+      }
+      case DG_CZ: {
+        int xb = getb(x, b), zb = getb(z, b);
+        fl = xa & xb & (za ^ zb);
+        if (xb) flipb(z, a);
+        if (xa) flipb(z, b);
+        break;
+      }
+    }
+    if (fl) atomicOr((unsigned long long*)&L.fmask[i >> 6], 1ull << (i & 63));
+    L.lead[i] = (int16_t)row_lead(x, z, n);
+  }
+  // the same column operations on the column-major copy
+  if (lane < W) {
+    const int w = lane;
+    uint64_t* cxa = &L.cx[a * SF_WMAX];
+    uint64_t* cza = &L.cz[a * SF_WMAX];
+    if (op == DG_H) {
+      uint64_t t = cxa[w]; cxa[w] = cza[w]; cza[w] = t;
+    } else if (op == DG_CNOT) {
+      L.cx[b * SF_WMAX + w] ^= cxa[w];
+      cza[w] ^= L.cz[b * SF_WMAX + w];
+    }
+  }
+  __syncthreads();
+  // sign flips broadcast to every phase vector: s0 ^= f
+  if (lane < SF_WMAX) L.s0[lane] ^= L.fmask[lane];
+  __syncthreads();
+  TOC(1);
+  TIC(2);
+  repair(L, n, d, false, 0);
+  TOC(2);
+  TIC(3);
+  rebuild_index(L, n);
+  if (dry) { TOC(3); return; }
+  const int knew = L.misc[0];
+  build_beta(L, n);
+  hull_images(L, L.hbN, d, false);
+  TOC(3);
+  // per-element phase factor omega(Y), sampled at the fitting points
+  const int dk = knew - kold;
+  const bool hsplit = op == DG_H && dk == 0;
+  TIC(4);
+  const int P = npoints(d);
+  for (int p = lane; p < P; p += TL) {
+    uint32_t Y = L.Ys[p];
+    uint64_t so[SF_WMAX], bo[SF_WMAX], bn[SF_WMAX], src[SF_WMAX];
+    point_vec(L.os0, L.oV, Y, 0, so);
+    point_vec(L.hbO[0], L.hbO, Y, 1, bo);
+    point_vec(L.hbN[0], L.hbN, Y, 1, bn);
+    int e = 0, t = 0;
+    int ba = getb(bn, a);
+    for (int w = 0; w < W; ++w) src[w] = bn[w];
+    if (op != DG_H) {
+      int mu = 0;
+      switch (op) {
+        case DG_S: mu = ba; break;
+        case DG_SDG: mu = (4 - ba) & 3; break;
+        case DG_X: flipb(src, a); break;
+        case DG_Z: mu = 2 * ba; break;
+        case DG_Y: flipb(src, a); mu = ba ? 1 : 3; break;
+        case DG_CNOT: if (ba) flipb(src, b); break;
+        case DG_CZ: mu = 2 * (ba & getb(bn, b)); break;
+      }
+      int u = uexp(L, so, bo, src);
+      if (u < 0) *err = TRK_E_INTERNAL;
+      e = mu + u;
+    } else {
+      uint64_t b1[SF_WMAX];
+      for (int w = 0; w < W; ++w) b1[w] = bn[w];
+      if (ba) flipb(src, a); else flipb(b1, a);   // src: bit a = 0, b1: bit a = 1
+      if (dk == 1) {
+        int u0 = uexp(L, so, bo, src);
+        int u1 = uexp(L, so, bo, b1);
+        if ((u0 < 0) == (u1 < 0)) *err = TRK_E_INTERNAL;
+        e = u0 >= 0 ? u0 : u1 + 2 * ba;
+      } else if (dk == -1) {
+        int u0 = uexp(L, so, bo, src);
+        if (u0 < 0) *err = TRK_E_INTERNAL;
+        e = u0;
+      } else {
+        int e0 = uexp(L, so, bo, src);
+        int e1 = uexp(L, so, bo, b1);
+        if (e0 < 0 || e1 < 0) *err = TRK_E_INTERNAL;
+        e1 += 2 * ba;
+        int dl = (e1 - e0) & 3;
+        if (!(dl & 1)) *err = TRK_E_INTERNAL;
+        e = e0;
+        t = dl == 3 ? 1 : 0;        // omega = exp(i pi (2 e0 + 1 - 2t)/4)
+      }
+    }
+    L.acc[p] = (uint8_t)((L.acc[p] + e) & 3);
+    if (hsplit) L.t0[p] = (uint8_t)t;
+  }
+  __syncthreads();
+  TOC(4);
+  if (hsplit) {
+    TIC(5);
+    fit_gf2(L, L.t0, d, &had_out[*nhad]);
+    *nhad += 1;
+    __syncthreads();
+    TOC(5);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// span test: delta with XOR_{j in delta} oV[j] == dq (slot bit vectors), or
+// 0xffffffff if dq is outside the span.  Single lane (d <= 30 vectors).
+// ---------------------------------------------------------------------------
+// Wave-parallel Gaussian elimination over the d vectors vecs[0..d) (one per
+// lane).  Returns delta with XOR_{j in delta} vecs[j] == target, or
+// 0xffffffff if the target is outside their span; tops[] receives the
+// leading-bit positions of the echelon basis (in the order found).
+static __device__ uint32_t span_reduce(const uint64_t (*vecs)[SF_WMAX], const uint64_t* target, int d,
+                                       int* tops, int* ntops) {
+  const int lane = lane_id();
+  uint64_t v[W];
+  uint32_t c = 0;
+  const bool is_t = lane == 63;
+  for (int w = 0; w < W; ++w) v[w] = lane < d ? vecs[lane][w] : (is_t && target ? target[w] : 0ull);
+  if (lane < d) c = 1u << lane;
+  bool used = false;
+  int nt = 0;
+  for (int round = 0; round < d; ++round) {
+    uint64_t any = 0;
+    for (int w = 0; w < W; ++w) any |= v[w];
+    uint64_t bal = __ballot(lane < d && !used && any != 0ull);
+    if (!bal) break;
+    const int pl = __builtin_ctzll(bal);
+    uint64_t pv[W];
+    for (int w = 0; w < W; ++w) pv[w] = __shfl(v[w], pl);
+    const uint32_t pc = __shfl(c, pl);
+    int top = -1;
+    for (int w = W - 1; w >= 0 && top < 0; --w) if (pv[w]) top = 64 * w + 63 - __builtin_clzll(pv[w]);
+    if (tops && lane == 0) tops[nt] = top;
+    ++nt;
+    if (lane == pl) used = true;
+    else if (getb(v, top)) {
+      for (int w = 0; w < W; ++w) v[w] ^= pv[w];
+      c ^= pc;
+    }
+  }
+  if (ntops) *ntops = nt;
+  uint64_t tany = 0;
+  for (int w = 0; w < W; ++w) tany |= v[w];
+  const uint64_t tz = __shfl(tany, 63);
+  const uint32_t tc = __shfl(c, 63);
+  return tz ? 0xffffffffu : tc;
+}
+
+// ---------------------------------------------------------------------------
+// Non-Clifford phase gate or measurement on q: COFACTOR (section 3)
+// ---------------------------------------------------------------------------
+static __device__ void det_functional(Lds& L, int q, int n, int d, uint32_t* c0, uint32_t* r, int* err) {
+  const int lane = lane_id();
+  int h = L.zpiv[q];
+  uint32_t rr = 0;
+  if (h < 0) { if (lane == 0) *err = TRK_E_INTERNAL; h = 0; }
+  else {
+    for (int w = 0; w < W; ++w) {
+      uint64_t want = (q >> 6) == w ? (1ull << (q & 63)) : 0ull;
+      if (L.rz[h * SF_WMAX + w] != want || L.rx[h * SF_WMAX + w] != 0ull) *err = TRK_E_INTERNAL;
+    }
+  }
+  rr = (uint32_t)__ballot(lane < d && getb(L.V[lane < d ? lane : 0], h));
+  *c0 = (uint32_t)getb(L.s0, h);
+  *r = rr;
+}
+
+// Filter step of a measurement on the hull: keep sigma(Y) with
+// c0 ^ parity(r & Y) == outcome, i.e. fix coordinate j0 and drop it.
+
+static __device__ void track_body(Lds& L, const TrackJob& job) {
+  TrackState* st = job.st;
+  const int lane = lane_id();
+  const int n = st->n;
+  int d = st->d;
+  int err = 0;
+  if (lane_id() < 12) L.tc[lane_id()] = 0;
+  __syncthreads();
+  TIC(7);
+  // load state
+  for (int i = lane; i < SF_NMAX * SF_WMAX; i += TL) {
+    L.rx[i] = i < n * SF_WMAX ? st->rx[i] : 0ull;
+    L.rz[i] = i < n * SF_WMAX ? st->rz[i] : 0ull;
+  }
+  if (lane < SF_WMAX) L.s0[lane] = st->s0[lane];
+  if (lane < d) for (int w = 0; w < SF_WMAX; ++w) L.V[lane][w] = st->V[lane][w];
+  __syncthreads();
+  // deferred filter of the last measurement (needs its outcome)
+  if (st->pend) apply_pending(L, st, job.dry ? nullptr : job.outcomes, &d);
+  build_cols(L, n);
+  rebuild_index(L, n);
+  if (!job.dry) {
+    build_beta(L, n);
+    hull_images(L, L.hbN, d, false);
+    build_points(L, d);
+  }
+  for (int p = lane; p < SF_PMAX; p += TL) L.acc[p] = 0;
+  __syncthreads();
+  int seg = 0, nhad = 0, had_base = 0, nmeas = st->nmeas, dmax = st->dmax;
+  int pend = 0, pend_j0 = -1, pend_c0 = 0, pend_meas = -1;
+  uint32_t pend_r = 0;
+  bool open = false;
+  for (int g = job.g0; g < job.g1 && !err; ++g) {
+    const DGate gt = job.gates[g];
+    if (gt.op < DG_NCPHASE) {
+      clifford_gate(L, gt.op, gt.q0, gt.q1, n, d, job.dry, job.had + had_base, &nhad, &err);
+      err = wave_max(err);
+      open = true;
+      continue;
+    }
+    TIC(6);
+    // terminal gate of the segment
+    const int q = gt.q0;
+    const bool is_meas = gt.op == DG_MEASURE;
+    SegProg* sp = job.dry ? nullptr : job.prog + seg;
+    const int R = (n + 63) / 64;
+    int rnd = 0;
+    for (int it = 0; it < R; ++it) {
+      int i = it * 64 + lane;
+      rnd |= __ballot(i < n && getb(&L.rx[i * SF_WMAX], q)) != 0ull;
+    }
+    int d_entry = d;
+    if (!job.dry) {
+      if (lane == 0) emit_header(sp, SEG_NONE, is_meas, d, d, nhad, had_base);
+      fit_z4(L, L.acc, d, &sp->E, &err);
+      __syncthreads();
+    }
+    if (!rnd) {
+      uint32_t c0, r;
+      det_functional(L, q, n, d, &c0, &r, &err);
+      if (!job.dry && lane == 0) {
+        if (is_meas) { sp->m_c0 = c0; sp->m_r = r; sp->m_j0 = r ? 31 - __builtin_clz(r) : -1; }
+        else { sp->kind = SEG_DET; sp->det_c = c0; sp->det_r = r; sp->ph_re = gt.c; sp->ph_im = gt.s; }
+      }
+      if (!job.dry) { zero_z4(&sp->B0); zero_z4(&sp->B1); }
+      if (is_meas) {
+        pend = 1; pend_r = r; pend_c0 = (int)c0; pend_j0 = r ? 31 - __builtin_clz(r) : -1;
+        pend_meas = nmeas;
+        if (!job.dry && lane == 0) sp->meas_index = nmeas;
+        nmeas++;
+      }
+    } else {
+      save_old(L, n, d);
+      // d_q: rows anticommuting with Z_q; pivot p = the one with the largest lead
+      if (lane < SF_WMAX) L.dq[lane] = 0;
+      __syncthreads();
+      int p = -1, pl = -1;
+      for (int it = 0; it < R; ++it) {
+        int i = it * 64 + lane;
+        bool has = i < n && getb(&L.rx[i * SF_WMAX], q);
+        uint64_t bb = __ballot(has);
+        if (lane == 0) L.dq[it] = bb;
+        int myl = has ? (int)L.lead[i] : -1;
+        for (int o = 32; o > 0; o >>= 1) {
+          int ol = __shfl_xor(myl, o);
+          myl = ol > myl ? ol : myl;
+        }
+        if (myl > pl) {
+          pl = myl;
+          uint64_t bw = __ballot(has && L.lead[i] == myl);
+          p = it * 64 + __builtin_ctzll(bw);
+        }
+      }
+      __syncthreads();
+      // rows i != p with X/Y at q: row_i <- row_i * row_p
+      if (lane == 0) for (int w = 0; w < SF_WMAX; ++w) { L.rmask[w] = 0; L.cmask[w] = 0; }
+      __syncthreads();
+      for (int it = 0; it < R; ++it) {
+        int i = it * 64 + lane;
+        if (i >= n || i == p || !getb(&L.dq[0], i)) continue;
+        int c = rowprod_sign(&L.rx[i * SF_WMAX], &L.rz[i * SF_WMAX], &L.rx[p * SF_WMAX], &L.rz[p * SF_WMAX]);
+        for (int w = 0; w < W; ++w) { L.rx[i * SF_WMAX + w] ^= L.rx[p * SF_WMAX + w]; L.rz[i * SF_WMAX + w] ^= L.rz[p * SF_WMAX + w]; }
+        atomicOr((unsigned long long*)&L.rmask[i >> 6], 1ull << (i & 63));
+        if (c) atomicOr((unsigned long long*)&L.cmask[i >> 6], 1ull << (i & 63));
+      }
+      __syncthreads();
+      cols_rowsum(L, p, n);
+      apply_rowsum_batch(L, p, d, false);
+      // row p := Z_q with sign x; child x of each element sets phase bit p to x
+      for (int it = 0; it < R; ++it) {
+        const int qq = it * 64 + lane;
+        if (qq < n) {
+          L.cx[qq * SF_WMAX + (p >> 6)] &= ~(1ull << (p & 63));
+          L.cz[qq * SF_WMAX + (p >> 6)] &= ~(1ull << (p & 63));
+        }
+      }
+      __syncthreads();
+      if (lane == 0) {
+        for (int w = 0; w < SF_WMAX; ++w) { L.rx[p * SF_WMAX + w] = 0; L.rz[p * SF_WMAX + w] = 0; L.u[w] = 0; }
+        flipb(&L.rz[p * SF_WMAX], q);
+        flipb(&L.cz[q * SF_WMAX], p);
+        flipb(L.u, p);
+        if (getb(L.s0, p)) flipb(L.s0, p);
+      }
+      __syncthreads();
+      if (lane < d && getb(L.V[lane], p)) flipb(L.V[lane], p);
+      for (int it = 0; it < R; ++it) {
+        int i = it * 64 + lane;
+        if (i >= n) continue;
+        L.lead[i] = (int16_t)row_lead(&L.rx[i * SF_WMAX], &L.rz[i * SF_WMAX], n);
+      }
+      __syncthreads();
+      repair(L, n, d, true, 0);
+      rebuild_index(L, n);
+      const uint32_t delta = span_reduce(L.oV, L.dq, d, nullptr, nullptr);
+      if (!job.dry) {
+        build_beta(L, n);
+        hull_images(L, L.hbN, d, true);
+        // cofactor amplitude factors beta_x(Y) (sampled, fitted)
+        const int P = npoints(d);
+        for (int pt = lane; pt < P; pt += TL) {
+          uint32_t Y = L.Ys[pt];
+          uint64_t so[SF_WMAX], bo[SF_WMAX], bc[SF_WMAX];
+          point_vec(L.os0, L.oV, Y, 0, so);
+          point_vec(L.hbO[0], L.hbO, Y, 1, bo);
+          point_vec(L.hbN[0], L.hbN, Y, 1, bc);
+          int e0 = uexp(L, so, bo, bc);
+          for (int w = 0; w < W; ++w) bc[w] ^= L.hbN[d + 1][w];
+          int e1 = uexp(L, so, bo, bc);
+          if (e0 < 0 || e1 < 0) err = TRK_E_INTERNAL;
+          L.t0[pt] = (uint8_t)(e0 & 3);
+          L.t1[pt] = (uint8_t)(e1 & 3);
+        }
+        __syncthreads();
+        fit_z4(L, L.t0, d, &sp->B0, &err);
+        fit_z4(L, L.t1, d, &sp->B1, &err);
+        __syncthreads();
+      }
+      // hull after the split
+      int kind;
+      if (delta == 0xffffffffu) {
+        kind = SEG_GROW;
+        if (lane == 0) for (int w = 0; w < SF_WMAX; ++w) L.V[d][w] = L.u[w];
+        __syncthreads();
+        d += 1;
+      } else {
+        kind = SEG_PAIR;
+        int j0 = 31 - __builtin_clz(delta);
+        if (lane == 0) {
+          uint64_t v[SF_WMAX], hbv[SF_WMAX];
+          for (int w = 0; w < SF_WMAX; ++w) { v[w] = L.u[w]; hbv[w] = L.hbN[d + 1][w]; }
+          for (int j = 0; j < d; ++j)
+            if (j != j0 && ((delta >> j) & 1u))
+              for (int w = 0; w < SF_WMAX; ++w) { v[w] ^= L.V[j][w]; hbv[w] ^= L.hbN[1 + j][w]; }
+          for (int w = 0; w < SF_WMAX; ++w) { L.V[j0][w] = v[w]; L.hbN[1 + j0][w] = hbv[w]; }
+        }
+        __syncthreads();
+        if (!job.dry && lane == 0) { sp->j0 = j0; sp->delta = delta; }
+      }
+      if (!job.dry && lane == 0) {
+        sp->kind = kind; sp->d_out = d;
+        if (!is_meas) { sp->ph_re = gt.c; sp->ph_im = gt.s; }
+      }
+      if (is_meas) {
+        uint32_t c0, r;
+        det_functional(L, q, n, d, &c0, &r, &err);
+        pend = 1; pend_r = r; pend_c0 = (int)c0; pend_j0 = r ? 31 - __builtin_clz(r) : -1;
+        pend_meas = nmeas;
+        if (!job.dry && lane == 0) { sp->m_c0 = c0; sp->m_r = r; sp->m_j0 = pend_j0; sp->meas_index = nmeas; }
+        nmeas++;
+      }
+    }
+    if (d > dmax) dmax = d;
+    if (d > SF_DMAX - 1) err = TRK_E_DIM;
+    err = wave_max(err);
+    (void)d_entry;
+    TOC(6);
+    // new segment
+    had_base += nhad;
+    nhad = 0;
+    ++seg;
+    open = false;
+    if (is_meas) {
+      if (job.dry) {
+        // outcome-independent part of the filter: the dimension
+        if (pend_r != 0) {
+          uint64_t vj0[SF_WMAX];
+          for (int w = 0; w < SF_WMAX; ++w) vj0[w] = L.V[pend_j0][w];
+          __syncthreads();
+          uint64_t mine[SF_WMAX];
+          if (lane < d) for (int w = 0; w < SF_WMAX; ++w) mine[w] = L.V[lane][w] ^ (((pend_r >> lane) & 1u) ? vj0[w] : 0ull);
+          __syncthreads();
+          if (lane < d && lane != pend_j0) {
+            int dst = lane < pend_j0 ? lane : lane - 1;
+            for (int w = 0; w < SF_WMAX; ++w) L.V[dst][w] = mine[w];
+          }
+          d -= 1;
+          __syncthreads();
+        }
+        pend = 0;
+      } else {
+        // the range ends at a measurement (the host splits ranges there)
+        break;
+      }
+    }
+    if (!job.dry) {
+      for (int pt = lane; pt < SF_PMAX; pt += TL) L.acc[pt] = 0;
+      build_points(L, d);
+    }
+    __syncthreads();
+  }
+  if (open && !job.dry && !err) {
+    SegProg* sp = job.prog + seg;
+    if (lane == 0) emit_header(sp, SEG_NONE, 0, d, d, nhad, had_base);
+    fit_z4(L, L.acc, d, &sp->E, &err);
+    zero_z4(&sp->B0);
+    zero_z4(&sp->B1);
+    ++seg;
+  }
+  __syncthreads();
+  // write back
+  for (int i = lane; i < n * SF_WMAX; i += TL) { st->rx[i] = L.rx[i]; st->rz[i] = L.rz[i]; }
+  if (lane < SF_WMAX) st->s0[lane] = L.s0[lane];
+  if (lane < d) for (int w = 0; w < SF_WMAX; ++w) st->V[lane][w] = L.V[lane][w];
+  if (lane == 0) {
+    st->d = d;
+    st->nmeas = nmeas;
+    st->pend = job.dry ? 0 : pend;
+    st->pend_r = pend_r; st->pend_c0 = pend_c0; st->pend_j0 = pend_j0; st->pend_meas = pend_meas;
+    st->dmax = dmax;
+    if (err && !st->error) st->error = err;
+    L.tc[7] += TCLOCK();
+    for (int k = 0; k < 12; ++k) st->cycles[k] += L.tc[k];
+  }
+}
+
+static __device__ void readout_body(Lds& L, int16_t* rank, const TrackState* st, const uint8_t* outcomes, ReadoutInfo* ri) {
+  const int lane = lane_id();
+  const int n = st->n;
+  int d = st->d;
+  for (int i = lane; i < SF_NMAX * SF_WMAX; i += TL) {
+    L.rx[i] = i < n * SF_WMAX ? st->rx[i] : 0ull;
+    L.rz[i] = i < n * SF_WMAX ? st->rz[i] : 0ull;
+  }
+  if (lane < SF_WMAX) L.s0[lane] = st->s0[lane];
+  if (lane < d) for (int w = 0; w < SF_WMAX; ++w) L.V[lane][w] = st->V[lane][w];
+  __syncthreads();
+  if (st->pend) apply_pending(L, st, outcomes, &d);
+  build_cols(L, n);
+  rebuild_index(L, n);
+  repair(L, n, d, false, 1);
+  rebuild_index(L, n);
+  for (int i = lane; i < n; i += TL) {
+    int r = 0, li = L.lead[i];
+    for (int j = 0; j < n; ++j) r += L.lead[j] < li;
+    rank[i] = (int16_t)r;
+  }
+  __syncthreads();
+  for (int i = lane; i < n; i += TL) {
+    int r = rank[i];
+    for (int w = 0; w < W; ++w) {
+      ri->tab[(size_t)r * 2 * W + w] = L.rx[i * SF_WMAX + w];
+      ri->tab[(size_t)r * 2 * W + W + w] = L.rz[i * SF_WMAX + w];
+    }
+  }
+  // hull in canonical row order
+  if (lane <= d) {
+    const uint64_t* vec = lane < d ? L.V[lane] : L.s0;
+    uint64_t out[SF_WMAX] = {0, 0, 0, 0};
+    for (int i = 0; i < n; ++i)
+      if (getb(vec, i)) flipb(out, rank[i]);
+    for (int w = 0; w < SF_WMAX; ++w) {
+      if (lane < d) ri->V[lane][w] = out[w];
+      else ri->s0[w] = out[w];
+      L.hbN[lane][w] = out[w];
+    }
+  }
+  __syncthreads();
+  // descending echelon pivots of span(V)
+  int nr = 0;
+  span_reduce(L.hbN, nullptr, d, (int*)L.ech, &nr);
+  __syncthreads();
+  if (lane == 0) {
+    int hb[SF_DMAX];
+    for (int a = 0; a < nr && a < SF_DMAX; ++a) hb[a] = (int)L.ech[a];
+    for (int a = 0; a < nr; ++a)  // descending
+      for (int b = a + 1; b < nr; ++b)
+        if (hb[b] > hb[a]) { int t = hb[a]; hb[a] = hb[b]; hb[b] = t; }
+    for (int a = 0; a < nr; ++a) ri->piv[a] = hb[a];
+    ri->n = n; ri->W = W; ri->d = d; ri->pad = nr == d ? 0 : 1;
+  }
+}
+};
+
+// One kernel per word count W (= ceil(n / 64)), so that each gets its own
+// register allocation.
+// One frame: the range given by value.
+template <int W>
+__device__ __forceinline__ void track_w(Lds& L, const TrackJob& job) {
+  if constexpr (W <= 2) Trk<W>::track_body(L, job);
+  else TrkL<W>::track_body(L, job);
+}
+
+template <int W>
+__global__ void __launch_bounds__(TL) sf_track_one(TrackJob one) {
+  __shared__ Lds L;
+  track_w<W>(L, one);
+}
+
+// Many frames of the same W: workgroup b runs jobs[b].
+template <int W>
+__global__ void __launch_bounds__(TL) sf_track_many(const TrackJob* __restrict__ jobs) {
   __shared__ Lds L;
   const TrackJob job = jobs[blockIdx.x];
-  track_dispatch(L, job);
+  track_w<W>(L, job);
 }
 
 // Readout: canonical (fully reduced, pivot-sorted) tableau, the hull in that
@@ -1304,7 +2252,7 @@ sf_readout_track(const TrackState* st, const uint8_t* outcomes, ReadoutInfo* ri)
   switch (st->W) {
     case 1: Trk<1>::readout_body(L, rank, st, outcomes, ri); break;
     case 2: Trk<2>::readout_body(L, rank, st, outcomes, ri); break;
-    case 3: Trk<3>::readout_body(L, rank, st, outcomes, ri); break;
-    default: Trk<4>::readout_body(L, rank, st, outcomes, ri); break;
+    case 3: TrkL<3>::readout_body(L, rank, st, outcomes, ri); break;
+    default: TrkL<4>::readout_body(L, rank, st, outcomes, ri); break;
   }
 }

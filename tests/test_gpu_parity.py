@@ -125,7 +125,7 @@ def test_library_expands_tof_and_cphase(eng):
     run_pair(eng, base, 5)
 
 
-@pytest.mark.parametrize("n", [63, 64, 65, 128, 200, 256])
+@pytest.mark.parametrize("n", [63, 64, 65, 128, 150, 192, 200, 256])
 def test_word_boundaries_and_max_qubits(eng, n):
     circ = wl.random_clifford_t(n, 4 * n, 6, 500 + n, measure_qubits=(0, n - 1, n // 2))
     cz_c = 63 % n if 63 % n != n - 1 else 0
