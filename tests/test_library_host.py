@@ -59,3 +59,13 @@ def test_engine_requires_library(monkeypatch, tmp_path):
     monkeypatch.setattr(sf, "_lib", None)
     with pytest.raises(ImportError):
         sf.load_library(str(tmp_path / "missing.so"))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip())["error"]
