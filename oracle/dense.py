@@ -16,7 +16,7 @@ from __future__ import annotations
 
 import numpy as np
 
-H, S, SDG, X, Y, Z, CNOT, CZ, T, TDG, PHASE, CPHASE, TOF, MEASURE = range(14)
+H, S, SDG, X, Y, Z, CNOT, CZ, T, TDG, PHASE, CPHASE, TOF, MEASURE, CPHASE_D, TOF_D = range(16)
 
 PAULI = {
     "I": np.eye(2, dtype=complex),
@@ -78,9 +78,9 @@ def apply_gate(psi, n, op, q0, q1=0, q2=0, num=0, den=1):
         return apply_controlled(psi, n, [q0], q1, PAULI["X"])
     if op == CZ:
         return apply_controlled(psi, n, [q0], q1, PAULI["Z"])
-    if op == CPHASE:
+    if op in (CPHASE, CPHASE_D):
         return apply_controlled(psi, n, [q0], q1, phase_matrix(np.pi * num / den))
-    if op == TOF:
+    if op in (TOF, TOF_D):
         return apply_controlled(psi, n, [q0, q1], q2, PAULI["X"])
     raise ValueError(op)
 
@@ -312,6 +312,24 @@ def simulate(n: int, gates, init_bits=None, seed: int = 0, trace: bool = False):
         elif op == CPHASE:
             psi = apply_gate(psi, n, op, q0, q1, num=num, den=den)
             raise NotImplementedError("tableau track of CPHASE: expand it first")
+        elif op == CPHASE_D:
+            # the direct form (Eq. 3): cofactor on both qubits, unless theta is
+            # a multiple of pi (identity or CZ)
+            psi = apply_gate(psi, n, op, q0, q1, num=num, den=den)
+            if den < 0:
+                num, den = -num, -den
+            if num % den == 0:
+                if (num // den) % 2:
+                    track.conjugate(CZ, q0, q1)
+            else:
+                track.cofactor(q0)
+                track.cofactor(q1)
+        elif op == TOF_D:
+            # the direct form (Eq. 2): cofactor on both controls; the X on the
+            # target leaves the unsigned matrix as it is
+            psi = apply_gate(psi, n, op, q0, q1, q2)
+            track.cofactor(q0)
+            track.cofactor(q1)
         elif op == MEASURE:
             p1 = qubit_prob1(psi, n, q0)
             u = measurement_u(seed, nmeas)

@@ -28,7 +28,7 @@
 #include <string.h>
 
 enum { OP_H, OP_S, OP_SDG, OP_X, OP_Y, OP_Z, OP_CNOT, OP_CZ, OP_T, OP_TDG,
-       OP_PHASE, OP_CPHASE, OP_TOF, OP_MEASURE };
+       OP_PHASE, OP_CPHASE, OP_TOF, OP_MEASURE, OP_CPHASE_D, OP_TOF_D };
 
 #define PRUNE_EPS 1e-12
 #define FRAGILE_AMP 1e-9
@@ -495,6 +495,75 @@ static int frame_cofactor(frame_t *F, int q, cplx ph1, int apply_phase) {
   return 1;
 }
 
+/* A Pauli gate (X, Y or Z on qubit a) applied only to the elements whose
+ * qubits with Z-row products m1 and m2 both read 1 (both qubits must be
+ * deterministic).  A Pauli leaves the unsigned matrix as it is, so each
+ * selected element gets the five-step factor of the gate and its sign flips;
+ * the others are unchanged.  Used by the direct Toffoli (Eq. 2). */
+static void frame_pauli_masked(frame_t *F, int op, int a, const uint64_t *m1, const uint64_t *m2) {
+  int W = F->W;
+  if (op != OP_X && op != OP_Y && op != OP_Z) abort();
+  tab_t t2; tab_copy(&t2, &F->t);
+  uint64_t f[8];
+  clifford_columns(&t2, op, a, 0, f);
+  tab_free(&t2);
+  bmap_t B; bmap_build(&B, &F->t);
+  uint64_t so[8], sn[8], bo[8], bn[8], bs[2][8];
+  cplx coef[2];
+  for (size_t j = 0; j < F->K; ++j) {
+    memcpy(so, SIG(F, j), W * 8);
+    if (!(parity_and(so, m1, W) & parity_and(so, m2, W))) continue;
+    for (int w = 0; w < W; ++w) sn[w] = so[w] ^ f[w];
+    bstar(&B, so, bo);
+    bstar(&B, sn, bn);
+    int m = gate_row(op, a, 0, bn, W, bs, coef);
+    cplx om = {0, 0};
+    for (int r = 0; r < m; ++r) {
+      cplx u;
+      if (amp_at(&F->t, &B, so, bo, bs[r], &u)) om = cadd(om, cmul(coef[r], u));
+    }
+    double mag = sqrt(om.re * om.re + om.im * om.im);
+    if (fabs(mag - 1.0) > 1e-9) { fprintf(stderr, "oracle: |omega| = %g\n", mag); abort(); }
+    F->amp[j] = cmul(F->amp[j], om);
+    memcpy(SIG(F, j), sn, W * 8);
+  }
+  frame_merge(F);
+  bmap_free(&B);
+}
+
+/* Direct controlled phase (Eq. 3): cofactor on c, then on t, then the phase
+ * exp(i theta) on the elements where both read 1.  theta a multiple of pi is
+ * Clifford (identity or CZ). */
+static int frame_cphase_direct(frame_t *F, int c, int t, int64_t num, int64_t den) {
+  if (den < 0) { num = -num; den = -den; }
+  if (num % den == 0) {
+    if ((((num / den) % 2) + 2) % 2) frame_clifford(F, OP_CZ, c, t);
+    return 0;
+  }
+  const cplx one = {1.0, 0.0};
+  frame_cofactor(F, c, one, 0);
+  frame_cofactor(F, t, one, 0);
+  uint64_t rc[8], rt[8];
+  if (!zq_rows(&F->t, c, rc) || !zq_rows(&F->t, t, rt)) abort();
+  double th = M_PI * (double)num / (double)den;
+  cplx ph = {cos(th), sin(th)};
+  for (size_t j = 0; j < F->K; ++j)
+    if (parity_and(SIG(F, j), rc, F->W) & parity_and(SIG(F, j), rt, F->W)) F->amp[j] = cmul(F->amp[j], ph);
+  return 0;
+}
+
+/* Direct Toffoli (Eq. 2): cofactor on both controls, then X on the target of
+ * the elements where both controls read 1. */
+static int frame_toffoli_direct(frame_t *F, int c1, int c2, int t) {
+  const cplx one = {1.0, 0.0};
+  frame_cofactor(F, c1, one, 0);
+  frame_cofactor(F, c2, one, 0);
+  uint64_t r1[8], r2[8];
+  if (!zq_rows(&F->t, c1, r1) || !zq_rows(&F->t, c2, r2)) abort();
+  frame_pauli_masked(F, OP_X, t, r1, r2);
+  return 0;
+}
+
 /* Pairwise sum over canonical order, padded with +0.0 to a power of two. */
 static double tree_sum(double *v, size_t K) {
   size_t P = 1;
@@ -637,6 +706,12 @@ int ofr_apply(frame_t *F, int op, int q0, int q1, int q2, int64_t num, int64_t d
       }
       return 0;
     case OP_MEASURE: return frame_measure(F, q0);
+    case OP_CPHASE_D:
+      if (den == 0 || q1 < 0 || q1 >= n || q1 == q0) return -1;
+      return frame_cphase_direct(F, q0, q1, num, den);
+    case OP_TOF_D:
+      if (q1 < 0 || q1 >= n || q2 < 0 || q2 >= n || q1 == q0 || q2 == q0 || q2 == q1) return -1;
+      return frame_toffoli_direct(F, q0, q1, q2);
   }
   return -1;
 }

@@ -18,9 +18,9 @@ from __future__ import annotations
 import numpy as np
 
 # Operation codes: an interface shared with include/sframe.h (same numbers).
-H, S, SDG, X, Y, Z, CNOT, CZ, T, TDG, PHASE, CPHASE, TOF, MEASURE = range(14)
+H, S, SDG, X, Y, Z, CNOT, CZ, T, TDG, PHASE, CPHASE, TOF, MEASURE, CPHASE_D, TOF_D = range(16)
 OP_NAMES = ["H", "S", "SDG", "X", "Y", "Z", "CNOT", "CZ", "T", "TDG", "PHASE",
-            "CPHASE", "TOF", "MEASURE"]
+            "CPHASE", "TOF", "MEASURE", "CPHASE_D", "TOF_D"]
 
 GATE_DTYPE = np.dtype([("op", "<u4"), ("q0", "<u4"), ("q1", "<u4"), ("q2", "<u4"),
                        ("num", "<i8"), ("den", "<i8")])
@@ -87,6 +87,8 @@ class Circuit:
     def tdg(self, q): return self.add(TDG, q)
     def phase(self, q, num, den): return self.add(PHASE, q, 0, 0, num, den)
     def measure(self, q): return self.add(MEASURE, q)
+    def cphase_direct(self, c, t, num, den): return self.add(CPHASE_D, c, t, 0, num, den)
+    def toffoli_direct(self, c1, c2, t): return self.add(TOF_D, c1, c2, t)
 
     def cphase_decomposed(self, c, t, num, den):
         """Controlled phase diag(1,1,1,e^{i*pi*num/den}) as three phase gates and two CNOTs.
@@ -245,13 +247,14 @@ def config3(trial: int) -> Circuit:
 # QFT and Cuccaro adder (configuration 5)
 # ----------------------------------------------------------------------------
 
-def qft(n: int, x_bits, max_k=None, name: str = "qft") -> Circuit:
+def qft(n: int, x_bits, max_k=None, name: str = "qft", direct: bool = False) -> Circuit:
     """QFT circuit without the final swaps on the basis state |x_bits>.
 
     Qubit j gets H and then controlled rotations R_k = diag(1, e^{2 pi i/2^k})
     from qubits j+1.., with k = distance + 1; rotations with k > max_k are
     dropped (approximate QFT).  Each controlled rotation is written as three
-    phase gates and two CNOTs.
+    phase gates and two CNOTs, or with ``direct`` as one direct controlled
+    phase (double cofactor).
     """
     c = Circuit(n, init_bits=x_bits, name=name)
     for j in range(n):
@@ -261,16 +264,20 @@ def qft(n: int, x_bits, max_k=None, name: str = "qft") -> Circuit:
             if max_k is not None and k > max_k:
                 continue
             # 2*pi/2^k = pi * 1/2^(k-1)
-            c.cphase_decomposed(ctl, j, 1, 1 << (k - 1))
+            if direct:
+                c.cphase_direct(ctl, j, 1, 1 << (k - 1))
+            else:
+                c.cphase_decomposed(ctl, j, 1, 1 << (k - 1))
     return c
 
 
-def cuccaro_adder(m: int, a_bits=None, b_bits=None, superpose=True, name="cuccaro") -> Circuit:
+def cuccaro_adder(m: int, a_bits=None, b_bits=None, superpose=True, name="cuccaro",
+                  direct: bool = False) -> Circuit:
     """Cuccaro ripple-carry adder of two m-bit registers (2m+2 qubits).
 
     Layout: qubit 0 is the ancilla c0, qubits 1+2i and 2+2i hold b_i and a_i,
     qubit 2m+1 is the carry z.  With ``superpose`` every input qubit first gets
-    an H.  Toffolis are 7-T networks.  On basis inputs the b register ends up
+    an H.  Toffolis are 7-T networks, or direct (double cofactor) with ``direct``.  On basis inputs the b register ends up
     holding a+b mod 2^m and z the carry out.
     """
     nq = 2 * m + 2
@@ -288,11 +295,13 @@ def cuccaro_adder(m: int, a_bits=None, b_bits=None, superpose=True, name="cuccar
             c.h(A(i))
             c.h(B(i))
 
+    tof = c.toffoli_direct if direct else c.toffoli_7t
+
     def maj(x, y, w):
-        c.cnot(w, y); c.cnot(w, x); c.toffoli_7t(x, y, w)
+        c.cnot(w, y); c.cnot(w, x); tof(x, y, w)
 
     def uma(x, y, w):
-        c.toffoli_7t(x, y, w); c.cnot(w, x); c.cnot(x, y)
+        tof(x, y, w); c.cnot(w, x); c.cnot(x, y)
 
     maj(0, B(0), A(0))
     for i in range(1, m):

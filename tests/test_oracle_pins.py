@@ -422,3 +422,88 @@ def test_measurement_outcomes_follow_seeded_coin():
     c = wl.random_clifford_t(6, 50, 3, 77, measure_qubits=range(6))
     for seed in range(5):
         oracle_vs_dense(c, seed=seed, every_gate=False)
+
+
+# ---------------------------------------------------------------------------
+# Direct controlled phase and Toffoli (double cofactor, Eqs. 2 and 3)
+# ---------------------------------------------------------------------------
+def _direct_mix(seed, n, n_gates=14):
+    """Random Clifford/T circuit on n qubits with direct CPHASE and Toffoli
+    gates and a measurement sprinkled in."""
+    rng = np.random.default_rng(seed)
+    c = wl.random_clifford_t(n, n_gates, 1, 900 + seed)
+    extra = []
+    for _ in range(3):
+        a, b, t = (int(v) for v in rng.permutation(n)[:3])
+        extra.append((wl.TOF_D, a, b, t, 0, 1))
+        num, den = [(1, 2), (1, 4), (-3, 8), (1, 1), (2, 1), (5, 6)][int(rng.integers(6))]
+        extra.append((wl.CPHASE_D, a, t, 0, num, den))
+    extra.append((wl.MEASURE, int(rng.integers(n)), 0, 0, 0, 1))
+    for g in extra:
+        c.gates.insert(int(rng.integers(0, len(c.gates) + 1)), g)
+    c.name = f"direct{seed}"
+    return c
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_direct_gates_vs_dense(seed):
+    """The direct forms give the expansion of the exact state in the basis of
+    the matrix the double cofactor leaves, gate by gate."""
+    oracle_vs_dense(_direct_mix(seed, 3 + seed % 4), seed=seed)
+
+
+def test_direct_and_decomposed_forms_give_the_same_state():
+    for trial in range(6):
+        base = wl.random_clifford_t(5, 16, 2, 400 + trial)
+        for direct, dec in (((wl.TOF_D, 1, 4, 2, 0, 1), (wl.TOF, 1, 4, 2, 0, 1)),
+                            ((wl.CPHASE_D, 3, 0, 0, 1, 4), (wl.CPHASE, 3, 0, 0, 1, 4))):
+            f1, f2 = OracleFrame(5), OracleFrame(5)
+            f1.run(base.array()); f2.run(base.array())
+            f1.apply(*direct); f2.apply(*dec)
+            assert np.allclose(_state_from_frame(f1), _state_from_frame(f2), atol=1e-11)
+
+
+def test_direct_toffoli_grows_a_frame_at_most_fourfold():
+    """Two cofactors and a controlled Pauli: at most 4x growth per Toffoli
+    (against up to 2^7 for the 7-T network)."""
+    c = wl.cuccaro_adder(3, direct=True)
+    f = OracleFrame(c.n, c.init_bits)
+    for g in c.gates:
+        before = f.size
+        f.apply(*g)
+        if g[0] == wl.TOF_D:
+            assert f.size <= 4 * before
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_cuccaro_direct_adds_basis_inputs(m):
+    rng = np.random.default_rng(50 + m)
+    for _ in range(3):
+        a = rng.integers(0, 2, size=m).tolist()
+        b = rng.integers(0, 2, size=m).tolist()
+        c = wl.cuccaro_adder(m, a, b, superpose=False, direct=True)
+        f = OracleFrame(c.n, c.init_bits)
+        f.run(c.array())
+        assert f.size == 1                       # controls on basis inputs are deterministic
+        psi = _state_from_frame(f)
+        idx = int(np.argmax(np.abs(psi)))
+        bits = [(idx >> (c.n - 1 - q)) & 1 for q in range(c.n)]
+        A = sum(a[i] << i for i in range(m)); B = sum(b[i] << i for i in range(m))
+        assert sum(bits[1 + 2 * i] << i for i in range(m)) == (A + B) % (1 << m)
+        assert bits[2 * m + 1] == (A + B) >> m
+
+
+@pytest.mark.parametrize("n", [2, 3, 5])
+def test_qft_direct_matches_closed_form(n):
+    x = [1] * n
+    c = wl.qft(n, x, direct=True)
+    f = OracleFrame(n, x)
+    f.run(c.array())
+    psi = _state_from_frame(f)
+    # Eq. 4 with the qubit order reversed (no final swaps): prod_j (|0> + e^{2 pi i 0.x_j..x_n}|1>)/sqrt2
+    X = sum(b << (n - 1 - q) for q, b in enumerate(x))
+    ref = np.zeros(1 << n, dtype=complex)
+    for y in range(1 << n):
+        yr = int(format(y, f"0{n}b")[::-1], 2)
+        ref[y] = np.exp(2j * np.pi * X * yr / (1 << n)) / np.sqrt(1 << n)
+    assert np.allclose(psi, ref, atol=1e-11)
