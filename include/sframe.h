@@ -57,7 +57,8 @@ typedef enum {
   SF_E_CANCELLED = 7
 } sf_status;
 
-/* Gate codes.  theta = pi * theta_num / theta_den for SF_PHASE / SF_CPHASE. */
+/* Gate codes.  theta = pi * theta_num / theta_den for SF_PHASE / SF_CPHASE /
+ * SF_CPHASE_D. */
 typedef enum {
   SF_H = 0, SF_S = 1, SF_SDG = 2, SF_X = 3, SF_Y = 4, SF_Z = 5,
   SF_CNOT = 6,    /* q0 control, q1 target */
@@ -68,7 +69,13 @@ typedef enum {
                      three phase gates and two CNOTs */
   SF_TOF = 12,    /* Toffoli (q0,q1 controls, q2 target); expanded at load into
                      the 7-T Clifford+T network */
-  SF_MEASURE = 13 /* Z-basis measurement of q0 */
+  SF_MEASURE = 13, /* Z-basis measurement of q0 */
+  SF_CPHASE_D = 14, /* diag(1,1,1,e^{i theta}) on (q0,q1), direct form (Eq. 3):
+                       cofactor on q0 and q1, then the phase on the elements
+                       where both read 1; theta a multiple of pi is I or CZ */
+  SF_TOF_D = 15     /* Toffoli (q0,q1 controls, q2 target), direct form (Eq. 2):
+                       cofactor on both controls, then X on q2 for the elements
+                       where both read 1 */
 } sf_op;
 
 typedef struct {

@@ -246,9 +246,12 @@ extern "C" const char* sf_last_error(const sf_ctx* ctx) { return ctx ? ctx->err 
 // ---------------------------------------------------------------------------
 // Circuit loading
 // ---------------------------------------------------------------------------
+// device gates that end a segment
+static bool is_terminal(int op) { return op >= DG_NCPHASE; }
+
 static DGate dg(int op, int q0, int q1 = 0) {
   DGate g;
-  g.op = op; g.q0 = q0; g.q1 = q1; g.pad = 0; g.c = 1.0; g.s = 0.0;
+  g.op = op; g.q0 = q0; g.q1 = q1; g.q2 = 0; g.c = 1.0; g.s = 0.0;
   return g;
 }
 
@@ -341,6 +344,37 @@ extern "C" sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n, const sf_gate* gat
         c->g.push_back(dg(DG_MEASURE, (int)G.q0));
         c->n_meas++;
         break;
+      case SF_CPHASE_D: {
+        if (!qok(G.q0, n) || !qok(G.q1, n)) return bad("qubit out of range");
+        if (G.q0 == G.q1) return bad("control equals target");
+        if (G.theta_den == 0) return bad("zero angle denominator");
+        int64_t num = G.theta_num, den = G.theta_den;
+        if (den < 0) { num = -num; den = -den; }
+        if (num % den == 0) {  // theta a multiple of pi: identity or CZ
+          if (((num / den) % 2 + 2) % 2) c->g.push_back(dg(DG_CZ, (int)G.q0, (int)G.q1));
+          break;
+        }
+        // cofactor on both qubits (a split with phase 1), then the phase on
+        // the elements where both read 1
+        c->g.push_back(dg(DG_NCPHASE, (int)G.q0));
+        c->g.push_back(dg(DG_NCPHASE, (int)G.q1));
+        DGate g = dg(DG_CPH2, (int)G.q0, (int)G.q1);
+        const double th = M_PI * (double)num / (double)den;
+        g.c = cos(th);
+        g.s = sin(th);
+        c->g.push_back(g);
+        break;
+      }
+      case SF_TOF_D: {
+        if (!qok(G.q0, n) || !qok(G.q1, n) || !qok(G.q2, n)) return bad("qubit out of range");
+        if (G.q0 == G.q1 || G.q0 == G.q2 || G.q1 == G.q2) return bad("repeated qubit");
+        c->g.push_back(dg(DG_NCPHASE, (int)G.q0));
+        c->g.push_back(dg(DG_NCPHASE, (int)G.q1));
+        DGate g = dg(DG_CX2, (int)G.q0, (int)G.q1);
+        g.q2 = (int)G.q2;
+        c->g.push_back(g);
+        break;
+      }
       default:
         return bad("unknown operation");
     }
@@ -355,7 +389,7 @@ extern "C" sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n, const sf_gate* gat
     for (size_t i = 0; i < c->g.size(); ++i) {
       int op = c->g[i].op;
       if (op == DG_H) ++had;
-      if (op == DG_NCPHASE || op == DG_MEASURE) { ++segs; open = false; }
+      if (is_terminal(op)) { ++segs; open = false; }
       else open = true;
       if (op == DG_MEASURE || i + 1 == c->g.size()) {
         int s = segs + (open ? 1 : 0);
@@ -567,7 +601,7 @@ static sf_status run_gates(sf_state* s, const DGate* dgates, const DGate* hg, si
   bool open = false, meas_last = false;
   for (size_t i = a; i < b; ++i) {
     int op = hg[i].op;
-    if (op == DG_NCPHASE || op == DG_MEASURE) { ++nseg; open = false; meas_last = op == DG_MEASURE; }
+    if (is_terminal(op)) { ++nseg; open = false; meas_last = op == DG_MEASURE; }
     else { open = true; meas_last = false; }
   }
   if (open) ++nseg;
@@ -865,9 +899,9 @@ static void plan_range(const sf_circuit* c, const Progress& pr, size_t* a, size_
   int terms = 0;
   while (o < c->orig_end.size()) {
     size_t end = c->orig_end[o];
-    for (size_t i = e; i < end; ++i) terms += c->g[i].op == DG_NCPHASE;
+    for (size_t i = e; i < end; ++i) terms += is_terminal(c->g[i].op) && c->g[i].op != DG_MEASURE;
     bool meas = end > e && c->g[end - 1].op == DG_MEASURE;
-    bool cut = cap > 0 && terms >= cap && end > e && c->g[end - 1].op == DG_NCPHASE;
+    bool cut = cap > 0 && terms >= cap && end > e && is_terminal(c->g[end - 1].op);
     e = end;
     ++o;
     if (meas || cut) break;
@@ -878,7 +912,7 @@ static void plan_range(const sf_circuit* c, const Progress& pr, size_t* a, size_
   bool open = false, ml = false;
   for (size_t i = *a; i < *b; ++i) {
     int op = c->g[i].op;
-    if (op == DG_NCPHASE || op == DG_MEASURE) { ++ns; open = false; ml = op == DG_MEASURE; }
+    if (is_terminal(op)) { ++ns; open = false; ml = op == DG_MEASURE; }
     else { open = true; ml = false; }
   }
   if (open) ++ns;

@@ -89,6 +89,11 @@ __device__ __forceinline__ double2 child(double2 a, const Z4Q* __restrict__ B, u
   return make_double2(__dmul_rn(r.x, s), __dmul_rn(r.y, s));
 }
 
+// both control functionals of a direct controlled step read 1
+__device__ __forceinline__ bool cond2(const SegProg* __restrict__ sp, uint32_t Y) {
+  return ((sp->det_c ^ (uint32_t)__popc(sp->det_r & Y)) & (sp->det2_c ^ (uint32_t)__popc(sp->det2_r & Y)) & 1u) != 0;
+}
+
 __device__ __forceinline__ uint32_t insert_zero(uint64_t r, int j) {
   uint64_t lo = r & ((1ull << j) - 1ull);
   return (uint32_t)(lo | ((r >> j) << (j + 1)));
@@ -128,14 +133,57 @@ __device__ __forceinline__ void seg_body(const SegProg* __restrict__ sp, const G
       amp[Y] = prune(c0);
       amp[Y + N] = prune(c1);
     }
+  } else if (kind == SEG_CX2P) {
+    // elements with both controls 1 move to Y ^ delta with the factor
+    // i^{B0(Y)}; a pair (Y, Y ^ delta) has equal control values, so the move
+    // is a swap (delta = 0: a phase in place)
+    const int j0 = sp->j0;
+    const uint32_t delta = sp->delta;
+    if (delta == 0) {
+      for (uint64_t Y = tid; Y < N; Y += stride) {
+        double2 a = amp[Y];
+        if (a.x == 0.0 && a.y == 0.0) continue;
+        a = rot8(a, seg_phase(sp, had, (uint32_t)Y));
+        if (cond2(sp, (uint32_t)Y)) a = rot8(a, 2 * evalZ4(&sp->B0, (uint32_t)Y));
+        amp[Y] = a;
+      }
+    } else {
+      for (uint64_t r = tid; r < (N >> 1); r += stride) {
+        const uint32_t Y = insert_zero(r, j0);
+        const uint32_t Yd = Y ^ delta;
+        double2 a = rot8(amp[Y], seg_phase(sp, had, Y));
+        double2 b = rot8(amp[Yd], seg_phase(sp, had, Yd));
+        if (cond2(sp, Y)) {
+          amp[Y] = rot8(b, 2 * evalZ4(&sp->B0, Yd));
+          amp[Yd] = rot8(a, 2 * evalZ4(&sp->B0, Y));
+        } else {
+          amp[Y] = a;
+          amp[Yd] = b;
+        }
+      }
+    }
+  } else if (kind == SEG_CX2G) {
+    // elements with both controls 1 move to the new half Y + 2^d
+    for (uint64_t Y = tid; Y < N; Y += stride) {
+      double2 a = rot8(amp[Y], seg_phase(sp, had, (uint32_t)Y));
+      const double2 z = make_double2(0.0, 0.0);
+      if (cond2(sp, (uint32_t)Y)) {
+        amp[Y] = z;
+        amp[Y + N] = rot8(a, 2 * evalZ4(&sp->B0, (uint32_t)Y));
+      } else {
+        amp[Y] = a;
+        amp[Y + N] = z;
+      }
+    }
   } else {
     const uint32_t dc = sp->det_c, dr = sp->det_r;
-    const bool det = kind == SEG_DET;
+    const bool det = kind == SEG_DET, det2 = kind == SEG_DET2;
     for (uint64_t Y = tid; Y < N; Y += stride) {
       double2 a = amp[Y];
       if (a.x == 0.0 && a.y == 0.0) continue;
       a = rot8(a, seg_phase(sp, had, (uint32_t)Y));
       if (det && ((dc ^ (uint32_t)__popc(dr & (uint32_t)Y)) & 1u)) a = cmul(a, pre, pim);
+      if (det2 && cond2(sp, (uint32_t)Y)) a = cmul(a, pre, pim);
       amp[Y] = a;
     }
   }

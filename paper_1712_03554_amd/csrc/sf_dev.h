@@ -20,10 +20,15 @@
 #define SF_PMAX (1 + SF_DMAX + SF_DMAX * (SF_DMAX - 1) / 2)
 
 // device gate codes (after load-time rewriting)
-enum { DG_H = 0, DG_S, DG_SDG, DG_X, DG_Y, DG_Z, DG_CNOT, DG_CZ, DG_NCPHASE, DG_MEASURE };
+// DG_NCPHASE and later codes end a segment: a non-Clifford phase (a split),
+// a measurement, and the last step of a direct controlled phase (DG_CPH2:
+// phase on the elements where q0 and q1 read 1) or direct Toffoli (DG_CX2: X
+// on q2 for the elements where q0 and q1 read 1), both after cofactors on
+// their two controls.
+enum { DG_H = 0, DG_S, DG_SDG, DG_X, DG_Y, DG_Z, DG_CNOT, DG_CZ, DG_NCPHASE, DG_MEASURE, DG_CPH2, DG_CX2 };
 
 struct DGate {            // 32 bytes
-  int32_t op, q0, q1, pad;
+  int32_t op, q0, q1, q2;
   double c, s;            // exp(i theta) of a non-Clifford phase gate
 };
 
@@ -40,11 +45,15 @@ struct GF2Q {
   uint32_t Q[32];
 };
 
-enum { SEG_NONE = 0, SEG_DET = 1, SEG_GROW = 2, SEG_PAIR = 3 };
+enum { SEG_NONE = 0, SEG_DET = 1, SEG_GROW = 2, SEG_PAIR = 3,
+       SEG_DET2 = 4,   // phase on the elements where two qubit functionals read 1
+       SEG_CX2P = 5,   // those elements move to Y ^ delta (delta = 0: stay) with factor i^{B0(Y)}
+       SEG_CX2G = 6 }; // those elements move to Y + 2^d with factor i^{B0(Y)}
 
 // Program of one segment: a run of Clifford gates (folded phase E plus one
 // GF(2) term per Hadamard whose support size is unchanged) followed by at most
-// one non-Clifford phase gate or measurement.
+// one terminal step (non-Clifford phase gate, measurement, or the last step of
+// a direct controlled phase / Toffoli).
 struct SegProg {
   int32_t kind;        // SEG_*
   int32_t is_meas;
@@ -59,6 +68,7 @@ struct SegProg {
   int32_t m_j0;            // highest set bit of m_r, or -1
   int32_t meas_index;
   int32_t nhad_total;      // odd part count (number of Hadamard half-steps)
+  uint32_t det2_c, det2_r; // SEG_DET2 / SEG_CX2*: second qubit functional
   int32_t pad;
   double ph_re, ph_im;     // exp(i theta) on the |1> branch
   Z4Q E;                   // folded Clifford phase exponent (units of i)

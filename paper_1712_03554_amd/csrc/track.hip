@@ -141,6 +141,7 @@ __device__ void emit_header(SegProg* sp, int kind, int is_meas, int d, int d_out
   sp->nhad = nhad; sp->had_off = had_off; sp->nhad_total = nhad;
   sp->j0 = -1; sp->delta = 0; sp->det_c = 0; sp->det_r = 0;
   sp->m_c0 = 0; sp->m_r = 0; sp->m_j0 = -1; sp->meas_index = -1; sp->pad = 0;
+  sp->det2_c = 0; sp->det2_r = 0;
   sp->ph_re = 1.0; sp->ph_im = 0.0;
 }
 
@@ -940,6 +941,90 @@ static __device__ void det_functional(Lds& L, int q, int n, int d, uint32_t* c0,
 // Filter step of a measurement on the hull: keep sigma(Y) with
 // c0 ^ parity(r & Y) == outcome, i.e. fix coordinate j0 and drop it.
 
+// ---------------------------------------------------------------------------
+// Last step of a direct controlled phase / Toffoli (Eqs. 2 and 3): after the
+// cofactors on the two controls both are deterministic, with values
+// f1(Y) = c1 ^ parity(r1 & Y) and f2(Y) = c2 ^ parity(r2 & Y).  DG_CPH2 puts
+// the phase on the elements with f1 & f2.  DG_CX2 applies X on q2 to them: X
+// leaves the unsigned matrix as it is and flips the signs of the rows with a z
+// bit at q2 (mask f), so such an element moves from sigma(Y) to sigma(Y) ^ f
+// with the factor omega(Y) = psi(M, sigma(Y))(b*(sigma(Y) ^ f) ^ e_q2), a Z4
+// quadratic form in Y (sampled and fitted as for the Clifford gates).  If f
+// is in span(V) (f = sum of V[j], j in delta) the element moves to Y ^ delta,
+// which has the same control values (f has no bit on the controls' Z rows);
+// otherwise the hull grows by the coordinate V[d] = f.
+// ---------------------------------------------------------------------------
+static __device__ void terminal_controlled(Lds& L, const TrackJob& job, const DGate& gt, int seg, int nhad,
+                                           int had_base, int n, int* dptr, int* err) {
+  const int lane = lane_id();
+  int d = *dptr;
+  SegProg* sp = job.dry ? nullptr : job.prog + seg;
+  if (!job.dry) {
+    if (lane == 0) emit_header(sp, SEG_DET2, 0, d, d, nhad, had_base);
+    fit_z4(L, L.acc, d, &sp->E, err);
+    __syncthreads();
+  }
+  uint32_t c1, r1, c2, r2;
+  det_functional(L, gt.q0, n, d, &c1, &r1, err);
+  det_functional(L, gt.q1, n, d, &c2, &r2, err);
+  if (!job.dry && lane == 0) { sp->det_c = c1; sp->det_r = r1; sp->det2_c = c2; sp->det2_r = r2; }
+  if (gt.op == DG_CPH2) {
+    if (!job.dry) {
+      if (lane == 0) { sp->kind = SEG_DET2; sp->ph_re = gt.c; sp->ph_im = gt.s; }
+      zero_z4(&sp->B0);
+      zero_z4(&sp->B1);
+    }
+    __syncthreads();
+    return;
+  }
+  const int t = gt.q2;
+  const int R = (n + 63) / 64;
+  for (int it = 0; it < SF_WMAX; ++it) {
+    const int i = it * 64 + lane;
+    const uint64_t b = __ballot(it < R && i < n && getb(&L.rz[i * SF_WMAX], t));
+    if (lane == 0) L.dq[it] = b;
+  }
+  __syncthreads();
+  save_old(L, n, d);
+  const uint32_t delta = span_reduce(L.oV, L.dq, d, nullptr, nullptr);
+  if (!job.dry) {
+    // b*(f): the images are linear, so b*(sigma(Y) ^ f) = b*(sigma(Y)) ^ b*(f)
+    if (lane == 0) bimage(L, L.dq, L.hbN[d + 1]);
+    __syncthreads();
+    const int P = npoints(d);
+    for (int pt = lane; pt < P; pt += TL) {
+      const uint32_t Y = L.Ys[pt];
+      uint64_t so[SF_WMAX], bo[SF_WMAX], src[SF_WMAX];
+      point_vec(L.os0, L.oV, Y, 0, so);
+      point_vec(L.hbO[0], L.hbO, Y, 1, bo);
+      for (int w = 0; w < W; ++w) src[w] = bo[w] ^ L.hbN[d + 1][w];
+      flipb(src, t);
+      const int e = uexp(L, so, bo, src);
+      if (e < 0) *err = TRK_E_INTERNAL;
+      L.t0[pt] = (uint8_t)(e & 3);
+    }
+    __syncthreads();
+    fit_z4(L, L.t0, d, &sp->B0, err);
+    zero_z4(&sp->B1);
+    __syncthreads();
+  }
+  if (delta != 0xffffffffu) {
+    if (!job.dry && lane == 0) {
+      sp->kind = SEG_CX2P;
+      sp->delta = delta;
+      sp->j0 = delta ? 31 - __builtin_clz(delta) : -1;
+      sp->d_out = d;
+    }
+  } else {
+    if (lane == 0)
+      for (int w = 0; w < SF_WMAX; ++w) L.V[d][w] = L.dq[w];
+    d += 1;
+    if (!job.dry && lane == 0) { sp->kind = SEG_CX2G; sp->d_out = d; }
+  }
+  __syncthreads();
+  *dptr = d;
+}
+
 static __device__ void track_body(Lds& L, const TrackJob& job) {
   TrackState* st = job.st;
   const int lane = lane_id();
@@ -994,6 +1079,26 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
     // terminal gate of the segment: works on the LDS copy of the tableau
     regs_store(L, TB, n, true);
     __syncthreads();
+    if (gt.op == DG_CPH2 || gt.op == DG_CX2) {
+      terminal_controlled(L, job, gt, seg, nhad, had_base, n, &d, &err);
+      if (d > dmax) dmax = d;
+      if (d > SF_DMAX - 1) err = TRK_E_DIM;
+      err = wave_max(err);
+      errw = err;
+      __syncthreads();
+      regs_load(L, TB, n);
+      TOC(6);
+      had_base += nhad;
+      nhad = 0;
+      ++seg;
+      open = false;
+      if (!job.dry) {
+        for (int pt = lane; pt < SF_PMAX; pt += TL) L.acc[pt] = 0;
+        build_points(L, d);
+      }
+      __syncthreads();
+      continue;
+    }
     const int q = gt.q0;
     const bool is_meas = gt.op == DG_MEASURE;
     SegProg* sp = job.dry ? nullptr : job.prog + seg;
@@ -1906,6 +2011,90 @@ static __device__ void det_functional(Lds& L, int q, int n, int d, uint32_t* c0,
 // Filter step of a measurement on the hull: keep sigma(Y) with
 // c0 ^ parity(r & Y) == outcome, i.e. fix coordinate j0 and drop it.
 
+// ---------------------------------------------------------------------------
+// Last step of a direct controlled phase / Toffoli (Eqs. 2 and 3): after the
+// cofactors on the two controls both are deterministic, with values
+// f1(Y) = c1 ^ parity(r1 & Y) and f2(Y) = c2 ^ parity(r2 & Y).  DG_CPH2 puts
+// the phase on the elements with f1 & f2.  DG_CX2 applies X on q2 to them: X
+// leaves the unsigned matrix as it is and flips the signs of the rows with a z
+// bit at q2 (mask f), so such an element moves from sigma(Y) to sigma(Y) ^ f
+// with the factor omega(Y) = psi(M, sigma(Y))(b*(sigma(Y) ^ f) ^ e_q2), a Z4
+// quadratic form in Y (sampled and fitted as for the Clifford gates).  If f
+// is in span(V) (f = sum of V[j], j in delta) the element moves to Y ^ delta,
+// which has the same control values (f has no bit on the controls' Z rows);
+// otherwise the hull grows by the coordinate V[d] = f.
+// ---------------------------------------------------------------------------
+static __device__ void terminal_controlled(Lds& L, const TrackJob& job, const DGate& gt, int seg, int nhad,
+                                           int had_base, int n, int* dptr, int* err) {
+  const int lane = lane_id();
+  int d = *dptr;
+  SegProg* sp = job.dry ? nullptr : job.prog + seg;
+  if (!job.dry) {
+    if (lane == 0) emit_header(sp, SEG_DET2, 0, d, d, nhad, had_base);
+    fit_z4(L, L.acc, d, &sp->E, err);
+    __syncthreads();
+  }
+  uint32_t c1, r1, c2, r2;
+  det_functional(L, gt.q0, n, d, &c1, &r1, err);
+  det_functional(L, gt.q1, n, d, &c2, &r2, err);
+  if (!job.dry && lane == 0) { sp->det_c = c1; sp->det_r = r1; sp->det2_c = c2; sp->det2_r = r2; }
+  if (gt.op == DG_CPH2) {
+    if (!job.dry) {
+      if (lane == 0) { sp->kind = SEG_DET2; sp->ph_re = gt.c; sp->ph_im = gt.s; }
+      zero_z4(&sp->B0);
+      zero_z4(&sp->B1);
+    }
+    __syncthreads();
+    return;
+  }
+  const int t = gt.q2;
+  const int R = (n + 63) / 64;
+  for (int it = 0; it < SF_WMAX; ++it) {
+    const int i = it * 64 + lane;
+    const uint64_t b = __ballot(it < R && i < n && getb(&L.rz[i * SF_WMAX], t));
+    if (lane == 0) L.dq[it] = b;
+  }
+  __syncthreads();
+  save_old(L, n, d);
+  const uint32_t delta = span_reduce(L.oV, L.dq, d, nullptr, nullptr);
+  if (!job.dry) {
+    // b*(f): the images are linear, so b*(sigma(Y) ^ f) = b*(sigma(Y)) ^ b*(f)
+    if (lane == 0) bimage(L, L.dq, L.hbN[d + 1]);
+    __syncthreads();
+    const int P = npoints(d);
+    for (int pt = lane; pt < P; pt += TL) {
+      const uint32_t Y = L.Ys[pt];
+      uint64_t so[SF_WMAX], bo[SF_WMAX], src[SF_WMAX];
+      point_vec(L.os0, L.oV, Y, 0, so);
+      point_vec(L.hbO[0], L.hbO, Y, 1, bo);
+      for (int w = 0; w < W; ++w) src[w] = bo[w] ^ L.hbN[d + 1][w];
+      flipb(src, t);
+      const int e = uexp(L, so, bo, src);
+      if (e < 0) *err = TRK_E_INTERNAL;
+      L.t0[pt] = (uint8_t)(e & 3);
+    }
+    __syncthreads();
+    fit_z4(L, L.t0, d, &sp->B0, err);
+    zero_z4(&sp->B1);
+    __syncthreads();
+  }
+  if (delta != 0xffffffffu) {
+    if (!job.dry && lane == 0) {
+      sp->kind = SEG_CX2P;
+      sp->delta = delta;
+      sp->j0 = delta ? 31 - __builtin_clz(delta) : -1;
+      sp->d_out = d;
+    }
+  } else {
+    if (lane == 0)
+      for (int w = 0; w < SF_WMAX; ++w) L.V[d][w] = L.dq[w];
+    d += 1;
+    if (!job.dry && lane == 0) { sp->kind = SEG_CX2G; sp->d_out = d; }
+  }
+  __syncthreads();
+  *dptr = d;
+}
+
 static __device__ void track_body(Lds& L, const TrackJob& job) {
   TrackState* st = job.st;
   const int lane = lane_id();
@@ -1948,6 +2137,23 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
     }
     TIC(6);
     // terminal gate of the segment
+    if (gt.op == DG_CPH2 || gt.op == DG_CX2) {
+      terminal_controlled(L, job, gt, seg, nhad, had_base, n, &d, &err);
+      if (d > dmax) dmax = d;
+      if (d > SF_DMAX - 1) err = TRK_E_DIM;
+      err = wave_max(err);
+      TOC(6);
+      had_base += nhad;
+      nhad = 0;
+      ++seg;
+      open = false;
+      if (!job.dry) {
+        for (int pt = lane; pt < SF_PMAX; pt += TL) L.acc[pt] = 0;
+        build_points(L, d);
+      }
+      __syncthreads();
+      continue;
+    }
     const int q = gt.q0;
     const bool is_meas = gt.op == DG_MEASURE;
     SegProg* sp = job.dry ? nullptr : job.prog + seg;

@@ -440,3 +440,66 @@ def test_autotune_keeps_results(eng):
     for c, st, ((ta, sa, aa), oa) in zip(circs, states, before):
         tb, sb, ab = st.read_frame()
         assert np.array_equal(sa, sb) and np.array_equal(aa.view(np.uint64), ab.view(np.uint64)), c.name
+
+
+def _direct_circuit(seed, n, n_cliff=40, n_t=2):
+    rng = np.random.default_rng(seed)
+    c = wl.random_clifford_t(n, n_cliff, n_t, 7700 + seed,
+                             measure_qubits=rng.permutation(n)[: int(rng.integers(0, 3))])
+    extra = []
+    for _ in range(4):
+        a, b, t = (int(v) for v in rng.permutation(n)[:3])
+        extra.append((wl.TOF_D, a, b, t, 0, 1))
+        num, den = [(1, 2), (1, 4), (-3, 8), (1, 1), (2, 1), (5, 6), (1, 32)][int(rng.integers(7))]
+        extra.append((wl.CPHASE_D, a, t, 0, num, den))
+    for g in extra:
+        c.gates.insert(int(rng.integers(0, len(c.gates) + 1)), g)
+    c.name = f"direct{seed}-n{n}"
+    return c
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_direct_controlled_gates(eng, seed):
+    """Direct controlled phase and Toffoli (double cofactor) against the oracle,
+    compared after every gate for the first circuits."""
+    circ = _direct_circuit(seed, 3 + seed % 6)
+    run_pair(eng, circ, seed, boundaries=range(1, len(circ)) if seed < 4 else ())
+
+
+@pytest.mark.parametrize("n", [6, 9])
+def test_qft_direct(eng, n):
+    x = [(i * 5 + 1) % 2 for i in range(n)]
+    run_pair(eng, wl.qft(n, x, max_k=6, direct=True), n)
+
+
+@pytest.mark.parametrize("m", [2, 3])
+def test_cuccaro_direct(eng, m):
+    run_pair(eng, wl.cuccaro_adder(m, direct=True), m)
+
+
+@pytest.mark.parametrize("n", [70, 150, 200])
+def test_direct_gates_wide(eng, n):
+    circ = wl.random_clifford_t(n, 3 * n, 3, 880 + n, measure_qubits=(0, n - 1))
+    circ.gates.insert(n, (wl.TOF_D, 0, n - 1, n // 2, 0, 1))
+    circ.gates.insert(2 * n, (wl.CPHASE_D, n // 3, 63 % n, 0, 1, 4))
+    circ.name = f"directwide{n}"
+    run_pair(eng, circ, n)
+
+
+def test_direct_in_batch_and_graph(eng):
+    circs = [_direct_circuit(s, 5 + s % 3) for s in range(20, 26)] + [wl.cuccaro_adder(2, direct=True)]
+    seeds = list(range(500, 500 + len(circs)))
+    alone = [_run_alone(eng, c, s) for c, s in zip(circs, seeds)]
+    loaded = [eng.load(c.n, c) for c in circs]
+    states = [l.state(c.init_bits, s) for l, c, s in zip(loaded, circs, seeds)]
+    eng.batch_run(states)
+    for c, st, ((ta, sa, aa), oa) in zip(circs, states, alone):
+        tb, sb, ab = st.read_frame()
+        assert np.array_equal(sa, sb) and np.array_equal(aa.view(np.uint64), ab.view(np.uint64)), c.name
+        assert st.outcomes() == oa, c.name
+    g = eng.batch_graph(states, [c.init_bits for c in circs], seeds)
+    g.launch()
+    for c, st, ((ta, sa, aa), oa) in zip(circs, states, alone):
+        tb, sb, ab = st.read_frame()
+        assert np.array_equal(sa, sb) and np.array_equal(aa.view(np.uint64), ab.view(np.uint64)), c.name
+    g.close()
