@@ -151,7 +151,35 @@ def batched_extra(eng, wl, name, circs, seeds, plain_sample):
             "plain_value": sum(Us[i] for i in sub) / tp, "plain_sample_frames": len(sub)}
 
 
-def serve_bench(eng, sf, wl, n_jobs, tick_segments, max_resident, budget_bytes, load_frac=0.7):
+def direct_vs_decomposed(eng, wl, reps=3):
+    """Wall time per circuit (plain path, one frame) of the decomposed and the
+    direct (double-cofactor) forms of controlled rotations and Toffolis."""
+    import torch
+    out = []
+    for name, mk in (("AQFT n=18 (k<=6)", lambda d: wl.qft(18, [1, 0, 1] * 6, max_k=6, direct=d)),
+                     ("Cuccaro adder m=10, inputs in superposition", lambda d: wl.cuccaro_adder(10, direct=d))):
+        rec = {"workload": name}
+        for direct in (False, True):
+            c = mk(direct)
+            lc = eng.load(c.n, c)
+            st = lc.state(c.init_bits, 1)
+            st.run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                st.reset(c.init_bits, 1)
+                st.run()
+            torch.cuda.synchronize()
+            key = "direct" if direct else "decomposed"
+            rec[key] = {"ms_per_circuit": (time.perf_counter() - t0) / reps * 1e3, "gates": len(c),
+                        "frame_bound_log2": lc.info()[0], "final_frame_size": st.frame_size()}
+            st.close()
+        rec["speedup"] = rec["decomposed"]["ms_per_circuit"] / rec["direct"]["ms_per_circuit"]
+        out.append(rec)
+    return out
+
+
+def serve_bench(eng, sf, wl, n_jobs, tick_segments, max_resident, budget_bytes, load_frac=0.7, direct=False):
     """Serving on the mixed request stream (AQFT 40%, Cuccaro adder 40%,
     random Clifford+T 20%).  First a saturation run (every job submitted at
     t=0) gives the batched capacity in jobs/s; then jobs arrive as a Poisson
@@ -159,7 +187,7 @@ def serve_bench(eng, sf, wl, n_jobs, tick_segments, max_resident, budget_bytes, 
     to its outcomes and frame size being on the host."""
     import numpy as np
     import torch
-    jobs = [wl.config5_job(j) for j in range(n_jobs)]
+    jobs = [wl.config5_job(j, direct=direct) for j in range(n_jobs)]
     seeds = [wl.derive_seed(5, j) for j in range(n_jobs)]
     loaded, rejected_load = {}, 0
     tl0 = time.perf_counter()
@@ -384,9 +412,14 @@ def main():
             batched_extra(eng, wl, "uneven random Clifford+T, 1024 circuits, n in 16..256", c4,
                           [wl.derive_seed(4, j) for j in range(1024)], 16),
         ]
+    if not args.no_extra:
+        line["direct_forms"] = direct_vs_decomposed(eng, wl)
     if args.serve_jobs > 0:
         line["serve"] = serve_bench(eng, sf, wl, args.serve_jobs, args.tick_segments, args.max_resident,
                                     int(args.serve_budget_gib * (1 << 30)))
+        line["serve_direct_forms"] = serve_bench(eng, sf, wl, args.serve_jobs, args.tick_segments,
+                                                 args.max_resident, int(args.serve_budget_gib * (1 << 30)),
+                                                 direct=True)
     if not args.no_cpu and args.workload == "cfg2":
         line["cpu_baseline"] = cpu_baseline(circs[0], seeds[0])
     if args.calib_copy_mib > 0:

@@ -313,18 +313,20 @@ def cuccaro_adder(m: int, a_bits=None, b_bits=None, superpose=True, name="cuccar
     return c
 
 
-def config5_job(job: int) -> Circuit:
-    """One served request: 40% AQFT, 40% Cuccaro adder, 20% config-4 shape."""
+def config5_job(job: int, direct: bool = False) -> Circuit:
+    """One served request: 40% AQFT, 40% Cuccaro adder, 20% config-4 shape.
+    With ``direct`` the controlled rotations and Toffolis use the direct
+    (double-cofactor) forms; the draws are the same."""
     seed = derive_seed(5, job)
     rng = np.random.default_rng(seed)
     u = rng.random()
     if u < 0.4:
         n = int(rng.integers(10, 21))
         x = rng.integers(0, 2, size=n).tolist()
-        return qft(n, x, max_k=6, name=f"cfg5a-{job}")
+        return qft(n, x, max_k=6, name=f"cfg5a-{job}", direct=direct)
     if u < 0.8:
         m = int(rng.integers(8, 33))
-        return cuccaro_adder(m, name=f"cfg5b-{job}")
+        return cuccaro_adder(m, name=f"cfg5b-{job}", direct=direct)
     c = config4(100000 + job)
     c.name = f"cfg5c-{job}"
     return c
