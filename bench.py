@@ -151,6 +151,52 @@ def batched_extra(eng, wl, name, circs, seeds, plain_sample):
             "plain_value": sum(Us[i] for i in sub) / tp, "plain_sample_frames": len(sub)}
 
 
+def hbm_probe(eng, wl, d=26, det_gates=24, reps=3):
+    """Element kernels in the HBM-bound regime: H then T on d qubits grows one
+    frame to 2^d elements (d GROW segments), then det_gates T gates on those
+    (now deterministic) qubits are phase-only passes over all 2^d slots
+    (32 B per slot: read and write 16 B).  Their bandwidth is the difference
+    of the segment-kernel time of the two circuits (with and without the
+    passes) over the bytes of the passes."""
+    import torch
+    n = d + 4
+
+    def circ(k):
+        c = wl.Circuit(n, name=f"hbm-probe-d{d}-{k}")
+        for q in range(d):
+            c.h(q)
+        for q in range(d):
+            c.t(q)
+        for i in range(k):
+            c.t(i % d)
+        return c
+
+    seg_ms = []
+    for k in (0, det_gates):
+        c = circ(k)
+        lc = eng.load(c.n, c)
+        st = lc.state(c.init_bits, 3)
+        st.run()
+        torch.cuda.synchronize()
+        eng.profile(True)
+        for _ in range(reps):
+            st.reset(c.init_bits, 3)
+            st.run()
+        torch.cuda.synchronize()
+        prof = eng.profile_read()
+        eng.profile(False)
+        seg_ms.append(prof["segment"][0] / reps)
+        K = st.frame_size()
+        st.close()
+    pass_bytes = 32.0 * (1 << d)
+    ms = (seg_ms[1] - seg_ms[0]) / det_gates
+    gbs = pass_bytes / (ms / 1e3) / 1e9
+    return {"frame_elements": K, "slots": 1 << d, "bytes_per_pass": pass_bytes, "ms_per_pass": ms,
+            "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+            "kernel": "sf_seg_kernel",
+            "note": f"phase-only segment passes over 2^{d} complex128 slots ({(16 << d) >> 20} MiB per buffer)"}
+
+
 def direct_vs_decomposed(eng, wl, reps=3):
     """Wall time per circuit (plain path, one frame) of the decomposed and the
     direct (double-cofactor) forms of controlled rotations and Toffolis."""
@@ -267,7 +313,7 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, one device-to-device copy of this size (counter calibration)")
     ap.add_argument("--tune-lo", type=int, default=8)
-    ap.add_argument("--tune-hi", type=int, default=24, help="below --tune-lo: no autotuning")
+    ap.add_argument("--tune-hi", type=int, default=26, help="below --tune-lo: no autotuning")
     ap.add_argument("--tick-segments", type=int, default=8)
     ap.add_argument("--max-resident", type=int, default=32)
     ap.add_argument("--serve-budget-gib", type=float, default=128.0)
@@ -414,6 +460,7 @@ def main():
         ]
     if not args.no_extra:
         line["direct_forms"] = direct_vs_decomposed(eng, wl)
+        line["element_hbm_probe"] = hbm_probe(eng, wl)
     if args.serve_jobs > 0:
         line["serve"] = serve_bench(eng, sf, wl, args.serve_jobs, args.tick_segments, args.max_resident,
                                     int(args.serve_budget_gib * (1 << 30)))
