@@ -112,14 +112,14 @@ def batched_extra(eng, wl, name, circs, seeds, plain_sample):
         for i in idx:
             states[i].reset(circs[i].init_bits, seeds[i])
 
-    allidx = range(len(states))
-    reset(allidx)
+    bases = [c.init_bits for c in circs]
+    eng.batch_reset(states, bases, seeds)
     eng.batch_run(states)  # warm-up
     torch.cuda.synchronize()
     reps = 3
     t0 = time.perf_counter()
     for _ in range(reps):
-        reset(allidx)
+        eng.batch_reset(states, bases, seeds)
         eng.batch_run(states)
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / reps
@@ -351,9 +351,10 @@ def main():
             st.reset(c.init_bits, s)
             st.run()
 
+    bases = [c.init_bits for c in circs]
+
     def batched_step():
-        for st, c, s in zip(states, circs, seeds):
-            st.reset(c.init_bits, s)
+        eng.batch_reset(states, bases, seeds)
         eng.batch_run(states)
 
     graph = None

@@ -150,6 +150,11 @@ sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t n_states);
  * if after this measurement the rest of the circuit would need more frame
  * elements than the state was sized for. */
 sf_status sf_measure(sf_state* s, uint32_t q, int* outcome);
+/* sf_state_reset for many states with one kernel launch: bases holds 4 words
+ * per state (bit q of state i at bases[4 i + q / 64]; NULL: |0...0>), seeds
+ * one per state (NULL: 0).  Synchronises. */
+sf_status sf_batch_reset(sf_ctx* ctx, sf_state* const* states, size_t n_states, const uint64_t* bases,
+                         const uint64_t* seeds);
 /* Graph form of sf_batch_run for frames that are run again and again (the
  * batched execution of section 3's frame updates over many independent
  * frames, recorded once).  Plans every round of a run of the given states

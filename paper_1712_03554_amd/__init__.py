@@ -24,7 +24,7 @@ SF_OK, SF_E_INVALID, SF_E_OOM, SF_E_DEVICE, SF_E_TOO_LARGE, SF_E_STATE, SF_E_BUF
 STATUS_NAMES = ["SF_OK", "SF_E_INVALID", "SF_E_OOM", "SF_E_DEVICE", "SF_E_TOO_LARGE", "SF_E_STATE",
                 "SF_E_BUFSIZE", "SF_E_CANCELLED"]
 
-EXPORTS = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_measure", "sf_batch_graph", "sf_autotune",
+EXPORTS = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_measure", "sf_batch_graph", "sf_autotune", "sf_batch_reset",
            "sf_graph_set_input", "sf_graph_launch", "sf_graph_destroy", "sf_circuit_load", "sf_circuit_info",
            "sf_circuit_destroy", "sf_state_init", "sf_state_destroy", "sf_step", "sf_run", "sf_sync",
            "sf_outcomes", "sf_frame_size", "sf_read_frame", "sf_state_info", "sf_state_reset",
@@ -78,6 +78,7 @@ def load_library(path: str = LIB_PATH):
         "sf_graph_launch": [vp],
         "sf_graph_destroy": [vp],
         "sf_autotune": [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp],
+        "sf_batch_reset": [vp, vp, sz, vp, vp],
         "sf_sync": [vp],
         "sf_outcomes": [vp, vp, sz, P(sz)],
         "sf_frame_size": [vp, P(u64)],
@@ -181,6 +182,18 @@ class Engine:
         """Run every remaining gate of the given states as one batch (synchronises)."""
         arr = (ctypes.c_void_p * max(1, len(states)))(*[s._h.value for s in states])
         self._check(self._L.sf_batch_run(self._h, ctypes.cast(arr, ctypes.c_void_p), len(states)))
+
+    def batch_reset(self, states, bases=None, seeds=None):
+        """Re-initialise the states with one launch (basis bit lists, seeds)."""
+        ns = len(states)
+        arr = (ctypes.c_void_p * max(1, ns))(*[s._h.value for s in states])
+        b = None
+        if bases is not None:
+            b = np.zeros((max(1, ns), 4), dtype=np.uint64)
+            for i, bits in enumerate(bases):
+                b[i] = _basis_words(states[i].n, bits)
+        sd = None if seeds is None else np.array([int(x) & ((1 << 64) - 1) for x in seeds] or [0], dtype=np.uint64)
+        self._check(self._L.sf_batch_reset(self._h, ctypes.cast(arr, ctypes.c_void_p), ns, _ptr(b), _ptr(sd)))
 
     def batch_graph(self, states, bases=None, seeds=None) -> "Graph":
         """Record a whole batched run of these states (see sf_batch_graph)."""

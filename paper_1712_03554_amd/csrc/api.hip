@@ -1094,15 +1094,44 @@ static sf_status batch_round(sf_ctx* ctx, sf_state* const* states, size_t ns, Ba
   *active = 0;
   if (!plan_round(states, ns, pr.data(), cap, nullptr, &rp, &err)) return err;
   *active = rp.na;
-  bs->keep_jobs.push_back(rp.jobs);
-  bs->keep_desc.push_back(rp.desc);
+  const size_t ndesc = rp.desc.size();
+  bs->keep_jobs.push_back(std::move(rp.jobs));
+  bs->keep_desc.push_back(std::move(rp.desc));
   HIPCHK(ctx, hipMemcpyAsync(bs->djobs.p, bs->keep_jobs.back().data(), rp.na * sizeof(TrackJob),
                              hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(ctx, hipMemcpyAsync(bs->ddesc.p, bs->keep_desc.back().data(), rp.desc.size() * sizeof(ElemDesc),
+  HIPCHK(ctx, hipMemcpyAsync(bs->ddesc.p, bs->keep_desc.back().data(), ndesc * sizeof(ElemDesc),
                              hipMemcpyHostToDevice, ctx->stream));
   launch_round(ctx, rp, (const TrackJob*)bs->djobs.p, (const ElemDesc*)bs->ddesc.p);
   HIPCHK(ctx, hipGetLastError());
   for (size_t i = 0; i < ns; ++i) set_progress(states[i], pr[i]);
+  return SF_OK;
+}
+
+// Device-side errors of many states with one gather launch and one copy.
+static sf_status check_tracks(sf_ctx* ctx, sf_state* const* states, size_t ns) {
+  if (ns == 0) return SF_OK;
+  if (ns == 1) return check_track(states[0]);
+  DevBuf buf;
+  const size_t off = (ns * sizeof(void*) + 255) & ~(size_t)255;
+  sf_status rc = dalloc(ctx, &buf, off + ns * sizeof(int));
+  if (rc) return rc;
+  std::vector<const TrackState*> ptr(ns);
+  for (size_t i = 0; i < ns; ++i) ptr[i] = (const TrackState*)states[i]->st.p;
+  std::vector<int> errs(ns, 0);
+  hipError_t e = hipMemcpyAsync(buf.p, ptr.data(), ns * sizeof(void*), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) {
+    const int grid = (int)std::min<size_t>(1024, (ns + EB - 1) / EB);
+    hipLaunchKernelGGL(sf_gather_errors, dim3(grid), dim3(EB), 0, ctx->stream, (const TrackState* const*)buf.p,
+                       (int)ns, (int*)((char*)buf.p + off));
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(errs.data(), (char*)buf.p + off, ns * sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  dfree(ctx, &buf);
+  if (e != hipSuccess) return fail(ctx, SF_E_DEVICE, "error check: %s", hipGetErrorString(e));
+  for (size_t i = 0; i < ns; ++i)
+    if (errs[i]) return fail(ctx, SF_E_DEVICE, "state %zu: tableau track reported error %d", i, errs[i]);
   return SF_OK;
 }
 
@@ -1122,9 +1151,51 @@ extern "C" sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t n
   scratch_free(ctx, &bs);
   if (rc != SF_OK) return rc;
   if (e != hipSuccess) return fail(ctx, SF_E_DEVICE, "batch run: %s", hipGetErrorString(e));
+  return check_tracks(ctx, states, ns);
+}
+
+// Re-initialise many states with one kernel launch (their basis states and
+// seeds given per state).  Synchronises.
+extern "C" sf_status sf_batch_reset(sf_ctx* ctx, sf_state* const* states, size_t ns, const uint64_t* bases,
+                                    const uint64_t* seeds) {
+  if (!ctx || (ns && !states)) return SF_E_INVALID;
+  if (ns == 0) return SF_OK;
+  for (size_t i = 0; i < ns; ++i)
+    if (!states[i] || states[i]->ctx != ctx) return fail(ctx, SF_E_INVALID, "state %zu is not of this context", i);
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t off_p = al(ns * sizeof(InitDesc)), total = off_p + ns * 8 * sizeof(uint64_t);
+  DevBuf buf;
+  sf_status rc = dalloc(ctx, &buf, total);
+  if (rc) return rc;
+  std::vector<char> host(total, 0);
+  uint64_t* par = (uint64_t*)(host.data() + off_p);
   for (size_t i = 0; i < ns; ++i) {
-    rc = check_track(states[i]);
-    if (rc != SF_OK) return rc;
+    sf_state* s = states[i];
+    const int W = words_of(s->c->n);
+    for (int w = 0; w < W; ++w) par[8 * i + w] = bases ? bases[4 * i + w] : 0;
+    par[8 * i + 4] = seeds ? seeds[i] : 0;
+    InitDesc d;
+    memset(&d, 0, sizeof d);
+    d.st = (TrackState*)s->st.p;
+    d.amp = (double2*)s->amp[0].p;
+    d.flags = (int*)s->flags.p;
+    d.params = (const uint64_t*)((char*)buf.p + off_p) + 8 * i;
+    d.n = (int)s->c->n;
+    memcpy(host.data() + i * sizeof(InitDesc), &d, sizeof d);
+  }
+  hipError_t e = hipMemcpyAsync(buf.p, host.data(), total, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) {
+    prof_begin(ctx, PK_INIT);
+    hipLaunchKernelGGL(sf_init_batch, dim3((unsigned)ns), dim3(EB), 0, ctx->stream, (const InitDesc*)buf.p);
+    prof_end(ctx);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  dfree(ctx, &buf);
+  if (e != hipSuccess) return fail(ctx, SF_E_DEVICE, "batch reset: %s", hipGetErrorString(e));
+  for (size_t i = 0; i < ns; ++i) {
+    set_progress(states[i], Progress{0, 0, 0, 0});
+    states[i]->seed = seeds ? seeds[i] : 0;
   }
   return SF_OK;
 }

@@ -505,3 +505,10 @@ extern "C" __global__ void __launch_bounds__(EB) sf_init_batch(const InitDesc* _
 extern "C" __global__ void __launch_bounds__(EB) sf_fill_unit(double2* __restrict__ amp, uint64_t N) {
   for (uint64_t i = TID; i < N; i += STRIDE) amp[i] = make_double2(1.0, 0.0);
 }
+
+// Error words of many tableau tracks in one launch (out[i] = sts[i]->error).
+extern "C" __global__ void __launch_bounds__(EB)
+sf_gather_errors(const TrackState* const* __restrict__ sts, int n, int* __restrict__ out) {
+  for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < n; i += (int)(gridDim.x * blockDim.x))
+    out[i] = sts[i]->error;
+}

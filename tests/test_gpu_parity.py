@@ -503,3 +503,24 @@ def test_direct_in_batch_and_graph(eng):
         tb, sb, ab = st.read_frame()
         assert np.array_equal(sa, sb) and np.array_equal(aa.view(np.uint64), ab.view(np.uint64)), c.name
     g.close()
+
+
+def test_batch_reset_matches_single_resets(eng):
+    """One-launch re-initialisation equals per-state resets (bit for bit)."""
+    circs = [wl.config1(j) for j in range(3)] + [wl.config3(t) for t in range(3)] + [wl.config4(1)]
+    rng = np.random.default_rng(77)
+    bases = [rng.integers(0, 2, size=c.n).tolist() for c in circs]
+    seeds = [int(rng.integers(0, 1 << 62)) for _ in circs]
+    loaded = [eng.load(c.n, c) for c in circs]
+    states = [l.state(c.init_bits, 0) for l, c in zip(loaded, circs)]
+    eng.batch_run(states)                      # dirty the states first
+    eng.batch_reset(states, bases, seeds)
+    eng.batch_run(states)
+    for l, c, st, b, s in zip(loaded, circs, states, bases, seeds):
+        alone = l.state(b, s)
+        alone.run()
+        ta, sa, aa = alone.read_frame()
+        tb, sb, ab = st.read_frame()
+        assert np.array_equal(ta, tb) and np.array_equal(sa, sb), c.name
+        assert np.array_equal(aa.view(np.uint64), ab.view(np.uint64)), c.name
+        assert alone.outcomes() == st.outcomes(), c.name
