@@ -228,7 +228,8 @@ sf_status sf_serve_stats(sf_server* sv, uint64_t* ticks, uint64_t* admitted, uin
 sf_status sf_serve_destroy(sf_server* sv);
 
 /* Per-kernel device time, measured with HIP events on the context stream.
- * sf_profile(ctx, 1) starts collecting (and clears the totals), 0 stops.
+ * sf_profile(ctx, mask) starts collecting (and clears the totals) for the
+ * kernel kinds whose bit is set in mask (-1: all), 0 stops.
  * sf_profile_read returns total milliseconds and launch counts per kernel
  * kind: 0 tableau track, 1 segment (phase + cofactor), 2 measurement
  * reduction, 3 measurement coin, 4 measurement filter, 5 readout, 6 state

@@ -208,8 +208,11 @@ class Engine:
         self._check(self._L.sf_autotune(self._h, d_lo, d_hi, _ptr(b), _ptr(g), _ptr(t)))
         return {d_lo + i: (int(b[i]), int(g[i]), float(t[i])) for i in range(k)}
 
-    def profile(self, enable: bool):
-        self._check(self._L.sf_profile(self._h, 1 if enable else 0))
+    def profile(self, enable: bool, kinds=None):
+        """Start (clearing the totals) or stop per-kernel timing; kinds limits
+        it to the named kernel kinds (KERNEL_KINDS)."""
+        mask = 0 if not enable else (-1 if kinds is None else sum(1 << KERNEL_KINDS.index(k) for k in kinds))
+        self._check(self._L.sf_profile(self._h, mask))
 
     def profile_read(self) -> dict:
         k = len(KERNEL_KINDS)

@@ -28,8 +28,9 @@ struct sf_ctx {
   int has_alloc;
   uint64_t budget, in_use;
   char err[512];
-  // per-kernel timing with HIP events on the context stream
-  int prof;
+  // per-kernel timing with HIP events on the context stream: bit k of prof
+  // enables kind k
+  int prof, prof_open;
   std::vector<hipEvent_t> ev;   // pairs (start, end)
   std::vector<int> ev_kind;
   size_t ev_used;
@@ -84,7 +85,8 @@ static void elem_shape(const sf_ctx* ctx, int d, int* block, int* grid) {
 }
 
 static void prof_begin(sf_ctx* ctx, int kind) {
-  if (!ctx->prof) return;
+  ctx->prof_open = 0;
+  if (!ctx->prof || !((ctx->prof >> kind) & 1)) return;
   size_t i = ctx->ev_used;
   if (2 * i + 2 > ctx->ev.size()) {
     hipEvent_t a, b;
@@ -95,12 +97,14 @@ static void prof_begin(sf_ctx* ctx, int kind) {
   }
   ctx->ev_kind[i] = kind;
   (void)hipEventRecord(ctx->ev[2 * i], ctx->stream);
+  ctx->prof_open = 1;
 }
 
 static void prof_end(sf_ctx* ctx) {
-  if (!ctx->prof || 2 * ctx->ev_used + 2 > ctx->ev.size()) return;
+  if (!ctx->prof_open) return;
   (void)hipEventRecord(ctx->ev[2 * ctx->ev_used + 1], ctx->stream);
   ctx->ev_used++;
+  ctx->prof_open = 0;
 }
 
 static void prof_collect(sf_ctx* ctx) {
@@ -207,6 +211,7 @@ extern "C" sf_status sf_ctx_create(int device, void* hip_stream, const sf_alloca
   c->in_use = 0;
   c->err[0] = 0;
   c->prof = 0;
+  c->prof_open = 0;
   c->ev_used = 0;
   for (int k = 0; k < PK_N; ++k) { c->prof_ms[k] = 0; c->prof_n[k] = 0; }
   for (int d = 0; d <= SF_DMAX; ++d) { c->tune_block[d] = EB; c->tune_grid[d] = grid_for(d); }
@@ -225,7 +230,8 @@ extern "C" sf_status sf_profile(sf_ctx* ctx, int enable) {
   if (!ctx) return SF_E_INVALID;
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   prof_collect(ctx);
-  ctx->prof = enable ? 1 : 0;
+  ctx->prof = enable;
+  ctx->prof_open = 0;
   for (int k = 0; k < PK_N; ++k) { ctx->prof_ms[k] = 0; ctx->prof_n[k] = 0; }
   return SF_OK;
 }
