@@ -134,12 +134,10 @@ def test_word_boundaries_and_max_qubits(eng, n):
     run_pair(eng, circ, n)
 
 
-@pytest.mark.parametrize("job", [0, 3, 5])
+@pytest.mark.parametrize("job", [0, 3, 5, 39, 42, 76])
 def test_config4_circuits(eng, job):
-    circ = wl.config4(job)
-    if circ.count([wl.T]) > 9:
-        circ = wl.random_clifford_t(circ.n, 10 * circ.n, 9, wl.derive_seed(4, job), name=circ.name + "t9")
-    run_pair(eng, circ, job)
+    """Uneven-batch circuits at full size (up to 12 T gates, up to 232 qubits)."""
+    run_pair(eng, wl.config4(job), job)
 
 
 def test_config2_full_size(eng):
@@ -524,3 +522,40 @@ def test_batch_reset_matches_single_resets(eng):
         assert np.array_equal(ta, tb) and np.array_equal(sa, sb), c.name
         assert np.array_equal(aa.view(np.uint64), ab.view(np.uint64)), c.name
         assert alone.outcomes() == st.outcomes(), c.name
+
+
+def test_api_error_paths(eng):
+    """Invalid calls of the newer entry points fail cleanly and leave the
+    states usable."""
+    import ctypes
+    import paper_1712_03554_amd as sf
+    L = eng._L
+    c = wl.config1(0)
+    lc = eng.load(c.n, c)
+    st = lc.state(c.init_bits, 9)
+    # autotune: bad ranges
+    for lo, hi in ((-1, 3), (5, 4), (0, 30)):
+        assert L.sf_autotune(eng._h, lo, hi, None, None, None) == sf.SF_E_INVALID
+    # graph: input index out of range; a state in a graph cannot be destroyed
+    g = eng.batch_graph([st], [c.init_bits], [9])
+    assert L.sf_graph_set_input(g._h, 1, None, ctypes.c_uint64(0)) != sf.SF_OK
+    assert L.sf_state_destroy(st._h) == sf.SF_E_STATE
+    g.launch()
+    g.close()
+    # the same state twice in one graph is refused
+    arr = (ctypes.c_void_p * 2)(st._h.value, st._h.value)
+    out = ctypes.c_void_p()
+    assert L.sf_batch_graph(eng._h, ctypes.cast(arr, ctypes.c_void_p), 2, None, None, ctypes.byref(out)) \
+        == sf.SF_E_INVALID
+    # a state of another context is refused by the batched calls
+    eng2 = sf.Engine(0)
+    arr1 = (ctypes.c_void_p * 1)(st._h.value)
+    assert L.sf_batch_run(eng2._h, ctypes.cast(arr1, ctypes.c_void_p), 1) == sf.SF_E_INVALID
+    assert L.sf_batch_reset(eng2._h, ctypes.cast(arr1, ctypes.c_void_p), 1, None, None) == sf.SF_E_INVALID
+    eng2.close()
+    # the state still runs to the oracle's result
+    st.reset(c.init_bits, 9)
+    st.run()
+    ref = OracleFrame(c.n, c.init_bits, 9)
+    ref.run(c.array())
+    _compare(st, ref, "after error paths")
