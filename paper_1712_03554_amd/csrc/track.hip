@@ -21,11 +21,16 @@
 
 #define TL 64  // one wavefront
 
-struct Lds {
-  uint64_t rx[SF_NMAX * SF_WMAX], rz[SF_NMAX * SF_WMAX];
-  uint64_t cx[SF_NMAX * SF_WMAX], cz[SF_NMAX * SF_WMAX];   // column q: slots with an x (z) bit at q
-  uint64_t ox[SF_NMAX * SF_WMAX], oz[SF_NMAX * SF_WMAX];
-  uint64_t beta[SF_NMAX * SF_WMAX];
+// LDS of one tableau-track workgroup.  NM row slots of WM words in the
+// row-indexed arrays (rows, column copy, pre-gate rows, b* basis, indexes);
+// the hull and sample arrays are sized for the largest frames.
+template <int NM, int WM>
+struct LdsT {
+  static constexpr int RN = NM, RW = WM;
+  uint64_t rx[NM * WM], rz[NM * WM];
+  uint64_t cx[NM * WM], cz[NM * WM];   // column q: slots with an x (z) bit at q
+  uint64_t ox[NM * WM], oz[NM * WM];
+  uint64_t beta[NM * WM];
   uint64_t s0[SF_WMAX], V[SF_DMAX][SF_WMAX], u[SF_WMAX];
   uint64_t os0[SF_WMAX], oV[SF_DMAX][SF_WMAX];
   uint64_t hbO[SF_DMAX + 2][SF_WMAX], hbN[SF_DMAX + 2][SF_WMAX];
@@ -35,13 +40,15 @@ struct Lds {
   uint64_t dq[SF_WMAX];
   uint32_t Ys[SF_PMAX];
   uint8_t acc[SF_PMAX], t0[SF_PMAX], t1[SF_PMAX];
-  int16_t lead[SF_NMAX], xpiv[SF_NMAX], zpiv[SF_NMAX], oxpiv[SF_NMAX];
-  uint8_t ow[SF_NMAX];
+  int16_t lead[NM], xpiv[NM], zpiv[NM], oxpiv[NM];
+  uint8_t ow[NM];
   uint32_t ech[SF_DMAX];          // scratch for span tests
-  uint32_t lst[2 * SF_NMAX];      // lead stamps of the elimination passes
+  uint32_t lst[2 * NM];           // lead stamps of the elimination passes
   int misc[8];                    // [0] X-block size, [1] last lead stamp
   uint64_t tc[16];                // per-phase shader clocks
 };
+
+typedef LdsT<SF_NMAX, SF_WMAX> Lds;
 
 typedef Lds TrackLdsProbe;
 
@@ -65,8 +72,9 @@ __device__ __forceinline__ int getb(const uint64_t* v, int q) { return (int)((v[
 __device__ __forceinline__ void flipb(uint64_t* v, int q) { v[q >> 6] ^= 1ull << (q & 63); }
 __device__ __forceinline__ int par64(uint64_t v) { return __popcll(v) & 1; }
 
-__device__ __forceinline__ int colbit(const Lds& L, int i, int col, int n) {
-  return col < n ? getb(&L.rx[i * SF_WMAX], col) : getb(&L.rz[i * SF_WMAX], col - n);
+template <class LT>
+__device__ __forceinline__ int colbit(const LT& L, int i, int col, int n) {
+  return col < n ? getb(&L.rx[i * LT::RW], col) : getb(&L.rz[i * LT::RW], col - n);
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x; }
@@ -83,7 +91,8 @@ __device__ __forceinline__ int pair_index(int j, int jj, int d) {
   return 1 + d + (j * (2 * d - j - 1)) / 2 + (jj - j - 1);
 }
 
-__device__ void build_points(Lds& L, int d) {
+template <class LT>
+__device__ void build_points(LT& L, int d) {
   const int lane = lane_id();
   if (lane == 0) L.Ys[0] = 0;
   for (int j = lane; j < d; j += TL) {
@@ -96,7 +105,8 @@ __device__ void build_points(Lds& L, int d) {
 __device__ __forceinline__ int npoints(int d) { return 1 + d + d * (d - 1) / 2; }
 
 // fit e(Y) mod 4 from samples f at the points (must be a Z4 quadratic form)
-__device__ void fit_z4(Lds& L, const uint8_t* f, int d, Z4Q* out, int* err) {
+template <class LT>
+__device__ void fit_z4(LT& L, const uint8_t* f, int d, Z4Q* out, int* err) {
   const int lane = lane_id();
   uint32_t q = 0;
   int l = 0;
@@ -115,7 +125,8 @@ __device__ void fit_z4(Lds& L, const uint8_t* f, int d, Z4Q* out, int* err) {
   if (lane == 0) { out->c = f[0] & 3; out->L1 = L1; out->L2 = L2; out->qnz = qnz; }
 }
 
-__device__ void fit_gf2(Lds& L, const uint8_t* t, int d, GF2Q* out) {
+template <class LT>
+__device__ void fit_gf2(LT& L, const uint8_t* t, int d, GF2Q* out) {
   const int lane = lane_id();
   uint32_t q = 0;
   int l = 0;
@@ -147,7 +158,8 @@ __device__ void emit_header(SegProg* sp, int kind, int is_meas, int d, int d_out
 
 // qubit value functional of a deterministic qubit q: sigma bit of the Z-row
 // that equals Z_q, as a function of Y
-__device__ void apply_pending(Lds& L, const TrackState* st, const uint8_t* outcomes, int* dptr) {
+template <class LT>
+__device__ void apply_pending(LT& L, const TrackState* st, const uint8_t* outcomes, int* dptr) {
   const int lane = lane_id();
   int d = *dptr;
   int o = outcomes ? (int)outcomes[st->pend_meas] : 0;
@@ -176,6 +188,9 @@ __device__ void apply_pending(Lds& L, const TrackState* st, const uint8_t* outco
 
 template <int W>
 struct Trk {
+// LDS sized for this word count: 64 W row slots of W words
+typedef LdsT<64 * W, W> LL;
+
 // The tableau as the Clifford loop keeps it: lane l holds row slots and
 // columns 64k + l (k < W); rows x/z (W words each), the column-major copy
 // cx/cz (slot masks of rows with an x / z bit at that qubit) and each row's
@@ -196,33 +211,33 @@ static __device__ __forceinline__ uint64_t bcast64(uint64_t v, int l) {
          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
 }
 
-static __device__ __forceinline__ void regs_load(const Lds& L, Regs& R, int n) {
+static __device__ __forceinline__ void regs_load(const LL& L, Regs& R, int n) {
   const int lane = lane_id();
   for (int k = 0; k < W; ++k) {
     const int i = 64 * k + lane;
     const bool ok = i < n;
     for (int w = 0; w < W; ++w) {
-      R.x[k][w] = ok ? L.rx[i * SF_WMAX + w] : 0ull;
-      R.z[k][w] = ok ? L.rz[i * SF_WMAX + w] : 0ull;
-      R.cx[k][w] = ok ? L.cx[i * SF_WMAX + w] : 0ull;
-      R.cz[k][w] = ok ? L.cz[i * SF_WMAX + w] : 0ull;
+      R.x[k][w] = ok ? L.rx[i * LL::RW + w] : 0ull;
+      R.z[k][w] = ok ? L.rz[i * LL::RW + w] : 0ull;
+      R.cx[k][w] = ok ? L.cx[i * LL::RW + w] : 0ull;
+      R.cz[k][w] = ok ? L.cz[i * LL::RW + w] : 0ull;
     }
     R.ld[k] = ok ? (int)L.lead[i] : -1;
   }
 }
 
 // rows, leads and (cols) the column-major copy into LDS; no barrier
-static __device__ __forceinline__ void regs_store(Lds& L, const Regs& R, int n, bool cols) {
+static __device__ __forceinline__ void regs_store(LL& L, const Regs& R, int n, bool cols) {
   const int lane = lane_id();
   for (int k = 0; k < W; ++k) {
     const int i = 64 * k + lane;
     if (i >= n) continue;
     for (int w = 0; w < W; ++w) {
-      L.rx[i * SF_WMAX + w] = R.x[k][w];
-      L.rz[i * SF_WMAX + w] = R.z[k][w];
+      L.rx[i * LL::RW + w] = R.x[k][w];
+      L.rz[i * LL::RW + w] = R.z[k][w];
       if (cols) {
-        L.cx[i * SF_WMAX + w] = R.cx[k][w];
-        L.cz[i * SF_WMAX + w] = R.cz[k][w];
+        L.cx[i * LL::RW + w] = R.cx[k][w];
+        L.cz[i * LL::RW + w] = R.cz[k][w];
       }
     }
     L.lead[i] = (int16_t)R.ld[k];
@@ -251,12 +266,12 @@ static __device__ int rowprod_sign(const uint64_t* x1, const uint64_t* z1, const
 // ---------------------------------------------------------------------------
 // Echelon bookkeeping
 // ---------------------------------------------------------------------------
-static __device__ void rebuild_index(Lds& L, int n) {
+static __device__ void rebuild_index(LL& L, int n) {
   const int lane = lane_id();
-  for (int i = lane; i < SF_NMAX; i += TL) { L.xpiv[i] = -1; L.zpiv[i] = -1; }
+  for (int i = lane; i < LL::RN; i += TL) { L.xpiv[i] = -1; L.zpiv[i] = -1; }
   __syncthreads();
   for (int i = lane; i < n; i += TL) {
-    int ld = row_lead(&L.rx[i * SF_WMAX], &L.rz[i * SF_WMAX], n);
+    int ld = row_lead(&L.rx[i * LL::RW], &L.rz[i * LL::RW], n);
     L.lead[i] = (int16_t)ld;
     if (ld >= 0 && ld < n) L.xpiv[ld] = (int16_t)i;
     else if (ld >= n) L.zpiv[ld - n] = (int16_t)i;
@@ -281,7 +296,7 @@ static __device__ void rebuild_index(Lds& L, int n) {
 
 // Tracked phase-vector images: s0 (affine), V[0..d) and optionally u (linear).
 // Apply sigma_i ^= sigma_m ^ c_i for every i in rmask (c in cmask).
-static __device__ void apply_rowsum_batch(Lds& L, int m, int d, bool with_u) {
+static __device__ void apply_rowsum_batch(LL& L, int m, int d, bool with_u) {
   const int lane = lane_id();
   uint64_t* vec = nullptr;
   bool affine = false;
@@ -298,7 +313,7 @@ static __device__ void apply_rowsum_batch(Lds& L, int m, int d, bool with_u) {
 // Column-major copy of the tableau: L.cx[q] / L.cz[q] hold the slots whose
 // row has an x (z) bit at qubit q.  Built by one transpose per launch and kept
 // in step with every row change.
-static __device__ void build_cols(Lds& L, int n) {
+static __device__ void build_cols(LL& L, int n) {
   const int lane = lane_id();
   const int R = (n + 63) / 64;
   for (int it = 0; it < R; ++it) {
@@ -307,12 +322,12 @@ static __device__ void build_cols(Lds& L, int n) {
     for (int w = 0; w < W; ++w) { cxv[w] = 0; czv[w] = 0; }
     if (q < n) {
       for (int i = 0; i < n; ++i) {
-        const uint64_t bx = (L.rx[i * SF_WMAX + (q >> 6)] >> (q & 63)) & 1ull;
-        const uint64_t bz = (L.rz[i * SF_WMAX + (q >> 6)] >> (q & 63)) & 1ull;
+        const uint64_t bx = (L.rx[i * LL::RW + (q >> 6)] >> (q & 63)) & 1ull;
+        const uint64_t bz = (L.rz[i * LL::RW + (q >> 6)] >> (q & 63)) & 1ull;
         cxv[i >> 6] |= bx << (i & 63);
         czv[i >> 6] |= bz << (i & 63);
       }
-      for (int w = 0; w < W; ++w) { L.cx[q * SF_WMAX + w] = cxv[w]; L.cz[q * SF_WMAX + w] = czv[w]; }
+      for (int w = 0; w < W; ++w) { L.cx[q * LL::RW + w] = cxv[w]; L.cz[q * LL::RW + w] = czv[w]; }
     }
   }
   __syncthreads();
@@ -320,16 +335,16 @@ static __device__ void build_cols(Lds& L, int n) {
 
 // rows in L.rmask received row m: toggle those slots in every column where
 // row m has a bit
-static __device__ void cols_rowsum(Lds& L, int m, int n) {
+static __device__ void cols_rowsum(LL& L, int m, int n) {
   const int lane = lane_id();
   const int R = (n + 63) / 64;
   for (int it = 0; it < R; ++it) {
     const int q = it * 64 + lane;
     if (q >= n) continue;
-    if (getb(&L.rx[m * SF_WMAX], q))
-      for (int w = 0; w < W; ++w) L.cx[q * SF_WMAX + w] ^= L.rmask[w];
-    if (getb(&L.rz[m * SF_WMAX], q))
-      for (int w = 0; w < W; ++w) L.cz[q * SF_WMAX + w] ^= L.rmask[w];
+    if (getb(&L.rx[m * LL::RW], q))
+      for (int w = 0; w < W; ++w) L.cx[q * LL::RW + w] ^= L.rmask[w];
+    if (getb(&L.rz[m * LL::RW], q))
+      for (int w = 0; w < W; ++w) L.cz[q * LL::RW + w] ^= L.rmask[w];
   }
 }
 
@@ -346,7 +361,7 @@ static __device__ void cols_rowsum(Lds& L, int m, int n) {
 // row slots and columns 64k + l (k < W) and hull vector l (V[l], then s0 at
 // lane d, u at lane d + 1).  The pivot row travels by readlane, the row masks
 // of each step by ballot; LDS is read on entry and written on exit only.
-static __device__ __forceinline__ void repair_core(Lds& L, Regs& R, int n, int d, bool with_u, int full) {
+static __device__ __forceinline__ void repair_core(LL& L, Regs& R, int n, int d, bool with_u, int full) {
   const int lane = lane_id();
   uint64_t (&x)[W][W] = R.x;
   uint64_t (&z)[W][W] = R.z;
@@ -473,7 +488,7 @@ static __device__ __forceinline__ void repair_core(Lds& L, Regs& R, int n, int d
 }
 
 // The same on the LDS copy of the tableau (terminal steps and readout).
-static __device__ void repair(Lds& L, int n, int d, bool with_u, int full) {
+static __device__ void repair(LL& L, int n, int d, bool with_u, int full) {
   Regs R;
   regs_load(L, R, n);
   repair_core(L, R, n, d, with_u, full);
@@ -488,25 +503,25 @@ static __device__ void repair(Lds& L, int n, int d, bool with_u, int full) {
 // leads.  So b*(sigma) = XOR over Z-rows h with sigma_h = 1 of beta_h, with
 // beta_h = e_{q_h} ^ (x-part of the X-row leading at q_h, if any).
 // ---------------------------------------------------------------------------
-static __device__ void build_beta(Lds& L, int n) {
+static __device__ void build_beta(LL& L, int n) {
   const int lane = lane_id();
   for (int h = lane; h < n; h += TL) {
-    uint64_t* b = &L.beta[h * SF_WMAX];
-    for (int w = 0; w < SF_WMAX; ++w) b[w] = 0;
+    uint64_t* b = &L.beta[h * LL::RW];
+    for (int w = 0; w < W; ++w) b[w] = 0;
     int ld = L.lead[h];
     if (ld >= n) {
       int q = ld - n;
       flipb(b, q);
       int l = L.xpiv[q];
       if (l >= 0)
-        for (int w = 0; w < W; ++w) b[w] ^= L.rx[l * SF_WMAX + w];
+        for (int w = 0; w < W; ++w) b[w] ^= L.rx[l * LL::RW + w];
     }
   }
   __syncthreads();
 }
 
 // The same from the register tableau (rows already in LDS, xpiv current).
-static __device__ __forceinline__ void build_beta_regs(Lds& L, const Regs& R, int n) {
+static __device__ __forceinline__ void build_beta_regs(LL& L, const Regs& R, int n) {
   const int lane = lane_id();
   // all pivot lookups first, then all row reads: two LDS round trips in all
   int l[W];
@@ -521,28 +536,28 @@ static __device__ __forceinline__ void build_beta_regs(Lds& L, const Regs& R, in
     const int q = ld - n;
     for (int w = 0; w < W; ++w) {
       uint64_t b = (ld >= n && w == (q >> 6)) ? 1ull << (q & 63) : 0ull;
-      if (l[k] >= 0) b ^= L.rx[l[k] * SF_WMAX + w];
-      L.beta[h * SF_WMAX + w] = b;
+      if (l[k] >= 0) b ^= L.rx[l[k] * LL::RW + w];
+      L.beta[h * LL::RW + w] = b;
     }
   }
   __syncthreads();
 }
 
-static __device__ void bimage(const Lds& L, const uint64_t* vec, uint64_t* out) {
+static __device__ void bimage(const LL& L, const uint64_t* vec, uint64_t* out) {
   uint64_t acc[SF_WMAX] = {0, 0, 0, 0};
   for (int w = 0; w < W; ++w) {
     uint64_t bits = vec[w] & L.zsm[w];
     while (bits) {
       int h = 64 * w + __builtin_ctzll(bits);
       bits &= bits - 1;
-      for (int v = 0; v < W; ++v) acc[v] ^= L.beta[h * SF_WMAX + v];
+      for (int v = 0; v < W; ++v) acc[v] ^= L.beta[h * LL::RW + v];
     }
   }
   for (int w = 0; w < W; ++w) out[w] = acc[w];
 }
 
 // images of s0 (index 0), V[j] (1+j) and, if with_u, u (index d+1) into hb
-static __device__ void hull_images(Lds& L, uint64_t (*hb)[SF_WMAX], int d, bool with_u) {
+static __device__ void hull_images(LL& L, uint64_t (*hb)[SF_WMAX], int d, bool with_u) {
   const int lane = lane_id();
   if (lane == 0) bimage(L, L.s0, hb[0]);
   else if (lane <= d) bimage(L, L.V[lane - 1], hb[lane]);
@@ -554,7 +569,7 @@ static __device__ void hull_images(Lds& L, uint64_t (*hb)[SF_WMAX], int d, bool 
 // the support.  The old X-block rows are stored by pivot column (ox/oz/ow at
 // q hold the row whose x-lead is q; oxpiv[q] is its slot, for its sign).  psi ~ prod_l (I + g_l)/2 |b*>: the amplitude at b* ^ x_S is the
 // phase of applying the X-block generators in S to |b*>.
-static __device__ int uexp(const Lds& L, const uint64_t* sig, const uint64_t* bO, const uint64_t* b) {
+static __device__ int uexp(const LL& L, const uint64_t* sig, const uint64_t* bO, const uint64_t* b) {
   uint64_t v[SF_WMAX];
   for (int w = 0; w < W; ++w) v[w] = bO[w];
   int e = 0;
@@ -565,9 +580,9 @@ static __device__ int uexp(const Lds& L, const uint64_t* sig, const uint64_t* bO
       D &= D - 1;
       const int l = L.oxpiv[q];
       uint64_t zv = 0;
-      for (int t = 0; t < W; ++t) zv ^= L.oz[q * SF_WMAX + t] & v[t];
+      for (int t = 0; t < W; ++t) zv ^= L.oz[q * LL::RW + t] & v[t];
       e += 2 * (getb(sig, l) ^ par64(zv)) + L.ow[q];
-      for (int t = 0; t < W; ++t) v[t] ^= L.ox[q * SF_WMAX + t];
+      for (int t = 0; t < W; ++t) v[t] ^= L.ox[q * LL::RW + t];
     }
   }
   for (int w = 0; w < W; ++w) if (v[w] != b[w]) return -1;
@@ -580,22 +595,22 @@ static __device__ int uexp(const Lds& L, const uint64_t* sig, const uint64_t* bO
 // ---------------------------------------------------------------------------
 // Save the pre-gate tableau and hull (needed by the phase evaluation)
 // ---------------------------------------------------------------------------
-static __device__ void save_old(Lds& L, int n, int d) {
+static __device__ void save_old(LL& L, int n, int d) {
   const int lane = lane_id();
   for (int i = lane; i < n; i += TL) {
     const int ld = L.lead[i];
     if (ld >= 0 && ld < n) {
       int c = 0;
       for (int w = 0; w < W; ++w) {
-        L.ox[ld * SF_WMAX + w] = L.rx[i * SF_WMAX + w];
-        L.oz[ld * SF_WMAX + w] = L.rz[i * SF_WMAX + w];
-        c += __popcll(L.rx[i * SF_WMAX + w] & L.rz[i * SF_WMAX + w]);
+        L.ox[ld * LL::RW + w] = L.rx[i * LL::RW + w];
+        L.oz[ld * LL::RW + w] = L.rz[i * LL::RW + w];
+        c += __popcll(L.rx[i * LL::RW + w] & L.rz[i * LL::RW + w]);
       }
       L.ow[ld] = (uint8_t)(c & 3);
     }
     L.oxpiv[i] = L.xpiv[i];
   }
-  for (int i = n + lane; i < SF_NMAX; i += TL) L.oxpiv[i] = -1;
+  for (int i = n + lane; i < LL::RN; i += TL) L.oxpiv[i] = -1;
   if (lane < d) for (int w = 0; w < SF_WMAX; ++w) L.oV[lane][w] = L.V[lane][w];
   if (lane == d) for (int w = 0; w < SF_WMAX; ++w) L.os0[w] = L.s0[w];
   if (lane <= d + 1) for (int w = 0; w < SF_WMAX; ++w) L.hbO[lane][w] = L.hbN[lane][w];
@@ -625,7 +640,7 @@ static __device__ __forceinline__ void point_vec(const uint64_t* base, const uin
 // Table 2 on the register tableau: conjugate every row by the gate, collect
 // the sign flips f (applied to every phase vector through s0 ^= f) and keep
 // the column-major copy in step.  No barrier.
-static __device__ __forceinline__ void conj_regs(Lds& L, Regs& R, int op, int a, int b, int n) {
+static __device__ __forceinline__ void conj_regs(LL& L, Regs& R, int op, int a, int b, int n) {
   const int lane = lane_id();
   const int wa = a >> 6, ba = a & 63, wb = b >> 6, bb = b & 63;
   const bool two = op == DG_CNOT || op == DG_CZ;
@@ -697,9 +712,9 @@ static __device__ __forceinline__ void conj_regs(Lds& L, Regs& R, int op, int a,
 
 // Pivot index from the register tableau (xpiv / zpiv / zsm / X-block size)
 // and the LDS snapshot of the rows and leads.  Ends with a barrier.
-static __device__ __forceinline__ void index_regs(Lds& L, const Regs& R, int n) {
+static __device__ __forceinline__ void index_regs(LL& L, const Regs& R, int n) {
   const int lane = lane_id();
-  for (int i = lane; i < SF_NMAX; i += TL) { L.xpiv[i] = -1; L.zpiv[i] = -1; }
+  for (int i = lane; i < LL::RN; i += TL) { L.xpiv[i] = -1; L.zpiv[i] = -1; }
   regs_store(L, R, n, false);
   __syncthreads();
   int kx = 0;
@@ -722,7 +737,7 @@ static __device__ __forceinline__ void index_regs(Lds& L, const Regs& R, int n) 
 
 // Pre-gate snapshot for the phase evaluation: rows, their Y counts, the
 // x-pivot index and mask, the hull and its b* images.
-static __device__ __forceinline__ void save_old_regs(Lds& L, const Regs& R, int n, int d) {
+static __device__ __forceinline__ void save_old_regs(LL& L, const Regs& R, int n, int d) {
   const int lane = lane_id();
   for (int k = 0; k < W; ++k) {
     const int i = 64 * k + lane;
@@ -730,13 +745,13 @@ static __device__ __forceinline__ void save_old_regs(Lds& L, const Regs& R, int 
     if (i >= n || ld < 0 || ld >= n) continue;
     int c = 0;
     for (int w = 0; w < W; ++w) {
-      L.ox[ld * SF_WMAX + w] = R.x[k][w];
-      L.oz[ld * SF_WMAX + w] = R.z[k][w];
+      L.ox[ld * LL::RW + w] = R.x[k][w];
+      L.oz[ld * LL::RW + w] = R.z[k][w];
       c += __popcll(R.x[k][w] & R.z[k][w]);
     }
     L.ow[ld] = (uint8_t)(c & 3);
   }
-  for (int i = lane; i < SF_NMAX; i += TL) L.oxpiv[i] = i < n ? L.xpiv[i] : (int16_t)-1;
+  for (int i = lane; i < LL::RN; i += TL) L.oxpiv[i] = i < n ? L.xpiv[i] : (int16_t)-1;
   if (lane < d) for (int w = 0; w < SF_WMAX; ++w) L.oV[lane][w] = L.V[lane][w];
   if (lane == d) for (int w = 0; w < SF_WMAX; ++w) L.os0[w] = L.s0[w];
   if (lane <= d + 1) for (int w = 0; w < SF_WMAX; ++w) L.hbO[lane][w] = L.hbN[lane][w];
@@ -751,7 +766,7 @@ static __device__ __forceinline__ void save_old_regs(Lds& L, const Regs& R, int 
 // ---------------------------------------------------------------------------
 // Clifford gate on the register tableau
 // ---------------------------------------------------------------------------
-static __device__ __forceinline__ void clifford_gate(Lds& L, Regs& R, int op, int a, int b, int n, int d, int dry, GF2Q* had_out,
+static __device__ __forceinline__ void clifford_gate(LL& L, Regs& R, int op, int a, int b, int n, int d, int dry, GF2Q* had_out,
                                      int* nhad, int* err) {
   const int lane = lane_id();
   if (op == DG_S || op == DG_SDG || op == DG_Z || op == DG_CZ) {
@@ -922,7 +937,7 @@ static __device__ uint32_t span_reduce(const uint64_t (*vecs)[SF_WMAX], const ui
 // ---------------------------------------------------------------------------
 // Non-Clifford phase gate or measurement on q: COFACTOR (section 3)
 // ---------------------------------------------------------------------------
-static __device__ void det_functional(Lds& L, int q, int n, int d, uint32_t* c0, uint32_t* r, int* err) {
+static __device__ void det_functional(LL& L, int q, int n, int d, uint32_t* c0, uint32_t* r, int* err) {
   const int lane = lane_id();
   int h = L.zpiv[q];
   uint32_t rr = 0;
@@ -930,7 +945,7 @@ static __device__ void det_functional(Lds& L, int q, int n, int d, uint32_t* c0,
   else {
     for (int w = 0; w < W; ++w) {
       uint64_t want = (q >> 6) == w ? (1ull << (q & 63)) : 0ull;
-      if (L.rz[h * SF_WMAX + w] != want || L.rx[h * SF_WMAX + w] != 0ull) *err = TRK_E_INTERNAL;
+      if (L.rz[h * LL::RW + w] != want || L.rx[h * LL::RW + w] != 0ull) *err = TRK_E_INTERNAL;
     }
   }
   rr = (uint32_t)__ballot(lane < d && getb(L.V[lane < d ? lane : 0], h));
@@ -954,7 +969,7 @@ static __device__ void det_functional(Lds& L, int q, int n, int d, uint32_t* c0,
 // which has the same control values (f has no bit on the controls' Z rows);
 // otherwise the hull grows by the coordinate V[d] = f.
 // ---------------------------------------------------------------------------
-static __device__ void terminal_controlled(Lds& L, const TrackJob& job, const DGate& gt, int seg, int nhad,
+static __device__ void terminal_controlled(LL& L, const TrackJob& job, const DGate& gt, int seg, int nhad,
                                            int had_base, int n, int* dptr, int* err) {
   const int lane = lane_id();
   int d = *dptr;
@@ -981,7 +996,7 @@ static __device__ void terminal_controlled(Lds& L, const TrackJob& job, const DG
   const int R = (n + 63) / 64;
   for (int it = 0; it < SF_WMAX; ++it) {
     const int i = it * 64 + lane;
-    const uint64_t b = __ballot(it < R && i < n && getb(&L.rz[i * SF_WMAX], t));
+    const uint64_t b = __ballot(it < R && i < n && getb(&L.rz[i * LL::RW], t));
     if (lane == 0) L.dq[it] = b;
   }
   __syncthreads();
@@ -1025,21 +1040,22 @@ static __device__ void terminal_controlled(Lds& L, const TrackJob& job, const DG
   *dptr = d;
 }
 
-static __device__ void track_body(Lds& L, const TrackJob& job) {
+static __device__ void track_body(LL& L, const TrackJob& job) {
   TrackState* st = job.st;
   const int lane = lane_id();
   const int n = st->n;
   int d = st->d;
   int err = 0;
   if (lane_id() < 16) L.tc[lane_id()] = 0;
-  for (int i = lane; i < 2 * SF_NMAX; i += TL) L.lst[i] = 0u;
+  for (int i = lane; i < 2 * LL::RN; i += TL) L.lst[i] = 0u;
   if (lane == 0) L.misc[1] = 0;
   __syncthreads();
   TIC(7);
   // load state
-  for (int i = lane; i < SF_NMAX * SF_WMAX; i += TL) {
-    L.rx[i] = i < n * SF_WMAX ? st->rx[i] : 0ull;
-    L.rz[i] = i < n * SF_WMAX ? st->rz[i] : 0ull;
+  for (int i = lane; i < LL::RN * LL::RW; i += TL) {
+    const int r = i / LL::RW, w = i % LL::RW;  // TrackState rows hold SF_WMAX words
+    L.rx[i] = r < n ? st->rx[r * SF_WMAX + w] : 0ull;
+    L.rz[i] = r < n ? st->rz[r * SF_WMAX + w] : 0ull;
   }
   if (lane < SF_WMAX) L.s0[lane] = st->s0[lane];
   if (lane < d) for (int w = 0; w < SF_WMAX; ++w) L.V[lane][w] = st->V[lane][w];
@@ -1106,7 +1122,7 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
     int rnd = 0;
     for (int it = 0; it < R; ++it) {
       int i = it * 64 + lane;
-      rnd |= __ballot(i < n && getb(&L.rx[i * SF_WMAX], q)) != 0ull;
+      rnd |= __ballot(i < n && getb(&L.rx[i * LL::RW], q)) != 0ull;
     }
     int d_entry = d;
     if (!job.dry) {
@@ -1136,7 +1152,7 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
       int p = -1, pl = -1;
       for (int it = 0; it < R; ++it) {
         int i = it * 64 + lane;
-        bool has = i < n && getb(&L.rx[i * SF_WMAX], q);
+        bool has = i < n && getb(&L.rx[i * LL::RW], q);
         uint64_t bb = __ballot(has);
         if (lane == 0) L.dq[it] = bb;
         int myl = has ? (int)L.lead[i] : -1;
@@ -1157,8 +1173,8 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
       for (int it = 0; it < R; ++it) {
         int i = it * 64 + lane;
         if (i >= n || i == p || !getb(&L.dq[0], i)) continue;
-        int c = rowprod_sign(&L.rx[i * SF_WMAX], &L.rz[i * SF_WMAX], &L.rx[p * SF_WMAX], &L.rz[p * SF_WMAX]);
-        for (int w = 0; w < W; ++w) { L.rx[i * SF_WMAX + w] ^= L.rx[p * SF_WMAX + w]; L.rz[i * SF_WMAX + w] ^= L.rz[p * SF_WMAX + w]; }
+        int c = rowprod_sign(&L.rx[i * LL::RW], &L.rz[i * LL::RW], &L.rx[p * LL::RW], &L.rz[p * LL::RW]);
+        for (int w = 0; w < W; ++w) { L.rx[i * LL::RW + w] ^= L.rx[p * LL::RW + w]; L.rz[i * LL::RW + w] ^= L.rz[p * LL::RW + w]; }
         atomicOr((unsigned long long*)&L.rmask[i >> 6], 1ull << (i & 63));
         if (c) atomicOr((unsigned long long*)&L.cmask[i >> 6], 1ull << (i & 63));
       }
@@ -1169,15 +1185,16 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
       for (int it = 0; it < R; ++it) {
         const int qq = it * 64 + lane;
         if (qq < n) {
-          L.cx[qq * SF_WMAX + (p >> 6)] &= ~(1ull << (p & 63));
-          L.cz[qq * SF_WMAX + (p >> 6)] &= ~(1ull << (p & 63));
+          L.cx[qq * LL::RW + (p >> 6)] &= ~(1ull << (p & 63));
+          L.cz[qq * LL::RW + (p >> 6)] &= ~(1ull << (p & 63));
         }
       }
       __syncthreads();
       if (lane == 0) {
-        for (int w = 0; w < SF_WMAX; ++w) { L.rx[p * SF_WMAX + w] = 0; L.rz[p * SF_WMAX + w] = 0; L.u[w] = 0; }
-        flipb(&L.rz[p * SF_WMAX], q);
-        flipb(&L.cz[q * SF_WMAX], p);
+        for (int w = 0; w < W; ++w) { L.rx[p * LL::RW + w] = 0; L.rz[p * LL::RW + w] = 0; }
+        for (int w = 0; w < SF_WMAX; ++w) L.u[w] = 0;
+        flipb(&L.rz[p * LL::RW], q);
+        flipb(&L.cz[q * LL::RW], p);
         flipb(L.u, p);
         if (getb(L.s0, p)) flipb(L.s0, p);
       }
@@ -1186,7 +1203,7 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
       for (int it = 0; it < R; ++it) {
         int i = it * 64 + lane;
         if (i >= n) continue;
-        L.lead[i] = (int16_t)row_lead(&L.rx[i * SF_WMAX], &L.rz[i * SF_WMAX], n);
+        L.lead[i] = (int16_t)row_lead(&L.rx[i * LL::RW], &L.rz[i * LL::RW], n);
       }
       __syncthreads();
       repair(L, n, d, true, 0);
@@ -1303,7 +1320,11 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
   regs_store(L, TB, n, false);
   __syncthreads();
   // write back
-  for (int i = lane; i < n * SF_WMAX; i += TL) { st->rx[i] = L.rx[i]; st->rz[i] = L.rz[i]; }
+  for (int i = lane; i < n * LL::RW; i += TL) {
+    const int r = i / LL::RW, w = i % LL::RW;
+    st->rx[r * SF_WMAX + w] = L.rx[i];
+    st->rz[r * SF_WMAX + w] = L.rz[i];
+  }
   if (lane < SF_WMAX) st->s0[lane] = L.s0[lane];
   if (lane < d) for (int w = 0; w < SF_WMAX; ++w) st->V[lane][w] = L.V[lane][w];
   if (lane == 0) {
@@ -1315,65 +1336,6 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
     if (err && !st->error) st->error = err;
     L.tc[7] += TCLOCK();
     for (int k = 0; k < 16; ++k) st->cycles[k] += L.tc[k];
-  }
-}
-
-static __device__ void readout_body(Lds& L, int16_t* rank, const TrackState* st, const uint8_t* outcomes, ReadoutInfo* ri) {
-  const int lane = lane_id();
-  const int n = st->n;
-  int d = st->d;
-  for (int i = lane; i < 2 * SF_NMAX; i += TL) L.lst[i] = 0u;
-  if (lane == 0) L.misc[1] = 0;
-  for (int i = lane; i < SF_NMAX * SF_WMAX; i += TL) {
-    L.rx[i] = i < n * SF_WMAX ? st->rx[i] : 0ull;
-    L.rz[i] = i < n * SF_WMAX ? st->rz[i] : 0ull;
-  }
-  if (lane < SF_WMAX) L.s0[lane] = st->s0[lane];
-  if (lane < d) for (int w = 0; w < SF_WMAX; ++w) L.V[lane][w] = st->V[lane][w];
-  __syncthreads();
-  if (st->pend) apply_pending(L, st, outcomes, &d);
-  build_cols(L, n);
-  rebuild_index(L, n);
-  repair(L, n, d, false, 1);
-  rebuild_index(L, n);
-  for (int i = lane; i < n; i += TL) {
-    int r = 0, li = L.lead[i];
-    for (int j = 0; j < n; ++j) r += L.lead[j] < li;
-    rank[i] = (int16_t)r;
-  }
-  __syncthreads();
-  for (int i = lane; i < n; i += TL) {
-    int r = rank[i];
-    for (int w = 0; w < W; ++w) {
-      ri->tab[(size_t)r * 2 * W + w] = L.rx[i * SF_WMAX + w];
-      ri->tab[(size_t)r * 2 * W + W + w] = L.rz[i * SF_WMAX + w];
-    }
-  }
-  // hull in canonical row order
-  if (lane <= d) {
-    const uint64_t* vec = lane < d ? L.V[lane] : L.s0;
-    uint64_t out[SF_WMAX] = {0, 0, 0, 0};
-    for (int i = 0; i < n; ++i)
-      if (getb(vec, i)) flipb(out, rank[i]);
-    for (int w = 0; w < SF_WMAX; ++w) {
-      if (lane < d) ri->V[lane][w] = out[w];
-      else ri->s0[w] = out[w];
-      L.hbN[lane][w] = out[w];
-    }
-  }
-  __syncthreads();
-  // descending echelon pivots of span(V)
-  int nr = 0;
-  span_reduce(L.hbN, nullptr, d, (int*)L.ech, &nr);
-  __syncthreads();
-  if (lane == 0) {
-    int hb[SF_DMAX];
-    for (int a = 0; a < nr && a < SF_DMAX; ++a) hb[a] = (int)L.ech[a];
-    for (int a = 0; a < nr; ++a)  // descending
-      for (int b = a + 1; b < nr; ++b)
-        if (hb[b] > hb[a]) { int t = hb[a]; hb[a] = hb[b]; hb[b] = t; }
-    for (int a = 0; a < nr; ++a) ri->piv[a] = hb[a];
-    ri->n = n; ri->W = W; ri->d = d; ri->pad = nr == d ? 0 : 1;
   }
 }
 };
@@ -2430,23 +2392,26 @@ static __device__ void readout_body(Lds& L, int16_t* rank, const TrackState* st,
 // register allocation.
 // One frame: the range given by value.
 template <int W>
-__device__ __forceinline__ void track_w(Lds& L, const TrackJob& job) {
-  if constexpr (W <= 2) Trk<W>::track_body(L, job);
-  else TrkL<W>::track_body(L, job);
+__device__ __forceinline__ void track_w(const TrackJob& job) {
+  if constexpr (W <= 2) {
+    __shared__ typename Trk<W>::LL L;
+    Trk<W>::track_body(L, job);
+  } else {
+    __shared__ Lds L;
+    TrkL<W>::track_body(L, job);
+  }
 }
 
 template <int W>
 __global__ void __launch_bounds__(TL) sf_track_one(TrackJob one) {
-  __shared__ Lds L;
-  track_w<W>(L, one);
+  track_w<W>(one);
 }
 
 // Many frames of the same W: workgroup b runs jobs[b].
 template <int W>
 __global__ void __launch_bounds__(TL) sf_track_many(const TrackJob* __restrict__ jobs) {
-  __shared__ Lds L;
   const TrackJob job = jobs[blockIdx.x];
-  track_w<W>(L, job);
+  track_w<W>(job);
 }
 
 // Readout: canonical (fully reduced, pivot-sorted) tableau, the hull in that
@@ -2456,8 +2421,8 @@ sf_readout_track(const TrackState* st, const uint8_t* outcomes, ReadoutInfo* ri)
   __shared__ Lds L;
   __shared__ int16_t rank[SF_NMAX];
   switch (st->W) {
-    case 1: Trk<1>::readout_body(L, rank, st, outcomes, ri); break;
-    case 2: Trk<2>::readout_body(L, rank, st, outcomes, ri); break;
+    case 1: TrkL<1>::readout_body(L, rank, st, outcomes, ri); break;
+    case 2: TrkL<2>::readout_body(L, rank, st, outcomes, ri); break;
     case 3: TrkL<3>::readout_body(L, rank, st, outcomes, ri); break;
     default: TrkL<4>::readout_body(L, rank, st, outcomes, ri); break;
   }
