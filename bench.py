@@ -310,6 +310,8 @@ def main():
     ap.add_argument("--path", default="batched", choices=["graph", "batched", "plain"])
     ap.add_argument("--serve-jobs", type=int, default=48, help="0 skips the serving run")
     ap.add_argument("--no-extra", action="store_true", help="skip the many-frame batched workloads")
+    ap.add_argument("--probe-only", action="store_true",
+                    help="run only the HBM-bound element probe and print its JSON (for counter runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, one device-to-device copy of this size (counter calibration)")
     ap.add_argument("--tune-lo", type=int, default=8)
@@ -328,6 +330,15 @@ def main():
 
     eng = sf.Engine(0)
     tuned = eng.autotune(args.tune_lo, args.tune_hi) if args.tune_hi >= args.tune_lo else {}
+    if args.probe_only:
+        probe = hbm_probe(eng, wl)
+        if args.calib_copy_mib > 0:
+            src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+        print(json.dumps({"element_hbm_probe": probe}), flush=True)
+        return
     if args.workload == "cfg2":
         circs = [wl.config2(j) for j in range(args.jobs)]
         seeds = [wl.derive_seed(2, j) for j in range(args.jobs)]
