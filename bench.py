@@ -68,9 +68,9 @@ def terminal_indices(circ, wl):
     return out
 
 
-def accounting(state, circ, seed, wl):
+def accounting(state, circ, seed, wl, sizes=None):
     """Untimed pass: U (sum over gates of |F| before the gate) and the hull
-    dimension on entry to every segment launch."""
+    dimension on entry to every segment launch (and, into sizes, |F| there)."""
     state.reset(circ.init_bits, seed)
     terms = terminal_indices(circ, wl)
     U, K, d, pos = 0, 1, 0, 0
@@ -78,6 +78,8 @@ def accounting(state, circ, seed, wl):
     ends = terms + ([len(circ.gates) - 1] if (not terms or terms[-1] != len(circ.gates) - 1) else [])
     for t in ends:
         seg_dims.append(d)
+        if sizes is not None:
+            sizes.append(K)
         U += K * (t - pos + 1)
         k = state.step(t + 1 - pos)
         assert k == t + 1 - pos, (k, t, pos)
@@ -197,6 +199,47 @@ def hbm_probe(eng, wl, d=26, det_gates=24, reps=3):
             "note": f"phase-only segment passes over 2^{d} complex128 slots ({(16 << d) >> 20} MiB per buffer)"}
 
 
+def large_frame(eng, wl, m=12, reps=2):
+    """Element kernels on a large frame of a real circuit: the Cuccaro adder
+    of the served mix (m-bit registers, inputs in superposition, Toffolis as
+    7-T networks) grows one frame to 2^(2m+2) elements.  Algorithmic bytes,
+    a lower bound for every segment kind: each of the 2^d slots on entry is
+    read once (16 B) and each of the |F| live elements written once (16 B); a
+    split writes every slot of both halves, so it moves more than this."""
+    import torch
+    c = wl.cuccaro_adder(m, name=f"cuccaro-m{m}")
+    lc = eng.load(c.n, c)
+    st = lc.state(c.init_bits, 1)
+    Ks = []
+    U, dims = accounting(st, c, 1, wl, sizes=Ks)
+    st.reset(c.init_bits, 1)
+    st.run()
+    torch.cuda.synchronize()
+    eng.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st.reset(c.init_bits, 1)
+        st.run()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    prof = eng.profile_read()
+    eng.profile(False)
+    seg_ms, seg_n = prof["segment"]
+    seg_ms /= reps
+    seg_bytes = sum(16.0 * (1 << d) + 16.0 * k for d, k in zip(dims, Ks))
+    gbs = seg_bytes / (seg_ms / 1e3) / 1e9 if seg_ms > 0 else 0.0
+    out = {"workload": f"Cuccaro adder m={m} ({c.n} qubits), inputs in superposition, 7-T Toffolis",
+           "gates": len(c), "max_frame_log2": max(dims + [st.dim()]), "final_frame_size": st.frame_size(),
+           "ms_per_circuit": wall * 1e3, "U": U, "value": U / wall,
+           "segment_ms": seg_ms, "segment_launches": seg_n // reps,
+           "track_ms": prof["track"][0] / reps,
+           "element_roofline": {"bound": "hbm", "kernel": "sf_seg_kernel", "achieved": gbs,
+                                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                                "bytes_per_circuit": seg_bytes}}
+    st.close()
+    return out
+
+
 def direct_vs_decomposed(eng, wl, reps=3):
     """Wall time per circuit (plain path, one frame) of the decomposed and the
     direct (double-cofactor) forms of controlled rotations and Toffolis."""
@@ -299,6 +342,18 @@ def serve_bench(eng, sf, wl, n_jobs, tick_segments, max_resident, budget_bytes, 
             "circuit_load_ms_mean": load_s / n_jobs * 1e3}
 
 
+def calib_copy(mib):
+    """One device-to-device copy of mib MiB: the reference for the HBM byte
+    counters (its FETCH_SIZE / WRITE_SIZE should read mib MiB each)."""
+    if mib <= 0:
+        return
+    import torch
+    src = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,6 +367,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the many-frame batched workloads")
     ap.add_argument("--probe-only", action="store_true",
                     help="run only the HBM-bound element probe and print its JSON (for counter runs)")
+    ap.add_argument("--large-only", action="store_true",
+                    help="run only the large-frame circuit (element kernels on a 2^26-element frame)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, one device-to-device copy of this size (counter calibration)")
     ap.add_argument("--tune-lo", type=int, default=8)
@@ -332,12 +389,13 @@ def main():
     tuned = eng.autotune(args.tune_lo, args.tune_hi) if args.tune_hi >= args.tune_lo else {}
     if args.probe_only:
         probe = hbm_probe(eng, wl)
-        if args.calib_copy_mib > 0:
-            src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
-            dst = torch.empty_like(src)
-            dst.copy_(src)
-            torch.cuda.synchronize()
+        calib_copy(args.calib_copy_mib)
         print(json.dumps({"element_hbm_probe": probe}), flush=True)
+        return
+    if args.large_only:
+        rec = large_frame(eng, wl)
+        calib_copy(args.calib_copy_mib)
+        print(json.dumps({"large_frame": rec}), flush=True)
         return
     if args.workload == "cfg2":
         circs = [wl.config2(j) for j in range(args.jobs)]
@@ -481,6 +539,7 @@ def main():
     if not args.no_extra:
         line["direct_forms"] = direct_vs_decomposed(eng, wl)
         line["element_hbm_probe"] = hbm_probe(eng, wl)
+        line["large_frame"] = large_frame(eng, wl)
     if args.serve_jobs > 0:
         line["serve"] = serve_bench(eng, sf, wl, args.serve_jobs, args.tick_segments, args.max_resident,
                                     int(args.serve_budget_gib * (1 << 30)))
@@ -489,11 +548,7 @@ def main():
                                                  direct=True)
     if not args.no_cpu and args.workload == "cfg2":
         line["cpu_baseline"] = cpu_baseline(circs[0], seeds[0])
-    if args.calib_copy_mib > 0:
-        src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
+    calib_copy(args.calib_copy_mib)
     print(json.dumps(line), flush=True)
 
 
