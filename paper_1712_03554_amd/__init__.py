@@ -32,7 +32,7 @@ EXPORTS = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_measure", "sf
            "sf_serve_create", "sf_serve_submit", "sf_serve_tick", "sf_serve_poll", "sf_serve_release",
            "sf_serve_cancel", "sf_serve_stats", "sf_serve_destroy"]
 
-KERNEL_KINDS = ["track", "segment", "meas_reduce", "meas_coin", "meas_filter", "readout", "init"]
+KERNEL_KINDS = ["track", "segment", "meas_reduce", "meas_coin", "meas_filter", "readout", "init", "phase", "fit"]
 
 
 class SFrameError(RuntimeError):

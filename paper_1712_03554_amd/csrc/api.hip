@@ -19,7 +19,7 @@
 #include "sf_dev.h"
 #include "track.hip"
 
-enum { PK_TRACK = 0, PK_SEG, PK_MREDUCE, PK_MFINAL, PK_MFILTER, PK_READOUT, PK_INIT, PK_N };
+enum { PK_TRACK = 0, PK_SEG, PK_MREDUCE, PK_MFINAL, PK_MFILTER, PK_READOUT, PK_INIT, PK_PHASE, PK_FIT, PK_N };
 
 struct sf_ctx {
   int device;
@@ -50,6 +50,19 @@ static int grid_for(int d) {
 
 static int words_of(uint32_t n) { return (int)((n + 63) / 64); }
 
+// Split form of the tableau track (frames of up to 128 qubits): bytes of one
+// per-gate record and words of one segment's phase sums.
+static bool split_form(uint32_t n) { return words_of(n) <= 2; }
+static int rec_stride_of(uint32_t n) {
+  const size_t W = (size_t)words_of(n);
+  const size_t b = (size_t)n * 2 * W * 8 + (SF_DMAX + 1) * W * 8 + 8;
+  return (int)((b + 255) & ~(size_t)255);
+}
+static int pe_of(int dmax) {
+  const int d = dmax < 0 ? 0 : dmax;
+  return (1 + d + d * (d - 1) / 2 + 3) & ~3;
+}
+
 static const void* track_many_fn(int W) {
   switch (W) {
     case 1: return (const void*)sf_track_many<1>;
@@ -67,6 +80,11 @@ static void launch_track_one(hipStream_t st, const TrackJob& job, int W) {
     default: hipLaunchKernelGGL(sf_track_one<4>, dim3(1), dim3(TL), 0, st, job); break;
   }
 }
+
+// Split form: the phase kernels of a track launch (len = longest range,
+// nseg = most segments among the jobs).
+static void launch_phase_one(sf_ctx* ctx, const TrackJob& job, int W);
+static void launch_phase_many(sf_ctx* ctx, const TrackJob* jobs, int count, int W, int len, int nseg);
 
 static void launch_track_many(hipStream_t st, const TrackJob* jobs, int count, int W) {
   switch (W) {
@@ -118,6 +136,33 @@ static void prof_collect(sf_ctx* ctx) {
   ctx->ev_used = 0;
 }
 
+static void launch_phase_one(sf_ctx* ctx, const TrackJob& job, int W) {
+  const int len = job.g1 - job.g0;
+  if (job.dry || !job.rec || len <= 0) return;
+  prof_begin(ctx, PK_PHASE);
+  if (W == 1) hipLaunchKernelGGL(sf_phase_one<1>, dim3(len), dim3(TL), 0, ctx->stream, job);
+  else hipLaunchKernelGGL(sf_phase_one<2>, dim3(len), dim3(TL), 0, ctx->stream, job);
+  prof_end(ctx);
+  if (job.nseg > 0) {
+    prof_begin(ctx, PK_FIT);
+    hipLaunchKernelGGL(sf_fit_one, dim3(job.nseg), dim3(TL), 0, ctx->stream, job);
+    prof_end(ctx);
+  }
+}
+
+static void launch_phase_many(sf_ctx* ctx, const TrackJob* jobs, int count, int W, int len, int nseg) {
+  if (W > 2 || count <= 0 || len <= 0) return;
+  prof_begin(ctx, PK_PHASE);
+  if (W == 1) hipLaunchKernelGGL(sf_phase_many<1>, dim3(len, count), dim3(TL), 0, ctx->stream, jobs);
+  else hipLaunchKernelGGL(sf_phase_many<2>, dim3(len, count), dim3(TL), 0, ctx->stream, jobs);
+  prof_end(ctx);
+  if (nseg > 0) {
+    prof_begin(ctx, PK_FIT);
+    hipLaunchKernelGGL(sf_fit_many, dim3(nseg, count), dim3(TL), 0, ctx->stream, jobs);
+    prof_end(ctx);
+  }
+}
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -133,12 +178,22 @@ struct sf_circuit {
   int max_segs, max_had;
   size_t n_meas;
   uint64_t projected;
+  // every path ends a device range at these gate indices (original-gate
+  // boundaries at most SF_RANGE_MAX gates apart), so that all paths split
+  // the circuit into the same segments; rec_len = longest range
+  std::vector<size_t> cuts;
+  int rec_len;
 };
+
+static bool is_cut(const sf_circuit* c, size_t e) {
+  return std::binary_search(c->cuts.begin(), c->cuts.end(), e);
+}
 
 struct sf_state {
   sf_ctx* ctx;
   const sf_circuit* c;
   DevBuf st, prog, had, amp[2], outcomes, pvals, scale, flags, partials, ri, count, adhoc;
+  DevBuf rec, ginfo, segacc;  // split form of the tableau track
   int cur;
   size_t orig_done, dev_done, nmeas;
   size_t meas_cap;  // capacity of outcomes / pvals (circuit measurements, grown by sf_measure)
@@ -405,6 +460,19 @@ extern "C" sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n, const sf_gate* gat
       }
     }
   }
+  {
+    size_t prev = 0, last = 0;
+    for (size_t e : c->orig_end) {
+      if (e - prev > SF_RANGE_MAX && last > prev) {
+        c->cuts.push_back(last);
+        prev = last;
+      }
+      last = e;
+    }
+    c->rec_len = (int)std::max<size_t>(1, std::min<size_t>(SF_RANGE_MAX, c->g.size()));
+    // a cut can leave one more (open) segment in a range
+    c->max_segs += 1;
+  }
   sf_status rc = dalloc(ctx, &c->dgates, sizeof(DGate) * std::max<size_t>(1, c->g.size()));
   if (rc != SF_OK) { delete c; return rc; }
   // dry run of the tableau track: frame bound of the whole circuit
@@ -453,6 +521,9 @@ extern "C" sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n, const sf_gate* gat
   uint64_t amp = (uint64_t)16 << dmax;
   c->projected = 2 * amp + sizeof(TrackState) + sizeof(ReadoutInfo) +
                  (uint64_t)c->max_segs * sizeof(SegProg) + (uint64_t)c->max_had * sizeof(GF2Q);
+  if (split_form(n))
+    c->projected += (uint64_t)(c->rec_len + 1) * rec_stride_of(n) + (uint64_t)c->rec_len * 8 +
+                    (uint64_t)c->max_segs * pe_of(dmax) * 4;
   *out = c;
   return SF_OK;
 }
@@ -477,7 +548,8 @@ extern "C" sf_status sf_circuit_destroy(sf_circuit* c) {
 static void state_free(sf_state* s) {
   sf_ctx* ctx = s->ctx;
   DevBuf* all[] = {&s->st, &s->prog, &s->had, &s->amp[0], &s->amp[1], &s->outcomes, &s->pvals,
-                   &s->scale, &s->flags, &s->partials, &s->ri, &s->count, &s->adhoc};
+                   &s->scale, &s->flags, &s->partials, &s->ri, &s->count, &s->adhoc,
+                   &s->rec, &s->ginfo, &s->segacc};
   for (DevBuf* b : all) dfree(ctx, b);
 }
 
@@ -549,7 +621,11 @@ extern "C" sf_status sf_state_init(sf_ctx* ctx, const sf_circuit* c, const uint6
       (rc = dalloc(ctx, &s->pvals, 8 * std::max<size_t>(1, c->n_meas))) ||
       (rc = dalloc(ctx, &s->scale, 8)) || (rc = dalloc(ctx, &s->flags, 8)) ||
       (rc = dalloc(ctx, &s->partials, 16 * (size_t)s->G)) || (rc = dalloc(ctx, &s->ri, sizeof(ReadoutInfo))) ||
-      (rc = dalloc(ctx, &s->count, 8))) {
+      (rc = dalloc(ctx, &s->count, 8)) ||
+      (split_form(c->n) &&
+       ((rc = dalloc(ctx, &s->rec, (size_t)(c->rec_len + 1) * rec_stride_of(c->n))) ||
+        (rc = dalloc(ctx, &s->ginfo, (size_t)c->rec_len * 8)) ||
+        (rc = dalloc(ctx, &s->segacc, (size_t)c->max_segs * pe_of(c->dmax) * 4))))) {
     state_free(s);
     delete s;
     return rc;
@@ -557,6 +633,8 @@ extern "C" sf_status sf_state_init(sf_ctx* ctx, const sf_circuit* c, const uint6
   sf_status r2 = queue_init(s, basis, seed);
   if (r2 == SF_OK) {
     hipError_t e = hipMemsetAsync(s->outcomes.p, 0, std::max<size_t>(1, c->n_meas), ctx->stream);
+    // gate info of the split form starts as "no segment, no Hadamard term"
+    if (e == hipSuccess && s->ginfo.p) e = hipMemsetAsync(s->ginfo.p, 0xff, s->ginfo.bytes, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) r2 = fail(ctx, SF_E_DEVICE, "state init: %s", hipGetErrorString(e));
   }
@@ -580,7 +658,18 @@ extern "C" sf_status sf_state_destroy(sf_state* s) {
 
 // Queue the device gates [a, b) of dgates (device copy) / hg (host copy); b
 // ends at most right after a measurement.
-static sf_status run_gates(sf_state* s, const DGate* dgates, const DGate* hg, size_t a, size_t b) {
+// The split-form buffers of a state in a track job (no-op for wider frames).
+static void split_fields(const sf_state* s, TrackJob* job, int nseg) {
+  job->nseg = nseg;
+  if (!split_form(s->c->n) || job->dry) return;
+  job->rec = (uint8_t*)s->rec.p;
+  job->ginfo = (int32_t*)s->ginfo.p;
+  job->segacc = (uint32_t*)s->segacc.p;
+  job->rec_stride = rec_stride_of(s->c->n);
+  job->pe = pe_of(s->c->dmax);
+}
+
+static sf_status run_chunk(sf_state* s, const DGate* dgates, const DGate* hg, size_t a, size_t b) {
   sf_ctx* ctx = s->ctx;
   const sf_circuit* c = s->c;
   if (a >= b) return SF_OK;
@@ -588,6 +677,17 @@ static sf_status run_gates(sf_state* s, const DGate* dgates, const DGate* hg, si
   for (size_t i = a; i < b; ++i) nm += hg[i].op == DG_MEASURE;
   if (s->nmeas + nm > s->meas_cap)
     return fail(ctx, SF_E_STATE, "outcome buffer holds %zu measurements, %zu needed", s->meas_cap, s->nmeas + nm);
+  // segments: one per non-Clifford phase gate or measurement, plus a final one
+  int nseg = 0;
+  bool open = false, meas_last = false;
+  for (size_t i = a; i < b; ++i) {
+    int op = hg[i].op;
+    if (is_terminal(op)) { ++nseg; open = false; meas_last = op == DG_MEASURE; }
+    else { open = true; meas_last = false; }
+  }
+  if (open) ++nseg;
+  if (nseg > c->max_segs || (split_form(c->n) && b - a > (size_t)c->rec_len))
+    return fail(ctx, SF_E_STATE, "range of %zu gates with %d segments exceeds the state's buffers", b - a, nseg);
   TrackJob job;
   memset(&job, 0, sizeof job);
   job.st = (TrackState*)s->st.p;
@@ -598,19 +698,12 @@ static sf_status run_gates(sf_state* s, const DGate* dgates, const DGate* hg, si
   job.had = (GF2Q*)s->had.p;
   job.outcomes = (const uint8_t*)s->outcomes.p;
   job.dry = 0;
+  split_fields(s, &job, nseg);
   prof_begin(ctx, PK_TRACK);
   launch_track_one(ctx->stream, job, words_of(c->n));
   prof_end(ctx);
+  launch_phase_one(ctx, job, words_of(c->n));
   HIPCHK(ctx, hipGetLastError());
-  // segments: one per non-Clifford phase gate or measurement, plus a final one
-  int nseg = 0;
-  bool open = false, meas_last = false;
-  for (size_t i = a; i < b; ++i) {
-    int op = hg[i].op;
-    if (is_terminal(op)) { ++nseg; open = false; meas_last = op == DG_MEASURE; }
-    else { open = true; meas_last = false; }
-  }
-  if (open) ++nseg;
   int eb, grid;
   elem_shape(ctx, c->dmax, &eb, &grid);
   const SegProg* prog = (const SegProg*)s->prog.p;
@@ -640,6 +733,21 @@ static sf_status run_gates(sf_state* s, const DGate* dgates, const DGate* hg, si
   }
   HIPCHK(ctx, hipGetLastError());
   return SF_OK;
+}
+
+// Device gates [a, b): in ranges that end at the circuit's cuts (the
+// circuit's own gates) so that every path forms the same segments.
+static sf_status run_gates(sf_state* s, const DGate* dgates, const DGate* hg, size_t a, size_t b) {
+  const sf_circuit* c = s->c;
+  if (dgates == (const DGate*)c->dgates.p) {
+    auto it = std::upper_bound(c->cuts.begin(), c->cuts.end(), a);
+    for (; it != c->cuts.end() && *it < b; ++it) {
+      sf_status rc = run_chunk(s, dgates, hg, a, *it);
+      if (rc != SF_OK) return rc;
+      a = *it;
+    }
+  }
+  return run_chunk(s, dgates, hg, a, b);
 }
 
 static sf_status run_range(sf_state* s, size_t a, size_t b) {
@@ -910,7 +1018,7 @@ static void plan_range(const sf_circuit* c, const Progress& pr, size_t* a, size_
     bool cut = cap > 0 && terms >= cap && end > e && is_terminal(c->g[end - 1].op);
     e = end;
     ++o;
-    if (meas || cut) break;
+    if (meas || cut || is_cut(c, e)) break;
   }
   *b = e;
   *orig_after = o;
@@ -953,6 +1061,8 @@ struct RoundPlan {
   int na = 0, kmax = 0, gx = 1, bx = EB, gm = 1;
   bool anym = false;
   int wcount[SF_WMAX + 1] = {0, 0, 0, 0, 0};  // frames per word count (jobs are ordered by it)
+  int wlen[SF_WMAX + 1] = {0, 0, 0, 0, 0};    // per word count: longest range, most segments
+  int wseg[SF_WMAX + 1] = {0, 0, 0, 0, 0};
 };
 
 // Plans the next round from the progress pr[] and advances it; false when no
@@ -979,7 +1089,7 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
   std::stable_sort(act.begin(), act.end(), [&](int u, int v) {
     return words_of(states[u]->c->n) < words_of(states[v]->c->n);
   });
-  for (int w = 0; w <= SF_WMAX; ++w) rp->wcount[w] = 0;
+  for (int w = 0; w <= SF_WMAX; ++w) rp->wcount[w] = rp->wlen[w] = rp->wseg[w] = 0;
   for (int i : act) rp->wcount[words_of(states[i]->c->n)]++;
   const int na = (int)act.size();
   rp->na = na;
@@ -1000,6 +1110,15 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
     jb.prog = (SegProg*)s->prog.p;
     jb.had = (GF2Q*)s->had.p;
     jb.outcomes = (const uint8_t*)s->outcomes.p;
+    if (NS[i] > s->c->max_segs || (split_form(s->c->n) && B[i] - A[i] > (size_t)s->c->rec_len)) {
+      *err = fail(s->ctx, SF_E_STATE, "state %d: range of %zu gates with %d segments exceeds its buffers", i,
+                  B[i] - A[i], NS[i]);
+      return false;
+    }
+    split_fields(s, &jb, NS[i]);
+    const int wi = words_of(s->c->n);
+    rp->wlen[wi] = std::max(rp->wlen[wi], (int)(B[i] - A[i]));
+    rp->wseg[wi] = std::max(rp->wseg[wi], NS[i]);
     rp->kmax = std::max(rp->kmax, NS[i]);
     dm = std::max(dm, s->c->dmax);
     rp->gm = std::max(rp->gm, s->G);
@@ -1066,6 +1185,7 @@ static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs
     prof_begin(ctx, PK_TRACK);
     launch_track_many(ctx->stream, djobs + off, rp.wcount[w], w);
     prof_end(ctx);
+    if (split_form(64 * w)) launch_phase_many(ctx, djobs + off, rp.wcount[w], w, rp.wlen[w], rp.wseg[w]);
     off += rp.wcount[w];
   }
   for (int k = 0; k < rp.kmax; ++k) {
@@ -1413,6 +1533,13 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
       const TrackJob* djw = dj + off;
       void* args[] = {(void*)&djw};
       e = add_kernel_node(g->graph, &last, track_many_fn(w), dim3(rp.wcount[w]), dim3(TL), args);
+      if (e == hipSuccess && split_form(64 * w) && rp.wlen[w] > 0) {
+        const void* ph = w == 1 ? (const void*)sf_phase_many<1> : (const void*)sf_phase_many<2>;
+        e = add_kernel_node(g->graph, &last, ph, dim3(rp.wlen[w], rp.wcount[w]), dim3(TL), args);
+        if (e == hipSuccess && rp.wseg[w] > 0)
+          e = add_kernel_node(g->graph, &last, (const void*)sf_fit_many, dim3(rp.wseg[w], rp.wcount[w]), dim3(TL),
+                              args);
+      }
       off += rp.wcount[w];
     }
     for (int k = 0; k < rp.kmax && e == hipSuccess; ++k) {

@@ -89,6 +89,18 @@ struct TrackState {
 };
 
 // One circuit range for the tableau-track kernel.
+//
+// Split form (frames of up to 128 qubits): the track kernel only conjugates,
+// repairs and records the state after every gate (rec: g1 - g0 + 1 records of
+// rec_stride bytes, record 0 = the state on entry; a record holds the rows
+// (x then z words of each slot), s0 and V[0..SF_DMAX) of W words, then d); a
+// phase kernel evaluates every Clifford gate's phase factor at the fitting
+// points from the records on both sides of it (one wavefront per gate) and
+// adds it into its segment's sums (segacc: pe words per segment); a fit
+// kernel turns each segment's sums into its program's phase E.
+// ginfo[2 i] = segment of gate g0 + i, ginfo[2 i + 1] = index of its GF(2)
+// Hadamard term in had (or -1).  rec == nullptr: everything in the track
+// kernel.
 struct TrackJob {
   TrackState* st;
   const DGate* gates;
@@ -97,8 +109,16 @@ struct TrackJob {
   GF2Q* had;
   const uint8_t* outcomes;
   int32_t dry;
-  int32_t pad;
+  int32_t nseg;            // segments of this range (split form)
+  uint8_t* rec;
+  int32_t* ginfo;
+  uint32_t* segacc;
+  int32_t rec_stride;      // bytes per record
+  int32_t pe;              // words per segment in segacc (>= points of the largest d)
 };
+
+// longest gate range of one split-form track launch (bounds the records)
+#define SF_RANGE_MAX 1024
 
 enum { TRK_OK = 0, TRK_E_DIM = 1, TRK_E_INTERNAL = 2, TRK_E_SEGS = 3 };
 

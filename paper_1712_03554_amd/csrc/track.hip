@@ -15,6 +15,15 @@
 //     every phase vector, and the amplitude factor of each cofactor.
 // The results are per-segment programs (SegProg) that the element kernels in
 // elem.hip apply to the amplitude array.
+//
+// For frames of up to 128 qubits the work is split over three kernels: the
+// track kernel walks the gates in order doing only what must be sequential
+// (the tableau update, the echelon repair with its replay on the hull, the
+// cofactors) and records the state after every gate; the phase kernel then
+// evaluates every Clifford gate's phase factor at the fitting points from the
+// records before and after it, one wavefront per gate, all gates at once; the
+// fit kernel sums each segment's factors and fits its quadratic form.  Wider
+// frames (TrkL) do all of it in the track kernel.
 #include <hip/hip_runtime.h>
 
 #include "sf_dev.h"
@@ -520,29 +529,6 @@ static __device__ void build_beta(LL& L, int n) {
   __syncthreads();
 }
 
-// The same from the register tableau (rows already in LDS, xpiv current).
-static __device__ __forceinline__ void build_beta_regs(LL& L, const Regs& R, int n) {
-  const int lane = lane_id();
-  // all pivot lookups first, then all row reads: two LDS round trips in all
-  int l[W];
-  for (int k = 0; k < W; ++k) {
-    const int ld = R.ld[k];
-    l[k] = (64 * k + lane < n && ld >= n) ? (int)L.xpiv[ld - n] : -1;
-  }
-  for (int k = 0; k < W; ++k) {
-    const int h = 64 * k + lane;
-    const int ld = R.ld[k];
-    if (h >= n) continue;
-    const int q = ld - n;
-    for (int w = 0; w < W; ++w) {
-      uint64_t b = (ld >= n && w == (q >> 6)) ? 1ull << (q & 63) : 0ull;
-      if (l[k] >= 0) b ^= L.rx[l[k] * LL::RW + w];
-      L.beta[h * LL::RW + w] = b;
-    }
-  }
-  __syncthreads();
-}
-
 static __device__ void bimage(const LL& L, const uint64_t* vec, uint64_t* out) {
   uint64_t acc[SF_WMAX] = {0, 0, 0, 0};
   for (int w = 0; w < W; ++w) {
@@ -710,185 +696,6 @@ static __device__ __forceinline__ void conj_regs(LL& L, Regs& R, int op, int a, 
     for (int w = 0; w < W; ++w) L.s0[w] ^= fm[w];
 }
 
-// Pivot index from the register tableau (xpiv / zpiv / zsm / X-block size)
-// and the LDS snapshot of the rows and leads.  Ends with a barrier.
-static __device__ __forceinline__ void index_regs(LL& L, const Regs& R, int n) {
-  const int lane = lane_id();
-  for (int i = lane; i < LL::RN; i += TL) { L.xpiv[i] = -1; L.zpiv[i] = -1; }
-  regs_store(L, R, n, false);
-  __syncthreads();
-  int kx = 0;
-  for (int k = 0; k < W; ++k) {
-    const int i = 64 * k + lane;
-    const int c = R.ld[k];
-    const bool ok = i < n;
-    if (ok && c >= 0 && c < n) L.xpiv[c] = (int16_t)i;
-    else if (ok && c >= n) L.zpiv[c - n] = (int16_t)i;
-    const uint64_t bx = __ballot(ok && c >= 0 && c < n), bz = __ballot(ok && c >= n);
-    kx += __popcll(bx);
-    if (lane == 0) L.zsm[k] = bz;
-  }
-  if (lane == 0) {
-    for (int k = W; k < SF_WMAX; ++k) L.zsm[k] = 0;
-    L.misc[0] = kx;
-  }
-  __syncthreads();
-}
-
-// Pre-gate snapshot for the phase evaluation: rows, their Y counts, the
-// x-pivot index and mask, the hull and its b* images.
-static __device__ __forceinline__ void save_old_regs(LL& L, const Regs& R, int n, int d) {
-  const int lane = lane_id();
-  for (int k = 0; k < W; ++k) {
-    const int i = 64 * k + lane;
-    const int ld = R.ld[k];
-    if (i >= n || ld < 0 || ld >= n) continue;
-    int c = 0;
-    for (int w = 0; w < W; ++w) {
-      L.ox[ld * LL::RW + w] = R.x[k][w];
-      L.oz[ld * LL::RW + w] = R.z[k][w];
-      c += __popcll(R.x[k][w] & R.z[k][w]);
-    }
-    L.ow[ld] = (uint8_t)(c & 3);
-  }
-  for (int i = lane; i < LL::RN; i += TL) L.oxpiv[i] = i < n ? L.xpiv[i] : (int16_t)-1;
-  if (lane < d) for (int w = 0; w < SF_WMAX; ++w) L.oV[lane][w] = L.V[lane][w];
-  if (lane == d) for (int w = 0; w < SF_WMAX; ++w) L.os0[w] = L.s0[w];
-  if (lane <= d + 1) for (int w = 0; w < SF_WMAX; ++w) L.hbO[lane][w] = L.hbN[lane][w];
-  for (int it = 0; it < SF_WMAX; ++it) {
-    const int q = it * 64 + lane;
-    const uint64_t m = __ballot(q < n && L.xpiv[q] >= 0);
-    if (lane == 0) L.oxpm[it] = m;
-  }
-  __syncthreads();
-}
-
-// ---------------------------------------------------------------------------
-// Clifford gate on the register tableau
-// ---------------------------------------------------------------------------
-static __device__ __forceinline__ void clifford_gate(LL& L, Regs& R, int op, int a, int b, int n, int d, int dry, GF2Q* had_out,
-                                     int* nhad, int* err) {
-  const int lane = lane_id();
-  if (op == DG_S || op == DG_SDG || op == DG_Z || op == DG_CZ) {
-    // Diagonal gates change only z bits of X-block rows and flip only X-block
-    // signs: the echelon form, the support and b*(sigma) stay as they are, and
-    // U|b*> = mu(b*) |b*>, so omega(Y) = mu(b*(sigma(Y))).
-    TIC(1);
-    conj_regs(L, R, op, a, b, n);
-    __syncthreads();
-    TOC(1);
-    if (dry) return;
-    TIC(4);
-    const int P = npoints(d);
-    for (int p = lane; p < P; p += TL) {
-      uint32_t Y = L.Ys[p];
-      int ba = getb(L.hbN[0], a), bb = op == DG_CZ ? getb(L.hbN[0], b) : 0;
-      while (Y) {
-        const int j = __builtin_ctz(Y);
-        Y &= Y - 1;
-        ba ^= getb(L.hbN[1 + j], a);
-        if (op == DG_CZ) bb ^= getb(L.hbN[1 + j], b);
-      }
-      int mu = op == DG_S ? ba : op == DG_SDG ? 3 * ba : op == DG_Z ? 2 * ba : 2 * (ba & bb);
-      L.acc[p] = (uint8_t)((L.acc[p] + mu) & 3);
-    }
-    __syncthreads();
-    TOC(4);
-    return;
-  }
-  TIC(0);
-  if (!dry) save_old_regs(L, R, n, d);
-  TOC(0);
-  const int kold = L.misc[0];
-  TIC(1);
-  conj_regs(L, R, op, a, b, n);
-  __syncthreads();
-  TOC(1);
-  TIC(2);
-  repair_core(L, R, n, d, false, 0);
-  TOC(2);
-  TIC(3);
-  TIC(12);
-  index_regs(L, R, n);
-  TOC(12);
-  if (dry) { TOC(3); return; }
-  const int knew = L.misc[0];
-  TIC(13);
-  build_beta_regs(L, R, n);
-  TOC(13);
-  TIC(14);
-  hull_images(L, L.hbN, d, false);
-  TOC(14);
-  TOC(3);
-#ifdef SF_TRACK_TIMERS
-  if (lane == 0) L.tc[15] += npoints(d);
-#endif
-  // per-element phase factor omega(Y), sampled at the fitting points
-  const int dk = knew - kold;
-  const bool hsplit = op == DG_H && dk == 0;
-  TIC(4);
-  const int P = npoints(d);
-  for (int p = lane; p < P; p += TL) {
-    uint32_t Y = L.Ys[p];
-    uint64_t so[SF_WMAX], bo[SF_WMAX], bn[SF_WMAX], src[SF_WMAX];
-    point_vec(L.os0, L.oV, Y, 0, so);
-    point_vec(L.hbO[0], L.hbO, Y, 1, bo);
-    point_vec(L.hbN[0], L.hbN, Y, 1, bn);
-    int e = 0, t = 0;
-    int ba = getb(bn, a);
-    for (int w = 0; w < W; ++w) src[w] = bn[w];
-    if (op != DG_H) {
-      int mu = 0;
-      switch (op) {
-        case DG_S: mu = ba; break;
-        case DG_SDG: mu = (4 - ba) & 3; break;
-        case DG_X: flipb(src, a); break;
-        case DG_Z: mu = 2 * ba; break;
-        case DG_Y: flipb(src, a); mu = ba ? 1 : 3; break;
-        case DG_CNOT: if (ba) flipb(src, b); break;
-        case DG_CZ: mu = 2 * (ba & getb(bn, b)); break;
-      }
-      int u = uexp(L, so, bo, src);
-      if (u < 0) *err = TRK_E_INTERNAL;
-      e = mu + u;
-    } else {
-      uint64_t b1[SF_WMAX];
-      for (int w = 0; w < W; ++w) b1[w] = bn[w];
-      if (ba) flipb(src, a); else flipb(b1, a);   // src: bit a = 0, b1: bit a = 1
-      if (dk == 1) {
-        int u0 = uexp(L, so, bo, src);
-        int u1 = uexp(L, so, bo, b1);
-        if ((u0 < 0) == (u1 < 0)) *err = TRK_E_INTERNAL;
-        e = u0 >= 0 ? u0 : u1 + 2 * ba;
-      } else if (dk == -1) {
-        int u0 = uexp(L, so, bo, src);
-        if (u0 < 0) *err = TRK_E_INTERNAL;
-        e = u0;
-      } else {
-        int e0 = uexp(L, so, bo, src);
-        int e1 = uexp(L, so, bo, b1);
-        if (e0 < 0 || e1 < 0) *err = TRK_E_INTERNAL;
-        e1 += 2 * ba;
-        int dl = (e1 - e0) & 3;
-        if (!(dl & 1)) *err = TRK_E_INTERNAL;
-        e = e0;
-        t = dl == 3 ? 1 : 0;        // omega = exp(i pi (2 e0 + 1 - 2t)/4)
-      }
-    }
-    L.acc[p] = (uint8_t)((L.acc[p] + e) & 3);
-    if (hsplit) L.t0[p] = (uint8_t)t;
-  }
-  __syncthreads();
-  TOC(4);
-  if (hsplit) {
-    TIC(5);
-    fit_gf2(L, L.t0, d, &had_out[*nhad]);
-    *nhad += 1;
-    __syncthreads();
-    TOC(5);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // span test: delta with XOR_{j in delta} oV[j] == dq (slot bit vectors), or
 // 0xffffffff if dq is outside the span.  Single lane (d <= 30 vectors).
@@ -975,8 +782,8 @@ static __device__ void terminal_controlled(LL& L, const TrackJob& job, const DGa
   int d = *dptr;
   SegProg* sp = job.dry ? nullptr : job.prog + seg;
   if (!job.dry) {
+    // (its Clifford phase E is fitted by the fit kernel)
     if (lane == 0) emit_header(sp, SEG_DET2, 0, d, d, nhad, had_base);
-    fit_z4(L, L.acc, d, &sp->E, err);
     __syncthreads();
   }
   uint32_t c1, r1, c2, r2;
@@ -1040,6 +847,200 @@ static __device__ void terminal_controlled(LL& L, const TrackJob& job, const DGa
   *dptr = d;
 }
 
+// ---------------------------------------------------------------------------
+// Split form: records of the state after every gate, the per-gate phase
+// evaluation from two records, and the per-segment sums.
+// ---------------------------------------------------------------------------
+static __device__ __forceinline__ int count_x(const Regs& R, int n) {
+  const int lane = lane_id();
+  int k = 0;
+  for (int kk = 0; kk < W; ++kk) {
+    const int ld = R.ld[kk];
+    k += __popcll(__ballot(64 * kk + lane < n && ld >= 0 && ld < n));
+  }
+  return k;
+}
+
+// record r: rows from the registers, s0 / V / d from LDS (current after the
+// barrier that ends every gate)
+static __device__ __forceinline__ void rec_write(const TrackJob& job, int r, const Regs& R, const LL& L, int n,
+                                                 int d) {
+  uint64_t* rw = (uint64_t*)(job.rec + (size_t)r * job.rec_stride);
+  const int lane = lane_id();
+  for (int k = 0; k < W; ++k) {
+    const int i = 64 * k + lane;
+    if (i < n)
+      for (int w = 0; w < W; ++w) {
+        rw[i * 2 * W + w] = R.x[k][w];
+        rw[i * 2 * W + W + w] = R.z[k][w];
+      }
+  }
+  uint64_t* hv = rw + (size_t)n * 2 * W;
+  if (lane <= d)
+    for (int w = 0; w < W; ++w) hv[lane * W + w] = lane == 0 ? L.s0[w] : L.V[lane - 1][w];
+  if (lane == 0) *(int32_t*)(hv + (SF_DMAX + 1) * W) = d;
+}
+
+static __device__ __forceinline__ int rec_d(const TrackJob& job, int r, int n) {
+  const uint64_t* rw = (const uint64_t*)(job.rec + (size_t)r * job.rec_stride);
+  return *(const int32_t*)(rw + (size_t)n * 2 * W + (SF_DMAX + 1) * W);
+}
+
+static __device__ void rec_load(LL& L, const TrackJob& job, int r, int n, int d) {
+  const uint64_t* rw = (const uint64_t*)(job.rec + (size_t)r * job.rec_stride);
+  const int lane = lane_id();
+  for (int idx = lane; idx < LL::RN * LL::RW; idx += TL) {
+    const int i = idx / LL::RW, w = idx % LL::RW;
+    L.rx[idx] = i < n ? rw[i * 2 * W + w] : 0ull;
+    L.rz[idx] = i < n ? rw[i * 2 * W + W + w] : 0ull;
+  }
+  const uint64_t* hv = rw + (size_t)n * 2 * W;
+  if (lane <= d)
+    for (int w = 0; w < SF_WMAX; ++w) {
+      const uint64_t v = w < W ? hv[lane * W + w] : 0ull;
+      if (lane == 0) L.s0[w] = v;
+      else L.V[lane - 1][w] = v;
+    }
+  __syncthreads();
+}
+
+// segment s starts: its sums start at zero
+static __device__ __forceinline__ void seg_clear(const TrackJob& job, int s, int d) {
+  if (s >= job.nseg) return;
+  const int P = min(npoints(d), job.pe);
+  for (int p = lane_id(); p < P; p += TL) job.segacc[(size_t)s * job.pe + p] = 0u;
+}
+
+// Clifford gate of the split form: Table 2 and the echelon repair only.
+// Returns whether the gate is a Hadamard that keeps the support size (a GF(2)
+// term of the segment); kx carries the X-block size.
+static __device__ __forceinline__ bool clifford_gate_rec(LL& L, Regs& R, int op, int a, int b, int n, int d,
+                                                         int* kx) {
+  TIC(1);
+  conj_regs(L, R, op, a, b, n);
+  __syncthreads();
+  TOC(1);
+  if (op == DG_S || op == DG_SDG || op == DG_Z || op == DG_CZ) return false;
+  TIC(2);
+  repair_core(L, R, n, d, false, 0);
+  TOC(2);
+  const int knew = count_x(R, n);
+  const bool hs = op == DG_H && knew == *kx;
+  *kx = knew;
+  return hs;
+}
+
+// Phase factor of Clifford gate g0 + i of a split-form range at the fitting
+// points (the same evaluation as clifford_gate, from the records before and
+// after the gate), added into its segment's sums.
+static __device__ void phase_body(LL& L, const TrackJob& job, int i) {
+  const int lane = lane_id();
+  const int len = job.g1 - job.g0;
+  if (i >= len) return;
+  const DGate gt = job.gates[job.g0 + i];
+  const int op = gt.op;
+  if (op >= DG_NCPHASE) return;
+  TrackState* st = job.st;
+  const int n = st->n;
+  const int d = rec_d(job, i + 1, n);
+  const int s = job.ginfo[2 * i];
+  if (d < 0 || d >= SF_DMAX || s < 0 || s >= job.nseg || npoints(d) > job.pe || rec_d(job, i, n) != d) {
+    if (lane == 0) st->error = TRK_E_INTERNAL;
+    return;
+  }
+  uint32_t* acc = job.segacc + (size_t)s * job.pe;
+  const int a = gt.q0, b = gt.q1;
+  int err = 0;
+  const int P = npoints(d);
+  if (op == DG_S || op == DG_SDG || op == DG_Z || op == DG_CZ) {
+    // b*(sigma) is the same before and after a diagonal gate
+    rec_load(L, job, i + 1, n, d);
+    rebuild_index(L, n);
+    build_beta(L, n);
+    hull_images(L, L.hbN, d, false);
+    build_points(L, d);
+    for (int p = lane; p < P; p += TL) {
+      uint32_t Y = L.Ys[p];
+      int ba = getb(L.hbN[0], a), bb = op == DG_CZ ? getb(L.hbN[0], b) : 0;
+      while (Y) {
+        const int j = __builtin_ctz(Y);
+        Y &= Y - 1;
+        ba ^= getb(L.hbN[1 + j], a);
+        if (op == DG_CZ) bb ^= getb(L.hbN[1 + j], b);
+      }
+      const int mu = op == DG_S ? ba : op == DG_SDG ? 3 * ba : op == DG_Z ? 2 * ba : 2 * (ba & bb);
+      atomicAdd(&acc[p], (uint32_t)(mu & 3));
+    }
+    return;
+  }
+  rec_load(L, job, i, n, d);
+  rebuild_index(L, n);
+  build_beta(L, n);
+  hull_images(L, L.hbN, d, false);
+  save_old(L, n, d);
+  const int kold = L.misc[0];
+  rec_load(L, job, i + 1, n, d);
+  rebuild_index(L, n);
+  build_beta(L, n);
+  hull_images(L, L.hbN, d, false);
+  const int knew = L.misc[0];
+  build_points(L, d);
+  const int dk = knew - kold;
+  const bool hsplit = op == DG_H && dk == 0;
+  for (int p = lane; p < P; p += TL) {
+    uint32_t Y = L.Ys[p];
+    uint64_t so[SF_WMAX], bo[SF_WMAX], bn[SF_WMAX], src[SF_WMAX];
+    point_vec(L.os0, L.oV, Y, 0, so);
+    point_vec(L.hbO[0], L.hbO, Y, 1, bo);
+    point_vec(L.hbN[0], L.hbN, Y, 1, bn);
+    int e = 0, t = 0;
+    int ba = getb(bn, a);
+    for (int w = 0; w < W; ++w) src[w] = bn[w];
+    if (op != DG_H) {
+      int mu = 0;
+      switch (op) {
+        case DG_X: flipb(src, a); break;
+        case DG_Y: flipb(src, a); mu = ba ? 1 : 3; break;
+        case DG_CNOT: if (ba) flipb(src, b); break;
+      }
+      int u = uexp(L, so, bo, src);
+      if (u < 0) err = TRK_E_INTERNAL;
+      e = mu + u;
+    } else {
+      uint64_t b1[SF_WMAX];
+      for (int w = 0; w < W; ++w) b1[w] = bn[w];
+      if (ba) flipb(src, a); else flipb(b1, a);   // src: bit a = 0, b1: bit a = 1
+      if (dk == 1) {
+        int u0 = uexp(L, so, bo, src);
+        int u1 = uexp(L, so, bo, b1);
+        if ((u0 < 0) == (u1 < 0)) err = TRK_E_INTERNAL;
+        e = u0 >= 0 ? u0 : u1 + 2 * ba;
+      } else if (dk == -1) {
+        int u0 = uexp(L, so, bo, src);
+        if (u0 < 0) err = TRK_E_INTERNAL;
+        e = u0;
+      } else {
+        int e0 = uexp(L, so, bo, src);
+        int e1 = uexp(L, so, bo, b1);
+        if (e0 < 0 || e1 < 0) err = TRK_E_INTERNAL;
+        e1 += 2 * ba;
+        int dl = (e1 - e0) & 3;
+        if (!(dl & 1)) err = TRK_E_INTERNAL;
+        e = e0;
+        t = dl == 3 ? 1 : 0;        // omega = exp(i pi (2 e0 + 1 - 2t)/4)
+      }
+    }
+    atomicAdd(&acc[p], (uint32_t)(e & 3));
+    if (hsplit) L.t0[p] = (uint8_t)t;
+  }
+  __syncthreads();
+  const int hi = job.ginfo[2 * i + 1];
+  if (hsplit != (hi >= 0)) err = TRK_E_INTERNAL;
+  else if (hsplit) fit_gf2(L, L.t0, d, &job.had[hi]);
+  err = wave_max(err);
+  if (err && lane == 0) st->error = err;
+}
+
 static __device__ void track_body(LL& L, const TrackJob& job) {
   TrackState* st = job.st;
   const int lane = lane_id();
@@ -1064,15 +1065,22 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
   if (st->pend) apply_pending(L, st, job.dry ? nullptr : job.outcomes, &d);
   build_cols(L, n);
   rebuild_index(L, n);
-  if (!job.dry) {
-    build_beta(L, n);
-    hull_images(L, L.hbN, d, false);
-    build_points(L, d);
-  }
-  for (int p = lane; p < SF_PMAX; p += TL) L.acc[p] = 0;
+  if (!job.dry) build_points(L, d);
   __syncthreads();
   Regs TB;
   regs_load(L, TB, n);
+  // this kernel conjugates, repairs and records; the phase kernels evaluate
+  // the Clifford gates' phases from the records
+  const bool rec = !job.dry;
+  if (rec && !job.rec) {
+    if (lane == 0 && !st->error) st->error = TRK_E_INTERNAL;
+    return;
+  }
+  int kx = count_x(TB, n);
+  if (rec) {
+    rec_write(job, 0, TB, L, n, d);
+    seg_clear(job, 0, d);
+  }
   int seg = 0, nhad = 0, had_base = 0, nmeas = st->nmeas, dmax = st->dmax;
   int pend = 0, pend_j0 = -1, pend_c0 = 0, pend_meas = -1;
   uint32_t pend_r = 0;
@@ -1086,8 +1094,17 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
   for (int g = job.g0; g < job.g1 && !errw; ++g) {
     const DGate gt = nxt;
     if (g + 1 < job.g1) nxt = job.gates[g + 1];  // next gate's load overlaps this one
+    const int gi = g - job.g0;
     if (gt.op < DG_NCPHASE) {
-      clifford_gate(L, TB, gt.op, gt.q0, gt.q1, n, d, job.dry, job.had + had_base, &nhad, &err);
+      const bool hs = clifford_gate_rec(L, TB, gt.op, gt.q0, gt.q1, n, d, &kx);
+      if (rec) {
+        if (lane == 0) {
+          job.ginfo[2 * gi] = seg;
+          job.ginfo[2 * gi + 1] = hs ? had_base + nhad : -1;
+        }
+        rec_write(job, gi + 1, TB, L, n, d);
+      }
+      if (hs) ++nhad;
       open = true;
       continue;
     }
@@ -1095,6 +1112,13 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
     // terminal gate of the segment: works on the LDS copy of the tableau
     regs_store(L, TB, n, true);
     __syncthreads();
+    // the Clifford steps keep no pivot index, b* basis or hull images
+    rebuild_index(L, n);
+    if (rec) {
+      build_beta(L, n);
+      hull_images(L, L.hbN, d, false);
+      if (lane == 0) { job.ginfo[2 * gi] = -1; job.ginfo[2 * gi + 1] = -1; }
+    }
     if (gt.op == DG_CPH2 || gt.op == DG_CX2) {
       terminal_controlled(L, job, gt, seg, nhad, had_base, n, &d, &err);
       if (d > dmax) dmax = d;
@@ -1103,15 +1127,17 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
       errw = err;
       __syncthreads();
       regs_load(L, TB, n);
+      kx = count_x(TB, n);
+      if (rec) {
+        rec_write(job, gi + 1, TB, L, n, d);
+        seg_clear(job, seg + 1, d);
+      }
       TOC(6);
       had_base += nhad;
       nhad = 0;
       ++seg;
       open = false;
-      if (!job.dry) {
-        for (int pt = lane; pt < SF_PMAX; pt += TL) L.acc[pt] = 0;
-        build_points(L, d);
-      }
+      if (!job.dry) build_points(L, d);
       __syncthreads();
       continue;
     }
@@ -1127,7 +1153,6 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
     int d_entry = d;
     if (!job.dry) {
       if (lane == 0) emit_header(sp, SEG_NONE, is_meas, d, d, nhad, had_base);
-      fit_z4(L, L.acc, d, &sp->E, &err);
       __syncthreads();
     }
     if (!rnd) {
@@ -1273,6 +1298,11 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
     (void)d_entry;
     __syncthreads();
     regs_load(L, TB, n);
+    kx = count_x(TB, n);
+    if (rec) {
+      rec_write(job, gi + 1, TB, L, n, d);
+      seg_clear(job, seg + 1, d);
+    }
     TOC(6);
     // new segment
     had_base += nhad;
@@ -1302,17 +1332,13 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
         break;
       }
     }
-    if (!job.dry) {
-      for (int pt = lane; pt < SF_PMAX; pt += TL) L.acc[pt] = 0;
-      build_points(L, d);
-    }
+    if (!job.dry) build_points(L, d);
     __syncthreads();
   }
   err = wave_max(err);
   if (open && !job.dry && !err) {
     SegProg* sp = job.prog + seg;
     if (lane == 0) emit_header(sp, SEG_NONE, 0, d, d, nhad, had_base);
-    fit_z4(L, L.acc, d, &sp->E, &err);
     zero_z4(&sp->B0);
     zero_z4(&sp->B1);
     ++seg;
@@ -2412,6 +2438,50 @@ template <int W>
 __global__ void __launch_bounds__(TL) sf_track_many(const TrackJob* __restrict__ jobs) {
   const TrackJob job = jobs[blockIdx.x];
   track_w<W>(job);
+}
+
+// Split form (W <= 2): the phase evaluation of every Clifford gate of a range,
+// one wavefront per gate (blockIdx.x = gate of the range, blockIdx.y = frame).
+template <int W>
+__global__ void __launch_bounds__(TL) sf_phase_one(TrackJob one) {
+  __shared__ typename Trk<W>::LL L;
+  Trk<W>::phase_body(L, one, (int)blockIdx.x);
+}
+
+template <int W>
+__global__ void __launch_bounds__(TL) sf_phase_many(const TrackJob* __restrict__ jobs) {
+  __shared__ typename Trk<W>::LL L;
+  const TrackJob job = jobs[blockIdx.y];
+  Trk<W>::phase_body(L, job, (int)blockIdx.x);
+}
+
+// ... and the fit of each segment's summed phase (blockIdx.x = segment).
+struct NoLds {};
+__device__ void fit_body(const TrackJob& job, int s) {
+  __shared__ uint8_t f[SF_PMAX];
+  if (s >= job.nseg || job.dry || !job.rec) return;
+  SegProg* sp = job.prog + s;
+  const int d = sp->d;
+  int err = 0;
+  if (d < 0 || d >= SF_DMAX || npoints(d) > job.pe) {
+    if (lane_id() == 0) job.st->error = TRK_E_INTERNAL;
+    return;
+  }
+  const int P = npoints(d);
+  const uint32_t* acc = job.segacc + (size_t)s * job.pe;
+  for (int p = lane_id(); p < P; p += TL) f[p] = (uint8_t)(acc[p] & 3u);
+  __syncthreads();
+  NoLds none;
+  fit_z4(none, f, d, &sp->E, &err);
+  err = wave_max(err);
+  if (err && lane_id() == 0) job.st->error = err;
+}
+
+extern "C" __global__ void __launch_bounds__(TL) sf_fit_one(TrackJob one) { fit_body(one, (int)blockIdx.x); }
+
+extern "C" __global__ void __launch_bounds__(TL) sf_fit_many(const TrackJob* __restrict__ jobs) {
+  const TrackJob job = jobs[blockIdx.y];
+  fit_body(job, (int)blockIdx.x);
 }
 
 // Readout: canonical (fully reduced, pivot-sorted) tableau, the hull in that
