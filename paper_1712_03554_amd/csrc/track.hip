@@ -88,12 +88,15 @@ __device__ __forceinline__ int colbit(const LT& L, int i, int col, int n) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x; }
 
+// (every lane holds the maximum after the butterfly; reading it from lane 0
+// tells the compiler that the result is wave-uniform, so branches and loop
+// exits that depend on it stay scalar)
 __device__ __forceinline__ int wave_max(int v) {
   for (int o = 32; o > 0; o >>= 1) {
     int t = __shfl_xor(v, o);
     v = t > v ? t : v;
   }
-  return v;
+  return __builtin_amdgcn_readfirstlane(v);
 }
 
 __device__ __forceinline__ int pair_index(int j, int jj, int d) {
@@ -370,7 +373,8 @@ static __device__ void cols_rowsum(LL& L, int m, int n) {
 // row slots and columns 64k + l (k < W) and hull vector l (V[l], then s0 at
 // lane d, u at lane d + 1).  The pivot row travels by readlane, the row masks
 // of each step by ballot; LDS is read on entry and written on exit only.
-static __device__ __forceinline__ void repair_core(LL& L, Regs& R, int n, int d, bool with_u, int full) {
+static __device__ __forceinline__ void repair_core(LL& L, Regs& R, uint64_t (&hv)[W], uint32_t& gen, int n, int d,
+                                                   bool with_u, int full) {
   const int lane = lane_id();
   uint64_t (&x)[W][W] = R.x;
   uint64_t (&z)[W][W] = R.z;
@@ -381,10 +385,6 @@ static __device__ __forceinline__ void repair_core(LL& L, Regs& R, int n, int d,
   for (int k = 0; k < W; ++k) valid[k] = 64 * k + lane < n;
   const bool has_vec = lane < d || lane == d || (lane == d + 1 && with_u);
   const bool affine = lane == d;
-  uint64_t hv[W];
-  for (int w = 0; w < W; ++w)
-    hv[w] = lane < d ? L.V[lane][w] : lane == d ? L.s0[w] : (lane == d + 1 && with_u) ? L.u[w] : 0ull;
-  uint32_t gen = (uint32_t)L.misc[1];
   for (int guard = 0; guard < 4 * SF_NMAX + 8; ++guard) {
 #ifdef SF_TRACK_TIMERS
     if (lane == 0) L.tc[11] += 1;  // elimination passes
@@ -488,20 +488,24 @@ static __device__ __forceinline__ void repair_core(LL& L, Regs& R, int n, int d,
     }
     TOC(10);
   }
+}
+
+// The same on the LDS copy of the tableau, hull and stamp generation
+// (terminal steps and readout).
+static __device__ void repair(LL& L, int n, int d, bool with_u, int full) {
+  const int lane = lane_id();
+  Regs R;
+  regs_load(L, R, n);
+  uint64_t hv[W];
+  for (int w = 0; w < W; ++w)
+    hv[w] = lane < d ? L.V[lane][w] : lane == d ? L.s0[w] : (lane == d + 1 && with_u) ? L.u[w] : 0ull;
+  uint32_t gen = (uint32_t)L.misc[1];
+  repair_core(L, R, hv, gen, n, d, with_u, full);
+  regs_store(L, R, n, true);
   if (lane < d) for (int w = 0; w < W; ++w) L.V[lane][w] = hv[w];
   else if (lane == d) for (int w = 0; w < W; ++w) L.s0[w] = hv[w];
   else if (lane == d + 1 && with_u) for (int w = 0; w < W; ++w) L.u[w] = hv[w];
-  __syncthreads();
   if (lane == 0) L.misc[1] = (int)gen;
-  __syncthreads();
-}
-
-// The same on the LDS copy of the tableau (terminal steps and readout).
-static __device__ void repair(LL& L, int n, int d, bool with_u, int full) {
-  Regs R;
-  regs_load(L, R, n);
-  repair_core(L, R, n, d, with_u, full);
-  regs_store(L, R, n, true);
   __syncthreads();
 }
 
@@ -624,9 +628,10 @@ static __device__ __forceinline__ void point_vec(const uint64_t* base, const uin
 // Clifford gate
 // ---------------------------------------------------------------------------
 // Table 2 on the register tableau: conjugate every row by the gate, collect
-// the sign flips f (applied to every phase vector through s0 ^= f) and keep
-// the column-major copy in step.  No barrier.
-static __device__ __forceinline__ void conj_regs(LL& L, Regs& R, int op, int a, int b, int n) {
+// the sign flips f (applied to every phase vector through s0 ^= f, s0 being
+// lane d's hull register) and keep the column-major copy in step.  Registers
+// only.
+static __device__ __forceinline__ void conj_regs(Regs& R, uint64_t (&hv)[W], int op, int a, int b, int n, int d) {
   const int lane = lane_id();
   const int wa = a >> 6, ba = a & 63, wb = b >> 6, bb = b & 63;
   const bool two = op == DG_CNOT || op == DG_CZ;
@@ -692,8 +697,8 @@ static __device__ __forceinline__ void conj_regs(LL& L, Regs& R, int op, int a, 
         if (k == wb && lane == bb) R.cz[k][w] ^= cxa[w];
       }
   }
-  if (lane == 0)
-    for (int w = 0; w < W; ++w) L.s0[w] ^= fm[w];
+  if (lane == d)
+    for (int w = 0; w < W; ++w) hv[w] ^= fm[w];
 }
 
 // ---------------------------------------------------------------------------
@@ -861,10 +866,9 @@ static __device__ __forceinline__ int count_x(const Regs& R, int n) {
   return k;
 }
 
-// record r: rows from the registers, s0 / V / d from LDS (current after the
-// barrier that ends every gate)
-static __device__ __forceinline__ void rec_write(const TrackJob& job, int r, const Regs& R, const LL& L, int n,
-                                                 int d) {
+// record r: rows and hull (lane j < d: V[j], lane d: s0) from the registers
+static __device__ __forceinline__ void rec_write(const TrackJob& job, int r, const Regs& R, const uint64_t (&hb)[W],
+                                                 int n, int d) {
   uint64_t* rw = (uint64_t*)(job.rec + (size_t)r * job.rec_stride);
   const int lane = lane_id();
   for (int k = 0; k < W; ++k) {
@@ -877,8 +881,21 @@ static __device__ __forceinline__ void rec_write(const TrackJob& job, int r, con
   }
   uint64_t* hv = rw + (size_t)n * 2 * W;
   if (lane <= d)
-    for (int w = 0; w < W; ++w) hv[lane * W + w] = lane == 0 ? L.s0[w] : L.V[lane - 1][w];
+    for (int w = 0; w < W; ++w) hv[(lane == d ? 0 : lane + 1) * W + w] = hb[w];
   if (lane == 0) *(int32_t*)(hv + (SF_DMAX + 1) * W) = d;
+}
+
+// the hull between LDS (terminal steps) and the registers of the Clifford
+// loop (lane j < d: V[j], lane d: s0)
+static __device__ __forceinline__ void hull_to_regs(const LL& L, uint64_t (&hb)[W], int d) {
+  const int lane = lane_id();
+  for (int w = 0; w < W; ++w) hb[w] = lane < d ? L.V[lane][w] : lane == d ? L.s0[w] : 0ull;
+}
+
+static __device__ __forceinline__ void hull_to_lds(LL& L, const uint64_t (&hb)[W], int d) {
+  const int lane = lane_id();
+  if (lane < d) for (int w = 0; w < W; ++w) L.V[lane][w] = hb[w];
+  else if (lane == d) for (int w = 0; w < W; ++w) L.s0[w] = hb[w];
 }
 
 static __device__ __forceinline__ int rec_d(const TrackJob& job, int r, int n) {
@@ -914,15 +931,14 @@ static __device__ __forceinline__ void seg_clear(const TrackJob& job, int s, int
 // Clifford gate of the split form: Table 2 and the echelon repair only.
 // Returns whether the gate is a Hadamard that keeps the support size (a GF(2)
 // term of the segment); kx carries the X-block size.
-static __device__ __forceinline__ bool clifford_gate_rec(LL& L, Regs& R, int op, int a, int b, int n, int d,
-                                                         int* kx) {
+static __device__ __forceinline__ bool clifford_gate_rec(LL& L, Regs& R, uint64_t (&hv)[W], uint32_t& gen, int op,
+                                                         int a, int b, int n, int d, int* kx) {
   TIC(1);
-  conj_regs(L, R, op, a, b, n);
-  __syncthreads();
+  conj_regs(R, hv, op, a, b, n, d);
   TOC(1);
   if (op == DG_S || op == DG_SDG || op == DG_Z || op == DG_CZ) return false;
   TIC(2);
-  repair_core(L, R, n, d, false, 0);
+  repair_core(L, R, hv, gen, n, d, false, 0);
   TOC(2);
   const int knew = count_x(R, n);
   const bool hs = op == DG_H && knew == *kx;
@@ -1076,9 +1092,14 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
     if (lane == 0 && !st->error) st->error = TRK_E_INTERNAL;
     return;
   }
+  // the Clifford loop keeps the hull and the lead-stamp generation in
+  // registers; terminal steps work on the LDS copies
+  uint64_t HB[W];
+  hull_to_regs(L, HB, d);
+  uint32_t gen = (uint32_t)L.misc[1];
   int kx = count_x(TB, n);
   if (rec) {
-    rec_write(job, 0, TB, L, n, d);
+    rec_write(job, 0, TB, HB, n, d);
     seg_clear(job, 0, d);
   }
   int seg = 0, nhad = 0, had_base = 0, nmeas = st->nmeas, dmax = st->dmax;
@@ -1096,13 +1117,15 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
     if (g + 1 < job.g1) nxt = job.gates[g + 1];  // next gate's load overlaps this one
     const int gi = g - job.g0;
     if (gt.op < DG_NCPHASE) {
-      const bool hs = clifford_gate_rec(L, TB, gt.op, gt.q0, gt.q1, n, d, &kx);
+      const bool hs = clifford_gate_rec(L, TB, HB, gen, gt.op, gt.q0, gt.q1, n, d, &kx);
       if (rec) {
+        TIC(0);
         if (lane == 0) {
           job.ginfo[2 * gi] = seg;
           job.ginfo[2 * gi + 1] = hs ? had_base + nhad : -1;
         }
-        rec_write(job, gi + 1, TB, L, n, d);
+        rec_write(job, gi + 1, TB, HB, n, d);
+        TOC(0);
       }
       if (hs) ++nhad;
       open = true;
@@ -1111,6 +1134,8 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
     TIC(6);
     // terminal gate of the segment: works on the LDS copy of the tableau
     regs_store(L, TB, n, true);
+    hull_to_lds(L, HB, d);
+    if (lane == 0) L.misc[1] = (int)gen;
     __syncthreads();
     // the Clifford steps keep no pivot index, b* basis or hull images
     rebuild_index(L, n);
@@ -1127,9 +1152,11 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
       errw = err;
       __syncthreads();
       regs_load(L, TB, n);
+      hull_to_regs(L, HB, d);
+      gen = (uint32_t)L.misc[1];
       kx = count_x(TB, n);
       if (rec) {
-        rec_write(job, gi + 1, TB, L, n, d);
+        rec_write(job, gi + 1, TB, HB, n, d);
         seg_clear(job, seg + 1, d);
       }
       TOC(6);
@@ -1298,9 +1325,11 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
     (void)d_entry;
     __syncthreads();
     regs_load(L, TB, n);
+    hull_to_regs(L, HB, d);
+    gen = (uint32_t)L.misc[1];
     kx = count_x(TB, n);
     if (rec) {
-      rec_write(job, gi + 1, TB, L, n, d);
+      rec_write(job, gi + 1, TB, HB, n, d);
       seg_clear(job, seg + 1, d);
     }
     TOC(6);
@@ -1327,6 +1356,7 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
           __syncthreads();
         }
         pend = 0;
+        hull_to_regs(L, HB, d);
       } else {
         // the range ends at a measurement (the host splits ranges there)
         break;
@@ -1344,6 +1374,7 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
     ++seg;
   }
   regs_store(L, TB, n, false);
+  hull_to_lds(L, HB, d);
   __syncthreads();
   // write back
   for (int i = lane; i < n * LL::RW; i += TL) {
