@@ -262,6 +262,14 @@ static __device__ int row_lead(const uint64_t* x, const uint64_t* z, int n) {
   return -1;
 }
 
+// The same with selects instead of branches (register rows of every lane).
+static __device__ __forceinline__ int row_lead_sel(const uint64_t (&x)[W], const uint64_t (&z)[W], int n) {
+  int ld = -1;
+  for (int w = W - 1; w >= 0; --w) ld = z[w] ? n + 64 * w + (int)__builtin_ctzll(z[w]) : ld;
+  for (int w = W - 1; w >= 0; --w) ld = x[w] ? 64 * w + (int)__builtin_ctzll(x[w]) : ld;
+  return ld;
+}
+
 // Sign bit c of row1 * row2 = (-1)^c (row1 xor row2) for commuting rows,
 // from the literal products of Table 1 (XY=iZ, YZ=iX, ZX=iY; reversed -i).
 static __device__ int rowprod_sign(const uint64_t* x1, const uint64_t* z1, const uint64_t* x2,
@@ -406,13 +414,20 @@ static __device__ __forceinline__ void repair_core(LL& L, Regs& R, uint64_t (&hv
       if (valid[k] && ld[k] >= 0) L.lst[ld[k]] = gen;
     __syncthreads();
     uint64_t px[W], pz[W];
+    // (all stamps are read at once: q < 64 W and n + q < 2 * 64 W are in
+    // range for every lane, so no read waits on a condition)
+    uint32_t sx[W], sz[W];
+    for (int k = 0; k < W; ++k) {
+      sx[k] = L.lst[64 * k + lane];
+      sz[k] = L.lst[n + 64 * k + lane];
+    }
     for (int k = 0; k < W; ++k) {
       const int q = 64 * k + lane;
       int a = 0, b = 0;
       for (int w = 0; w < W; ++w) { a += __popcll(cxr[k][w]); b += __popcll(czr[k][w] & zs[w]); }
       const bool ok = q < n;
-      px[k] = __ballot(ok && a >= 2 && L.lst[q] == gen);
-      pz[k] = __ballot(ok && b >= 2 && L.lst[n + q] == gen);
+      px[k] = __ballot(ok & (a >= 2) & (sx[k] == gen));
+      pz[k] = __ballot(ok & (b >= 2) & (sz[k] == gen));
     }
     int col = -1;
     for (int k = 0; k < W; ++k) if (col < 0 && px[k]) col = 64 * k + __builtin_ctzll(px[k]);
@@ -449,24 +464,27 @@ static __device__ __forceinline__ void repair_core(LL& L, Regs& R, uint64_t (&hv
         xa |= x[k][w];
         if ((cb >> 6) == w) wsel = xcol ? x[k][w] : z[k][w];
       }
-      const bool hit = valid[k] && i != m && (xcol || full || xa == 0ull) && ((wsel >> (cb & 63)) & 1ull);
-      int c = 0;
-      if (hit) {
-        // P(x1,z1) P(x2,z2) = i^e P(x1^x2, z1^z2) with
-        // e = |x1 z1| + |x2 z2| + 2 |z1 x2| - |(x1^x2)(z1^z2)|  (Y = iXZ);
-        // for commuting rows e is even and the sign is (-1)^(e/2)
-        int e = wm;
-        for (int w = 0; w < W; ++w) {
-          const uint64_t nx = x[k][w] ^ xm[w], nz = z[k][w] ^ zm[w];
-          e += __popcll(x[k][w] & z[k][w]) + 2 * __popcll(z[k][w] & xm[w]) - __popcll(nx & nz);
-          x[k][w] = nx;
-          z[k][w] = nz;
-        }
-        c = (e & 3) >> 1;
-        ld[k] = row_lead(x[k], z[k], n);
+      const bool hit = valid[k] & (i != m) & (xcol | (full != 0) | (xa == 0ull)) & (((wsel >> (cb & 63)) & 1ull) != 0);
+      // P(x1,z1) P(x2,z2) = i^e P(x1^x2, z1^z2) with
+      // e = |x1 z1| + |x2 z2| + 2 |z1 x2| - |(x1^x2)(z1^z2)|  (Y = iXZ);
+      // for commuting rows e is even and the sign is (-1)^(e/2).  Every
+      // lane computes the product; the hit rows take it.
+      int e = wm;
+      uint64_t nx[W], nz[W];
+      for (int w = 0; w < W; ++w) {
+        nx[w] = x[k][w] ^ xm[w];
+        nz[w] = z[k][w] ^ zm[w];
+        e += __popcll(x[k][w] & z[k][w]) + 2 * __popcll(z[k][w] & xm[w]) - __popcll(nx[w] & nz[w]);
       }
+      const int c = (e & 3) >> 1;
+      const int nl = row_lead_sel(nx, nz, n);
+      for (int w = 0; w < W; ++w) {
+        x[k][w] = hit ? nx[w] : x[k][w];
+        z[k][w] = hit ? nz[w] : z[k][w];
+      }
+      ld[k] = hit ? nl : ld[k];
       rm[k] = __ballot(hit);
-      cm[k] = __ballot(hit && c);
+      cm[k] = __ballot(hit & (c != 0));
     }
     // the column-major copy: columns where row m has a bit get the hit rows
     for (int k = 0; k < W; ++k) {
@@ -655,7 +673,7 @@ static __device__ __forceinline__ void conj_regs(Regs& R, uint64_t (&hv)[W], int
       R.x[k][w] ^= ((w == wa ? (uint64_t)fxa << ba : 0ull) | (w == wb ? (uint64_t)fxb << bb : 0ull));
       R.z[k][w] ^= ((w == wa ? (uint64_t)fza << ba : 0ull) ^ (w == wb ? (uint64_t)fzb << bb : 0ull));
     }
-    if (fxa | fza | fxb | fzb) R.ld[k] = row_lead(R.x[k], R.z[k], n);
+    R.ld[k] = (fxa | fza | fxb | fzb) ? row_lead_sel(R.x[k], R.z[k], n) : R.ld[k];
     fm[k] = __ballot(fl);
   }
   // column-major copy
