@@ -1078,8 +1078,10 @@ static __device__ void phase_body(LL& L, const TrackJob& job, int i) {
 static __device__ void track_body(LL& L, const TrackJob& job) {
   TrackState* st = job.st;
   const int lane = lane_id();
-  const int n = st->n;
-  int d = st->d;
+  // (sizes and gate fields are the same in every lane: read as scalars so
+  // that the gate dispatch and the bit positions stay scalar)
+  const int n = __builtin_amdgcn_readfirstlane(st->n);
+  int d = __builtin_amdgcn_readfirstlane(st->d);
   int err = 0;
   if (lane_id() < 16) L.tc[lane_id()] = 0;
   for (int i = lane; i < 2 * LL::RN; i += TL) L.lst[i] = 0u;
@@ -1131,7 +1133,11 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
   memset(&nxt, 0, sizeof nxt);
   if (job.g0 < job.g1) nxt = job.gates[job.g0];
   for (int g = job.g0; g < job.g1 && !errw; ++g) {
-    const DGate gt = nxt;
+    DGate gt = nxt;
+    gt.op = __builtin_amdgcn_readfirstlane(gt.op);
+    gt.q0 = __builtin_amdgcn_readfirstlane(gt.q0);
+    gt.q1 = __builtin_amdgcn_readfirstlane(gt.q1);
+    gt.q2 = __builtin_amdgcn_readfirstlane(gt.q2);
     if (g + 1 < job.g1) nxt = job.gates[g + 1];  // next gate's load overlaps this one
     const int gi = g - job.g0;
     if (gt.op < DG_NCPHASE) {
