@@ -559,3 +559,45 @@ def test_api_error_paths(eng):
     ref = OracleFrame(c.n, c.init_bits, 9)
     ref.run(c.array())
     _compare(st, ref, "after error paths")
+
+
+@pytest.mark.parametrize("n", [40, 100])
+def test_long_ranges_same_segments_on_every_path(eng, n):
+    """Circuits longer than two device ranges (frames of up to 128 qubits are
+    tracked in ranges of at most 1024 gates): the plain, batched and graph
+    paths form the same segments, so their frames agree bit for bit; a run in
+    small steps (more range ends) agrees within the amplitude bound; all
+    match the oracle.  A measurement sits just after the first range end."""
+    circ = wl.random_clifford_t(n, 2600, 12, 8800 + n, measure_qubits=(3, 10, n - 1))
+    circ.gates.insert(1030, (wl.MEASURE, 7, 0, 0, 0, 1))
+    circ.name = f"long-n{n}"
+    seed = 77 + n
+    print(f"case {circ.name} gates={len(circ)}", flush=True)
+    lc = eng.load(circ.n, circ)
+    plain = lc.state(circ.init_bits, seed)
+    plain.run()
+    tp, sp, ap = plain.read_frame()
+    batched = lc.state(circ.init_bits, seed)
+    eng.batch_run([batched])
+    tb, sb, ab = batched.read_frame()
+    assert np.array_equal(tp, tb) and np.array_equal(sp, sb)
+    assert np.array_equal(ap.view(np.uint64), ab.view(np.uint64))
+    assert plain.outcomes() == batched.outcomes()
+    gs = lc.state(circ.init_bits, 0)
+    g = eng.batch_graph([gs], [circ.init_bits], [seed])
+    g.launch()
+    tg, sg, ag = gs.read_frame()
+    assert np.array_equal(tp, tg) and np.array_equal(sp, sg)
+    assert np.array_equal(ap.view(np.uint64), ag.view(np.uint64))
+    assert plain.outcomes() == gs.outcomes()
+    g.close()
+    stepped = lc.state(circ.init_bits, seed)
+    while stepped.step(37):
+        pass
+    ref = OracleFrame(circ.n, circ.init_bits, seed)
+    ref.run(circ.array())
+    _compare(plain, ref, f"{circ.name} plain")
+    _compare(stepped, ref, f"{circ.name} stepped")
+    assert plain.outcomes() == ref.outcomes() == stepped.outcomes()
+    for st in (plain, batched, gs, stepped):
+        st.close()
