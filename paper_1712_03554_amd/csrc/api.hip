@@ -84,7 +84,7 @@ static void launch_track_one(hipStream_t st, const TrackJob& job, int W) {
 // Split form: the phase kernels of a track launch (len = longest range,
 // nseg = most segments among the jobs).
 static void launch_phase_one(sf_ctx* ctx, const TrackJob& job, int W);
-static void launch_phase_many(sf_ctx* ctx, const TrackJob* jobs, int count, int W, int len, int nseg);
+static void launch_phase_many(sf_ctx* ctx, const TrackJob* jobs, int count, int W, int nchunk, int nseg);
 
 static void launch_track_many(hipStream_t st, const TrackJob* jobs, int count, int W) {
   switch (W) {
@@ -136,12 +136,21 @@ static void prof_collect(sf_ctx* ctx) {
   ctx->ev_used = 0;
 }
 
+// Phase-kernel wavefronts of a launch: enough to fill the GPU, each walking
+// pchunk consecutive gates (one gate per wavefront when frames are few).
+#define SF_PHASE_WAVES 4096
+static int phase_chunk(size_t total_gates) {
+  return (int)std::max<size_t>(1, (total_gates + SF_PHASE_WAVES - 1) / SF_PHASE_WAVES);
+}
+
 static void launch_phase_one(sf_ctx* ctx, const TrackJob& job, int W) {
   const int len = job.g1 - job.g0;
   if (job.dry || !job.rec || len <= 0) return;
+  const int k = job.pchunk > 0 ? job.pchunk : 1;
+  const int nchunk = (len + k - 1) / k;
   prof_begin(ctx, PK_PHASE);
-  if (W == 1) hipLaunchKernelGGL(sf_phase_one<1>, dim3(len), dim3(TL), 0, ctx->stream, job);
-  else hipLaunchKernelGGL(sf_phase_one<2>, dim3(len), dim3(TL), 0, ctx->stream, job);
+  if (W == 1) hipLaunchKernelGGL(sf_phase_one<1>, dim3(nchunk), dim3(TL), 0, ctx->stream, job);
+  else hipLaunchKernelGGL(sf_phase_one<2>, dim3(nchunk), dim3(TL), 0, ctx->stream, job);
   prof_end(ctx);
   if (job.nseg > 0) {
     prof_begin(ctx, PK_FIT);
@@ -150,11 +159,11 @@ static void launch_phase_one(sf_ctx* ctx, const TrackJob& job, int W) {
   }
 }
 
-static void launch_phase_many(sf_ctx* ctx, const TrackJob* jobs, int count, int W, int len, int nseg) {
-  if (W > 2 || count <= 0 || len <= 0) return;
+static void launch_phase_many(sf_ctx* ctx, const TrackJob* jobs, int count, int W, int nchunk, int nseg) {
+  if (W > 2 || count <= 0 || nchunk <= 0) return;
   prof_begin(ctx, PK_PHASE);
-  if (W == 1) hipLaunchKernelGGL(sf_phase_many<1>, dim3(len, count), dim3(TL), 0, ctx->stream, jobs);
-  else hipLaunchKernelGGL(sf_phase_many<2>, dim3(len, count), dim3(TL), 0, ctx->stream, jobs);
+  if (W == 1) hipLaunchKernelGGL(sf_phase_many<1>, dim3(nchunk, count), dim3(TL), 0, ctx->stream, jobs);
+  else hipLaunchKernelGGL(sf_phase_many<2>, dim3(nchunk, count), dim3(TL), 0, ctx->stream, jobs);
   prof_end(ctx);
   if (nseg > 0) {
     prof_begin(ctx, PK_FIT);
@@ -667,6 +676,7 @@ static void split_fields(const sf_state* s, TrackJob* job, int nseg) {
   job->segacc = (uint32_t*)s->segacc.p;
   job->rec_stride = rec_stride_of(s->c->n);
   job->pe = pe_of(s->c->dmax);
+  job->pchunk = 1;
 }
 
 static sf_status run_chunk(sf_state* s, const DGate* dgates, const DGate* hg, size_t a, size_t b) {
@@ -1061,8 +1071,9 @@ struct RoundPlan {
   int na = 0, kmax = 0, gx = 1, bx = EB, gm = 1;
   bool anym = false;
   int wcount[SF_WMAX + 1] = {0, 0, 0, 0, 0};  // frames per word count (jobs are ordered by it)
-  int wlen[SF_WMAX + 1] = {0, 0, 0, 0, 0};    // per word count: longest range, most segments
-  int wseg[SF_WMAX + 1] = {0, 0, 0, 0, 0};
+  int wlen[SF_WMAX + 1] = {0, 0, 0, 0, 0};    // per word count: longest range, most segments,
+  int wseg[SF_WMAX + 1] = {0, 0, 0, 0, 0};    // phase-kernel chunks of the longest range
+  int wchunk[SF_WMAX + 1] = {0, 0, 0, 0, 0};
 };
 
 // Plans the next round from the progress pr[] and advances it; false when no
@@ -1089,7 +1100,7 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
   std::stable_sort(act.begin(), act.end(), [&](int u, int v) {
     return words_of(states[u]->c->n) < words_of(states[v]->c->n);
   });
-  for (int w = 0; w <= SF_WMAX; ++w) rp->wcount[w] = rp->wlen[w] = rp->wseg[w] = 0;
+  for (int w = 0; w <= SF_WMAX; ++w) rp->wcount[w] = rp->wlen[w] = rp->wseg[w] = rp->wchunk[w] = 0;
   for (int i : act) rp->wcount[words_of(states[i]->c->n)]++;
   const int na = (int)act.size();
   rp->na = na;
@@ -1123,6 +1134,21 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
     dm = std::max(dm, s->c->dmax);
     rp->gm = std::max(rp->gm, s->G);
     rp->anym |= ML[i] != 0;
+  }
+  // phase-kernel chunk per word count: the group's gates over SF_PHASE_WAVES
+  {
+    size_t gates[SF_WMAX + 1] = {0, 0, 0, 0, 0};
+    for (int j = 0; j < na; ++j) {
+      const TrackJob& jb = rp->jobs[j];
+      if (jb.rec) gates[words_of(states[act[j]]->c->n)] += (size_t)(jb.g1 - jb.g0);
+    }
+    int kw[SF_WMAX + 1];
+    for (int w = 0; w <= SF_WMAX; ++w) {
+      kw[w] = phase_chunk(gates[w]);
+      rp->wchunk[w] = rp->wlen[w] > 0 ? (rp->wlen[w] + kw[w] - 1) / kw[w] : 0;
+    }
+    for (int j = 0; j < na; ++j)
+      if (rp->jobs[j].rec) rp->jobs[j].pchunk = kw[words_of(states[act[j]]->c->n)];
   }
   elem_shape(states[act[0]]->ctx, dm, &rp->bx, &rp->gx);
   const int kmax = rp->kmax;
@@ -1185,7 +1211,7 @@ static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs
     prof_begin(ctx, PK_TRACK);
     launch_track_many(ctx->stream, djobs + off, rp.wcount[w], w);
     prof_end(ctx);
-    if (split_form(64 * w)) launch_phase_many(ctx, djobs + off, rp.wcount[w], w, rp.wlen[w], rp.wseg[w]);
+    if (split_form(64 * w)) launch_phase_many(ctx, djobs + off, rp.wcount[w], w, rp.wchunk[w], rp.wseg[w]);
     off += rp.wcount[w];
   }
   for (int k = 0; k < rp.kmax; ++k) {
@@ -1533,9 +1559,9 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
       const TrackJob* djw = dj + off;
       void* args[] = {(void*)&djw};
       e = add_kernel_node(g->graph, &last, track_many_fn(w), dim3(rp.wcount[w]), dim3(TL), args);
-      if (e == hipSuccess && split_form(64 * w) && rp.wlen[w] > 0) {
+      if (e == hipSuccess && split_form(64 * w) && rp.wchunk[w] > 0) {
         const void* ph = w == 1 ? (const void*)sf_phase_many<1> : (const void*)sf_phase_many<2>;
-        e = add_kernel_node(g->graph, &last, ph, dim3(rp.wlen[w], rp.wcount[w]), dim3(TL), args);
+        e = add_kernel_node(g->graph, &last, ph, dim3(rp.wchunk[w], rp.wcount[w]), dim3(TL), args);
         if (e == hipSuccess && rp.wseg[w] > 0)
           e = add_kernel_node(g->graph, &last, (const void*)sf_fit_many, dim3(rp.wseg[w], rp.wcount[w]), dim3(TL),
                               args);

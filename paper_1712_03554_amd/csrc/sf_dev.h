@@ -95,8 +95,9 @@ struct TrackState {
 // rec_stride bytes, record 0 = the state on entry; a record holds the rows
 // (x then z words of each slot), s0 and V[0..SF_DMAX) of W words, then d); a
 // phase kernel evaluates every Clifford gate's phase factor at the fitting
-// points from the records on both sides of it (one wavefront per gate) and
-// adds it into its segment's sums (segacc: pe words per segment); a fit
+// points from the records on both sides of it (one wavefront per pchunk
+// consecutive gates) and adds it into its segment's sums (segacc: pe words
+// per segment); a fit
 // kernel turns each segment's sums into its program's phase E.
 // ginfo[2 i] = segment of gate g0 + i, ginfo[2 i + 1] = index of its GF(2)
 // Hadamard term in had (or -1).  rec == nullptr: everything in the track
@@ -115,6 +116,8 @@ struct TrackJob {
   uint32_t* segacc;
   int32_t rec_stride;      // bytes per record
   int32_t pe;              // words per segment in segacc (>= points of the largest d)
+  int32_t pchunk;          // consecutive gates per phase-kernel wavefront
+  int32_t pad2;
 };
 
 // longest gate range of one split-form track launch (bounds the records)

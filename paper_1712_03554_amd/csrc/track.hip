@@ -921,18 +921,40 @@ static __device__ __forceinline__ int rec_d(const TrackJob& job, int r, int n) {
   return *(const int32_t*)(rw + (size_t)n * 2 * W + (SF_DMAX + 1) * W);
 }
 
-static __device__ void rec_load(LL& L, const TrackJob& job, int r, int n, int d) {
+// A record held in registers (lane l: row slots l + 64 k, hull entry l), so
+// that the phase kernel can fetch the next record while it works on a gate.
+struct RecRegs {
+  uint64_t x[W][W], z[W][W], h[W];
+  int d;
+};
+
+static __device__ __forceinline__ void rec_fetch(const TrackJob& job, int r, int n, RecRegs& R) {
   const uint64_t* rw = (const uint64_t*)(job.rec + (size_t)r * job.rec_stride);
   const int lane = lane_id();
-  for (int idx = lane; idx < LL::RN * LL::RW; idx += TL) {
-    const int i = idx / LL::RW, w = idx % LL::RW;
-    L.rx[idx] = i < n ? rw[i * 2 * W + w] : 0ull;
-    L.rz[idx] = i < n ? rw[i * 2 * W + W + w] : 0ull;
+  for (int k = 0; k < W; ++k) {
+    const int i = 64 * k + lane;
+    for (int w = 0; w < W; ++w) {
+      R.x[k][w] = i < n ? rw[i * 2 * W + w] : 0ull;
+      R.z[k][w] = i < n ? rw[i * 2 * W + W + w] : 0ull;
+    }
   }
   const uint64_t* hv = rw + (size_t)n * 2 * W;
+  for (int w = 0; w < W; ++w) R.h[w] = lane <= SF_DMAX ? hv[lane * W + w] : 0ull;
+  R.d = *(const int32_t*)(hv + (SF_DMAX + 1) * W);
+}
+
+static __device__ __forceinline__ void rec_put(LL& L, const RecRegs& R, int d) {
+  const int lane = lane_id();
+  for (int k = 0; k < W; ++k) {
+    const int i = 64 * k + lane;
+    for (int w = 0; w < W; ++w) {
+      L.rx[i * LL::RW + w] = R.x[k][w];
+      L.rz[i * LL::RW + w] = R.z[k][w];
+    }
+  }
   if (lane <= d)
     for (int w = 0; w < SF_WMAX; ++w) {
-      const uint64_t v = w < W ? hv[lane * W + w] : 0ull;
+      const uint64_t v = w < W ? R.h[w] : 0ull;
       if (lane == 0) L.s0[w] = v;
       else L.V[lane - 1][w] = v;
     }
@@ -964,113 +986,142 @@ static __device__ __forceinline__ bool clifford_gate_rec(LL& L, Regs& R, uint64_
   return hs;
 }
 
-// Phase factor of Clifford gate g0 + i of a split-form range at the fitting
-// points (the same evaluation as clifford_gate, from the records before and
-// after the gate), added into its segment's sums.
-static __device__ void phase_body(LL& L, const TrackJob& job, int i) {
+// Phase factors of the Clifford gates g0 + i, i in [c k, (c + 1) k) with
+// k = pchunk, of a split-form range at the fitting points (the evaluation of
+// the five-step procedure from the states before and after each gate), added
+// into their segments' sums.  The wavefront rebuilds the pivot index, b* basis
+// and hull images from the record before its first gate and then carries
+// them: a non-diagonal gate saves them as its pre-gate view and rebuilds from
+// the record after it; a diagonal gate changes only z bits of X-block rows
+// and X-block signs, which leave the index, the b* basis and the images as
+// they are, so only the rows and hull are reloaded; after a terminal step
+// everything is rebuilt.
+static __device__ void phase_body(LL& L, const TrackJob& job, int c) {
   const int lane = lane_id();
   const int len = job.g1 - job.g0;
-  if (i >= len) return;
-  const DGate gt = job.gates[job.g0 + i];
-  const int op = gt.op;
-  if (op >= DG_NCPHASE) return;
+  const int k = job.pchunk > 0 ? job.pchunk : 1;
+  const int i0 = c * k;
+  if (i0 >= len) return;
+  const int i1 = min(len, i0 + k);
   TrackState* st = job.st;
-  const int n = st->n;
-  const int d = rec_d(job, i + 1, n);
-  const int s = job.ginfo[2 * i];
-  if (d < 0 || d >= SF_DMAX || s < 0 || s >= job.nseg || npoints(d) > job.pe || rec_d(job, i, n) != d) {
+  const int n = __builtin_amdgcn_readfirstlane(st->n);
+  int err = 0;
+  RecRegs pf;
+  rec_fetch(job, i0, n, pf);
+  int d = __builtin_amdgcn_readfirstlane(pf.d);
+  if (d < 0 || d >= SF_DMAX) {
     if (lane == 0) st->error = TRK_E_INTERNAL;
     return;
   }
-  uint32_t* acc = job.segacc + (size_t)s * job.pe;
-  const int a = gt.q0, b = gt.q1;
-  int err = 0;
-  const int P = npoints(d);
-  if (op == DG_S || op == DG_SDG || op == DG_Z || op == DG_CZ) {
-    // b*(sigma) is the same before and after a diagonal gate
-    rec_load(L, job, i + 1, n, d);
+  rec_put(L, pf, d);
+  rec_fetch(job, i0 + 1, n, pf);
+  rebuild_index(L, n);
+  build_beta(L, n);
+  hull_images(L, L.hbN, d, false);
+  build_points(L, d);
+  for (int i = i0; i < i1 && !err; ++i) {
+    // nx: the record after gate i; the one after gate i + 1 loads meanwhile
+    const RecRegs nx = pf;
+    if (i + 1 < i1) rec_fetch(job, i + 2, n, pf);
+    const DGate gt = job.gates[job.g0 + i];
+    const int op = __builtin_amdgcn_readfirstlane(gt.op);
+    const int a = __builtin_amdgcn_readfirstlane(gt.q0), b = __builtin_amdgcn_readfirstlane(gt.q1);
+    const int dn = __builtin_amdgcn_readfirstlane(nx.d);
+    if (op >= DG_NCPHASE) {
+      // terminal step: the next gate starts from the record after it
+      if (i + 1 < i1) {
+        if (dn < 0 || dn >= SF_DMAX) { err = TRK_E_INTERNAL; break; }
+        d = dn;
+        rec_put(L, nx, d);
+        rebuild_index(L, n);
+        build_beta(L, n);
+        hull_images(L, L.hbN, d, false);
+        build_points(L, d);
+      }
+      continue;
+    }
+    const int s = __builtin_amdgcn_readfirstlane(job.ginfo[2 * i]);
+    if (dn != d || s < 0 || s >= job.nseg || npoints(d) > job.pe) { err = TRK_E_INTERNAL; break; }
+    uint32_t* acc = job.segacc + (size_t)s * job.pe;
+    const int P = npoints(d);
+    if (op == DG_S || op == DG_SDG || op == DG_Z || op == DG_CZ) {
+      for (int p = lane; p < P; p += TL) {
+        uint32_t Y = L.Ys[p];
+        int ba = getb(L.hbN[0], a), bb = op == DG_CZ ? getb(L.hbN[0], b) : 0;
+        while (Y) {
+          const int j = __builtin_ctz(Y);
+          Y &= Y - 1;
+          ba ^= getb(L.hbN[1 + j], a);
+          if (op == DG_CZ) bb ^= getb(L.hbN[1 + j], b);
+        }
+        const int mu = op == DG_S ? ba : op == DG_SDG ? 3 * ba : op == DG_Z ? 2 * ba : 2 * (ba & bb);
+        atomicAdd(&acc[p], (uint32_t)(mu & 3));
+      }
+      if (i + 1 < i1) rec_put(L, nx, d);
+      continue;
+    }
+    save_old(L, n, d);
+    const int kold = L.misc[0];
+    rec_put(L, nx, d);
     rebuild_index(L, n);
     build_beta(L, n);
     hull_images(L, L.hbN, d, false);
-    build_points(L, d);
+    const int knew = L.misc[0];
+    const int dk = knew - kold;
+    const bool hsplit = op == DG_H && dk == 0;
     for (int p = lane; p < P; p += TL) {
       uint32_t Y = L.Ys[p];
-      int ba = getb(L.hbN[0], a), bb = op == DG_CZ ? getb(L.hbN[0], b) : 0;
-      while (Y) {
-        const int j = __builtin_ctz(Y);
-        Y &= Y - 1;
-        ba ^= getb(L.hbN[1 + j], a);
-        if (op == DG_CZ) bb ^= getb(L.hbN[1 + j], b);
-      }
-      const int mu = op == DG_S ? ba : op == DG_SDG ? 3 * ba : op == DG_Z ? 2 * ba : 2 * (ba & bb);
-      atomicAdd(&acc[p], (uint32_t)(mu & 3));
-    }
-    return;
-  }
-  rec_load(L, job, i, n, d);
-  rebuild_index(L, n);
-  build_beta(L, n);
-  hull_images(L, L.hbN, d, false);
-  save_old(L, n, d);
-  const int kold = L.misc[0];
-  rec_load(L, job, i + 1, n, d);
-  rebuild_index(L, n);
-  build_beta(L, n);
-  hull_images(L, L.hbN, d, false);
-  const int knew = L.misc[0];
-  build_points(L, d);
-  const int dk = knew - kold;
-  const bool hsplit = op == DG_H && dk == 0;
-  for (int p = lane; p < P; p += TL) {
-    uint32_t Y = L.Ys[p];
-    uint64_t so[SF_WMAX], bo[SF_WMAX], bn[SF_WMAX], src[SF_WMAX];
-    point_vec(L.os0, L.oV, Y, 0, so);
-    point_vec(L.hbO[0], L.hbO, Y, 1, bo);
-    point_vec(L.hbN[0], L.hbN, Y, 1, bn);
-    int e = 0, t = 0;
-    int ba = getb(bn, a);
-    for (int w = 0; w < W; ++w) src[w] = bn[w];
-    if (op != DG_H) {
-      int mu = 0;
-      switch (op) {
-        case DG_X: flipb(src, a); break;
-        case DG_Y: flipb(src, a); mu = ba ? 1 : 3; break;
-        case DG_CNOT: if (ba) flipb(src, b); break;
-      }
-      int u = uexp(L, so, bo, src);
-      if (u < 0) err = TRK_E_INTERNAL;
-      e = mu + u;
-    } else {
-      uint64_t b1[SF_WMAX];
-      for (int w = 0; w < W; ++w) b1[w] = bn[w];
-      if (ba) flipb(src, a); else flipb(b1, a);   // src: bit a = 0, b1: bit a = 1
-      if (dk == 1) {
-        int u0 = uexp(L, so, bo, src);
-        int u1 = uexp(L, so, bo, b1);
-        if ((u0 < 0) == (u1 < 0)) err = TRK_E_INTERNAL;
-        e = u0 >= 0 ? u0 : u1 + 2 * ba;
-      } else if (dk == -1) {
-        int u0 = uexp(L, so, bo, src);
-        if (u0 < 0) err = TRK_E_INTERNAL;
-        e = u0;
+      uint64_t so[SF_WMAX], bo[SF_WMAX], bn[SF_WMAX], src[SF_WMAX];
+      point_vec(L.os0, L.oV, Y, 0, so);
+      point_vec(L.hbO[0], L.hbO, Y, 1, bo);
+      point_vec(L.hbN[0], L.hbN, Y, 1, bn);
+      int e = 0, t = 0;
+      int ba = getb(bn, a);
+      for (int w = 0; w < W; ++w) src[w] = bn[w];
+      if (op != DG_H) {
+        int mu = 0;
+        switch (op) {
+          case DG_X: flipb(src, a); break;
+          case DG_Y: flipb(src, a); mu = ba ? 1 : 3; break;
+          case DG_CNOT: if (ba) flipb(src, b); break;
+        }
+        int u = uexp(L, so, bo, src);
+        if (u < 0) err = TRK_E_INTERNAL;
+        e = mu + u;
       } else {
-        int e0 = uexp(L, so, bo, src);
-        int e1 = uexp(L, so, bo, b1);
-        if (e0 < 0 || e1 < 0) err = TRK_E_INTERNAL;
-        e1 += 2 * ba;
-        int dl = (e1 - e0) & 3;
-        if (!(dl & 1)) err = TRK_E_INTERNAL;
-        e = e0;
-        t = dl == 3 ? 1 : 0;        // omega = exp(i pi (2 e0 + 1 - 2t)/4)
+        uint64_t b1[SF_WMAX];
+        for (int w = 0; w < W; ++w) b1[w] = bn[w];
+        if (ba) flipb(src, a); else flipb(b1, a);   // src: bit a = 0, b1: bit a = 1
+        if (dk == 1) {
+          int u0 = uexp(L, so, bo, src);
+          int u1 = uexp(L, so, bo, b1);
+          if ((u0 < 0) == (u1 < 0)) err = TRK_E_INTERNAL;
+          e = u0 >= 0 ? u0 : u1 + 2 * ba;
+        } else if (dk == -1) {
+          int u0 = uexp(L, so, bo, src);
+          if (u0 < 0) err = TRK_E_INTERNAL;
+          e = u0;
+        } else {
+          int e0 = uexp(L, so, bo, src);
+          int e1 = uexp(L, so, bo, b1);
+          if (e0 < 0 || e1 < 0) err = TRK_E_INTERNAL;
+          e1 += 2 * ba;
+          int dl = (e1 - e0) & 3;
+          if (!(dl & 1)) err = TRK_E_INTERNAL;
+          e = e0;
+          t = dl == 3 ? 1 : 0;        // omega = exp(i pi (2 e0 + 1 - 2t)/4)
+        }
       }
+      atomicAdd(&acc[p], (uint32_t)(e & 3));
+      if (hsplit) L.t0[p] = (uint8_t)t;
     }
-    atomicAdd(&acc[p], (uint32_t)(e & 3));
-    if (hsplit) L.t0[p] = (uint8_t)t;
+    __syncthreads();
+    const int hi = __builtin_amdgcn_readfirstlane(job.ginfo[2 * i + 1]);
+    if (hsplit != (hi >= 0)) err = TRK_E_INTERNAL;
+    else if (hsplit) fit_gf2(L, L.t0, d, &job.had[hi]);
+    __syncthreads();
+    err = wave_max(err);
   }
-  __syncthreads();
-  const int hi = job.ginfo[2 * i + 1];
-  if (hsplit != (hi >= 0)) err = TRK_E_INTERNAL;
-  else if (hsplit) fit_gf2(L, L.t0, d, &job.had[hi]);
   err = wave_max(err);
   if (err && lane == 0) st->error = err;
 }
