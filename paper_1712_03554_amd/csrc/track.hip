@@ -1019,11 +1019,20 @@ static __device__ void phase_body(LL& L, const TrackJob& job, int c) {
   build_beta(L, n);
   hull_images(L, L.hbN, d, false);
   build_points(L, d);
+  // gate i and its info, fetched one gate ahead like the records
+  DGate gnext = job.gates[job.g0 + i0];
+  int snext = job.ginfo[2 * i0], hnext = job.ginfo[2 * i0 + 1];
   for (int i = i0; i < i1 && !err; ++i) {
     // nx: the record after gate i; the one after gate i + 1 loads meanwhile
     const RecRegs nx = pf;
-    if (i + 1 < i1) rec_fetch(job, i + 2, n, pf);
-    const DGate gt = job.gates[job.g0 + i];
+    const DGate gt = gnext;
+    const int sg = snext, hg = hnext;
+    if (i + 1 < i1) {
+      rec_fetch(job, i + 2, n, pf);
+      gnext = job.gates[job.g0 + i + 1];
+      snext = job.ginfo[2 * (i + 1)];
+      hnext = job.ginfo[2 * (i + 1) + 1];
+    }
     const int op = __builtin_amdgcn_readfirstlane(gt.op);
     const int a = __builtin_amdgcn_readfirstlane(gt.q0), b = __builtin_amdgcn_readfirstlane(gt.q1);
     const int dn = __builtin_amdgcn_readfirstlane(nx.d);
@@ -1040,7 +1049,7 @@ static __device__ void phase_body(LL& L, const TrackJob& job, int c) {
       }
       continue;
     }
-    const int s = __builtin_amdgcn_readfirstlane(job.ginfo[2 * i]);
+    const int s = __builtin_amdgcn_readfirstlane(sg);
     if (dn != d || s < 0 || s >= job.nseg || npoints(d) > job.pe) { err = TRK_E_INTERNAL; break; }
     uint32_t* acc = job.segacc + (size_t)s * job.pe;
     const int P = npoints(d);
@@ -1116,7 +1125,7 @@ static __device__ void phase_body(LL& L, const TrackJob& job, int c) {
       if (hsplit) L.t0[p] = (uint8_t)t;
     }
     __syncthreads();
-    const int hi = __builtin_amdgcn_readfirstlane(job.ginfo[2 * i + 1]);
+    const int hi = __builtin_amdgcn_readfirstlane(hg);
     if (hsplit != (hi >= 0)) err = TRK_E_INTERNAL;
     else if (hsplit) fit_gf2(L, L.t0, d, &job.had[hi]);
     __syncthreads();
