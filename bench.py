@@ -240,6 +240,48 @@ def large_frame(eng, wl, m=12, reps=2):
     return out
 
 
+def clifford_only(eng, wl, sizes=(128, 256), batch=8, reps=3):
+    """The paper's Clifford-only workload (random stabilizer circuits, n log2 n
+    H/S/CNOT gates, then every qubit measured) at the sizes this build
+    supports: one circuit at a time and `batch` circuits per batched run.  The
+    frame keeps one element, so U = gates applied."""
+    import torch
+    out = []
+    for n in sizes:
+        circs = [wl.stabilizer_circuit(n, 9300 + 17 * n + j) for j in range(batch)]
+        loaded = [eng.load(c.n, c) for c in circs]
+        states = [l.state(c.init_bits, j) for j, (l, c) in enumerate(zip(loaded, circs))]
+        st = states[0]
+        st.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st.reset(circs[0].init_bits, 0)
+            st.run()
+        torch.cuda.synchronize()
+        plain_s = (time.perf_counter() - t0) / reps
+        bases = [c.init_bits for c in circs]
+        seeds = list(range(batch))
+        eng.batch_reset(states, bases, seeds)
+        eng.batch_run(states)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            eng.batch_reset(states, bases, seeds)
+            eng.batch_run(states)
+        torch.cuda.synchronize()
+        batch_s = (time.perf_counter() - t0) / reps
+        sizes_after = [s.frame_size() for s in states]
+        out.append({"workload": f"stabilizer circuits n={n}, {len(circs[0])} gates incl. {n} measurements",
+                    "plain_ms_per_circuit": plain_s * 1e3, "plain_gates_per_s": len(circs[0]) / plain_s,
+                    "batched_circuits": batch, "batched_ms": batch_s * 1e3,
+                    "batched_gates_per_s": sum(len(c) for c in circs) / batch_s,
+                    "frame_sizes_after": sorted(set(sizes_after))})
+        for s in states:
+            s.close()
+    return out
+
+
 def direct_vs_decomposed(eng, wl, reps=3):
     """Wall time per circuit (plain path, one frame) of the decomposed and the
     direct (double-cofactor) forms of controlled rotations and Toffolis."""
@@ -540,6 +582,7 @@ def main():
         line["direct_forms"] = direct_vs_decomposed(eng, wl)
         line["element_hbm_probe"] = hbm_probe(eng, wl)
         line["large_frame"] = large_frame(eng, wl)
+        line["clifford_only"] = clifford_only(eng, wl)
     if args.serve_jobs > 0:
         line["serve"] = serve_bench(eng, sf, wl, args.serve_jobs, args.tick_segments, args.max_resident,
                                     int(args.serve_budget_gib * (1 << 30)))

@@ -601,3 +601,26 @@ def test_long_ranges_same_segments_on_every_path(eng, n):
     assert plain.outcomes() == ref.outcomes() == stepped.outcomes()
     for st in (plain, batched, gs, stepped):
         st.close()
+
+
+@pytest.mark.parametrize("n", [100, 200])
+def test_stabilizer_circuits_keep_one_element(eng, n):
+    """The paper's Clifford-only workload (n log2 n random H/S/CNOT, then every
+    qubit measured): the frame keeps one element throughout, and tableau,
+    amplitude and outcomes match the oracle."""
+    circ = wl.stabilizer_circuit(n, 9100 + n)
+    seed = 13 + n
+    print(f"case {circ.name} gates={len(circ)}", flush=True)
+    st = eng.load(circ.n, circ).state(circ.init_bits, seed)
+    done = 0
+    while True:
+        k = st.step(max(1, len(circ) // 7))
+        if not k:
+            break
+        done += k
+        assert st.frame_size() == 1, done
+    ref = OracleFrame(circ.n, circ.init_bits, seed)
+    ref.run(circ.array())
+    _compare(st, ref, circ.name)
+    assert st.outcomes() == ref.outcomes()
+    st.close()
