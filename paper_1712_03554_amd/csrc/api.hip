@@ -712,7 +712,10 @@ static sf_status run_chunk(sf_state* s, const DGate* dgates, const DGate* hg, si
   prof_begin(ctx, PK_TRACK);
   launch_track_one(ctx->stream, job, words_of(c->n));
   prof_end(ctx);
-  launch_phase_one(ctx, job, words_of(c->n));
+  // (a range without Clifford gates keeps the zero phase the track wrote)
+  bool anycliff = false;
+  for (size_t i = a; i < b && !anycliff; ++i) anycliff = hg[i].op < DG_NCPHASE;
+  if (anycliff) launch_phase_one(ctx, job, words_of(c->n));
   HIPCHK(ctx, hipGetLastError());
   int eb, grid;
   elem_shape(ctx, c->dmax, &eb, &grid);
@@ -1073,7 +1076,7 @@ struct RoundPlan {
   int wcount[SF_WMAX + 1] = {0, 0, 0, 0, 0};  // frames per word count (jobs are ordered by it)
   int wlen[SF_WMAX + 1] = {0, 0, 0, 0, 0};    // per word count: longest range, most segments,
   int wseg[SF_WMAX + 1] = {0, 0, 0, 0, 0};    // phase-kernel chunks of the longest range
-  int wchunk[SF_WMAX + 1] = {0, 0, 0, 0, 0};
+  int wchunk[SF_WMAX + 1] = {0, 0, 0, 0, 0};  // 0: no Clifford gate in the group's ranges
 };
 
 // Plans the next round from the progress pr[] and advances it; false when no
@@ -1142,10 +1145,17 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
       const TrackJob& jb = rp->jobs[j];
       if (jb.rec) gates[words_of(states[act[j]]->c->n)] += (size_t)(jb.g1 - jb.g0);
     }
+    bool cliff[SF_WMAX + 1] = {false, false, false, false, false};
+    for (int j = 0; j < na; ++j) {
+      const TrackJob& jb = rp->jobs[j];
+      const sf_circuit* c = states[act[j]]->c;
+      bool& cw = cliff[words_of(c->n)];
+      for (int g = jb.g0; g < jb.g1 && !cw; ++g) cw = c->g[g].op < DG_NCPHASE;
+    }
     int kw[SF_WMAX + 1];
     for (int w = 0; w <= SF_WMAX; ++w) {
       kw[w] = phase_chunk(gates[w]);
-      rp->wchunk[w] = rp->wlen[w] > 0 ? (rp->wlen[w] + kw[w] - 1) / kw[w] : 0;
+      rp->wchunk[w] = (rp->wlen[w] > 0 && cliff[w]) ? (rp->wlen[w] + kw[w] - 1) / kw[w] : 0;
     }
     for (int j = 0; j < na; ++j)
       if (rp->jobs[j].rec) rp->jobs[j].pchunk = kw[words_of(states[act[j]]->c->n)];

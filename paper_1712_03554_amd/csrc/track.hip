@@ -805,8 +805,10 @@ static __device__ void terminal_controlled(LL& L, const TrackJob& job, const DGa
   int d = *dptr;
   SegProg* sp = job.dry ? nullptr : job.prog + seg;
   if (!job.dry) {
-    // (its Clifford phase E is fitted by the fit kernel)
+    // (its Clifford phase E is fitted by the fit kernel when the range has
+    // Clifford gates; zero until then)
     if (lane == 0) emit_header(sp, SEG_DET2, 0, d, d, nhad, had_base);
+    zero_z4(&sp->E);
     __syncthreads();
   }
   uint32_t c1, r1, c2, r2;
@@ -1264,6 +1266,7 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
     int d_entry = d;
     if (!job.dry) {
       if (lane == 0) emit_header(sp, SEG_NONE, is_meas, d, d, nhad, had_base);
+      zero_z4(&sp->E);
       __syncthreads();
     }
     if (!rnd) {
@@ -1453,6 +1456,7 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
   if (open && !job.dry && !err) {
     SegProg* sp = job.prog + seg;
     if (lane == 0) emit_header(sp, SEG_NONE, 0, d, d, nhad, had_base);
+    zero_z4(&sp->E);
     zero_z4(&sp->B0);
     zero_z4(&sp->B1);
     ++seg;
