@@ -50,8 +50,11 @@ static int grid_for(int d) {
 
 static int words_of(uint32_t n) { return (int)((n + 63) / 64); }
 
-// Split form of the tableau track (frames of up to 128 qubits): bytes of one
-// per-gate record and words of one segment's phase sums.
+// Split form of the tableau track: always for frames of up to 128 qubits;
+// for wider frames only in launches with at most SF_SPLIT_WIDE_MAX of them
+// (with more the GPU is already full and the split costs more than it
+// saves).  Bytes of one per-gate record and words of one segment's sums.
+#define SF_SPLIT_WIDE_MAX 64
 static bool split_form(uint32_t n) { return words_of(n) <= 2; }
 static int rec_stride_of(uint32_t n) {
   const size_t W = (size_t)words_of(n);
@@ -61,6 +64,15 @@ static int rec_stride_of(uint32_t n) {
 static int pe_of(int dmax) {
   const int d = dmax < 0 ? 0 : dmax;
   return (1 + d + d * (d - 1) / 2 + 3) & ~3;
+}
+
+static const void* phase_many_fn(int W) {
+  switch (W) {
+    case 1: return (const void*)sf_phase_many<1>;
+    case 2: return (const void*)sf_phase_many<2>;
+    case 3: return (const void*)sf_phase_many<3>;
+    default: return (const void*)sf_phase_many<4>;
+  }
 }
 
 static const void* track_many_fn(int W) {
@@ -149,8 +161,12 @@ static void launch_phase_one(sf_ctx* ctx, const TrackJob& job, int W) {
   const int k = job.pchunk > 0 ? job.pchunk : 1;
   const int nchunk = (len + k - 1) / k;
   prof_begin(ctx, PK_PHASE);
-  if (W == 1) hipLaunchKernelGGL(sf_phase_one<1>, dim3(nchunk), dim3(TL), 0, ctx->stream, job);
-  else hipLaunchKernelGGL(sf_phase_one<2>, dim3(nchunk), dim3(TL), 0, ctx->stream, job);
+  switch (W) {
+    case 1: hipLaunchKernelGGL(sf_phase_one<1>, dim3(nchunk), dim3(TL), 0, ctx->stream, job); break;
+    case 2: hipLaunchKernelGGL(sf_phase_one<2>, dim3(nchunk), dim3(TL), 0, ctx->stream, job); break;
+    case 3: hipLaunchKernelGGL(sf_phase_one<3>, dim3(nchunk), dim3(TL), 0, ctx->stream, job); break;
+    default: hipLaunchKernelGGL(sf_phase_one<4>, dim3(nchunk), dim3(TL), 0, ctx->stream, job); break;
+  }
   prof_end(ctx);
   if (job.nseg > 0) {
     prof_begin(ctx, PK_FIT);
@@ -160,10 +176,14 @@ static void launch_phase_one(sf_ctx* ctx, const TrackJob& job, int W) {
 }
 
 static void launch_phase_many(sf_ctx* ctx, const TrackJob* jobs, int count, int W, int nchunk, int nseg) {
-  if (W > 2 || count <= 0 || nchunk <= 0) return;
+  if (count <= 0 || nchunk <= 0) return;
   prof_begin(ctx, PK_PHASE);
-  if (W == 1) hipLaunchKernelGGL(sf_phase_many<1>, dim3(nchunk, count), dim3(TL), 0, ctx->stream, jobs);
-  else hipLaunchKernelGGL(sf_phase_many<2>, dim3(nchunk, count), dim3(TL), 0, ctx->stream, jobs);
+  switch (W) {
+    case 1: hipLaunchKernelGGL(sf_phase_many<1>, dim3(nchunk, count), dim3(TL), 0, ctx->stream, jobs); break;
+    case 2: hipLaunchKernelGGL(sf_phase_many<2>, dim3(nchunk, count), dim3(TL), 0, ctx->stream, jobs); break;
+    case 3: hipLaunchKernelGGL(sf_phase_many<3>, dim3(nchunk, count), dim3(TL), 0, ctx->stream, jobs); break;
+    default: hipLaunchKernelGGL(sf_phase_many<4>, dim3(nchunk, count), dim3(TL), 0, ctx->stream, jobs); break;
+  }
   prof_end(ctx);
   if (nseg > 0) {
     prof_begin(ctx, PK_FIT);
@@ -530,9 +550,8 @@ extern "C" sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n, const sf_gate* gat
   uint64_t amp = (uint64_t)16 << dmax;
   c->projected = 2 * amp + sizeof(TrackState) + sizeof(ReadoutInfo) +
                  (uint64_t)c->max_segs * sizeof(SegProg) + (uint64_t)c->max_had * sizeof(GF2Q);
-  if (split_form(n))
-    c->projected += (uint64_t)(c->rec_len + 1) * rec_stride_of(n) + (uint64_t)c->rec_len * 8 +
-                    (uint64_t)c->max_segs * pe_of(dmax) * 4;
+  c->projected += (uint64_t)(c->rec_len + 1) * rec_stride_of(n) + (uint64_t)c->rec_len * 8 +
+                  (uint64_t)c->max_segs * pe_of(dmax) * 4;
   *out = c;
   return SF_OK;
 }
@@ -667,10 +686,31 @@ extern "C" sf_status sf_state_destroy(sf_state* s) {
 
 // Queue the device gates [a, b) of dgates (device copy) / hg (host copy); b
 // ends at most right after a measurement.
-// The split-form buffers of a state in a track job (no-op for wider frames).
-static void split_fields(const sf_state* s, TrackJob* job, int nseg) {
+// Record, gate-info and segment-sum buffers of a wide frame, allocated when a
+// launch first runs it in split form (frames of up to 128 qubits get them at
+// init).
+static sf_status ensure_split_buffers(sf_state* s) {
+  if (s->rec.p) return SF_OK;
+  sf_ctx* ctx = s->ctx;
+  const sf_circuit* c = s->c;
+  sf_status rc;
+  if ((rc = dalloc(ctx, &s->rec, (size_t)(c->rec_len + 1) * rec_stride_of(c->n))) ||
+      (rc = dalloc(ctx, &s->ginfo, (size_t)c->rec_len * 8)) ||
+      (rc = dalloc(ctx, &s->segacc, (size_t)c->max_segs * pe_of(c->dmax) * 4))) {
+    dfree(ctx, &s->rec);
+    dfree(ctx, &s->ginfo);
+    dfree(ctx, &s->segacc);
+    return rc;
+  }
+  HIPCHK(ctx, hipMemsetAsync(s->ginfo.p, 0xff, s->ginfo.bytes, ctx->stream));
+  return SF_OK;
+}
+
+// The split-form buffers of a state in a track job (use: this launch runs the
+// frame in split form).
+static void split_fields(const sf_state* s, TrackJob* job, int nseg, bool use = true) {
   job->nseg = nseg;
-  if (!split_form(s->c->n) || job->dry) return;
+  if (!use || !s->rec.p || job->dry) return;
   job->rec = (uint8_t*)s->rec.p;
   job->ginfo = (int32_t*)s->ginfo.p;
   job->segacc = (uint32_t*)s->segacc.p;
@@ -696,8 +736,11 @@ static sf_status run_chunk(sf_state* s, const DGate* dgates, const DGate* hg, si
     else { open = true; meas_last = false; }
   }
   if (open) ++nseg;
-  if (nseg > c->max_segs || (split_form(c->n) && b - a > (size_t)c->rec_len))
+  if (nseg > c->max_segs || b - a > (size_t)c->rec_len)
     return fail(ctx, SF_E_STATE, "range of %zu gates with %d segments exceeds the state's buffers", b - a, nseg);
+  // one frame: the split form pays for every width
+  sf_status rs = ensure_split_buffers(s);
+  if (rs != SF_OK) return rs;
   TrackJob job;
   memset(&job, 0, sizeof job);
   job.st = (TrackState*)s->st.p;
@@ -1124,12 +1167,14 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
     jb.prog = (SegProg*)s->prog.p;
     jb.had = (GF2Q*)s->had.p;
     jb.outcomes = (const uint8_t*)s->outcomes.p;
-    if (NS[i] > s->c->max_segs || (split_form(s->c->n) && B[i] - A[i] > (size_t)s->c->rec_len)) {
+    if (NS[i] > s->c->max_segs || B[i] - A[i] > (size_t)s->c->rec_len) {
       *err = fail(s->ctx, SF_E_STATE, "state %d: range of %zu gates with %d segments exceeds its buffers", i,
                   B[i] - A[i], NS[i]);
       return false;
     }
-    split_fields(s, &jb, NS[i]);
+    const bool use = split_form(s->c->n) || rp->wcount[words_of(s->c->n)] <= SF_SPLIT_WIDE_MAX;
+    if (use && (*err = ensure_split_buffers(s)) != SF_OK) return false;
+    split_fields(s, &jb, NS[i], use);
     const int wi = words_of(s->c->n);
     rp->wlen[wi] = std::max(rp->wlen[wi], (int)(B[i] - A[i]));
     rp->wseg[wi] = std::max(rp->wseg[wi], NS[i]);
@@ -1155,7 +1200,7 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
     int kw[SF_WMAX + 1];
     for (int w = 0; w <= SF_WMAX; ++w) {
       kw[w] = phase_chunk(gates[w]);
-      rp->wchunk[w] = (rp->wlen[w] > 0 && cliff[w]) ? (rp->wlen[w] + kw[w] - 1) / kw[w] : 0;
+      rp->wchunk[w] = (rp->wlen[w] > 0 && cliff[w] && gates[w] > 0) ? (rp->wlen[w] + kw[w] - 1) / kw[w] : 0;
     }
     for (int j = 0; j < na; ++j)
       if (rp->jobs[j].rec) rp->jobs[j].pchunk = kw[words_of(states[act[j]]->c->n)];
@@ -1221,7 +1266,7 @@ static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs
     prof_begin(ctx, PK_TRACK);
     launch_track_many(ctx->stream, djobs + off, rp.wcount[w], w);
     prof_end(ctx);
-    if (split_form(64 * w)) launch_phase_many(ctx, djobs + off, rp.wcount[w], w, rp.wchunk[w], rp.wseg[w]);
+    launch_phase_many(ctx, djobs + off, rp.wcount[w], w, rp.wchunk[w], rp.wseg[w]);
     off += rp.wcount[w];
   }
   for (int k = 0; k < rp.kmax; ++k) {
@@ -1569,9 +1614,8 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
       const TrackJob* djw = dj + off;
       void* args[] = {(void*)&djw};
       e = add_kernel_node(g->graph, &last, track_many_fn(w), dim3(rp.wcount[w]), dim3(TL), args);
-      if (e == hipSuccess && split_form(64 * w) && rp.wchunk[w] > 0) {
-        const void* ph = w == 1 ? (const void*)sf_phase_many<1> : (const void*)sf_phase_many<2>;
-        e = add_kernel_node(g->graph, &last, ph, dim3(rp.wchunk[w], rp.wcount[w]), dim3(TL), args);
+      if (e == hipSuccess && rp.wchunk[w] > 0) {
+        e = add_kernel_node(g->graph, &last, phase_many_fn(w), dim3(rp.wchunk[w], rp.wcount[w]), dim3(TL), args);
         if (e == hipSuccess && rp.wseg[w] > 0)
           e = add_kernel_node(g->graph, &last, (const void*)sf_fit_many, dim3(rp.wseg[w], rp.wcount[w]), dim3(TL),
                               args);

@@ -1858,10 +1858,13 @@ static __device__ __forceinline__ void point_vec(const uint64_t* base, const uin
 // ---------------------------------------------------------------------------
 // Clifford gate
 // ---------------------------------------------------------------------------
+// rec: split form (the phase kernel evaluates the phase factor; *hs_out tells
+// whether this is a Hadamard that keeps the support size).
 static __device__ void clifford_gate(Lds& L, int op, int a, int b, int n, int d, int dry, GF2Q* had_out,
-                              int* nhad, int* err) {
+                              int* nhad, int* err, bool rec, bool* hs_out) {
   const int lane = lane_id();
   const int R = (n + 63) / 64;
+  *hs_out = false;
   if (op == DG_S || op == DG_SDG || op == DG_Z || op == DG_CZ) {
     // Diagonal gates change only z bits of X-block rows and flip only X-block
     // signs: the echelon form, the support and b*(sigma) stay as they are, and
@@ -1899,7 +1902,7 @@ static __device__ void clifford_gate(Lds& L, int op, int a, int b, int n, int d,
     if (lane < SF_WMAX) L.s0[lane] ^= L.fmask[lane];
     __syncthreads();
     TOC(1);
-    if (dry) return;
+    if (dry || rec) return;
     TIC(4);
     const int P = npoints(d);
     for (int p = lane; p < P; p += TL) {
@@ -1919,7 +1922,7 @@ static __device__ void clifford_gate(Lds& L, int op, int a, int b, int n, int d,
     return;
   }
   TIC(0);
-  if (!dry) save_old(L, n, d);
+  if (!dry && !rec) save_old(L, n, d);
   TOC(0);
   const int kold = L.misc[0];
   if (lane == 0)
@@ -1982,6 +1985,11 @@ static __device__ void clifford_gate(Lds& L, int op, int a, int b, int n, int d,
   rebuild_index(L, n);
   if (dry) { TOC(3); return; }
   const int knew = L.misc[0];
+  if (rec) {
+    *hs_out = op == DG_H && knew == kold;
+    TOC(3);
+    return;
+  }
   build_beta(L, n);
   hull_images(L, L.hbN, d, false);
   TOC(3);
@@ -2132,13 +2140,14 @@ static __device__ void det_functional(Lds& L, int q, int n, int d, uint32_t* c0,
 // otherwise the hull grows by the coordinate V[d] = f.
 // ---------------------------------------------------------------------------
 static __device__ void terminal_controlled(Lds& L, const TrackJob& job, const DGate& gt, int seg, int nhad,
-                                           int had_base, int n, int* dptr, int* err) {
+                                           int had_base, int n, int* dptr, int* err, bool rec) {
   const int lane = lane_id();
   int d = *dptr;
   SegProg* sp = job.dry ? nullptr : job.prog + seg;
   if (!job.dry) {
     if (lane == 0) emit_header(sp, SEG_DET2, 0, d, d, nhad, had_base);
-    fit_z4(L, L.acc, d, &sp->E, err);
+    if (rec) zero_z4(&sp->E);   // fitted by the fit kernel when the range has Clifford gates
+    else fit_z4(L, L.acc, d, &sp->E, err);
     __syncthreads();
   }
   uint32_t c1, r1, c2, r2;
@@ -2202,6 +2211,172 @@ static __device__ void terminal_controlled(Lds& L, const TrackJob& job, const DG
   *dptr = d;
 }
 
+// ---------------------------------------------------------------------------
+// Split form for launches with few wide frames (as in Trk): records of the
+// state after every gate from LDS, and the per-gate phase evaluation of the
+// phase kernel.  Records hold W words per row part (LDS rows hold SF_WMAX).
+// ---------------------------------------------------------------------------
+static __device__ void rec_write(const TrackJob& job, int r, const Lds& L, int n, int d) {
+  uint64_t* rw = (uint64_t*)(job.rec + (size_t)r * job.rec_stride);
+  const int lane = lane_id();
+  for (int idx = lane; idx < n * W; idx += TL) {
+    const int i = idx / W, w = idx % W;
+    rw[i * 2 * W + w] = L.rx[i * SF_WMAX + w];
+    rw[i * 2 * W + W + w] = L.rz[i * SF_WMAX + w];
+  }
+  uint64_t* hv = rw + (size_t)n * 2 * W;
+  if (lane <= d)
+    for (int w = 0; w < W; ++w) hv[lane * W + w] = lane == 0 ? L.s0[w] : L.V[lane - 1][w];
+  if (lane == 0) *(int32_t*)(hv + (SF_DMAX + 1) * W) = d;
+}
+
+static __device__ int rec_d(const TrackJob& job, int r, int n) {
+  const uint64_t* rw = (const uint64_t*)(job.rec + (size_t)r * job.rec_stride);
+  return *(const int32_t*)(rw + (size_t)n * 2 * W + (SF_DMAX + 1) * W);
+}
+
+static __device__ void rec_load(Lds& L, const TrackJob& job, int r, int n, int d) {
+  const uint64_t* rw = (const uint64_t*)(job.rec + (size_t)r * job.rec_stride);
+  const int lane = lane_id();
+  for (int idx = lane; idx < SF_NMAX * SF_WMAX; idx += TL) {
+    const int i = idx / SF_WMAX, w = idx % SF_WMAX;
+    const bool in = i < n && w < W;
+    L.rx[idx] = in ? rw[i * 2 * W + w] : 0ull;
+    L.rz[idx] = in ? rw[i * 2 * W + W + w] : 0ull;
+  }
+  const uint64_t* hv = rw + (size_t)n * 2 * W;
+  if (lane <= d)
+    for (int w = 0; w < SF_WMAX; ++w) {
+      const uint64_t v = w < W ? hv[lane * W + w] : 0ull;
+      if (lane == 0) L.s0[w] = v;
+      else L.V[lane - 1][w] = v;
+    }
+  __syncthreads();
+}
+
+static __device__ void seg_clear(const TrackJob& job, int s, int d) {
+  if (s >= job.nseg) return;
+  const int P = min(npoints(d), job.pe);
+  for (int p = lane_id(); p < P; p += TL) job.segacc[(size_t)s * job.pe + p] = 0u;
+}
+
+// Phase factor of Clifford gate g0 + i from the records before and after it,
+// added into its segment's sums (the evaluation of clifford_gate).
+static __device__ void phase_gate(Lds& L, const TrackJob& job, int i) {
+  const int lane = lane_id();
+  const DGate gt = job.gates[job.g0 + i];
+  const int op = __builtin_amdgcn_readfirstlane(gt.op);
+  if (op >= DG_NCPHASE) return;
+  TrackState* st = job.st;
+  const int n = __builtin_amdgcn_readfirstlane(st->n);
+  const int d = __builtin_amdgcn_readfirstlane(rec_d(job, i + 1, n));
+  const int s = __builtin_amdgcn_readfirstlane(job.ginfo[2 * i]);
+  if (d < 0 || d >= SF_DMAX || s < 0 || s >= job.nseg || npoints(d) > job.pe ||
+      __builtin_amdgcn_readfirstlane(rec_d(job, i, n)) != d) {
+    if (lane == 0) st->error = TRK_E_INTERNAL;
+    return;
+  }
+  uint32_t* acc = job.segacc + (size_t)s * job.pe;
+  const int a = __builtin_amdgcn_readfirstlane(gt.q0), b = __builtin_amdgcn_readfirstlane(gt.q1);
+  int err = 0;
+  const int P = npoints(d);
+  if (op == DG_S || op == DG_SDG || op == DG_Z || op == DG_CZ) {
+    rec_load(L, job, i + 1, n, d);
+    rebuild_index(L, n);
+    build_beta(L, n);
+    hull_images(L, L.hbN, d, false);
+    build_points(L, d);
+    for (int p = lane; p < P; p += TL) {
+      uint32_t Y = L.Ys[p];
+      int ba = getb(L.hbN[0], a), bb = op == DG_CZ ? getb(L.hbN[0], b) : 0;
+      while (Y) {
+        const int j = __builtin_ctz(Y);
+        Y &= Y - 1;
+        ba ^= getb(L.hbN[1 + j], a);
+        if (op == DG_CZ) bb ^= getb(L.hbN[1 + j], b);
+      }
+      const int mu = op == DG_S ? ba : op == DG_SDG ? 3 * ba : op == DG_Z ? 2 * ba : 2 * (ba & bb);
+      atomicAdd(&acc[p], (uint32_t)(mu & 3));
+    }
+    return;
+  }
+  rec_load(L, job, i, n, d);
+  rebuild_index(L, n);
+  build_beta(L, n);
+  hull_images(L, L.hbN, d, false);
+  save_old(L, n, d);
+  const int kold = L.misc[0];
+  rec_load(L, job, i + 1, n, d);
+  rebuild_index(L, n);
+  build_beta(L, n);
+  hull_images(L, L.hbN, d, false);
+  const int knew = L.misc[0];
+  build_points(L, d);
+  const int dk = knew - kold;
+  const bool hsplit = op == DG_H && dk == 0;
+  for (int p = lane; p < P; p += TL) {
+    uint32_t Y = L.Ys[p];
+    uint64_t so[SF_WMAX], bo[SF_WMAX], bn[SF_WMAX], src[SF_WMAX];
+    point_vec(L.os0, L.oV, Y, 0, so);
+    point_vec(L.hbO[0], L.hbO, Y, 1, bo);
+    point_vec(L.hbN[0], L.hbN, Y, 1, bn);
+    int e = 0, t = 0;
+    int ba = getb(bn, a);
+    for (int w = 0; w < W; ++w) src[w] = bn[w];
+    if (op != DG_H) {
+      int mu = 0;
+      switch (op) {
+        case DG_X: flipb(src, a); break;
+        case DG_Y: flipb(src, a); mu = ba ? 1 : 3; break;
+        case DG_CNOT: if (ba) flipb(src, b); break;
+      }
+      int u = uexp(L, so, bo, src);
+      if (u < 0) err = TRK_E_INTERNAL;
+      e = mu + u;
+    } else {
+      uint64_t b1[SF_WMAX];
+      for (int w = 0; w < W; ++w) b1[w] = bn[w];
+      if (ba) flipb(src, a); else flipb(b1, a);   // src: bit a = 0, b1: bit a = 1
+      if (dk == 1) {
+        int u0 = uexp(L, so, bo, src);
+        int u1 = uexp(L, so, bo, b1);
+        if ((u0 < 0) == (u1 < 0)) err = TRK_E_INTERNAL;
+        e = u0 >= 0 ? u0 : u1 + 2 * ba;
+      } else if (dk == -1) {
+        int u0 = uexp(L, so, bo, src);
+        if (u0 < 0) err = TRK_E_INTERNAL;
+        e = u0;
+      } else {
+        int e0 = uexp(L, so, bo, src);
+        int e1 = uexp(L, so, bo, b1);
+        if (e0 < 0 || e1 < 0) err = TRK_E_INTERNAL;
+        e1 += 2 * ba;
+        int dl = (e1 - e0) & 3;
+        if (!(dl & 1)) err = TRK_E_INTERNAL;
+        e = e0;
+        t = dl == 3 ? 1 : 0;        // omega = exp(i pi (2 e0 + 1 - 2t)/4)
+      }
+    }
+    atomicAdd(&acc[p], (uint32_t)(e & 3));
+    if (hsplit) L.t0[p] = (uint8_t)t;
+  }
+  __syncthreads();
+  const int hi = __builtin_amdgcn_readfirstlane(job.ginfo[2 * i + 1]);
+  if (hsplit != (hi >= 0)) err = TRK_E_INTERNAL;
+  else if (hsplit) fit_gf2(L, L.t0, d, &job.had[hi]);
+  __syncthreads();
+  err = wave_max(err);
+  if (err && lane == 0) st->error = err;
+}
+
+// chunk c of pchunk gates, one gate at a time
+static __device__ void phase_body(Lds& L, const TrackJob& job, int c) {
+  const int len = job.g1 - job.g0;
+  const int k = job.pchunk > 0 ? job.pchunk : 1;
+  const int i1 = min(len, (c + 1) * k);
+  for (int i = c * k; i < i1; ++i) phase_gate(L, job, i);
+}
+
 static __device__ void track_body(Lds& L, const TrackJob& job) {
   TrackState* st = job.st;
   const int lane = lane_id();
@@ -2230,25 +2405,53 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
   }
   for (int p = lane; p < SF_PMAX; p += TL) L.acc[p] = 0;
   __syncthreads();
+  // split form (when the job brings records): this kernel records, the phase
+  // kernels evaluate
+  const bool rec = !job.dry && job.rec != nullptr;
+  if (rec) {
+    rec_write(job, 0, L, n, d);
+    seg_clear(job, 0, d);
+  }
   int seg = 0, nhad = 0, had_base = 0, nmeas = st->nmeas, dmax = st->dmax;
   int pend = 0, pend_j0 = -1, pend_c0 = 0, pend_meas = -1;
   uint32_t pend_r = 0;
   bool open = false;
   for (int g = job.g0; g < job.g1 && !err; ++g) {
     const DGate gt = job.gates[g];
+    const int gi = g - job.g0;
     if (gt.op < DG_NCPHASE) {
-      clifford_gate(L, gt.op, gt.q0, gt.q1, n, d, job.dry, job.had + had_base, &nhad, &err);
+      bool hs = false;
+      clifford_gate(L, gt.op, gt.q0, gt.q1, n, d, job.dry, job.had + had_base, &nhad, &err, rec, &hs);
       err = wave_max(err);
+      if (rec) {
+        if (lane == 0) {
+          job.ginfo[2 * gi] = seg;
+          job.ginfo[2 * gi + 1] = hs ? had_base + nhad : -1;
+        }
+        if (hs) ++nhad;
+        rec_write(job, gi + 1, L, n, d);
+      }
       open = true;
       continue;
     }
     TIC(6);
+    if (rec) {
+      // the Clifford steps of the split form keep no b* basis or images
+      build_beta(L, n);
+      hull_images(L, L.hbN, d, false);
+      if (lane == 0) { job.ginfo[2 * gi] = -1; job.ginfo[2 * gi + 1] = -1; }
+    }
     // terminal gate of the segment
     if (gt.op == DG_CPH2 || gt.op == DG_CX2) {
-      terminal_controlled(L, job, gt, seg, nhad, had_base, n, &d, &err);
+      terminal_controlled(L, job, gt, seg, nhad, had_base, n, &d, &err, rec);
       if (d > dmax) dmax = d;
       if (d > SF_DMAX - 1) err = TRK_E_DIM;
       err = wave_max(err);
+      __syncthreads();
+      if (rec) {
+        rec_write(job, gi + 1, L, n, d);
+        seg_clear(job, seg + 1, d);
+      }
       TOC(6);
       had_base += nhad;
       nhad = 0;
@@ -2273,7 +2476,8 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
     int d_entry = d;
     if (!job.dry) {
       if (lane == 0) emit_header(sp, SEG_NONE, is_meas, d, d, nhad, had_base);
-      fit_z4(L, L.acc, d, &sp->E, &err);
+      if (rec) zero_z4(&sp->E);
+      else fit_z4(L, L.acc, d, &sp->E, &err);
       __syncthreads();
     }
     if (!rnd) {
@@ -2415,6 +2619,11 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
     if (d > SF_DMAX - 1) err = TRK_E_DIM;
     err = wave_max(err);
     (void)d_entry;
+    __syncthreads();
+    if (rec) {
+      rec_write(job, gi + 1, L, n, d);
+      seg_clear(job, seg + 1, d);
+    }
     TOC(6);
     // new segment
     had_base += nhad;
@@ -2453,7 +2662,8 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
   if (open && !job.dry && !err) {
     SegProg* sp = job.prog + seg;
     if (lane == 0) emit_header(sp, SEG_NONE, 0, d, d, nhad, had_base);
-    fit_z4(L, L.acc, d, &sp->E, &err);
+    if (rec) zero_z4(&sp->E);
+    else fit_z4(L, L.acc, d, &sp->E, &err);
     zero_z4(&sp->B0);
     zero_z4(&sp->B1);
     ++seg;
@@ -2559,19 +2769,28 @@ __global__ void __launch_bounds__(TL) sf_track_many(const TrackJob* __restrict__
   track_w<W>(job);
 }
 
-// Split form (W <= 2): the phase evaluation of every Clifford gate of a range,
-// one wavefront per gate (blockIdx.x = gate of the range, blockIdx.y = frame).
+// Split form: the phase evaluation of the Clifford gates of a range, one
+// wavefront per chunk of gates (blockIdx.x = chunk, blockIdx.y = frame).
+template <int W>
+__device__ __forceinline__ void phase_w(const TrackJob& job, int c) {
+  if constexpr (W <= 2) {
+    __shared__ typename Trk<W>::LL L;
+    Trk<W>::phase_body(L, job, c);
+  } else {
+    __shared__ Lds L;
+    TrkL<W>::phase_body(L, job, c);
+  }
+}
+
 template <int W>
 __global__ void __launch_bounds__(TL) sf_phase_one(TrackJob one) {
-  __shared__ typename Trk<W>::LL L;
-  Trk<W>::phase_body(L, one, (int)blockIdx.x);
+  phase_w<W>(one, (int)blockIdx.x);
 }
 
 template <int W>
 __global__ void __launch_bounds__(TL) sf_phase_many(const TrackJob* __restrict__ jobs) {
-  __shared__ typename Trk<W>::LL L;
   const TrackJob job = jobs[blockIdx.y];
-  Trk<W>::phase_body(L, job, (int)blockIdx.x);
+  phase_w<W>(job, (int)blockIdx.x);
 }
 
 // ... and the fit of each segment's summed phase (blockIdx.x = segment).
