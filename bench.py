@@ -114,15 +114,22 @@ def batched_extra(eng, wl, name, circs, seeds, plain_sample):
         for i in idx:
             states[i].reset(circs[i].init_bits, seeds[i])
 
-    bases = [c.init_bits for c in circs]
-    eng.batch_reset(states, bases, seeds)
-    eng.batch_run(states)  # warm-up
+    import numpy as np
+    import paper_1712_03554_amd as sf
+    batch = sf.StateBatch(states)
+    nmax = max(c.n for c in circs)
+    bases = np.zeros((len(circs), nmax), dtype=np.uint8)
+    for i, c in enumerate(circs):
+        bases[i, :c.n] = np.asarray(c.init_bits, dtype=np.uint8)
+    seed_arr = np.asarray(seeds, dtype=np.uint64)
+    eng.batch_reset(batch, bases, seed_arr)
+    eng.batch_run(batch)  # warm-up
     torch.cuda.synchronize()
     reps = 3
     t0 = time.perf_counter()
     for _ in range(reps):
-        eng.batch_reset(states, bases, seeds)
-        eng.batch_run(states)
+        eng.batch_reset(batch, bases, seed_arr)
+        eng.batch_run(batch)
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / reps
     g = eng.batch_graph(states, [c.init_bits for c in circs], seeds)
@@ -464,9 +471,11 @@ def main():
 
     bases = [c.init_bits for c in circs]
 
+    batch = sf.StateBatch(states)
+
     def batched_step():
-        eng.batch_reset(states, bases, seeds)
-        eng.batch_run(states)
+        eng.batch_reset(batch, bases, seeds)
+        eng.batch_run(batch)
 
     graph = None
 

@@ -179,21 +179,23 @@ class Engine:
         return Circuit(self, h, n)
 
     def batch_run(self, states):
-        """Run every remaining gate of the given states as one batch (synchronises)."""
-        arr = (ctypes.c_void_p * max(1, len(states)))(*[s._h.value for s in states])
-        self._check(self._L.sf_batch_run(self._h, ctypes.cast(arr, ctypes.c_void_p), len(states)))
+        """Run every remaining gate of the given states as one batch
+        (synchronises).  states: a list of State or a StateBatch."""
+        sb = states if isinstance(states, StateBatch) else StateBatch(states)
+        self._check(self._L.sf_batch_run(self._h, sb.handles(), len(sb)))
 
     def batch_reset(self, states, bases=None, seeds=None):
-        """Re-initialise the states with one launch (basis bit lists, seeds)."""
-        ns = len(states)
-        arr = (ctypes.c_void_p * max(1, ns))(*[s._h.value for s in states])
-        b = None
-        if bases is not None:
-            b = np.zeros((max(1, ns), 4), dtype=np.uint64)
-            for i, bits in enumerate(bases):
-                b[i] = _basis_words(states[i].n, bits)
-        sd = None if seeds is None else np.array([int(x) & ((1 << 64) - 1) for x in seeds] or [0], dtype=np.uint64)
-        self._check(self._L.sf_batch_reset(self._h, ctypes.cast(arr, ctypes.c_void_p), ns, _ptr(b), _ptr(sd)))
+        """Re-initialise the states with one launch.  states: a list of State
+        or a StateBatch; bases: basis bit lists, or an array of shape
+        (states, qubits) of 0/1; seeds: integers."""
+        sb = states if isinstance(states, StateBatch) else StateBatch(states)
+        ns = len(sb)
+        b = None if bases is None else _basis_word_rows(bases, ns)
+        sd = None
+        if seeds is not None:
+            sd = np.asarray(seeds, dtype=np.uint64) if isinstance(seeds, np.ndarray) else \
+                np.array([int(x) & ((1 << 64) - 1) for x in seeds] or [0], dtype=np.uint64)
+        self._check(self._L.sf_batch_reset(self._h, sb.handles(), ns, _ptr(b), _ptr(sd)))
 
     def batch_graph(self, states, bases=None, seeds=None) -> "Graph":
         """Record a whole batched run of these states (see sf_batch_graph)."""
@@ -409,6 +411,37 @@ class Server:
 
     def __del__(self):
         self.close()
+
+
+class StateBatch:
+    """A fixed list of states with their handle array built once (for
+    repeated batched runs of many states)."""
+
+    def __init__(self, states):
+        self.states = list(states)
+        self._arr = (ctypes.c_void_p * max(1, len(self.states)))(*[s._h.value for s in self.states])
+
+    def __len__(self):
+        return len(self.states)
+
+    def __iter__(self):
+        return iter(self.states)
+
+    def handles(self):
+        return ctypes.cast(self._arr, ctypes.c_void_p)
+
+
+def _basis_word_rows(bases, ns: int) -> np.ndarray:
+    """Basis bits per state (lists, or an array of 0/1 of shape (states, n))
+    as 4 little-endian 64-bit words per state."""
+    bits = np.zeros((max(1, ns), 256), dtype=np.uint8)
+    if isinstance(bases, np.ndarray):
+        bits[:bases.shape[0], :bases.shape[1]] = bases.astype(np.uint8) & 1
+    else:
+        for i, row in enumerate(bases):
+            if row is not None and len(row):
+                bits[i, :len(row)] = np.asarray(row, dtype=np.uint8) & 1
+    return np.ascontiguousarray(np.packbits(bits, axis=1, bitorder="little").view(np.uint64))
 
 
 def _basis_words(n: int, bits):

@@ -69,3 +69,21 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=60)
     assert r.returncode == 2
     assert "one GPU" in json.loads(r.stdout.strip())["error"]
+
+
+def test_basis_word_packing():
+    """The batched reset's basis words (lists or an array of bits) equal the
+    per-state packing: bit q in word q / 64, position q % 64."""
+    import numpy as np
+    from paper_1712_03554_amd import _basis_word_rows, _basis_words
+    rng = np.random.default_rng(7)
+    for n in (1, 13, 63, 64, 65, 128, 200, 256):
+        rows = [rng.integers(0, 2, size=n).tolist() for _ in range(6)]
+        ref = np.stack([_basis_words(n, r) for r in rows])
+        assert np.array_equal(_basis_word_rows(rows, 6), ref)
+        assert np.array_equal(_basis_word_rows(np.array(rows, dtype=np.uint8), 6), ref)
+        q = int(rng.integers(n))
+        one = [0] * n
+        one[q] = 1
+        w = _basis_word_rows([one], 1)[0]
+        assert int(w[q >> 6]) == 1 << (q & 63) and int(w.sum()) == 1 << (q & 63)
