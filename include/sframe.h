@@ -139,7 +139,10 @@ sf_status sf_run(sf_state* s);
 /* Run every remaining gate of n_states states (all of this context) as one
  * batch: per round, the tableau tracks of all frames share one launch (one
  * wavefront each) and the element kernels of all frames share one launch per
- * segment.  Results are identical to running each state alone.  Synchronises. */
+ * segment.  Results are identical to running each state alone.  The
+ * per-round launch descriptors are staged through pinned host memory that the
+ * context keeps (allocated on first use, freed by sf_ctx_destroy).
+ * Synchronises. */
 sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t n_states);
 /* Measure qubit q in the Z basis now, between circuit gates (the state must
  * be at a gate boundary, as after sf_step).  Same rule and random stream as

@@ -39,7 +39,40 @@ struct sf_ctx {
   // launch shape of the elementwise frame kernels (segment, measurement
   // filter) per hull dimension d: threads per block and blocks (grid-stride)
   int tune_block[SF_DMAX + 1], tune_grid[SF_DMAX + 1];
+  // pinned host chunks that stage batched-round descriptors for async copies;
+  // reused after the stream has been synchronised
+  std::vector<std::pair<char*, size_t>> pin;
+  size_t pin_cur = 0, pin_off = 0;
 };
+
+// Pinned staging memory for an async host-to-device copy (nullptr if none
+// can be had: the caller copies from pageable memory instead).
+static void* pin_take(sf_ctx* ctx, size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  while (ctx->pin_cur < ctx->pin.size()) {
+    auto& ch = ctx->pin[ctx->pin_cur];
+    if (ctx->pin_off + bytes <= ch.second) {
+      void* p = ch.first + ctx->pin_off;
+      ctx->pin_off += bytes;
+      return p;
+    }
+    ctx->pin_cur++;
+    ctx->pin_off = 0;
+  }
+  const size_t sz = std::max<size_t>(bytes, (size_t)8 << 20);
+  void* p = nullptr;
+  if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess || !p) return nullptr;
+  ctx->pin.push_back({(char*)p, sz});
+  ctx->pin_cur = ctx->pin.size() - 1;
+  ctx->pin_off = bytes;
+  return p;
+}
+
+// after a stream synchronisation: every staged copy has completed
+static void pin_release(sf_ctx* ctx) {
+  ctx->pin_cur = 0;
+  ctx->pin_off = 0;
+}
 
 static int grid_for(int d) {
   uint64_t blocks = ((1ull << d) + EB - 1) / EB;
@@ -265,7 +298,7 @@ static sf_status dalloc(sf_ctx* ctx, DevBuf* b, size_t bytes) {
 static void dfree(sf_ctx* ctx, DevBuf* b) {
   if (!b->p) return;
   if (ctx->has_alloc) ctx->alloc.free(b->p, b->bytes, (void*)ctx->stream, ctx->alloc.user);
-  else hipFree(b->p);
+  else (void)hipFree(b->p);
   ctx->in_use -= b->bytes;
   b->p = nullptr;
   b->bytes = 0;
@@ -305,7 +338,9 @@ extern "C" sf_status sf_ctx_create(int device, void* hip_stream, const sf_alloca
 
 extern "C" sf_status sf_ctx_destroy(sf_ctx* ctx) {
   if (!ctx) return SF_OK;
+  (void)hipStreamSynchronize(ctx->stream);
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  for (auto& ch : ctx->pin) (void)hipHostFree(ch.first);
   delete ctx;
   return SF_OK;
 }
@@ -678,7 +713,7 @@ extern "C" sf_status sf_state_init(sf_ctx* ctx, const sf_circuit* c, const uint6
 extern "C" sf_status sf_state_destroy(sf_state* s) {
   if (!s) return SF_OK;
   if (s->graph_refs) return fail(s->ctx, SF_E_STATE, "state is part of a graph; destroy the graph first");
-  hipStreamSynchronize(s->ctx->stream);
+  (void)hipStreamSynchronize(s->ctx->stream);
   state_free(s);
   delete s;
   return SF_OK;
@@ -1292,8 +1327,10 @@ static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs
 // up to and including its next measurement (or its cap-th non-Clifford phase
 // gate).  *active = number of states that had work.  Asynchronous; the
 // scratch must be large enough.
+// staged: the descriptors go through pinned memory (the caller synchronises
+// the stream and releases it before the next batch).
 static sf_status batch_round(sf_ctx* ctx, sf_state* const* states, size_t ns, BatchScratch* bs, int* active,
-                             int cap = 0) {
+                             int cap = 0, bool staged = false) {
   std::vector<Progress> pr(ns);
   for (size_t i = 0; i < ns; ++i) pr[i] = progress_of(states[i]);
   RoundPlan rp;
@@ -1301,6 +1338,21 @@ static sf_status batch_round(sf_ctx* ctx, sf_state* const* states, size_t ns, Ba
   *active = 0;
   if (!plan_round(states, ns, pr.data(), cap, nullptr, &rp, &err)) return err;
   *active = rp.na;
+  if (staged) {
+    const size_t bj = rp.na * sizeof(TrackJob), bd = rp.desc.size() * sizeof(ElemDesc);
+    void* hj = pin_take(ctx, bj);
+    void* hd = hj ? pin_take(ctx, bd) : nullptr;
+    if (hj && hd) {
+      memcpy(hj, rp.jobs.data(), bj);
+      memcpy(hd, rp.desc.data(), bd);
+      HIPCHK(ctx, hipMemcpyAsync(bs->djobs.p, hj, bj, hipMemcpyHostToDevice, ctx->stream));
+      HIPCHK(ctx, hipMemcpyAsync(bs->ddesc.p, hd, bd, hipMemcpyHostToDevice, ctx->stream));
+      launch_round(ctx, rp, (const TrackJob*)bs->djobs.p, (const ElemDesc*)bs->ddesc.p);
+      HIPCHK(ctx, hipGetLastError());
+      for (size_t i = 0; i < ns; ++i) set_progress(states[i], pr[i]);
+      return SF_OK;
+    }
+  }
   const size_t ndesc = rp.desc.size();
   bs->keep_jobs.push_back(std::move(rp.jobs));
   bs->keep_desc.push_back(std::move(rp.desc));
@@ -1353,8 +1405,9 @@ extern "C" sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t n
   BatchScratch bs;
   sf_status rc = scratch_reserve(ctx, &bs, ns, maxseg);
   int active = 1;
-  while (rc == SF_OK && active) rc = batch_round(ctx, states, ns, &bs, &active);
+  while (rc == SF_OK && active) rc = batch_round(ctx, states, ns, &bs, &active, 0, true);
   hipError_t e = hipStreamSynchronize(ctx->stream);
+  pin_release(ctx);
   scratch_free(ctx, &bs);
   if (rc != SF_OK) return rc;
   if (e != hipSuccess) return fail(ctx, SF_E_DEVICE, "batch run: %s", hipGetErrorString(e));

@@ -624,3 +624,36 @@ def test_stabilizer_circuits_keep_one_element(eng, n):
     _compare(st, ref, circ.name)
     assert st.outcomes() == ref.outcomes()
     st.close()
+
+
+def test_many_wide_frames_in_one_batch(eng):
+    """More wide frames (n > 128) in one batched launch than take the split
+    track: they evaluate the phase factors inside the track kernel.  Each
+    result equals the same frame run alone (split track) bit for bit and
+    matches the oracle."""
+    circs = []
+    for j in range(136):
+        # 68 frames of three words (n in 129..192), 68 of four (193..256)
+        n = 129 + (j * 37) % 64 + (64 if j % 2 else 0)
+        c = wl.random_clifford_t(n, n, 1 + j % 4, 9100 + j,
+                                 measure_qubits=(j % n, n - 1) if j % 3 == 0 else ())
+        c.name = f"batchwide{j}-n{n}"
+        circs.append(c)
+    seeds = [300 + j for j in range(len(circs))]
+    print(f"case batch of {len(circs)} wide frames", flush=True)
+    loaded = [eng.load(c.n, c) for c in circs]
+    states = [l.state(c.init_bits, s) for l, c, s in zip(loaded, circs, seeds)]
+    eng.batch_run(states)
+    for j, (c, s, st) in enumerate(zip(circs, seeds, states)):
+        tab, sig, amp = st.read_frame()
+        if j % 16 < 2:
+            (ta, sa, aa), oa = _run_alone(eng, c, s)
+            assert np.array_equal(tab, ta) and np.array_equal(sig, sa), c.name
+            assert np.array_equal(amp.view(np.uint64), aa.view(np.uint64)), c.name
+            assert st.outcomes() == oa, c.name
+        ref = OracleFrame(c.n, c.init_bits, s)
+        ref.run(c.array())
+        rtab, rsig, ramp = ref.read()
+        assert np.array_equal(tab, rtab), c.name
+        assert_frames_equal(sigma_ints(sig), amp, sigma_ints(rsig), ramp, what=c.name)
+        assert st.outcomes() == ref.outcomes(), c.name
