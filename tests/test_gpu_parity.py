@@ -626,19 +626,24 @@ def test_stabilizer_circuits_keep_one_element(eng, n):
     st.close()
 
 
-def test_many_wide_frames_in_one_batch(eng):
-    """More wide frames (n > 128) in one batched launch than take the split
-    track: they evaluate the phase factors inside the track kernel.  Each
-    result equals the same frame run alone (split track) bit for bit and
-    matches the oracle."""
+def _wide_frames(count):
+    """count frames of 129..256 qubits, alternately three and four words."""
     circs = []
-    for j in range(136):
-        # 68 frames of three words (n in 129..192), 68 of four (193..256)
+    for j in range(count):
         n = 129 + (j * 37) % 64 + (64 if j % 2 else 0)
         c = wl.random_clifford_t(n, n, 1 + j % 4, 9100 + j,
                                  measure_qubits=(j % n, n - 1) if j % 3 == 0 else ())
         c.name = f"batchwide{j}-n{n}"
         circs.append(c)
+    return circs
+
+
+def test_many_wide_frames_in_one_batch(eng):
+    """More wide frames (n > 128) in one batched launch than take the split
+    track: they evaluate the phase factors inside the track kernel.  Each
+    result equals the same frame run alone (split track) bit for bit and
+    matches the oracle."""
+    circs = _wide_frames(136)
     seeds = [300 + j for j in range(len(circs))]
     print(f"case batch of {len(circs)} wide frames", flush=True)
     loaded = [eng.load(c.n, c) for c in circs]
@@ -657,3 +662,41 @@ def test_many_wide_frames_in_one_batch(eng):
         assert np.array_equal(tab, rtab), c.name
         assert_frames_equal(sigma_ints(sig), amp, sigma_ints(rsig), ramp, what=c.name)
         assert st.outcomes() == ref.outcomes(), c.name
+
+
+@pytest.mark.parametrize("count", [6, 136])
+def test_graph_with_wide_frames(eng, count):
+    """The graph form of a batch of wide frames (split track for a few of
+    them, in-kernel phase evaluation for more than 64 of one word count)
+    gives the eager batched results bit for bit, on two replays with new
+    inputs."""
+    import paper_1712_03554_amd as sf
+    circs = _wide_frames(count) + [wl.config3(1), _mixed_circuit(3, 6)]
+    loaded = [eng.load(c.n, c) for c in circs]
+    states = [l.state(c.init_bits, 0) for l, c in zip(loaded, circs)]
+    g = eng.batch_graph(states, [c.init_bits for c in circs], [7] * len(circs))
+    rng = np.random.default_rng(77 + count)
+    for rep in range(2):
+        print(f"case graph of {count} wide frames, replay {rep}", flush=True)
+        bases = [rng.integers(0, 2, size=c.n).tolist() for c in circs]
+        seeds = [int(rng.integers(0, 1 << 62)) for _ in circs]
+        for i in range(len(circs)):
+            g.set_input(i, bases[i], seeds[i])
+        g.launch()
+        eager = [l.state(b, s) for l, b, s in zip(loaded, bases, seeds)]
+        eng.batch_run(eager)
+        for c, st, e in zip(circs, states, eager):
+            ta, sa, aa = e.read_frame()
+            tb, sb, ab = st.read_frame()
+            assert np.array_equal(ta, tb) and np.array_equal(sa, sb), (rep, c.name)
+            assert np.array_equal(aa.view(np.uint64), ab.view(np.uint64)), (rep, c.name)
+            assert e.outcomes() == st.outcomes(), (rep, c.name)
+            e.close()
+        i = rep * 3
+        ref = OracleFrame(circs[i].n, bases[i], seeds[i])
+        ref.run(circs[i].array())
+        _compare(states[i], ref, f"graph of wide frames, replay {rep}")
+        assert states[i].outcomes() == ref.outcomes()
+    g.close()
+    for st in states:
+        st.close()
