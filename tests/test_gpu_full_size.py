@@ -1,0 +1,116 @@
+"""The benchmark workloads at full size, in the launch configuration the
+benchmark times (one batched reset and one batched run of every frame, and
+the graph form), checked against the oracle (needs an MI355X).
+
+* 3 random Clifford+T circuits, n = 128, 2000 Cliffords + 16 T, 16
+  measurements (the headline step): every frame against the oracle.
+* 4096 Steane fault-injection trials: every trial against the oracle.
+* 1024 uneven random Clifford+T circuits (n in 16..256, up to 12 T): every
+  frame's norm and size bound; the oracle on all circuits of at most 72
+  qubits and on the two narrowest of each wider word count (the oracle's
+  per-gate elimination makes the 200-qubit circuits take seconds each).
+
+Eager and graph results agree bit for bit on every frame.
+"""
+import numpy as np
+import pytest
+
+from oracle.frame import OracleFrame
+from paper_1712_03554_amd import workloads as wl
+from tests.oracle_helpers import assert_frames_equal, sigma_ints
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1712_03554_amd as sf
+    return sf.Engine(0)
+
+
+def _full_batch(eng, circs, seeds):
+    """Batched reset + run of all frames, then the graph form with the same
+    inputs (checked equal bit for bit); returns the eager results per frame:
+    ((tableau, sigma, amplitudes), outcomes, fragile flag)."""
+    import paper_1712_03554_amd as sf
+    loaded = [eng.load(c.n, c) for c in circs]
+    states = [l.state(c.init_bits, s) for l, c, s in zip(loaded, circs, seeds)]
+    batch = sf.StateBatch(states)
+    nmax = max(c.n for c in circs)
+    bases = np.zeros((len(circs), nmax), dtype=np.uint8)
+    for i, c in enumerate(circs):
+        bases[i, :c.n] = np.asarray(c.init_bits, dtype=np.uint8)
+    seed_arr = np.asarray(seeds, dtype=np.uint64)
+    # run once from other inputs so that the reset has state to clear
+    eng.batch_run(batch)
+    eng.batch_reset(batch, bases, seed_arr)
+    eng.batch_run(batch)
+    eager = [(st.read_frame(), st.outcomes(), st.info()[1]) for st in states]
+    g = eng.batch_graph(states, [c.init_bits for c in circs], seeds)
+    g.launch()
+    for i, (c, st) in enumerate(zip(circs, states)):
+        (ta, sa, aa), oa, _ = eager[i]
+        tb, sb, ab = st.read_frame()
+        assert np.array_equal(ta, tb) and np.array_equal(sa, sb), c.name
+        assert np.array_equal(aa.view(np.uint64), ab.view(np.uint64)), c.name
+        assert st.outcomes() == oa, c.name
+    g.close()
+    for st in states:
+        st.close()
+    return eager
+
+
+def _check_oracle(c, seed, res):
+    (tab, sig, amp), outs, frag = res
+    assert not frag, c.name
+    ref = OracleFrame(c.n, c.init_bits, seed)
+    ref.run(c.array())
+    rtab, rsig, ramp = ref.read()
+    assert not ref.fragile, c.name
+    assert np.array_equal(tab, rtab), c.name
+    assert_frames_equal(sigma_ints(sig), amp, sigma_ints(rsig), ramp, what=c.name)
+    assert outs == ref.outcomes(), c.name
+
+
+def test_random_clifford_t_n128_full_batch(eng):
+    circs = [wl.config2(j) for j in range(3)]
+    seeds = [wl.derive_seed(2, j) for j in range(3)]
+    print("case 3 x n=128 Clifford+T circuits, batched and graph", flush=True)
+    eager = _full_batch(eng, circs, seeds)
+    for c, s, res in zip(circs, seeds, eager):
+        assert len(res[1]) == 16, c.name
+        _check_oracle(c, s, res)
+
+
+def test_steane_trials_full_batch(eng):
+    circs = [wl.config3(t) for t in range(4096)]
+    seeds = [wl.derive_seed(3, t) for t in range(4096)]
+    print("case 4096 Steane trials, batched and graph", flush=True)
+    eager = _full_batch(eng, circs, seeds)
+    for c, s, res in zip(circs, seeds, eager):
+        amp = res[0][2]
+        assert 1 <= len(amp) <= 2, c.name
+        assert len(res[1]) == 6, c.name
+        _check_oracle(c, s, res)
+
+
+def test_uneven_batch_full_size(eng):
+    circs = [wl.config4(j) for j in range(1024)]
+    seeds = [wl.derive_seed(4, j) for j in range(1024)]
+    print("case 1024 uneven circuits, batched and graph", flush=True)
+    eager = _full_batch(eng, circs, seeds)
+    picked = {j for j, c in enumerate(circs) if c.n <= 72}
+    for words in (2, 3, 4):
+        wider = sorted((c.n, j) for j, c in enumerate(circs) if (c.n + 63) // 64 == words)
+        picked.update(j for _, j in wider[:2])
+    for j, (c, s, res) in enumerate(zip(circs, seeds, eager)):
+        (tab, sig, amp), outs, frag = res
+        n_t = sum(1 for g in c.gates if g[0] in (wl.T, wl.TDG))
+        assert 1 <= len(amp) <= 2 ** n_t, c.name
+        assert abs(float(np.sum(amp.real ** 2 + amp.imag ** 2)) - 1.0) <= 1e-12, c.name
+        assert not frag, c.name
+        if j in picked:
+            _check_oracle(c, s, res)
