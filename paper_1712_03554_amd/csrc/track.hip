@@ -88,6 +88,30 @@ __device__ __forceinline__ int colbit(const LT& L, int i, int col, int n) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x; }
 
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int s) {
+  const int lo = __shfl_xor((int)(uint32_t)v, s);
+  const int hi = __shfl_xor((int)(uint32_t)(v >> 32), s);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// 64 x 64 bit transpose across the wavefront: on entry lane r holds row r
+// (bit c = entry (r, c)), on exit lane c holds column c (bit r = entry
+// (r, c)).  Six butterfly stages swap the off-diagonal blocks of 32, 16, ...,
+// 1 bits between lanes r and r ^ s.  Every lane must take part.
+__device__ __forceinline__ uint64_t transpose64(uint64_t v) {
+  const int lane = lane_id();
+  const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                             0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+    const int s = 32 >> t;
+    const uint64_t m = masks[t];
+    const uint64_t p = shfl_xor64(v, s);
+    v = (lane & s) ? (((p >> s) & m) | (v & ~m)) : ((v & m) | ((p & m) << s));
+  }
+  return v;
+}
+
 // (every lane holds the maximum after the butterfly; reading it from lane 0
 // tells the compiler that the result is wave-uniform, so branches and loop
 // exits that depend on it stay scalar)
@@ -335,19 +359,15 @@ static __device__ void apply_rowsum_batch(LL& L, int m, int d, bool with_u) {
 // in step with every row change.
 static __device__ void build_cols(LL& L, int n) {
   const int lane = lane_id();
-  const int R = (n + 63) / 64;
-  for (int it = 0; it < R; ++it) {
-    const int q = it * 64 + lane;
-    uint64_t cxv[W], czv[W];
-    for (int w = 0; w < W; ++w) { cxv[w] = 0; czv[w] = 0; }
-    if (q < n) {
-      for (int i = 0; i < n; ++i) {
-        const uint64_t bx = (L.rx[i * LL::RW + (q >> 6)] >> (q & 63)) & 1ull;
-        const uint64_t bz = (L.rz[i * LL::RW + (q >> 6)] >> (q & 63)) & 1ull;
-        cxv[i >> 6] |= bx << (i & 63);
-        czv[i >> 6] |= bz << (i & 63);
-      }
-      for (int w = 0; w < W; ++w) { L.cx[q * LL::RW + w] = cxv[w]; L.cz[q * LL::RW + w] = czv[w]; }
+  // 64 x 64 blocks: rows 64 k.., columns 64 w..; after the transpose lane c
+  // holds word k of column 64 w + c
+  for (int k = 0; k < W; ++k) {
+    const int i = 64 * k + lane;
+    for (int w = 0; w < W; ++w) {
+      const uint64_t tx = transpose64(i < n ? L.rx[i * LL::RW + w] : 0ull);
+      const uint64_t tz = transpose64(i < n ? L.rz[i * LL::RW + w] : 0ull);
+      const int q = 64 * w + lane;
+      if (q < n) { L.cx[q * LL::RW + k] = tx; L.cz[q * LL::RW + k] = tz; }
     }
   }
   __syncthreads();
@@ -1561,19 +1581,15 @@ static __device__ void apply_rowsum_batch(Lds& L, int m, int d, bool with_u) {
 // in step with every row change.
 static __device__ void build_cols(Lds& L, int n) {
   const int lane = lane_id();
-  const int R = (n + 63) / 64;
-  for (int it = 0; it < R; ++it) {
-    const int q = it * 64 + lane;
-    uint64_t cxv[W], czv[W];
-    for (int w = 0; w < W; ++w) { cxv[w] = 0; czv[w] = 0; }
-    if (q < n) {
-      for (int i = 0; i < n; ++i) {
-        const uint64_t bx = (L.rx[i * SF_WMAX + (q >> 6)] >> (q & 63)) & 1ull;
-        const uint64_t bz = (L.rz[i * SF_WMAX + (q >> 6)] >> (q & 63)) & 1ull;
-        cxv[i >> 6] |= bx << (i & 63);
-        czv[i >> 6] |= bz << (i & 63);
-      }
-      for (int w = 0; w < W; ++w) { L.cx[q * SF_WMAX + w] = cxv[w]; L.cz[q * SF_WMAX + w] = czv[w]; }
+  // 64 x 64 blocks: rows 64 k.., columns 64 w..; after the transpose lane c
+  // holds word k of column 64 w + c
+  for (int k = 0; k < W; ++k) {
+    const int i = 64 * k + lane;
+    for (int w = 0; w < W; ++w) {
+      const uint64_t tx = transpose64(i < n ? L.rx[i * SF_WMAX + w] : 0ull);
+      const uint64_t tz = transpose64(i < n ? L.rz[i * SF_WMAX + w] : 0ull);
+      const int q = 64 * w + lane;
+      if (q < n) { L.cx[q * SF_WMAX + k] = tx; L.cz[q * SF_WMAX + k] = tz; }
     }
   }
   __syncthreads();
