@@ -693,7 +693,10 @@ static __device__ __forceinline__ void conj_regs(Regs& R, uint64_t (&hv)[W], int
       R.x[k][w] ^= ((w == wa ? (uint64_t)fxa << ba : 0ull) | (w == wb ? (uint64_t)fxb << bb : 0ull));
       R.z[k][w] ^= ((w == wa ? (uint64_t)fza << ba : 0ull) ^ (w == wb ? (uint64_t)fzb << bb : 0ull));
     }
-    R.ld[k] = (fxa | fza | fxb | fzb) ? row_lead_sel(R.x[k], R.z[k], n) : R.ld[k];
+    // only H and CNOT move leads: the diagonal gates change z bits of rows
+    // that have an x bit (whose lead is an x column), the Paulis no bits
+    if (op == DG_H || op == DG_CNOT)
+      R.ld[k] = (fxa | fza | fxb | fzb) ? row_lead_sel(R.x[k], R.z[k], n) : R.ld[k];
     fm[k] = __ballot(fl);
   }
   // column-major copy
@@ -998,12 +1001,15 @@ static __device__ __forceinline__ bool clifford_gate_rec(LL& L, Regs& R, uint64_
   TIC(1);
   conj_regs(R, hv, op, a, b, n, d);
   TOC(1);
-  if (op == DG_S || op == DG_SDG || op == DG_Z || op == DG_CZ) return false;
+  // the diagonal gates keep the echelon form, the Paulis change signs only
+  if (op != DG_H && op != DG_CNOT) return false;
   TIC(2);
   repair_core(L, R, hv, gen, n, d, false, 0);
   TOC(2);
+  // CNOT keeps the rank of the x part, so the X-block size
+  if (op != DG_H) return false;
   const int knew = count_x(R, n);
-  const bool hs = op == DG_H && knew == *kx;
+  const bool hs = knew == *kx;
   *kx = knew;
   return hs;
 }
