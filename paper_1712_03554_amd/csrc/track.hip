@@ -603,14 +603,33 @@ static __device__ int uexp(const LL& L, const uint64_t* sig, const uint64_t* bO,
   int e = 0;
   for (int w = 0; w < W; ++w) {
     uint64_t D = (b[w] ^ bO[w]) & L.oxpm[w];
+    // two generators per pass: their rows are read before either is applied
+    // (the reads depend on the pivot columns only, not on v)
     while (D) {
-      int q = 64 * w + __builtin_ctzll(D);
+      const int q0 = 64 * w + __builtin_ctzll(D);
       D &= D - 1;
-      const int l = L.oxpiv[q];
+      const bool two = D != 0;
+      const int q1 = two ? 64 * w + __builtin_ctzll(D) : q0;
+      D &= two ? D - 1 : D;
+      const int l0 = L.oxpiv[q0], l1 = L.oxpiv[q1];
+      const int w0 = L.ow[q0], w1 = L.ow[q1];
+      uint64_t oz0[W], ox0[W], oz1[W], ox1[W];
+      for (int t = 0; t < W; ++t) {
+        oz0[t] = L.oz[q0 * LL::RW + t];
+        ox0[t] = L.ox[q0 * LL::RW + t];
+        oz1[t] = L.oz[q1 * LL::RW + t];
+        ox1[t] = L.ox[q1 * LL::RW + t];
+      }
       uint64_t zv = 0;
-      for (int t = 0; t < W; ++t) zv ^= L.oz[q * LL::RW + t] & v[t];
-      e += 2 * (getb(sig, l) ^ par64(zv)) + L.ow[q];
-      for (int t = 0; t < W; ++t) v[t] ^= L.ox[q * LL::RW + t];
+      for (int t = 0; t < W; ++t) zv ^= oz0[t] & v[t];
+      e += 2 * (getb(sig, l0) ^ par64(zv)) + w0;
+      for (int t = 0; t < W; ++t) v[t] ^= ox0[t];
+      if (two) {
+        zv = 0;
+        for (int t = 0; t < W; ++t) zv ^= oz1[t] & v[t];
+        e += 2 * (getb(sig, l1) ^ par64(zv)) + w1;
+        for (int t = 0; t < W; ++t) v[t] ^= ox1[t];
+      }
     }
   }
   for (int w = 0; w < W; ++w) if (v[w] != b[w]) return -1;
