@@ -74,6 +74,10 @@ static void pin_release(sf_ctx* ctx) {
   ctx->pin_off = 0;
 }
 
+// Circuits whose hull never exceeds this dimension (2^8 = EB slots, one
+// reduction block) measure with one fused kernel per measurement.
+#define SF_MSMALL_D 8
+
 static int grid_for(int d) {
   uint64_t blocks = ((1ull << d) + EB - 1) / EB;
   if (blocks > 8192) blocks = 8192;
@@ -804,7 +808,16 @@ static sf_status run_chunk(sf_state* s, const DGate* dgates, const DGate* hg, si
                        (double2*)s->amp[s->cur].p);
     prof_end(ctx);
   }
-  if (meas_last) {
+  if (meas_last && c->dmax <= SF_MSMALL_D) {
+    const SegProg* sp = prog + (nseg - 1);
+    prof_begin(ctx, PK_MFINAL);
+    hipLaunchKernelGGL(sf_meas_small, dim3(1), dim3(EB), 0, ctx->stream, sp, (const double2*)s->amp[s->cur].p,
+                       (double2*)s->amp[s->cur ^ 1].p, s->seed, (uint8_t*)s->outcomes.p, (double*)s->pvals.p,
+                       (double*)s->scale.p, (int*)s->flags.p);
+    prof_end(ctx);
+    s->cur ^= 1;
+    s->nmeas++;
+  } else if (meas_last) {
     const SegProg* sp = prog + (nseg - 1);
     prof_begin(ctx, PK_MREDUCE);
     hipLaunchKernelGGL(sf_meas_reduce, dim3(s->G), dim3(EB), 0, ctx->stream, sp, (const double2*)s->amp[s->cur].p,
@@ -1151,6 +1164,7 @@ struct RoundPlan {
   std::vector<ElemDesc> desc;
   int na = 0, kmax = 0, gx = 1, bx = EB, gm = 1;
   bool anym = false;
+  bool msmall = false;  // every frame's hull stays within SF_MSMALL_D: fused measurement kernel
   int wcount[SF_WMAX + 1] = {0, 0, 0, 0, 0};  // frames per word count (jobs are ordered by it)
   int wlen[SF_WMAX + 1] = {0, 0, 0, 0, 0};    // per word count: longest range, most segments,
   int wseg[SF_WMAX + 1] = {0, 0, 0, 0, 0};    // phase-kernel chunks of the longest range
@@ -1241,6 +1255,7 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
       if (rp->jobs[j].rec) rp->jobs[j].pchunk = kw[words_of(states[act[j]]->c->n)];
   }
   elem_shape(states[act[0]]->ctx, dm, &rp->bx, &rp->gx);
+  rp->msmall = dm <= SF_MSMALL_D;
   const int kmax = rp->kmax;
   rp->desc.assign((size_t)(kmax + 1) * na, ElemDesc{});
   for (int k = 0; k <= kmax; ++k)
@@ -1309,7 +1324,12 @@ static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs
     hipLaunchKernelGGL(sf_seg_batch, dim3(rp.gx, na), dim3(rp.bx), 0, ctx->stream, dd + (size_t)k * na);
     prof_end(ctx);
   }
-  if (rp.anym) {
+  if (rp.anym && rp.msmall) {
+    const ElemDesc* dm = dd + (size_t)rp.kmax * na;
+    prof_begin(ctx, PK_MFINAL);
+    hipLaunchKernelGGL(sf_meas_small_batch, dim3(na), dim3(EB), 0, ctx->stream, dm);
+    prof_end(ctx);
+  } else if (rp.anym) {
     const ElemDesc* dm = dd + (size_t)rp.kmax * na;
     prof_begin(ctx, PK_MREDUCE);
     hipLaunchKernelGGL(sf_meas_reduce_batch, dim3(rp.gm, na), dim3(EB), 0, ctx->stream, dm);
@@ -1680,7 +1700,11 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
       void* args[] = {(void*)&dk};
       e = add_kernel_node(g->graph, &last, (const void*)sf_seg_batch, dim3(rp.gx, na), dim3(rp.bx), args);
     }
-    if (rp.anym && e == hipSuccess) {
+    if (rp.anym && rp.msmall && e == hipSuccess) {
+      const ElemDesc* dm = dd + (size_t)rp.kmax * na;
+      void* args[] = {(void*)&dm};
+      e = add_kernel_node(g->graph, &last, (const void*)sf_meas_small_batch, dim3(na), dim3(EB), args);
+    } else if (rp.anym && e == hipSuccess) {
       const ElemDesc* dm = dd + (size_t)rp.kmax * na;
       void* args[] = {(void*)&dm};
       e = add_kernel_node(g->graph, &last, (const void*)sf_meas_reduce_batch, dim3(rp.gm, na), dim3(EB), args);

@@ -285,6 +285,71 @@ __device__ __forceinline__ void meas_filter_body(const SegProg* __restrict__ sp,
   }
 }
 
+// Frames of at most EB slots (hull dimension <= 8 for the whole circuit, so
+// one reduction block, G = 1): reduction, coin and filter of a measurement in
+// one block.  The sums equal those of the three-kernel form: the single
+// block's tree gives the only non-zero partial, and the final pass adds only
+// +0.0 to it (exact for a non-negative sum).
+__device__ __forceinline__ void meas_small_body(const SegProg* __restrict__ sp, const double2* __restrict__ src,
+                                                double2* __restrict__ dst, uint64_t seed,
+                                                uint8_t* __restrict__ outcomes, double* __restrict__ pvals,
+                                                double* __restrict__ scale, int* __restrict__ flags) {
+  __shared__ double s0[EB], s1[EB];
+  __shared__ double s_scale;
+  __shared__ uint32_t s_out;
+  const uint64_t N = 1ull << sp->d_out;
+  const uint32_t c0 = sp->m_c0, r = sp->m_r;
+  double p0 = 0.0, p1 = 0.0;
+  for (uint64_t Y = threadIdx.x; Y < N; Y += EB) {
+    double v = norm2(src[Y]);
+    if ((c0 ^ (uint32_t)__popc(r & (uint32_t)Y)) & 1u) p1 = __dadd_rn(p1, v);
+    else p0 = __dadd_rn(p0, v);
+  }
+  s0[threadIdx.x] = p0;
+  s1[threadIdx.x] = p1;
+  __syncthreads();
+  for (int h = EB / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      s0[threadIdx.x] = __dadd_rn(s0[threadIdx.x], s0[threadIdx.x + h]);
+      s1[threadIdx.x] = __dadd_rn(s1[threadIdx.x], s1[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int mi = sp->meas_index;
+    double P0 = __dadd_rn(0.0, s0[0]), P1 = __dadd_rn(0.0, s1[0]);
+    double u = (double)(splitmix64_at(seed, (uint64_t)mi) >> 11) * (1.0 / 9007199254740992.0);
+    int o = u < P1 ? 1 : 0;
+    outcomes[mi] = (uint8_t)o;
+    pvals[mi] = P1;
+    double po = o ? P1 : P0;
+    const double sc = po > 0.0 ? 1.0 / sqrt(po) : 0.0;
+    scale[0] = sc;
+    if (fabs(u - P1) < 1e-12 || po <= 0.0) atomicOr(flags, 1);
+    s_out = (uint32_t)o;
+    s_scale = sc;
+  }
+  __syncthreads();
+  const uint32_t o = s_out;
+  const double sc = s_scale;
+  const int j0 = sp->m_j0;
+  const int dout = sp->d_out;
+  if (r == 0) {
+    for (uint64_t Y = threadIdx.x; Y < N; Y += EB) {
+      double2 a = src[Y];
+      dst[Y] = make_double2(__dmul_rn(a.x, sc), __dmul_rn(a.y, sc));
+    }
+  } else {
+    const uint64_t Nh = 1ull << (dout - 1);
+    for (uint64_t Yp = threadIdx.x; Yp < Nh; Yp += EB) {
+      uint32_t rest = insert_zero(Yp, j0);
+      uint32_t bit = (o ^ c0 ^ (uint32_t)__popc(r & rest)) & 1u;
+      double2 a = src[rest | (bit << j0)];
+      dst[Yp] = make_double2(__dmul_rn(a.x, sc), __dmul_rn(a.y, sc));
+    }
+  }
+}
+
 #define TID ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x)
 #define STRIDE ((uint64_t)gridDim.x * blockDim.x)
 
@@ -309,6 +374,13 @@ extern "C" __global__ void __launch_bounds__(EB)
 sf_meas_filter(const SegProg* __restrict__ sp, const double2* __restrict__ src, double2* __restrict__ dst,
                const uint8_t* __restrict__ outcomes, const double* __restrict__ scale) {
   meas_filter_body(sp, src, dst, outcomes, scale, TID, STRIDE);
+}
+
+extern "C" __global__ void __launch_bounds__(EB)
+sf_meas_small(const SegProg* __restrict__ sp, const double2* __restrict__ src, double2* __restrict__ dst,
+              uint64_t seed, uint8_t* __restrict__ outcomes, double* __restrict__ pvals, double* __restrict__ scale,
+              int* __restrict__ flags) {
+  meas_small_body(sp, src, dst, seed, outcomes, pvals, scale, flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -340,6 +412,13 @@ extern "C" __global__ void __launch_bounds__(EB) sf_meas_filter_batch(const Elem
   const ElemDesc& e = D[blockIdx.y];
   if (!e.prog) return;
   meas_filter_body(e.prog, e.amp, e.amp_other, e.outcomes, e.scale, BTID, BSTRIDE);
+}
+
+// one block per frame (blockIdx.x)
+extern "C" __global__ void __launch_bounds__(EB) sf_meas_small_batch(const ElemDesc* __restrict__ D) {
+  const ElemDesc& e = D[blockIdx.x];
+  if (!e.prog) return;
+  meas_small_body(e.prog, e.amp, e.amp_other, e.seedp ? *e.seedp : e.seed, e.outcomes, e.pvals, e.scale, e.flags);
 }
 
 // Number of non-zero amplitudes (frame size |F|).
