@@ -550,7 +550,10 @@ extern "C" sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n, const sf_gate* gat
   TrackState* h = (TrackState*)calloc(1, sizeof(TrackState));
   h->n = (int)n;
   h->W = (int)((n + 63) / 64);
-  for (uint32_t q = 0; q < n; ++q) h->rz[q * SF_WMAX + (q >> 6)] = 1ull << (q & 63);
+  for (uint32_t q = 0; q < n; ++q) {
+    h->rz[q * SF_WMAX + (q >> 6)] = 1ull << (q & 63);
+    h->cz[q * SF_WMAX + (q >> 6)] = 1ull << (q & 63);
+  }
   hipError_t e = hipMemcpyAsync(dst.p, h, sizeof(TrackState), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess && !c->g.empty())
     e = hipMemcpyAsync(c->dgates.p, c->g.data(), sizeof(DGate) * c->g.size(), hipMemcpyHostToDevice, ctx->stream);

@@ -546,10 +546,14 @@ sf_compact_write(const uint8_t* __restrict__ flag, const uint64_t* __restrict__ 
 __device__ void init_body(TrackState* __restrict__ st, int n, uint64_t b0, uint64_t b1, uint64_t b2, uint64_t b3,
                           double2* __restrict__ amp, int* __restrict__ flags) {
   const int W = (n + 63) / 64;
-  for (int i = threadIdx.x; i < SF_NMAX * SF_WMAX; i += blockDim.x) {
+  // (slots and qubits from n on are never read: every reader masks them)
+  for (int i = threadIdx.x; i < n * SF_WMAX; i += blockDim.x) {
     int q = i / SF_WMAX, w = i % SF_WMAX;
+    const uint64_t z = w == (q >> 6) ? (1ull << (q & 63)) : 0ull;
     st->rx[i] = 0ull;
-    st->rz[i] = (q < n && w == (q >> 6)) ? (1ull << (q & 63)) : 0ull;
+    st->rz[i] = z;
+    st->cx[i] = 0ull;
+    st->cz[i] = z;  // the basis form is its own transpose
   }
   if (threadIdx.x == 0) {
     st->n = n; st->W = W; st->d = 0; st->nmeas = 0;

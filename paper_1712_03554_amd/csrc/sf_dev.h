@@ -83,6 +83,10 @@ struct TrackState {
   int32_t dmax, error, pad;
   uint64_t rx[SF_NMAX * SF_WMAX];
   uint64_t rz[SF_NMAX * SF_WMAX];
+  // column-major copy kept with the rows: cx / cz at qubit q hold the slots
+  // whose row has an x / z bit there
+  uint64_t cx[SF_NMAX * SF_WMAX];
+  uint64_t cz[SF_NMAX * SF_WMAX];
   uint64_t s0[SF_WMAX];
   uint64_t V[SF_DMAX][SF_WMAX];
   uint64_t cycles[16];     // shader clocks spent per phase of the track (profiling)

@@ -1200,13 +1200,14 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
     const int r = i / LL::RW, w = i % LL::RW;  // TrackState rows hold SF_WMAX words
     L.rx[i] = r < n ? st->rx[r * SF_WMAX + w] : 0ull;
     L.rz[i] = r < n ? st->rz[r * SF_WMAX + w] : 0ull;
+    L.cx[i] = r < n ? st->cx[r * SF_WMAX + w] : 0ull;
+    L.cz[i] = r < n ? st->cz[r * SF_WMAX + w] : 0ull;
   }
   if (lane < SF_WMAX) L.s0[lane] = st->s0[lane];
   if (lane < d) for (int w = 0; w < SF_WMAX; ++w) L.V[lane][w] = st->V[lane][w];
   __syncthreads();
   // deferred filter of the last measurement (needs its outcome)
   if (st->pend) apply_pending(L, st, job.dry ? nullptr : job.outcomes, &d);
-  build_cols(L, n);
   rebuild_index(L, n);
   if (!job.dry) build_points(L, d);
   __syncthreads();
@@ -1506,7 +1507,7 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
     zero_z4(&sp->B1);
     ++seg;
   }
-  regs_store(L, TB, n, false);
+  regs_store(L, TB, n, true);
   hull_to_lds(L, HB, d);
   __syncthreads();
   // write back
@@ -1514,6 +1515,8 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
     const int r = i / LL::RW, w = i % LL::RW;
     st->rx[r * SF_WMAX + w] = L.rx[i];
     st->rz[r * SF_WMAX + w] = L.rz[i];
+    st->cx[r * SF_WMAX + w] = L.cx[i];
+    st->cz[r * SF_WMAX + w] = L.cz[i];
   }
   if (lane < SF_WMAX) st->s0[lane] = L.s0[lane];
   if (lane < d) for (int w = 0; w < SF_WMAX; ++w) st->V[lane][w] = L.V[lane][w];
@@ -2431,13 +2434,14 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
   for (int i = lane; i < SF_NMAX * SF_WMAX; i += TL) {
     L.rx[i] = i < n * SF_WMAX ? st->rx[i] : 0ull;
     L.rz[i] = i < n * SF_WMAX ? st->rz[i] : 0ull;
+    L.cx[i] = i < n * SF_WMAX ? st->cx[i] : 0ull;
+    L.cz[i] = i < n * SF_WMAX ? st->cz[i] : 0ull;
   }
   if (lane < SF_WMAX) L.s0[lane] = st->s0[lane];
   if (lane < d) for (int w = 0; w < SF_WMAX; ++w) L.V[lane][w] = st->V[lane][w];
   __syncthreads();
   // deferred filter of the last measurement (needs its outcome)
   if (st->pend) apply_pending(L, st, job.dry ? nullptr : job.outcomes, &d);
-  build_cols(L, n);
   rebuild_index(L, n);
   if (!job.dry) {
     build_beta(L, n);
@@ -2711,7 +2715,12 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
   }
   __syncthreads();
   // write back
-  for (int i = lane; i < n * SF_WMAX; i += TL) { st->rx[i] = L.rx[i]; st->rz[i] = L.rz[i]; }
+  for (int i = lane; i < n * SF_WMAX; i += TL) {
+    st->rx[i] = L.rx[i];
+    st->rz[i] = L.rz[i];
+    st->cx[i] = L.cx[i];
+    st->cz[i] = L.cz[i];
+  }
   if (lane < SF_WMAX) st->s0[lane] = L.s0[lane];
   if (lane < d) for (int w = 0; w < SF_WMAX; ++w) st->V[lane][w] = L.V[lane][w];
   if (lane == 0) {
