@@ -354,25 +354,6 @@ static __device__ void apply_rowsum_batch(LL& L, int m, int d, bool with_u) {
   __syncthreads();
 }
 
-// Column-major copy of the tableau: L.cx[q] / L.cz[q] hold the slots whose
-// row has an x (z) bit at qubit q.  Built by one transpose per launch and kept
-// in step with every row change.
-static __device__ void build_cols(LL& L, int n) {
-  const int lane = lane_id();
-  // 64 x 64 blocks: rows 64 k.., columns 64 w..; after the transpose lane c
-  // holds word k of column 64 w + c
-  for (int k = 0; k < W; ++k) {
-    const int i = 64 * k + lane;
-    for (int w = 0; w < W; ++w) {
-      const uint64_t tx = transpose64(i < n ? L.rx[i * LL::RW + w] : 0ull);
-      const uint64_t tz = transpose64(i < n ? L.rz[i * LL::RW + w] : 0ull);
-      const int q = 64 * w + lane;
-      if (q < n) { L.cx[q * LL::RW + k] = tx; L.cz[q * LL::RW + k] = tz; }
-    }
-  }
-  __syncthreads();
-}
-
 // rows in L.rmask received row m: toggle those slots in every column where
 // row m has a bit
 static __device__ void cols_rowsum(LL& L, int m, int n) {
@@ -1605,8 +1586,8 @@ static __device__ void apply_rowsum_batch(Lds& L, int m, int d, bool with_u) {
 }
 
 // Column-major copy of the tableau: L.cx[q] / L.cz[q] hold the slots whose
-// row has an x (z) bit at qubit q.  Built by one transpose per launch and kept
-// in step with every row change.
+// row has an x (z) bit at qubit q.  The track kernels keep it in the state, in
+// step with every row change; the readout builds it from the rows.
 static __device__ void build_cols(Lds& L, int n) {
   const int lane = lane_id();
   // 64 x 64 blocks: rows 64 k.., columns 64 w..; after the transpose lane c
