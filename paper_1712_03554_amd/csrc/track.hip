@@ -1189,11 +1189,13 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
   __syncthreads();
   // deferred filter of the last measurement (needs its outcome)
   if (st->pend) apply_pending(L, st, job.dry ? nullptr : job.outcomes, &d);
-  rebuild_index(L, n);
   if (!job.dry) build_points(L, d);
   __syncthreads();
   Regs TB;
   regs_load(L, TB, n);
+  // the Clifford loop needs only each row's lead (terminal steps rebuild the
+  // pivot index from the rows)
+  for (int k = 0; k < W; ++k) TB.ld[k] = 64 * k + lane < n ? row_lead_sel(TB.x[k], TB.z[k], n) : -1;
   // this kernel conjugates, repairs and records; the phase kernels evaluate
   // the Clifford gates' phases from the records
   const bool rec = !job.dry;
