@@ -805,22 +805,28 @@ static sf_status run_chunk(sf_state* s, const DGate* dgates, const DGate* hg, si
   int eb, grid;
   elem_shape(ctx, c->dmax, &eb, &grid);
   const SegProg* prog = (const SegProg*)s->prog.p;
+  if (c->dmax <= SF_MSMALL_D) {
+    // small frame: the range's segments and its measurement in one block
+    prof_begin(ctx, PK_SEG);
+    hipLaunchKernelGGL(sf_elem_small, dim3(1), dim3(EB), 0, ctx->stream, (const SegProg*)prog, nseg,
+                       (const GF2Q*)s->had.p, (double2*)s->amp[s->cur].p, (double2*)s->amp[s->cur ^ 1].p,
+                       meas_last ? 1 : 0, s->seed, (uint8_t*)s->outcomes.p, (double*)s->pvals.p,
+                       (double*)s->scale.p, (int*)s->flags.p);
+    prof_end(ctx);
+    if (meas_last) {
+      s->cur ^= 1;
+      s->nmeas++;
+    }
+    HIPCHK(ctx, hipGetLastError());
+    return SF_OK;
+  }
   for (int k = 0; k < nseg; ++k) {
     prof_begin(ctx, PK_SEG);
     hipLaunchKernelGGL(sf_seg_kernel, dim3(grid), dim3(eb), 0, ctx->stream, prog + k, (const GF2Q*)s->had.p,
                        (double2*)s->amp[s->cur].p);
     prof_end(ctx);
   }
-  if (meas_last && c->dmax <= SF_MSMALL_D) {
-    const SegProg* sp = prog + (nseg - 1);
-    prof_begin(ctx, PK_MFINAL);
-    hipLaunchKernelGGL(sf_meas_small, dim3(1), dim3(EB), 0, ctx->stream, sp, (const double2*)s->amp[s->cur].p,
-                       (double2*)s->amp[s->cur ^ 1].p, s->seed, (uint8_t*)s->outcomes.p, (double*)s->pvals.p,
-                       (double*)s->scale.p, (int*)s->flags.p);
-    prof_end(ctx);
-    s->cur ^= 1;
-    s->nmeas++;
-  } else if (meas_last) {
+  if (meas_last) {
     const SegProg* sp = prog + (nseg - 1);
     prof_begin(ctx, PK_MREDUCE);
     hipLaunchKernelGGL(sf_meas_reduce, dim3(s->G), dim3(EB), 0, ctx->stream, sp, (const double2*)s->amp[s->cur].p,
@@ -1322,17 +1328,22 @@ static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs
     launch_phase_many(ctx, djobs + off, rp.wcount[w], w, rp.wchunk[w], rp.wseg[w]);
     off += rp.wcount[w];
   }
+  if (rp.msmall) {
+    // small frames: each frame's segments and measurement in one block
+    if (rp.kmax > 0 || rp.anym) {
+      prof_begin(ctx, PK_SEG);
+      hipLaunchKernelGGL(sf_elem_small_batch, dim3(na), dim3(EB), 0, ctx->stream, dd, rp.kmax, na,
+                         rp.anym ? 1 : 0);
+      prof_end(ctx);
+    }
+    return;
+  }
   for (int k = 0; k < rp.kmax; ++k) {
     prof_begin(ctx, PK_SEG);
     hipLaunchKernelGGL(sf_seg_batch, dim3(rp.gx, na), dim3(rp.bx), 0, ctx->stream, dd + (size_t)k * na);
     prof_end(ctx);
   }
-  if (rp.anym && rp.msmall) {
-    const ElemDesc* dm = dd + (size_t)rp.kmax * na;
-    prof_begin(ctx, PK_MFINAL);
-    hipLaunchKernelGGL(sf_meas_small_batch, dim3(na), dim3(EB), 0, ctx->stream, dm);
-    prof_end(ctx);
-  } else if (rp.anym) {
+  if (rp.anym) {
     const ElemDesc* dm = dd + (size_t)rp.kmax * na;
     prof_begin(ctx, PK_MREDUCE);
     hipLaunchKernelGGL(sf_meas_reduce_batch, dim3(rp.gm, na), dim3(EB), 0, ctx->stream, dm);
@@ -1698,16 +1709,21 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
       }
       off += rp.wcount[w];
     }
+    if (rp.msmall) {
+      if ((rp.kmax > 0 || rp.anym) && e == hipSuccess) {
+        const ElemDesc* d0 = dd;
+        int kmax = rp.kmax, nna = na, meas = rp.anym ? 1 : 0;
+        void* args[] = {(void*)&d0, (void*)&kmax, (void*)&nna, (void*)&meas};
+        e = add_kernel_node(g->graph, &last, (const void*)sf_elem_small_batch, dim3(na), dim3(EB), args);
+      }
+      continue;
+    }
     for (int k = 0; k < rp.kmax && e == hipSuccess; ++k) {
       const ElemDesc* dk = dd + (size_t)k * na;
       void* args[] = {(void*)&dk};
       e = add_kernel_node(g->graph, &last, (const void*)sf_seg_batch, dim3(rp.gx, na), dim3(rp.bx), args);
     }
-    if (rp.anym && rp.msmall && e == hipSuccess) {
-      const ElemDesc* dm = dd + (size_t)rp.kmax * na;
-      void* args[] = {(void*)&dm};
-      e = add_kernel_node(g->graph, &last, (const void*)sf_meas_small_batch, dim3(na), dim3(EB), args);
-    } else if (rp.anym && e == hipSuccess) {
+    if (rp.anym && e == hipSuccess) {
       const ElemDesc* dm = dd + (size_t)rp.kmax * na;
       void* args[] = {(void*)&dm};
       e = add_kernel_node(g->graph, &last, (const void*)sf_meas_reduce_batch, dim3(rp.gm, na), dim3(EB), args);

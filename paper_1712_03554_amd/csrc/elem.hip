@@ -376,13 +376,6 @@ sf_meas_filter(const SegProg* __restrict__ sp, const double2* __restrict__ src, 
   meas_filter_body(sp, src, dst, outcomes, scale, TID, STRIDE);
 }
 
-extern "C" __global__ void __launch_bounds__(EB)
-sf_meas_small(const SegProg* __restrict__ sp, const double2* __restrict__ src, double2* __restrict__ dst,
-              uint64_t seed, uint8_t* __restrict__ outcomes, double* __restrict__ pvals, double* __restrict__ scale,
-              int* __restrict__ flags) {
-  meas_small_body(sp, src, dst, seed, outcomes, pvals, scale, flags);
-}
-
 // ---------------------------------------------------------------------------
 // Batched forms: blockIdx.y selects the frame (ElemDesc), blockIdx.x and the
 // block's threads stride over that frame's slots.
@@ -414,9 +407,33 @@ extern "C" __global__ void __launch_bounds__(EB) sf_meas_filter_batch(const Elem
   meas_filter_body(e.prog, e.amp, e.amp_other, e.outcomes, e.scale, BTID, BSTRIDE);
 }
 
-// one block per frame (blockIdx.x)
-extern "C" __global__ void __launch_bounds__(EB) sf_meas_small_batch(const ElemDesc* __restrict__ D) {
-  const ElemDesc& e = D[blockIdx.x];
+// Frames of at most EB slots: every segment of a round, then its
+// measurement, in one block per frame (segments in order, a barrier between
+// them; each slot's arithmetic is that of the separate launches).
+extern "C" __global__ void __launch_bounds__(EB)
+sf_elem_small(const SegProg* __restrict__ prog, int nseg, const GF2Q* __restrict__ had_all,
+              double2* __restrict__ amp, double2* __restrict__ amp_other, int meas, uint64_t seed,
+              uint8_t* __restrict__ outcomes, double* __restrict__ pvals, double* __restrict__ scale,
+              int* __restrict__ flags) {
+  for (int k = 0; k < nseg; ++k) {
+    seg_body(prog + k, had_all, amp, threadIdx.x, EB);
+    __syncthreads();
+  }
+  if (meas) meas_small_body(prog + (nseg - 1), amp, amp_other, seed, outcomes, pvals, scale, flags);
+}
+
+// batched form: block j = frame j; rows k < kmax of D are the segments (row
+// k, column j), row kmax the measurements
+extern "C" __global__ void __launch_bounds__(EB)
+sf_elem_small_batch(const ElemDesc* __restrict__ D, int kmax, int na, int meas) {
+  const int j = blockIdx.x;
+  for (int k = 0; k < kmax; ++k) {
+    const ElemDesc& e = D[(size_t)k * na + j];
+    if (e.prog) seg_body(e.prog, e.had, e.amp, threadIdx.x, EB);
+    __syncthreads();
+  }
+  if (!meas) return;
+  const ElemDesc& e = D[(size_t)kmax * na + j];
   if (!e.prog) return;
   meas_small_body(e.prog, e.amp, e.amp_other, e.seedp ? *e.seedp : e.seed, e.outcomes, e.pvals, e.scale, e.flags);
 }
