@@ -700,3 +700,32 @@ def test_graph_with_wide_frames(eng, count):
     g.close()
     for st in states:
         st.close()
+
+
+def test_small_frames_same_alone_and_in_mixed_rounds(eng):
+    """Frames whose hull stays within 256 slots run their element stage in one
+    block when alone (or batched only with such frames) and through the
+    separate segment and measurement launches when batched with a larger
+    frame; both give the same bits (one reduction block either way)."""
+    small = [wl.config1(j) for j in range(3)] + [wl.config3(t) for t in range(3)] + \
+            [_mixed_circuit(s, 4 + s) for s in range(2)]
+    big = wl.random_clifford_t(20, 200, 14, 4242, measure_qubits=(0, 5, 19))  # frame reaches 512
+    big.name = "big20"
+    assert eng.load(big.n, big).info()[0] > 8
+    for c in small:
+        assert eng.load(c.n, c).info()[0] <= 8, c.name
+    seeds = list(range(700, 700 + len(small) + 1))
+    alone = [_run_alone(eng, c, s) for c, s in zip(small, seeds)]
+    for with_big in (False, True):
+        circs = small + ([big] if with_big else [])
+        loaded = [eng.load(c.n, c) for c in circs]
+        states = [l.state(c.init_bits, s) for l, c, s in zip(loaded, circs, seeds)]
+        print(f"case small frames batched, with a larger frame: {with_big}", flush=True)
+        eng.batch_run(states)
+        for c, st, ((ta, sa, aa), oa) in zip(small, states, alone):
+            tb, sb, ab = st.read_frame()
+            assert np.array_equal(ta, tb) and np.array_equal(sa, sb), (with_big, c.name)
+            assert np.array_equal(aa.view(np.uint64), ab.view(np.uint64)), (with_big, c.name)
+            assert st.outcomes() == oa, (with_big, c.name)
+        for st in states:
+            st.close()
