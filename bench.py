@@ -3,13 +3,20 @@
 
 Workload (default): the n=128 random Clifford+T circuits (2000 H/S/CNOT drawn
 uniformly, 16 T at uniform slots, then 16 Z measurements), three seeded
-circuits per step, run through the plain path (one tableau-track launch per
-measurement-delimited range and one element launch per segment).  U counts,
-for every gate applied, the frame size just before it; value = U / wall time
-of the timed steps, with states already resident in HBM (a step resets each
-state on the device and runs its circuit).
+circuits per step, run through the batched path (--path): one batched reset
+and one sf_batch_run over the three states per step, whose rounds launch the
+tableau tracks of all frames together and their element kernels together.  U
+counts, for every gate applied, the frame size just before it; value = U /
+wall time of the timed steps, with states already resident in HBM.  The plain
+path (one state at a time), the graph replay, the many-frame workloads, the
+direct forms, the HBM probes, the Clifford-only circuits and the serving run
+are reported beside it.
 
-Prints one JSON line (see the design doc for the fields).
+Prints one JSON line: metric, value, unit, the timing fields, the roofline of
+the dominant kernel (achieved rate from HIP events around its launches in the
+timed region, the peak it is held against, HBM traffic per launch from the
+committed counter measurements when they match the current sources), the
+oracle's rate on the host (cpu_baseline) and the extra workloads.
 """
 from __future__ import annotations
 

@@ -8,7 +8,7 @@
  * Only tests, the smoke check and the bench's CPU-baseline leg may load it;
  * the HIP library never does, and the two share no code.
  *
- * Conventions (readings of the paper, listed in the design doc):
+ * Conventions (readings of the paper where it leaves the choice open):
  *  - Pauli literal bits: (x,z) = 00 I, 01 Z, 10 X, 11 Y (section 2.2).
  *    A row with bits (x,z) and sign bit s is (-1)^s (x) literals.
  *  - Canonical form: fully reduced row echelon form of the n x 2n bit matrix

@@ -11,7 +11,8 @@ Gate records use the layout of ``sf_gate`` in ``include/sframe.h``:
 Workload shapes follow the evaluation section of Garcia & Markov (random
 stabilizer circuits of section 6 with H/P/CNOT drawn with probability 1/3
 each; Cuccaro adders on an equal superposition; QFT on basis states) plus the
-batched and served mixes described in the design doc.
+batched mixes (Steane-code fault-injection trials, uneven random circuits) and
+the served mix (AQFT, Cuccaro adders, one uneven circuit).
 """
 from __future__ import annotations
 
