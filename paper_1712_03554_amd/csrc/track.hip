@@ -88,6 +88,28 @@ __device__ __forceinline__ int colbit(const LT& L, int i, int col, int n) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x; }
 
+// Global-memory view of a pointer.  Accesses through a generic pointer become
+// flat instructions, which count against the LDS wait counter as well: every
+// LDS wait of the gate loop would then also wait for the record stores and
+// the next gate's prefetch.  Through these the compiler emits global
+// instructions, which only the vector-memory counter tracks.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
+__device__ __forceinline__ DGate load_gate(const DGate* p) {
+  auto q = gmem(p);
+  DGate g;
+  g.op = q->op;
+  g.q0 = q->q0;
+  g.q1 = q->q1;
+  g.q2 = q->q2;
+  g.c = q->c;
+  g.s = q->s;
+  return g;
+}
+
 __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int s) {
   const int lo = __shfl_xor((int)(uint32_t)v, s);
   const int hi = __shfl_xor((int)(uint32_t)(v >> 32), s);
@@ -912,7 +934,7 @@ static __device__ __forceinline__ int count_x(const Regs& R, int n) {
 // record r: rows and hull (lane j < d: V[j], lane d: s0) from the registers
 static __device__ __forceinline__ void rec_write(const TrackJob& job, int r, const Regs& R, const uint64_t (&hb)[W],
                                                  int n, int d) {
-  uint64_t* rw = (uint64_t*)(job.rec + (size_t)r * job.rec_stride);
+  auto rw = gmem((uint64_t*)(job.rec + (size_t)r * job.rec_stride));
   const int lane = lane_id();
   for (int k = 0; k < W; ++k) {
     const int i = 64 * k + lane;
@@ -922,10 +944,10 @@ static __device__ __forceinline__ void rec_write(const TrackJob& job, int r, con
         rw[i * 2 * W + W + w] = R.z[k][w];
       }
   }
-  uint64_t* hv = rw + (size_t)n * 2 * W;
+  auto hv = rw + (size_t)n * 2 * W;
   if (lane <= d)
     for (int w = 0; w < W; ++w) hv[(lane == d ? 0 : lane + 1) * W + w] = hb[w];
-  if (lane == 0) *(int32_t*)(hv + (SF_DMAX + 1) * W) = d;
+  if (lane == 0) *gmem((int32_t*)(job.rec + (size_t)r * job.rec_stride + ((size_t)n * 2 * W + (SF_DMAX + 1) * W) * 8)) = d;
 }
 
 // the hull between LDS (terminal steps) and the registers of the Clifford
@@ -954,7 +976,7 @@ struct RecRegs {
 };
 
 static __device__ __forceinline__ void rec_fetch(const TrackJob& job, int r, int n, RecRegs& R) {
-  const uint64_t* rw = (const uint64_t*)(job.rec + (size_t)r * job.rec_stride);
+  auto rw = gmem((const uint64_t*)(job.rec + (size_t)r * job.rec_stride));
   const int lane = lane_id();
   for (int k = 0; k < W; ++k) {
     const int i = 64 * k + lane;
@@ -963,9 +985,9 @@ static __device__ __forceinline__ void rec_fetch(const TrackJob& job, int r, int
       R.z[k][w] = i < n ? rw[i * 2 * W + W + w] : 0ull;
     }
   }
-  const uint64_t* hv = rw + (size_t)n * 2 * W;
+  auto hv = rw + (size_t)n * 2 * W;
   for (int w = 0; w < W; ++w) R.h[w] = lane <= SF_DMAX ? hv[lane * W + w] : 0ull;
-  R.d = *(const int32_t*)(hv + (SF_DMAX + 1) * W);
+  R.d = *gmem((const int32_t*)(job.rec + (size_t)r * job.rec_stride + ((size_t)n * 2 * W + (SF_DMAX + 1) * W) * 8));
 }
 
 static __device__ __forceinline__ void rec_put(LL& L, const RecRegs& R, int d) {
@@ -1048,8 +1070,8 @@ static __device__ void phase_body(LL& L, const TrackJob& job, int c) {
   hull_images(L, L.hbN, d, false);
   build_points(L, d);
   // gate i and its info, fetched one gate ahead like the records
-  DGate gnext = job.gates[job.g0 + i0];
-  int snext = job.ginfo[2 * i0], hnext = job.ginfo[2 * i0 + 1];
+  DGate gnext = load_gate(job.gates + job.g0 + i0);
+  int snext = *gmem(job.ginfo + 2 * i0), hnext = *gmem(job.ginfo + 2 * i0 + 1);
   for (int i = i0; i < i1 && !err; ++i) {
     // nx: the record after gate i; the one after gate i + 1 loads meanwhile
     const RecRegs nx = pf;
@@ -1057,9 +1079,9 @@ static __device__ void phase_body(LL& L, const TrackJob& job, int c) {
     const int sg = snext, hg = hnext;
     if (i + 1 < i1) {
       rec_fetch(job, i + 2, n, pf);
-      gnext = job.gates[job.g0 + i + 1];
-      snext = job.ginfo[2 * (i + 1)];
-      hnext = job.ginfo[2 * (i + 1) + 1];
+      gnext = load_gate(job.gates + job.g0 + i + 1);
+      snext = *gmem(job.ginfo + 2 * (i + 1));
+      hnext = *gmem(job.ginfo + 2 * (i + 1) + 1);
     }
     const int op = __builtin_amdgcn_readfirstlane(gt.op);
     const int a = __builtin_amdgcn_readfirstlane(gt.q0), b = __builtin_amdgcn_readfirstlane(gt.q1);
@@ -1222,22 +1244,22 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
   int errw = 0;
   DGate nxt;
   memset(&nxt, 0, sizeof nxt);
-  if (job.g0 < job.g1) nxt = job.gates[job.g0];
+  if (job.g0 < job.g1) nxt = load_gate(job.gates + job.g0);
   for (int g = job.g0; g < job.g1 && !errw; ++g) {
     DGate gt = nxt;
     gt.op = __builtin_amdgcn_readfirstlane(gt.op);
     gt.q0 = __builtin_amdgcn_readfirstlane(gt.q0);
     gt.q1 = __builtin_amdgcn_readfirstlane(gt.q1);
     gt.q2 = __builtin_amdgcn_readfirstlane(gt.q2);
-    if (g + 1 < job.g1) nxt = job.gates[g + 1];  // next gate's load overlaps this one
+    if (g + 1 < job.g1) nxt = load_gate(job.gates + g + 1);  // next gate's load overlaps this one
     const int gi = g - job.g0;
     if (gt.op < DG_NCPHASE) {
       const bool hs = clifford_gate_rec(L, TB, HB, gen, gt.op, gt.q0, gt.q1, n, d, &kx);
       if (rec) {
         TIC(0);
         if (lane == 0) {
-          job.ginfo[2 * gi] = seg;
-          job.ginfo[2 * gi + 1] = hs ? had_base + nhad : -1;
+          *gmem(job.ginfo + 2 * gi) = seg;
+          *gmem(job.ginfo + 2 * gi + 1) = hs ? had_base + nhad : -1;
         }
         rec_write(job, gi + 1, TB, HB, n, d);
         TOC(0);
@@ -1257,7 +1279,7 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
     if (rec) {
       build_beta(L, n);
       hull_images(L, L.hbN, d, false);
-      if (lane == 0) { job.ginfo[2 * gi] = -1; job.ginfo[2 * gi + 1] = -1; }
+      if (lane == 0) { *gmem(job.ginfo + 2 * gi) = -1; *gmem(job.ginfo + 2 * gi + 1) = -1; }
     }
     if (gt.op == DG_CPH2 || gt.op == DG_CX2) {
       terminal_controlled(L, job, gt, seg, nhad, had_base, n, &d, &err);
