@@ -179,8 +179,9 @@ __device__ void fit_z4(LT& L, const uint8_t* f, int d, Z4Q* out, int* err) {
   uint32_t L1 = (uint32_t)__ballot(lane < d && (l & 1));
   uint32_t L2 = (uint32_t)__ballot(lane < d && (l >> 1));
   uint32_t qnz = (uint32_t)__ballot(lane < d && q != 0);
-  if (lane < 32) out->Q[lane] = lane < d ? q : 0u;
-  if (lane == 0) { out->c = f[0] & 3; out->L1 = L1; out->L2 = L2; out->qnz = qnz; }
+  auto o = gmem(out);
+  if (lane < 32) o->Q[lane] = lane < d ? q : 0u;
+  if (lane == 0) { o->c = f[0] & 3; o->L1 = L1; o->L2 = L2; o->qnz = qnz; }
 }
 
 template <class LT>
@@ -195,17 +196,20 @@ __device__ void fit_gf2(LT& L, const uint8_t* t, int d, GF2Q* out) {
   }
   uint32_t Lm = (uint32_t)__ballot(lane < d && l);
   uint32_t qnz = (uint32_t)__ballot(lane < d && q != 0);
-  if (lane < 32) out->Q[lane] = lane < d ? q : 0u;
-  if (lane == 0) { out->c = t[0] & 1; out->L = Lm; out->qnz = qnz; out->pad = 0; }
+  auto o = gmem(out);
+  if (lane < 32) o->Q[lane] = lane < d ? q : 0u;
+  if (lane == 0) { o->c = t[0] & 1; o->L = Lm; o->qnz = qnz; o->pad = 0; }
 }
 
 __device__ void zero_z4(Z4Q* out) {
   const int lane = lane_id();
-  if (lane < 32) out->Q[lane] = 0;
-  if (lane == 0) { out->c = 0; out->L1 = 0; out->L2 = 0; out->qnz = 0; }
+  auto o = gmem(out);
+  if (lane < 32) o->Q[lane] = 0;
+  if (lane == 0) { o->c = 0; o->L1 = 0; o->L2 = 0; o->qnz = 0; }
 }
 
-__device__ void emit_header(SegProg* sp, int kind, int is_meas, int d, int d_out, int nhad, int had_off) {
+__device__ void emit_header(SegProg* out, int kind, int is_meas, int d, int d_out, int nhad, int had_off) {
+  auto sp = gmem(out);
   sp->kind = kind; sp->is_meas = is_meas; sp->d = d; sp->d_out = d_out;
   sp->nhad = nhad; sp->had_off = had_off; sp->nhad_total = nhad;
   sp->j0 = -1; sp->delta = 0; sp->det_c = 0; sp->det_r = 0;
@@ -1012,7 +1016,7 @@ static __device__ __forceinline__ void rec_put(LL& L, const RecRegs& R, int d) {
 static __device__ __forceinline__ void seg_clear(const TrackJob& job, int s, int d) {
   if (s >= job.nseg) return;
   const int P = min(npoints(d), job.pe);
-  for (int p = lane_id(); p < P; p += TL) job.segacc[(size_t)s * job.pe + p] = 0u;
+  for (int p = lane_id(); p < P; p += TL) *gmem(job.segacc + (size_t)s * job.pe + p) = 0u;
 }
 
 // Clifford gate of the split form: Table 2 and the echelon repair only.
@@ -1114,7 +1118,7 @@ static __device__ void phase_body(LL& L, const TrackJob& job, int c) {
           if (op == DG_CZ) bb ^= getb(L.hbN[1 + j], b);
         }
         const int mu = op == DG_S ? ba : op == DG_SDG ? 3 * ba : op == DG_Z ? 2 * ba : 2 * (ba & bb);
-        atomicAdd(&acc[p], (uint32_t)(mu & 3));
+        __hip_atomic_fetch_add(gmem(&acc[p]), (uint32_t)(mu & 3), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       if (i + 1 < i1) rec_put(L, nx, d);
       continue;
@@ -1171,7 +1175,7 @@ static __device__ void phase_body(LL& L, const TrackJob& job, int c) {
           t = dl == 3 ? 1 : 0;        // omega = exp(i pi (2 e0 + 1 - 2t)/4)
         }
       }
-      atomicAdd(&acc[p], (uint32_t)(e & 3));
+      __hip_atomic_fetch_add(gmem(&acc[p]), (uint32_t)(e & 3), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (hsplit) L.t0[p] = (uint8_t)t;
     }
     __syncthreads();
@@ -2266,17 +2270,17 @@ static __device__ void terminal_controlled(Lds& L, const TrackJob& job, const DG
 // phase kernel.  Records hold W words per row part (LDS rows hold SF_WMAX).
 // ---------------------------------------------------------------------------
 static __device__ void rec_write(const TrackJob& job, int r, const Lds& L, int n, int d) {
-  uint64_t* rw = (uint64_t*)(job.rec + (size_t)r * job.rec_stride);
+  auto rw = gmem((uint64_t*)(job.rec + (size_t)r * job.rec_stride));
   const int lane = lane_id();
   for (int idx = lane; idx < n * W; idx += TL) {
     const int i = idx / W, w = idx % W;
     rw[i * 2 * W + w] = L.rx[i * SF_WMAX + w];
     rw[i * 2 * W + W + w] = L.rz[i * SF_WMAX + w];
   }
-  uint64_t* hv = rw + (size_t)n * 2 * W;
+  auto hv = rw + (size_t)n * 2 * W;
   if (lane <= d)
     for (int w = 0; w < W; ++w) hv[lane * W + w] = lane == 0 ? L.s0[w] : L.V[lane - 1][w];
-  if (lane == 0) *(int32_t*)(hv + (SF_DMAX + 1) * W) = d;
+  if (lane == 0) *gmem((int32_t*)(job.rec + (size_t)r * job.rec_stride + ((size_t)n * 2 * W + (SF_DMAX + 1) * W) * 8)) = d;
 }
 
 static __device__ int rec_d(const TrackJob& job, int r, int n) {
@@ -2285,7 +2289,7 @@ static __device__ int rec_d(const TrackJob& job, int r, int n) {
 }
 
 static __device__ void rec_load(Lds& L, const TrackJob& job, int r, int n, int d) {
-  const uint64_t* rw = (const uint64_t*)(job.rec + (size_t)r * job.rec_stride);
+  auto rw = gmem((const uint64_t*)(job.rec + (size_t)r * job.rec_stride));
   const int lane = lane_id();
   for (int idx = lane; idx < SF_NMAX * SF_WMAX; idx += TL) {
     const int i = idx / SF_WMAX, w = idx % SF_WMAX;
@@ -2293,7 +2297,7 @@ static __device__ void rec_load(Lds& L, const TrackJob& job, int r, int n, int d
     L.rx[idx] = in ? rw[i * 2 * W + w] : 0ull;
     L.rz[idx] = in ? rw[i * 2 * W + W + w] : 0ull;
   }
-  const uint64_t* hv = rw + (size_t)n * 2 * W;
+  auto hv = rw + (size_t)n * 2 * W;
   if (lane <= d)
     for (int w = 0; w < SF_WMAX; ++w) {
       const uint64_t v = w < W ? hv[lane * W + w] : 0ull;
@@ -2306,20 +2310,20 @@ static __device__ void rec_load(Lds& L, const TrackJob& job, int r, int n, int d
 static __device__ void seg_clear(const TrackJob& job, int s, int d) {
   if (s >= job.nseg) return;
   const int P = min(npoints(d), job.pe);
-  for (int p = lane_id(); p < P; p += TL) job.segacc[(size_t)s * job.pe + p] = 0u;
+  for (int p = lane_id(); p < P; p += TL) *gmem(job.segacc + (size_t)s * job.pe + p) = 0u;
 }
 
 // Phase factor of Clifford gate g0 + i from the records before and after it,
 // added into its segment's sums (the evaluation of clifford_gate).
 static __device__ void phase_gate(Lds& L, const TrackJob& job, int i) {
   const int lane = lane_id();
-  const DGate gt = job.gates[job.g0 + i];
+  const DGate gt = load_gate(job.gates + job.g0 + i);
   const int op = __builtin_amdgcn_readfirstlane(gt.op);
   if (op >= DG_NCPHASE) return;
   TrackState* st = job.st;
   const int n = __builtin_amdgcn_readfirstlane(st->n);
   const int d = __builtin_amdgcn_readfirstlane(rec_d(job, i + 1, n));
-  const int s = __builtin_amdgcn_readfirstlane(job.ginfo[2 * i]);
+  const int s = __builtin_amdgcn_readfirstlane(*gmem(job.ginfo + 2 * i));
   if (d < 0 || d >= SF_DMAX || s < 0 || s >= job.nseg || npoints(d) > job.pe ||
       __builtin_amdgcn_readfirstlane(rec_d(job, i, n)) != d) {
     if (lane == 0) st->error = TRK_E_INTERNAL;
@@ -2345,7 +2349,7 @@ static __device__ void phase_gate(Lds& L, const TrackJob& job, int i) {
         if (op == DG_CZ) bb ^= getb(L.hbN[1 + j], b);
       }
       const int mu = op == DG_S ? ba : op == DG_SDG ? 3 * ba : op == DG_Z ? 2 * ba : 2 * (ba & bb);
-      atomicAdd(&acc[p], (uint32_t)(mu & 3));
+      __hip_atomic_fetch_add(gmem(&acc[p]), (uint32_t)(mu & 3), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return;
   }
@@ -2406,11 +2410,11 @@ static __device__ void phase_gate(Lds& L, const TrackJob& job, int i) {
         t = dl == 3 ? 1 : 0;        // omega = exp(i pi (2 e0 + 1 - 2t)/4)
       }
     }
-    atomicAdd(&acc[p], (uint32_t)(e & 3));
+    __hip_atomic_fetch_add(gmem(&acc[p]), (uint32_t)(e & 3), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (hsplit) L.t0[p] = (uint8_t)t;
   }
   __syncthreads();
-  const int hi = __builtin_amdgcn_readfirstlane(job.ginfo[2 * i + 1]);
+  const int hi = __builtin_amdgcn_readfirstlane(*gmem(job.ginfo + 2 * i + 1));
   if (hsplit != (hi >= 0)) err = TRK_E_INTERNAL;
   else if (hsplit) fit_gf2(L, L.t0, d, &job.had[hi]);
   __syncthreads();
@@ -2466,8 +2470,12 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
   int pend = 0, pend_j0 = -1, pend_c0 = 0, pend_meas = -1;
   uint32_t pend_r = 0;
   bool open = false;
+  DGate nxt;
+  memset(&nxt, 0, sizeof nxt);
+  if (job.g0 < job.g1) nxt = load_gate(job.gates + job.g0);
   for (int g = job.g0; g < job.g1 && !err; ++g) {
-    const DGate gt = job.gates[g];
+    const DGate gt = nxt;
+    if (g + 1 < job.g1) nxt = load_gate(job.gates + g + 1);  // next gate's load overlaps this one
     const int gi = g - job.g0;
     if (gt.op < DG_NCPHASE) {
       bool hs = false;
@@ -2475,8 +2483,8 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
       err = wave_max(err);
       if (rec) {
         if (lane == 0) {
-          job.ginfo[2 * gi] = seg;
-          job.ginfo[2 * gi + 1] = hs ? had_base + nhad : -1;
+          *gmem(job.ginfo + 2 * gi) = seg;
+          *gmem(job.ginfo + 2 * gi + 1) = hs ? had_base + nhad : -1;
         }
         if (hs) ++nhad;
         rec_write(job, gi + 1, L, n, d);
@@ -2489,7 +2497,7 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
       // the Clifford steps of the split form keep no b* basis or images
       build_beta(L, n);
       hull_images(L, L.hbN, d, false);
-      if (lane == 0) { job.ginfo[2 * gi] = -1; job.ginfo[2 * gi + 1] = -1; }
+      if (lane == 0) { *gmem(job.ginfo + 2 * gi) = -1; *gmem(job.ginfo + 2 * gi + 1) = -1; }
     }
     // terminal gate of the segment
     if (gt.op == DG_CPH2 || gt.op == DG_CX2) {
