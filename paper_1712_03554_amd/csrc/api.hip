@@ -249,11 +249,22 @@ struct sf_circuit {
   // the circuit into the same segments; rec_len = longest range
   std::vector<size_t> cuts;
   int rec_len;
+  // the device ranges of a run from the first gate without a cap, planned
+  // once at load (planning depends on the circuit only): rstart[dev index] =
+  // the range starting there, or -1
+  struct Range {
+    size_t o0, a, b, o;
+    int ns, ml;
+  };
+  std::vector<Range> ranges;
+  std::vector<int32_t> rstart;
 };
 
 static bool is_cut(const sf_circuit* c, size_t e) {
   return std::binary_search(c->cuts.begin(), c->cuts.end(), e);
 }
+
+static void build_range_table(sf_circuit* c);
 
 struct sf_state {
   sf_ctx* ctx;
@@ -541,6 +552,7 @@ extern "C" sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n, const sf_gate* gat
     // a cut can leave one more (open) segment in a range
     c->max_segs += 1;
   }
+  build_range_table(c);
   sf_status rc = dalloc(ctx, &c->dgates, sizeof(DGate) * std::max<size_t>(1, c->g.size()));
   if (rc != SF_OK) { delete c; return rc; }
   // dry run of the tableau track: frame bound of the whole circuit
@@ -1121,6 +1133,18 @@ static void set_progress(sf_state* s, const Progress& p) {
 // those of the uncapped run).
 static void plan_range(const sf_circuit* c, const Progress& pr, size_t* a, size_t* b, size_t* orig_after, int* nseg,
                        int* meas_last, int cap = 0) {
+  if (cap == 0 && pr.dev_done < c->rstart.size()) {
+    const int k = c->rstart[pr.dev_done];
+    if (k >= 0 && c->ranges[(size_t)k].o0 == pr.orig_done) {
+      const sf_circuit::Range& r = c->ranges[(size_t)k];
+      *a = r.a;
+      *b = r.b;
+      *orig_after = r.o;
+      *nseg = r.ns;
+      *meas_last = r.ml;
+      return;
+    }
+  }
   size_t o = pr.orig_done, e = pr.dev_done;
   *a = pr.dev_done;
   int terms = 0;
@@ -1145,6 +1169,24 @@ static void plan_range(const sf_circuit* c, const Progress& pr, size_t* a, size_
   if (open) ++ns;
   *nseg = ns;
   *meas_last = ml ? 1 : 0;
+}
+
+// Plans the uncapped ranges of a run from the first gate once (the walk of
+// plan_range for every range start of that run).
+static void build_range_table(sf_circuit* c) {
+  c->ranges.clear();
+  c->rstart.assign(c->g.size() + 1, -1);
+  Progress p{0, 0, 0, 0};
+  while (p.orig_done < c->orig_end.size()) {
+    sf_circuit::Range r;
+    r.o0 = p.orig_done;
+    plan_range(c, p, &r.a, &r.b, &r.o, &r.ns, &r.ml, 0);
+    if (r.b <= r.a && r.o <= r.o0) break;  // no progress: leave the rest to the walk
+    c->rstart[r.a] = (int32_t)c->ranges.size();
+    c->ranges.push_back(r);
+    p.orig_done = r.o;
+    p.dev_done = r.b;
+  }
 }
 
 static ElemDesc elem_desc(const sf_state* s, int cur, const SegProg* prog, const uint64_t* seedp) {
