@@ -1242,12 +1242,21 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
     act.push_back((int)i);
   }
   if (act.empty()) return false;
-  // one track launch per word count: order the frames by it
-  std::stable_sort(act.begin(), act.end(), [&](int u, int v) {
-    return words_of(states[u]->c->n) < words_of(states[v]->c->n);
-  });
+  // one track launch per word count: order the frames by it (a stable
+  // counting sort over the word counts)
   for (int w = 0; w <= SF_WMAX; ++w) rp->wcount[w] = rp->wlen[w] = rp->wseg[w] = rp->wchunk[w] = 0;
-  for (int i : act) rp->wcount[words_of(states[i]->c->n)]++;
+  {
+    std::vector<int> wof(act.size());
+    for (size_t t = 0; t < act.size(); ++t) {
+      wof[t] = words_of(states[act[t]]->c->n);
+      rp->wcount[wof[t]]++;
+    }
+    int start[SF_WMAX + 2] = {0};
+    for (int w = 0; w <= SF_WMAX; ++w) start[w + 1] = start[w] + rp->wcount[w];
+    std::vector<int> sorted(act.size());
+    for (size_t t = 0; t < act.size(); ++t) sorted[start[wof[t]]++] = act[t];
+    act.swap(sorted);
+  }
   const int na = (int)act.size();
   rp->na = na;
   rp->jobs.assign(na, TrackJob{});
@@ -1317,7 +1326,8 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
       const SegProg* p = nullptr;
       if (k < kmax) p = k < NS[i] ? base + k : nullptr;
       else p = ML[i] ? base + (NS[i] - 1) : nullptr;  // measurement descriptors
-      rp->desc[(size_t)k * na + j] = elem_desc(s, pr[i].cur, p, seedp ? seedp[i] : nullptr);
+      // (an idle entry only needs its null program, which assign left)
+      if (p) rp->desc[(size_t)k * na + j] = elem_desc(s, pr[i].cur, p, seedp ? seedp[i] : nullptr);
     }
   for (int j = 0; j < na; ++j) {
     const int i = act[j];
