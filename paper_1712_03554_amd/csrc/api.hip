@@ -254,7 +254,7 @@ struct sf_circuit {
   // the range starting there, or -1
   struct Range {
     size_t o0, a, b, o;
-    int ns, ml;
+    int ns, ml, cl;  // segments, ends in a measurement, has a Clifford gate
   };
   std::vector<Range> ranges;
   std::vector<int32_t> rstart;
@@ -1132,7 +1132,7 @@ static void set_progress(sf_state* s, const Progress& p) {
 // (a segment boundary either way, so the segments and their arithmetic are
 // those of the uncapped run).
 static void plan_range(const sf_circuit* c, const Progress& pr, size_t* a, size_t* b, size_t* orig_after, int* nseg,
-                       int* meas_last, int cap = 0) {
+                       int* meas_last, int cap = 0, int* has_cliff = nullptr) {
   if (cap == 0 && pr.dev_done < c->rstart.size()) {
     const int k = c->rstart[pr.dev_done];
     if (k >= 0 && c->ranges[(size_t)k].o0 == pr.orig_done) {
@@ -1142,6 +1142,7 @@ static void plan_range(const sf_circuit* c, const Progress& pr, size_t* a, size_
       *orig_after = r.o;
       *nseg = r.ns;
       *meas_last = r.ml;
+      if (has_cliff) *has_cliff = r.cl;
       return;
     }
   }
@@ -1160,15 +1161,16 @@ static void plan_range(const sf_circuit* c, const Progress& pr, size_t* a, size_
   *b = e;
   *orig_after = o;
   int ns = 0;
-  bool open = false, ml = false;
+  bool open = false, ml = false, cl = false;
   for (size_t i = *a; i < *b; ++i) {
     int op = c->g[i].op;
     if (is_terminal(op)) { ++ns; open = false; ml = op == DG_MEASURE; }
-    else { open = true; ml = false; }
+    else { open = true; ml = false; cl = true; }
   }
   if (open) ++ns;
   *nseg = ns;
   *meas_last = ml ? 1 : 0;
+  if (has_cliff) *has_cliff = cl ? 1 : 0;
 }
 
 // Plans the uncapped ranges of a run from the first gate once (the walk of
@@ -1180,7 +1182,7 @@ static void build_range_table(sf_circuit* c) {
   while (p.orig_done < c->orig_end.size()) {
     sf_circuit::Range r;
     r.o0 = p.orig_done;
-    plan_range(c, p, &r.a, &r.b, &r.o, &r.ns, &r.ml, 0);
+    plan_range(c, p, &r.a, &r.b, &r.o, &r.ns, &r.ml, 0, &r.cl);
     if (r.b <= r.a && r.o <= r.o0) break;  // no progress: leave the rest to the walk
     c->rstart[r.a] = (int32_t)c->ranges.size();
     c->ranges.push_back(r);
@@ -1228,12 +1230,12 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
                        RoundPlan* rp, sf_status* err) {
   std::vector<int> act;
   std::vector<size_t> A(ns), B(ns), O(ns);
-  std::vector<int> NS(ns), ML(ns);
+  std::vector<int> NS(ns), ML(ns), CL(ns);
   *err = SF_OK;
   for (size_t i = 0; i < ns; ++i) {
     const sf_circuit* c = states[i]->c;
     if (pr[i].orig_done >= c->orig_end.size()) continue;
-    plan_range(c, pr[i], &A[i], &B[i], &O[i], &NS[i], &ML[i], cap);
+    plan_range(c, pr[i], &A[i], &B[i], &O[i], &NS[i], &ML[i], cap, &CL[i]);
     if (ML[i] && pr[i].nmeas + 1 > states[i]->meas_cap) {
       *err = fail(states[i]->ctx, SF_E_STATE, "state %zu: outcome buffer holds %zu measurements", i,
                   states[i]->meas_cap);
@@ -1294,17 +1296,16 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
   }
   // phase-kernel chunk per word count: the group's gates over SF_PHASE_WAVES
   {
+    // (jobs are ordered by word count: job j's count follows from the counts)
+    std::vector<int> jw(na);
+    for (int w = 0, j = 0; w <= SF_WMAX; ++w)
+      for (int t = 0; t < rp->wcount[w]; ++t) jw[j++] = w;
     size_t gates[SF_WMAX + 1] = {0, 0, 0, 0, 0};
-    for (int j = 0; j < na; ++j) {
-      const TrackJob& jb = rp->jobs[j];
-      if (jb.rec) gates[words_of(states[act[j]]->c->n)] += (size_t)(jb.g1 - jb.g0);
-    }
     bool cliff[SF_WMAX + 1] = {false, false, false, false, false};
     for (int j = 0; j < na; ++j) {
       const TrackJob& jb = rp->jobs[j];
-      const sf_circuit* c = states[act[j]]->c;
-      bool& cw = cliff[words_of(c->n)];
-      for (int g = jb.g0; g < jb.g1 && !cw; ++g) cw = c->g[g].op < DG_NCPHASE;
+      if (jb.rec) gates[jw[j]] += (size_t)(jb.g1 - jb.g0);
+      cliff[jw[j]] = cliff[jw[j]] || CL[act[j]] != 0;
     }
     int kw[SF_WMAX + 1];
     for (int w = 0; w <= SF_WMAX; ++w) {
@@ -1312,7 +1313,7 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
       rp->wchunk[w] = (rp->wlen[w] > 0 && cliff[w] && gates[w] > 0) ? (rp->wlen[w] + kw[w] - 1) / kw[w] : 0;
     }
     for (int j = 0; j < na; ++j)
-      if (rp->jobs[j].rec) rp->jobs[j].pchunk = kw[words_of(states[act[j]]->c->n)];
+      if (rp->jobs[j].rec) rp->jobs[j].pchunk = kw[jw[j]];
   }
   elem_shape(states[act[0]]->ctx, dm, &rp->bx, &rp->gx);
   rp->msmall = dm <= SF_MSMALL_D;
