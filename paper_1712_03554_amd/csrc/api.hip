@@ -1347,9 +1347,12 @@ struct BatchScratch {
   std::vector<std::vector<ElemDesc>> keep_desc;
 };
 
+// jobs then (at a 256-byte boundary) descriptors: one copy per round
+static size_t desc_offset(size_t job_bytes) { return (job_bytes + 255) & ~(size_t)255; }
+
 static sf_status scratch_reserve(sf_ctx* ctx, BatchScratch* bs, size_t ns, int maxseg) {
-  size_t need_j = std::max<size_t>(1, ns) * sizeof(TrackJob);
   size_t need_d = (size_t)(maxseg + 1) * std::max<size_t>(1, ns) * sizeof(ElemDesc);
+  size_t need_j = desc_offset(std::max<size_t>(1, ns) * sizeof(TrackJob)) + need_d;
   sf_status rc;
   if (bs->djobs.bytes < need_j) {
     dfree(ctx, &bs->djobs);
@@ -1427,14 +1430,13 @@ static sf_status batch_round(sf_ctx* ctx, sf_state* const* states, size_t ns, Ba
   *active = rp.na;
   if (staged) {
     const size_t bj = rp.na * sizeof(TrackJob), bd = rp.desc.size() * sizeof(ElemDesc);
-    void* hj = pin_take(ctx, bj);
-    void* hd = hj ? pin_take(ctx, bd) : nullptr;
-    if (hj && hd) {
-      memcpy(hj, rp.jobs.data(), bj);
-      memcpy(hd, rp.desc.data(), bd);
-      HIPCHK(ctx, hipMemcpyAsync(bs->djobs.p, hj, bj, hipMemcpyHostToDevice, ctx->stream));
-      HIPCHK(ctx, hipMemcpyAsync(bs->ddesc.p, hd, bd, hipMemcpyHostToDevice, ctx->stream));
-      launch_round(ctx, rp, (const TrackJob*)bs->djobs.p, (const ElemDesc*)bs->ddesc.p);
+    const size_t offd = desc_offset(bj);
+    char* h = offd + bd <= bs->djobs.bytes ? (char*)pin_take(ctx, offd + bd) : nullptr;
+    if (h) {
+      memcpy(h, rp.jobs.data(), bj);
+      memcpy(h + offd, rp.desc.data(), bd);
+      HIPCHK(ctx, hipMemcpyAsync(bs->djobs.p, h, offd + bd, hipMemcpyHostToDevice, ctx->stream));
+      launch_round(ctx, rp, (const TrackJob*)bs->djobs.p, (const ElemDesc*)((char*)bs->djobs.p + offd));
       HIPCHK(ctx, hipGetLastError());
       for (size_t i = 0; i < ns; ++i) set_progress(states[i], pr[i]);
       return SF_OK;
