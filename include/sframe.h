@@ -234,11 +234,12 @@ sf_status sf_serve_destroy(sf_server* sv);
  * sf_profile(ctx, mask) starts collecting (and clears the totals) for the
  * kernel kinds whose bit is set in mask (-1: all), 0 stops.
  * sf_profile_read returns total milliseconds and launch counts per kernel
- * kind: 0 tableau track, 1 segment (phase + cofactor), 2 measurement
- * reduction, 3 measurement coin, 4 measurement filter, 5 readout, 6 state
- * initialisation, 7 per-gate phase evaluation and 8 per-segment phase fit
- * (the parallel part of the tableau track of frames of up to 128 qubits).
- * Both synchronise. */
+ * kind: 0 tableau track, 1 segment (phase + cofactor; for frames of at most
+ * 256 slots the whole element stage of a round), 2 measurement reduction,
+ * 3 unused (the coin is drawn by the filter kernel; kept for the numbering),
+ * 4 measurement coin and filter, 5 readout, 6 state initialisation, 7
+ * per-gate phase evaluation and 8 per-segment phase fit (the parallel part of
+ * the tableau track of frames of up to 128 qubits).  Both synchronise. */
 sf_status sf_profile(sf_ctx* ctx, int enable);
 sf_status sf_profile_read(sf_ctx* ctx, double* ms, uint64_t* launches, int n_kinds);
 /* Shader clocks the tableau track of this state spent per phase since the

@@ -844,14 +844,10 @@ static sf_status run_chunk(sf_state* s, const DGate* dgates, const DGate* hg, si
     hipLaunchKernelGGL(sf_meas_reduce, dim3(s->G), dim3(EB), 0, ctx->stream, sp, (const double2*)s->amp[s->cur].p,
                        (double2*)s->partials.p);
     prof_end(ctx);
-    prof_begin(ctx, PK_MFINAL);
-    hipLaunchKernelGGL(sf_meas_final, dim3(1), dim3(EB), 0, ctx->stream, sp, (const double2*)s->partials.p, s->G,
-                       s->seed, (uint8_t*)s->outcomes.p, (double*)s->pvals.p, (double*)s->scale.p,
-                       (int*)s->flags.p);
-    prof_end(ctx);
     prof_begin(ctx, PK_MFILTER);
-    hipLaunchKernelGGL(sf_meas_filter, dim3(grid), dim3(eb), 0, ctx->stream, sp, (const double2*)s->amp[s->cur].p,
-                       (double2*)s->amp[s->cur ^ 1].p, (const uint8_t*)s->outcomes.p, (const double*)s->scale.p);
+    hipLaunchKernelGGL(sf_meas_filter, dim3(grid), dim3(eb), 0, ctx->stream, sp, (const double2*)s->partials.p, s->G,
+                       s->seed, (uint8_t*)s->outcomes.p, (double*)s->pvals.p, (double*)s->scale.p,
+                       (int*)s->flags.p, (const double2*)s->amp[s->cur].p, (double2*)s->amp[s->cur ^ 1].p);
     prof_end(ctx);
     s->cur ^= 1;
     s->nmeas++;
@@ -1404,9 +1400,6 @@ static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs
     prof_begin(ctx, PK_MREDUCE);
     hipLaunchKernelGGL(sf_meas_reduce_batch, dim3(rp.gm, na), dim3(EB), 0, ctx->stream, dm);
     prof_end(ctx);
-    prof_begin(ctx, PK_MFINAL);
-    hipLaunchKernelGGL(sf_meas_final_batch, dim3(1, na), dim3(EB), 0, ctx->stream, dm);
-    prof_end(ctx);
     prof_begin(ctx, PK_MFILTER);
     hipLaunchKernelGGL(sf_meas_filter_batch, dim3(rp.gx, na), dim3(rp.bx), 0, ctx->stream, dm);
     prof_end(ctx);
@@ -1782,8 +1775,6 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
       const ElemDesc* dm = dd + (size_t)rp.kmax * na;
       void* args[] = {(void*)&dm};
       e = add_kernel_node(g->graph, &last, (const void*)sf_meas_reduce_batch, dim3(rp.gm, na), dim3(EB), args);
-      if (e == hipSuccess)
-        e = add_kernel_node(g->graph, &last, (const void*)sf_meas_final_batch, dim3(1, na), dim3(EB), args);
       if (e == hipSuccess)
         e = add_kernel_node(g->graph, &last, (const void*)sf_meas_filter_batch, dim3(rp.gx, na), dim3(rp.bx), args);
     }

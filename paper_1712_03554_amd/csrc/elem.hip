@@ -224,47 +224,62 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t state, uint64_t index
   return z ^ (z >> 31);
 }
 
-// One block: fixed-order sum of the partials, seeded biased coin, outcome.
-__device__ __forceinline__ void meas_final_body(const SegProg* __restrict__ sp, const double2* __restrict__ partials,
-                                                int G, uint64_t seed, uint8_t* __restrict__ outcomes,
+// The coin inside each filter block: the sum of the partials in the one-block
+// shape of the final step (slot t of EB adds partials t, t + EB, ... in
+// order, then the pairwise tree; the block's threads share the slots, and
+// within a tree level the additions are independent), the seeded coin and
+// the scale.  Every block computes the same values; the writer block stores
+// them.  One launch less per measurement than a separate coin kernel.
+__device__ __forceinline__ void meas_coin_local(const SegProg* __restrict__ sp, const double2* __restrict__ partials,
+                                                int G, uint64_t seed, bool writer, uint8_t* __restrict__ outcomes,
                                                 double* __restrict__ pvals, double* __restrict__ scale,
-                                                int* __restrict__ flags) {
-  __shared__ double s0[EB], s1[EB];
-  double p0 = 0.0, p1 = 0.0;
-  for (int i = threadIdx.x; i < G; i += EB) {
-    p0 = __dadd_rn(p0, partials[i].x);
-    p1 = __dadd_rn(p1, partials[i].y);
+                                                int* __restrict__ flags, uint32_t* o_out, double* sc_out) {
+  __shared__ double v0[EB], v1[EB];
+  __shared__ uint32_t s_o;
+  __shared__ double s_sc;
+  const int nt = blockDim.x;
+  for (int t = threadIdx.x; t < EB; t += nt) {
+    double p0 = 0.0, p1 = 0.0;
+    for (int i = t; i < G; i += EB) {
+      p0 = __dadd_rn(p0, partials[i].x);
+      p1 = __dadd_rn(p1, partials[i].y);
+    }
+    v0[t] = p0;
+    v1[t] = p1;
   }
-  s0[threadIdx.x] = p0;
-  s1[threadIdx.x] = p1;
   __syncthreads();
   for (int h = EB / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h) {
-      s0[threadIdx.x] = __dadd_rn(s0[threadIdx.x], s0[threadIdx.x + h]);
-      s1[threadIdx.x] = __dadd_rn(s1[threadIdx.x], s1[threadIdx.x + h]);
+    for (int t = threadIdx.x; t < h; t += nt) {
+      v0[t] = __dadd_rn(v0[t], v0[t + h]);
+      v1[t] = __dadd_rn(v1[t], v1[t + h]);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     const int mi = sp->meas_index;
-    double P0 = s0[0], P1 = s1[0];
+    double P0 = v0[0], P1 = v1[0];
     double u = (double)(splitmix64_at(seed, (uint64_t)mi) >> 11) * (1.0 / 9007199254740992.0);
     int o = u < P1 ? 1 : 0;
-    outcomes[mi] = (uint8_t)o;
-    pvals[mi] = P1;
     double po = o ? P1 : P0;
-    scale[0] = po > 0.0 ? 1.0 / sqrt(po) : 0.0;
-    if (fabs(u - P1) < 1e-12 || po <= 0.0) atomicOr(flags, 1);
+    const double sc = po > 0.0 ? 1.0 / sqrt(po) : 0.0;
+    if (writer) {
+      outcomes[mi] = (uint8_t)o;
+      pvals[mi] = P1;
+      scale[0] = sc;
+      if (fabs(u - P1) < 1e-12 || po <= 0.0) atomicOr(flags, 1);
+    }
+    s_o = (uint32_t)o;
+    s_sc = sc;
   }
+  __syncthreads();
+  *o_out = s_o;
+  *sc_out = s_sc;
 }
 
 // Keep the elements consistent with the outcome and renormalise (new buffer).
 __device__ __forceinline__ void meas_filter_body(const SegProg* __restrict__ sp, const double2* __restrict__ src,
-                                                 double2* __restrict__ dst, const uint8_t* __restrict__ outcomes,
-                                                 const double* __restrict__ scale, uint64_t tid, uint64_t stride) {
-  const int mi = sp->meas_index;
-  const uint32_t o = outcomes[mi];
-  const double s = scale[0];
+                                                 double2* __restrict__ dst, uint32_t o, double s, uint64_t tid,
+                                                 uint64_t stride) {
   const uint32_t c0 = sp->m_c0, r = sp->m_r;
   const int j0 = sp->m_j0;
   const int dout = sp->d_out;
@@ -364,16 +379,13 @@ sf_meas_reduce(const SegProg* __restrict__ sp, const double2* __restrict__ amp, 
 }
 
 extern "C" __global__ void __launch_bounds__(EB)
-sf_meas_final(const SegProg* __restrict__ sp, const double2* __restrict__ partials, int G, uint64_t seed,
-              uint8_t* __restrict__ outcomes, double* __restrict__ pvals, double* __restrict__ scale,
-              int* __restrict__ flags) {
-  meas_final_body(sp, partials, G, seed, outcomes, pvals, scale, flags);
-}
-
-extern "C" __global__ void __launch_bounds__(EB)
-sf_meas_filter(const SegProg* __restrict__ sp, const double2* __restrict__ src, double2* __restrict__ dst,
-               const uint8_t* __restrict__ outcomes, const double* __restrict__ scale) {
-  meas_filter_body(sp, src, dst, outcomes, scale, TID, STRIDE);
+sf_meas_filter(const SegProg* __restrict__ sp, const double2* __restrict__ partials, int G, uint64_t seed,
+               uint8_t* __restrict__ outcomes, double* __restrict__ pvals, double* __restrict__ scale,
+               int* __restrict__ flags, const double2* __restrict__ src, double2* __restrict__ dst) {
+  uint32_t o;
+  double sc;
+  meas_coin_local(sp, partials, G, seed, blockIdx.x == 0, outcomes, pvals, scale, flags, &o, &sc);
+  meas_filter_body(sp, src, dst, o, sc, TID, STRIDE);
 }
 
 // ---------------------------------------------------------------------------
@@ -395,16 +407,14 @@ extern "C" __global__ void __launch_bounds__(EB) sf_meas_reduce_batch(const Elem
   meas_reduce_body(e.prog, e.amp, e.partials, blockIdx.x, e.G);
 }
 
-extern "C" __global__ void __launch_bounds__(EB) sf_meas_final_batch(const ElemDesc* __restrict__ D) {
-  const ElemDesc& e = D[blockIdx.y];
-  if (!e.prog) return;
-  meas_final_body(e.prog, e.partials, e.G, e.seedp ? *e.seedp : e.seed, e.outcomes, e.pvals, e.scale, e.flags);
-}
-
 extern "C" __global__ void __launch_bounds__(EB) sf_meas_filter_batch(const ElemDesc* __restrict__ D) {
   const ElemDesc& e = D[blockIdx.y];
   if (!e.prog) return;
-  meas_filter_body(e.prog, e.amp, e.amp_other, e.outcomes, e.scale, BTID, BSTRIDE);
+  uint32_t o;
+  double sc;
+  meas_coin_local(e.prog, e.partials, e.G, e.seedp ? *e.seedp : e.seed, blockIdx.x == 0, e.outcomes, e.pvals,
+                  e.scale, e.flags, &o, &sc);
+  meas_filter_body(e.prog, e.amp, e.amp_other, o, sc, BTID, BSTRIDE);
 }
 
 // Frames of at most EB slots: every segment of a round, then its
