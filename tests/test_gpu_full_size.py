@@ -9,6 +9,8 @@ the graph form), checked against the oracle (needs an MI355X).
   frame's norm and size bound; the oracle on all circuits of at most 72
   qubits and on the two narrowest of each wider word count (the oracle's
   per-gate elimination makes the 200-qubit circuits take seconds each).
+* The large frame (Cuccaro adder, m = 12, on an equal superposition: 2^26
+  elements): every qubit measured afterwards gives a consistent addition.
 
 Eager and graph results agree bit for bit on every frame.
 """
@@ -114,3 +116,31 @@ def test_uneven_batch_full_size(eng):
         assert not frag, c.name
         if j in picked:
             _check_oracle(c, s, res)
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_cuccaro_adder_m12_superposed_measured(eng, seed):
+    """The large-frame workload at its full size (Cuccaro adder of two 12-bit
+    registers on an equal superposition: a frame of 2^26 elements), checked by
+    a property that holds at any size: measured afterwards, every outcome is
+    a consistent addition (sum register s = a + b mod 2^m, carry = [s < a],
+    ancilla 0), and one element of modulus 1 remains."""
+    m = 12
+    c = wl.cuccaro_adder(m, superpose=True, name=f"cuccaro{m}-measured")
+    for q in range(c.n):
+        c.add(wl.MEASURE, q)
+    print(f"case {c.name} seed={seed}", flush=True)
+    lc = eng.load(c.n, c)
+    assert lc.info()[0] >= 2 * m
+    st = lc.state(c.init_bits, seed)
+    st.run()
+    outs = st.outcomes()
+    assert len(outs) == c.n
+    a = sum(outs[2 + 2 * i] << i for i in range(m))
+    s = sum(outs[1 + 2 * i] << i for i in range(m))
+    assert outs[0] == 0
+    assert outs[2 * m + 1] == (1 if s < a else 0)
+    _, _, amp = st.read_frame()
+    assert len(amp) == 1 and abs(abs(amp[0]) - 1.0) <= 1e-10
+    assert not st.info()[1]
+    st.close()
