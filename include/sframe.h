@@ -7,9 +7,11 @@
  * Frames", Definition 1): a stabilizer matrix shared by a set of phase vectors,
  * each with a complex amplitude, such that the state is
  *   Psi = sum_j a_j psi(M, sigma_j).
- * The calls follow the paper's problem statement (section 2.3: initialise a
+ * The calls follow the paper's problem statement (section 2.1: initialise a
  * basis state, apply the gates one at a time, measure) and its frame
- * operations (section 3: ROTATE, COFACTOR; section 4: measuring a frame).
+ * operations (section 3: ROTATE, COFACTOR; section 4: the gate rules and
+ * "Measuring F").  Calls marked "not in the paper" are additions of this
+ * library (batching, graphs, serving, tuning, profiling).
  *
  * Conventions
  *  - Qubit q of a packed bit vector is word q>>6, bit q&63; W = ceil(n/64).
@@ -97,7 +99,8 @@ typedef struct sf_state sf_state;
 typedef struct sf_server sf_server;
 typedef struct sf_graph sf_graph;
 
-/* Create a context on HIP device `device` that queues work on `hip_stream`
+/* Not in the paper (runtime set-up).
+ * Create a context on HIP device `device` that queues work on `hip_stream`
  * (a hipStream_t; NULL = the null stream).  `alloc` may be NULL.
  * hbm_budget_bytes bounds the device memory of all states (0 = no bound). */
 sf_status sf_ctx_create(int device, void* hip_stream, const sf_allocator* alloc,
@@ -105,7 +108,11 @@ sf_status sf_ctx_create(int device, void* hip_stream, const sf_allocator* alloc,
 sf_status sf_ctx_destroy(sf_ctx* ctx);
 const char* sf_last_error(const sf_ctx* ctx);
 
-/* Validate and load a circuit on n_qubits (1..256).  Qubit indices must be
+/* Section 2.1 (the circuit C as a gate sequence) and section 4 (the gate
+ * rules: Eq. 2 Toffoli, Eq. 3 controlled phase, the T rule of the
+ * technology-dependent decompositions); the frame bound follows COFACTOR
+ * (section 3: a frame keeps or doubles its size).
+ * Validate and load a circuit on n_qubits (1..256).  Qubit indices must be
  * < n_qubits and distinct within a gate; theta_den != 0 for phase gates.
  * Loading rewrites phase gates whose angle is a multiple of pi/2 into
  * I/S/Z/S-dagger, expands SF_CPHASE and SF_TOF, and runs the tableau track
@@ -114,29 +121,40 @@ const char* sf_last_error(const sf_ctx* ctx);
  * Returns SF_E_TOO_LARGE when the bound exceeds 29. */
 sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n_qubits, const sf_gate* gates, size_t n_gates,
                           sf_circuit** out);
-/* Frame bound (log2) and the device bytes a state of this circuit needs. */
+/* Not in the paper (admission).  Frame bound (log2) and the device bytes a
+ * state of this circuit needs. */
 sf_status sf_circuit_info(const sf_circuit* c, uint64_t* max_frame_bound_log2, uint64_t* projected_bytes);
 sf_status sf_circuit_destroy(sf_circuit* c);
 
-/* Allocate a state and set it to the basis state |b>: basis_bits holds W
+/* Section 2.1 (the simulation starts from a basis state) and Figure 2a
+ * (the basis form of its stabilizer matrix: row q = Z_q, sign b_q).
+ * Allocate a state and set it to the basis state |b>: basis_bits holds W
  * words, bit q = b_q (NULL = all zeros).  `seed` seeds the measurement coin. */
 sf_status sf_state_init(sf_ctx* ctx, const sf_circuit* c, const uint64_t* basis_bits, uint64_t seed,
                         sf_state** out);
 sf_status sf_state_destroy(sf_state* s);
-/* Set an existing state back to |b> with a new seed, without allocating;
+/* As sf_state_init (section 2.1, Figure 2a), on an existing state.
+ * Set an existing state back to |b> with a new seed, without allocating;
  * the circuit restarts from its first gate.  Asynchronous. */
 sf_status sf_state_reset(sf_state* s, const uint64_t* basis_bits, uint64_t seed);
-/* Dimension of the affine hull of the current phase vectors (|F| <= 2^d);
+/* Not in the paper (a bound on |F| of Definition 1).
+ * Dimension of the affine hull of the current phase vectors (|F| <= 2^d);
  * synchronises. */
 sf_status sf_state_dim(sf_state* s, uint32_t* d);
 
-/* Queue up to max_gates further gates of the circuit (counted as given to
+/* Section 3 (ROTATE with global-phase maintenance, Eq. 1; COFACTOR) and
+ * section 4 (non-Clifford gates, "Measuring F"): the gates applied one at a
+ * time as in the problem statement of section 2.1.
+ * Queue up to max_gates further gates of the circuit (counted as given to
  * sf_circuit_load); stops after each measurement.  *gates_applied receives
  * the number queued (0 at the end of the circuit).  Asynchronous. */
 sf_status sf_step(sf_state* s, size_t max_gates, size_t* gates_applied);
-/* Queue every remaining gate.  Asynchronous. */
+/* As sf_step (sections 3 and 4), to the end of the circuit.
+ * Queue every remaining gate.  Asynchronous. */
 sf_status sf_run(sf_state* s);
-/* Run every remaining gate of n_states states (all of this context) as one
+/* Not in the paper (batching of independent frames; each frame follows
+ * sections 3 and 4).
+ * Run every remaining gate of n_states states (all of this context) as one
  * batch: per round, the tableau tracks of all frames share one launch (one
  * wavefront each) and the element kernels of all frames share one launch per
  * segment.  Results are identical to running each state alone.  The
@@ -144,23 +162,23 @@ sf_status sf_run(sf_state* s);
  * context keeps (allocated on first use, freed by sf_ctx_destroy).
  * Synchronises. */
 sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t n_states);
-/* Measure qubit q in the Z basis now, between circuit gates (the state must
+/* Section 4, "Measuring F" (with COFACTOR of section 3).
+ * Measure qubit q in the Z basis now, between circuit gates (the state must
  * be at a gate boundary, as after sf_step).  Same rule and random stream as
- * a MEASURE gate at this point of the circuit (section 3, measurement of a
- * stabilizer frame): the outcome takes the next measurement index, so later
+ * a MEASURE gate at this point of the circuit: the outcome takes the next measurement index, so later
  * circuit measurements draw the following ones.  *outcome receives 0 or 1.
  * Synchronises.  SF_E_INVALID for q >= n; SF_E_TOO_LARGE (state unchanged)
  * if after this measurement the rest of the circuit would need more frame
  * elements than the state was sized for. */
 sf_status sf_measure(sf_state* s, uint32_t q, int* outcome);
-/* sf_state_reset for many states with one kernel launch: bases holds 4 words
+/* Not in the paper (batching).
+ * sf_state_reset for many states with one kernel launch: bases holds 4 words
  * per state (bit q of state i at bases[4 i + q / 64]; NULL: |0...0>), seeds
  * one per state (NULL: 0).  Synchronises. */
 sf_status sf_batch_reset(sf_ctx* ctx, sf_state* const* states, size_t n_states, const uint64_t* bases,
                          const uint64_t* seeds);
-/* Graph form of sf_batch_run for frames that are run again and again (the
- * batched execution of section 3's frame updates over many independent
- * frames, recorded once).  Plans every round of a run of the given states
+/* Not in the paper (batching, recorded once as a HIP graph).
+ * Graph form of sf_batch_run for frames that are run again and again.  Plans every round of a run of the given states
  * from their initial basis states and records the initialisation and all
  * launches as one hipGraph of kernel nodes; basis[i] (W words, or NULL for
  * |0...0>) and seeds[i] are the inputs of frame i (basis and seeds may be
@@ -169,16 +187,18 @@ sf_status sf_batch_reset(sf_ctx* ctx, sf_state* const* states, size_t n_states, 
  * would have to grow their outcome buffers.  Synchronises. */
 sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t n_states, const uint64_t* const* basis,
                          const uint64_t* seeds, sf_graph** out);
-/* Change the inputs of frame i for the next launch. */
+/* Not in the paper.  Change the inputs of frame i for the next launch. */
 sf_status sf_graph_set_input(sf_graph* g, size_t i, const uint64_t* basis_bits, uint64_t seed);
-/* Re-initialise every frame of the graph from its inputs and run all its
+/* Not in the paper.
+ * Re-initialise every frame of the graph from its inputs and run all its
  * gates (asynchronous, one graph launch on the context's stream).  Results
  * are those of sf_state_reset + sf_batch_run with the same inputs. */
 sf_status sf_graph_launch(sf_graph* g);
-/* Synchronises, frees the graph and releases its states. */
+/* Not in the paper.  Synchronises, frees the graph and releases its states. */
 sf_status sf_graph_destroy(sf_graph* g);
-/* Autotuner of the elementwise frame kernels (segment update and measurement
- * filter; implementation choice, not from the paper): for every hull
+/* Not in the paper (tuning).
+ * Autotuner of the elementwise frame kernels (segment update and measurement
+ * filter): for every hull
  * dimension d in [d_lo, d_hi] (0 <= d_lo <= d_hi <= 29) it times the segment
  * kernel over 2^d slots at each candidate shape (64/128/256 threads per
  * block x 1..32 slots per thread) and keeps the fastest for later launches of
@@ -187,25 +207,32 @@ sf_status sf_graph_destroy(sf_graph* g);
  * launch.  Allocates 16 * 2^d_hi bytes of scratch while it runs.
  * Synchronises. */
 sf_status sf_autotune(sf_ctx* ctx, int d_lo, int d_hi, int* blocks, int* grids, float* ms);
-/* Wait for queued work; reports device-side failures of the queued steps. */
+/* Not in the paper.  Wait for queued work; reports device-side failures of
+ * the queued steps. */
 sf_status sf_sync(sf_state* s);
 
-/* Measurement outcomes so far (synchronises).  *count receives their number;
+/* Section 4, "Measuring F": the outcomes drawn so far.
+ * Measurement outcomes so far (synchronises).  *count receives their number;
  * at most cap are written. */
 sf_status sf_outcomes(sf_state* s, uint8_t* out, size_t cap, size_t* count);
-/* Number of frame elements |F| (synchronises). */
+/* Definition 1: the size |F| of the frame.
+ * Number of frame elements |F| (synchronises). */
 sf_status sf_frame_size(sf_state* s, uint64_t* K);
-/* Read the frame in canonical form (synchronises): tableau (n rows of 2W
+/* Definition 1 (the frame: stabilizer matrix M and the pairs of phase vector
+ * sigma_j and amplitude a_j), with M in the echelon form of Invariant 1.
+ * Read the frame in canonical form (synchronises): tableau (n rows of 2W
  * words), sigma (K rows of W words), amp (K interleaved re,im).  With
  * cap_K < K nothing is written, *K_out = K and SF_E_BUFSIZE is returned.
  * Any output pointer may be NULL. */
 sf_status sf_read_frame(sf_state* s, uint64_t* tableau, uint64_t* sigma, double* amp, size_t cap_K,
                         size_t* K_out);
-/* Gates of the circuit applied so far and whether a measurement result was
+/* Not in the paper.
+ * Gates of the circuit applied so far and whether a measurement result was
  * fragile (|u - p(1)| < 1e-12 or p(outcome) = 0). */
 sf_status sf_state_info(sf_state* s, size_t* gates_done, int* fragile);
 
-/* Serving with continuous batching.  Jobs are admitted in arrival order while
+/* Not in the paper (serving with continuous batching; each job's frame
+ * follows sections 3 and 4).  Jobs are admitted in arrival order while
  * their projected device bytes (sf_circuit_info) fit budget_bytes (0 = no
  * bound) and fewer than max_resident jobs are resident.  Each sf_serve_tick
  * admits what fits, runs one batched round over all resident frames (each
@@ -222,7 +249,8 @@ sf_status sf_serve_create(sf_ctx* ctx, uint64_t budget_bytes, uint32_t max_resid
 sf_status sf_serve_submit(sf_server* sv, const sf_circuit* c, const uint64_t* basis_bits, uint64_t seed,
                           uint64_t* job_id);
 sf_status sf_serve_tick(sf_server* sv, uint32_t* n_resident, uint32_t* n_queued);
-/* *state receives the finished state (owned by the server) when status is 2. */
+/* Not in the paper.  *state receives the finished state (owned by the
+ * server) when status is 2. */
 sf_status sf_serve_poll(sf_server* sv, uint64_t job_id, int* status, sf_state** state);
 sf_status sf_serve_release(sf_server* sv, uint64_t job_id);
 sf_status sf_serve_cancel(sf_server* sv, uint64_t job_id);
@@ -230,7 +258,8 @@ sf_status sf_serve_stats(sf_server* sv, uint64_t* ticks, uint64_t* admitted, uin
                          uint64_t* used_bytes);
 sf_status sf_serve_destroy(sf_server* sv);
 
-/* Per-kernel device time, measured with HIP events on the context stream.
+/* Not in the paper (profiling).
+ * Per-kernel device time, measured with HIP events on the context stream.
  * sf_profile(ctx, mask) starts collecting (and clears the totals) for the
  * kernel kinds whose bit is set in mask (-1: all), 0 stops.
  * sf_profile_read returns total milliseconds and launch counts per kernel
@@ -242,7 +271,8 @@ sf_status sf_serve_destroy(sf_server* sv);
  * the tableau track of frames of up to 128 qubits).  Both synchronise. */
 sf_status sf_profile(sf_ctx* ctx, int enable);
 sf_status sf_profile_read(sf_ctx* ctx, double* ms, uint64_t* launches, int n_kinds);
-/* Shader clocks the tableau track of this state spent per phase since the
+/* Not in the paper (profiling).
+ * Shader clocks the tableau track of this state spent per phase since the
  * last init/reset: 0 saving the pre-gate tableau, 1 column updates, 2 echelon
  * repair, 3 index and b* images, 4 phase sampling, 5 fitting of Hadamard
  * terms, 6 cofactor/measurement steps, 7 total, 8-10 parts of the repair (checks,

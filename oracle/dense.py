@@ -1,7 +1,7 @@
 """Dense state-vector checker -- TEST INFRASTRUCTURE ONLY.
 
 The plain definition of what single-frame simulation computes (Garcia &
-Markov, sections 2.3-3): the exact state vector of the circuit, and its
+Markov, sections 2.2-4): the exact state vector of the circuit, and its
 expansion in the orthonormal basis of stabilizer states that the frame's
 stabilizer matrix defines (Observation 2, Definition 1).  Written
 independently of oracle/frame.c and of the HIP library; n <= 12.
@@ -162,7 +162,7 @@ class TableauTrack:
     """Unsigned generators of the group G_t (section 3): conjugated by each
     Clifford gate, and on a random non-Clifford gate or measurement of q
     replaced by {g in G : g commutes with Z_q} together with Z_q (forced-outcome
-    measurement, section 2.3).  Rows are n x 2n bits [x | z]."""
+    measurement, section 2.2).  Rows are n x 2n bits [x | z]."""
 
     def __init__(self, n: int):
         self.n = n

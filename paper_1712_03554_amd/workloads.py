@@ -167,7 +167,7 @@ def random_clifford_t(n: int, n_cliff: int, n_t: int, seed: int, measure_qubits=
 
 def stabilizer_circuit(n: int, seed: int, beta: float = 1.0) -> Circuit:
     """Random stabilizer circuit of the paper's Clifford-only experiments
-    (section 5): ceil(beta n log2 n) gates uniform over {H, S, CNOT}, then a
+    (section 6): ceil(beta n log2 n) gates uniform over {H, S, CNOT}, then a
     Z measurement of every qubit."""
     gates = int(np.ceil(beta * n * np.log2(n)))
     return random_clifford_t(n, gates, 0, seed, measure_qubits=range(n), name=f"stab-n{n}")

@@ -354,7 +354,7 @@ def test_cuccaro_adds_basis_inputs(m):
 
 def test_invariants_along_random_circuits():
     """Rows commute and are independent; norm 1; distinct phase vectors;
-    Clifford-only circuits keep one element (section 2.3, Definition 1)."""
+    Clifford-only circuits keep one element (Theorem 1, Definition 1, section 3)."""
     for seed in range(6):
         n = 5
         c = wl.random_clifford_t(n, 60, 4 if seed % 2 else 0, 500 + seed)
@@ -375,7 +375,7 @@ def test_invariants_along_random_circuits():
 
 
 def test_stabilizer_measurement_probabilities():
-    """Clifford-only states measure with p in {0, 1/2, 1} (section 2.3)."""
+    """Clifford-only states measure with p in {0, 1/2, 1} (section 2.2)."""
     for seed in range(10):
         c = wl.random_clifford_t(5, 30, 0, 900 + seed)
         psi, _, _ = dense.simulate(5, c.gates)
