@@ -232,9 +232,14 @@ sf_status sf_read_frame(sf_state* s, uint64_t* tableau, uint64_t* sigma, double*
 sf_status sf_state_info(sf_state* s, size_t* gates_done, int* fragile);
 
 /* Not in the paper (serving with continuous batching; each job's frame
- * follows sections 3 and 4).  Jobs are admitted in arrival order while
- * their projected device bytes (sf_circuit_info) fit budget_bytes (0 = no
- * bound) and fewer than max_resident jobs are resident.  Each sf_serve_tick
+ * follows sections 3 and 4).  Queued jobs are considered in arrival order
+ * and admitted while their projected device bytes (sf_circuit_info) fit
+ * budget_bytes (0 = no bound) and fewer than max_resident jobs are resident;
+ * a job that does not fit yet is passed by later jobs that do, in at most 16
+ * ticks, after which nothing behind it is admitted before it.  A job whose
+ * state cannot be allocated waits while others are resident and fails (status
+ * 4) when none is; a resident job whose round cannot be planned (its buffers
+ * cannot be allocated) fails and the other jobs go on.  Each sf_serve_tick
  * admits what fits, runs one batched round over all resident frames (each
  * advances to its next measurement or to its end, or, with tick_segments > 0,
  * stops earlier right after its tick_segments-th non-Clifford phase gate, so

@@ -781,3 +781,655 @@ void ofr_canonicalize_signed(int n, uint64_t *x, uint64_t *z, uint64_t *sig) {
   free(L.op);
   tab_free(&t);
 }
+
+/* ------------------------------------------------------------------------- */
+/* Multiframes (section 4, "Multiframe simulation" and "Orthogonality of      */
+/* multiframes"): a list of frames F_1..F_s with their own stabilizer         */
+/* matrices; the state is the sum of every frame's expansion.                 */
+/*                                                                            */
+/* Readings (the paper leaves these open):                                    */
+/*  - Coalescing runs after every gate that cofactors (non-Clifford phase     */
+/*    gates, the direct controlled phase and Toffoli); the 7-T Toffoli and    */
+/*    the three-phase-gate controlled phase are applied gate by gate.         */
+/*  - Candidate pairs: elements are scanned in canonical order; an unpaired   */
+/*    element takes, among the later unpaired elements that differ from it   */
+/*    only on Z_k rows (rows equal to +-Z_k) and whose amplitude equals its   */
+/*    own times i^d (d in 0..3, relative tolerance COAL_TOL), the one that    */
+/*    differs on the fewest rows (then the first in canonical order).         */
+/*  - Orientation: v_1 is the smallest qubit of the differing Z_k rows, r'    */
+/*    the element of the pair whose sign on the Z_{v_1} row is +, and d is    */
+/*    fixed by a_j' = i^d a_r'.  Then a_r' psi_r' + a_j' psi_j' =             */
+/*    sqrt2 a_r' C psi_r' with C = CNOT_{v1,v2}..CNOT_{v1,vm} P^d H_{v1}      */
+/*    (Step 3 of COALESCE), so the coalesced element is the element           */
+/*    (sigma_r', sqrt2 a_r') rotated by C; every pair of one class (same      */
+/*    differing rows, same d) goes to one new frame with matrix C M C^dag.    */
+/*  - Frames are kept sorted by their canonical matrix (row-major words);     */
+/*    frames with equal matrices are merged (equal phase vectors add).        */
+/*  - Measurement: cofactor every frame on q, merge equal matrices, check     */
+/*    Invariant 2 exactly and orthogonalize if it fails, then p(1) as the     */
+/*    pairwise tree sum over the frames in order and their elements in       */
+/*    canonical order, the coin, and the filter.                              */
+/*  - Orthogonality of two states: psi_A and psi_B are orthogonal exactly     */
+/*    when some Pauli P has P in S(psi_A) and -P in S(psi_B) (the footnote of */
+/*    Observation 2; the converse holds for stabilizer states).  P ranges    */
+/*    over the intersection of the two unsigned groups; the sign difference  */
+/*    is linear on it, so a basis of the intersection decides.               */
+/*  - Orthogonalization pivot: the smallest qubit whose column carries a      */
+/*    different set of Pauli literals in two of the frames' matrices; if no   */
+/*    column does but several frames remain, the smallest qubit whose column  */
+/*    differs at all.                                                         */
+/* ------------------------------------------------------------------------- */
+#define COAL_TOL 1e-9
+
+typedef struct {
+  int n, W;
+  frame_t **fr;
+  size_t nf, cap;
+  uint64_t seed, nmeas;
+  uint8_t *out;
+  size_t nout, outcap;
+  int fragile;
+  int general;  /* coalesce through the basis circuit (the extension) */
+  size_t ortho_runs, coalesced;
+} mframe_t;
+
+static frame_t *frame_empty_like(const frame_t *src) {
+  frame_t *F = calloc(1, sizeof(frame_t));
+  tab_copy(&F->t, &src->t);
+  F->n = src->n; F->W = src->W;
+  frame_reserve(F, 1);
+  F->K = 0;
+  return F;
+}
+
+static void frame_push(frame_t *F, const uint64_t *sig, cplx a) {
+  frame_reserve(F, F->K + 1);
+  memcpy(SIG(F, F->K), sig, F->W * 8);
+  F->amp[F->K] = a;
+  F->K++;
+}
+
+static void frame_destroy(frame_t *F) { ofr_free(F); }
+
+static int tab_cmp(const tab_t *a, const tab_t *b) {
+  size_t words = (size_t)a->n * a->W;
+  for (size_t i = 0; i < (size_t)a->n; ++i) {
+    int c = memcmp(a->x + i * a->W, b->x + i * a->W, a->W * 8);
+    if (c) return c;
+    c = memcmp(a->z + i * a->W, b->z + i * a->W, a->W * 8);
+    if (c) return c;
+  }
+  (void)words;
+  return 0;
+}
+
+static void mf_push(mframe_t *M, frame_t *F) {
+  if (M->nf == M->cap) { M->cap = M->cap ? 2 * M->cap : 8; M->fr = realloc(M->fr, M->cap * sizeof(frame_t *)); }
+  M->fr[M->nf++] = F;
+}
+
+static int frame_ptr_cmp(const void *a, const void *b) {
+  const frame_t *x = *(frame_t *const *)a, *y = *(frame_t *const *)b;
+  return tab_cmp(&x->t, &y->t);
+}
+
+/* Merge frames with equal matrices, drop empty frames, sort by matrix. */
+static void mf_merge_equal(mframe_t *M) {
+  qsort(M->fr, M->nf, sizeof(frame_t *), frame_ptr_cmp);
+  size_t o = 0;
+  for (size_t i = 0; i < M->nf;) {
+    frame_t *F = M->fr[i];
+    size_t j = i + 1;
+    int grew = 0;
+    while (j < M->nf && tab_cmp(&M->fr[j]->t, &F->t) == 0) {
+      frame_t *G = M->fr[j];
+      for (size_t e = 0; e < G->K; ++e) frame_push(F, SIG(G, e), G->amp[e]);
+      frame_destroy(G);
+      grew = 1;
+      ++j;
+    }
+    if (grew) frame_merge(F);
+    if (F->fragile) M->fragile = 1;
+    if (F->K) M->fr[o++] = F;
+    else frame_destroy(F);
+    i = j;
+  }
+  M->nf = o;
+}
+
+/* COALESCE(F) (section 4): candidate pairs leave F and become the elements of
+ * new frames appended to M.  Returns the number of pairs coalesced. */
+static size_t frame_coalesce(frame_t *F, mframe_t *M) {
+  const int n = F->n, W = F->W;
+  uint64_t zr[8] = {0};
+  int *zq = malloc(sizeof(int) * (size_t)n);
+  for (int i = 0; i < n; ++i) {
+    int xany = 0, zc = 0;
+    for (int w = 0; w < W; ++w) { xany |= RX(&F->t, i)[w] != 0; zc += __builtin_popcountll(RZ(&F->t, i)[w]); }
+    zq[i] = (!xany && zc == 1) ? lowest_bit(RZ(&F->t, i), W) : -1;
+    if (zq[i] >= 0) setbit(zr, i, 1);
+  }
+  const size_t K = F->K;
+  long *part = malloc(sizeof(long) * (K ? K : 1));
+  int *dd = malloc(sizeof(int) * (K ? K : 1));
+  for (size_t j = 0; j < K; ++j) part[j] = -1;
+  size_t npairs = 0;
+  uint64_t diff[8];
+  for (size_t r = 0; r < K; ++r) {
+    if (part[r] >= 0) continue;
+    long best = -1;
+    int bestpop = 1 << 30, bestd = 0;
+    for (size_t j = r + 1; j < K; ++j) {
+      if (part[j] >= 0) continue;
+      int outside = 0, pop = 0, e1 = -1, v1 = 1 << 30;
+      for (int w = 0; w < W; ++w) {
+        diff[w] = SIG(F, r)[w] ^ SIG(F, j)[w];
+        outside |= (diff[w] & ~zr[w]) != 0;
+        pop += __builtin_popcountll(diff[w]);
+      }
+      if (outside || pop == 0 || pop >= bestpop) continue;
+      for (int i = 0; i < n; ++i)
+        if (getbit(diff, i) && zq[i] < v1) { v1 = zq[i]; e1 = i; }
+      /* r' has sign + on the Z_{v1} row */
+      size_t rp = getbit(SIG(F, r), e1) ? j : r, jp = rp == r ? j : r;
+      cplx ar = F->amp[rp], aj = F->amp[jp];
+      double mr = sqrt(ar.re * ar.re + ar.im * ar.im), mj = sqrt(aj.re * aj.re + aj.im * aj.im);
+      double tol = COAL_TOL * (mr > mj ? mr : mj);
+      for (int d = 0; d < 4; ++d) {
+        cplx t = cmul(ipow(d), ar);
+        if (fabs(aj.re - t.re) <= tol && fabs(aj.im - t.im) <= tol) {
+          best = (long)j; bestpop = pop; bestd = d;
+          break;
+        }
+      }
+    }
+    if (best >= 0) {
+      part[r] = best; part[best] = (long)r;
+      dd[r] = dd[best] = bestd;
+      ++npairs;
+    }
+  }
+  if (npairs) {
+    /* classes in order of their first pair (canonical order of r) */
+    uint8_t *done = calloc(K ? K : 1, 1);
+    for (size_t r = 0; r < K; ++r) {
+      if (part[r] < 0 || done[r] || (size_t)part[r] < r) continue;
+      uint64_t cls[8];
+      for (int w = 0; w < W; ++w) cls[w] = SIG(F, r)[w] ^ SIG(F, part[r])[w];
+      const int dcls = dd[r];
+      int v[512] = {0}, m = 0;
+      for (int i = 0; i < n; ++i) if (getbit(cls, i)) v[m++] = zq[i];
+      /* v ascending */
+      for (int a = 0; a < m; ++a)
+        for (int b = a + 1; b < m; ++b)
+          if (v[b] < v[a]) { int t = v[a]; v[a] = v[b]; v[b] = t; }
+      int e1 = -1;
+      for (int i = 0; i < n; ++i) if (getbit(cls, i) && zq[i] == v[0]) e1 = i;
+      frame_t *N = frame_empty_like(F);
+      for (size_t s = r; s < K; ++s) {
+        if (part[s] < 0 || done[s] || (size_t)part[s] < s || dd[s] != dcls) continue;
+        int same = 1;
+        for (int w = 0; w < W; ++w) same &= (SIG(F, s)[w] ^ SIG(F, part[s])[w]) == cls[w];
+        if (!same) continue;
+        size_t rp = getbit(SIG(F, s), e1) ? (size_t)part[s] : s;
+        frame_push(N, SIG(F, rp), cscale(F->amp[rp], sqrt(2.0)));
+        done[s] = done[part[s]] = 1;
+      }
+      frame_sort(N);
+      frame_clifford(N, OP_H, v[0], 0);
+      if (dcls == 1) frame_clifford(N, OP_S, v[0], 0);
+      else if (dcls == 2) frame_clifford(N, OP_Z, v[0], 0);
+      else if (dcls == 3) frame_clifford(N, OP_SDG, v[0], 0);
+      for (int l = 1; l < m; ++l) frame_clifford(N, OP_CNOT, v[0], v[l]);
+      if (N->fragile) M->fragile = 1;
+      mf_push(M, N);
+    }
+    free(done);
+    /* the unpaired elements stay */
+    size_t o = 0;
+    for (size_t j = 0; j < K; ++j) {
+      if (part[j] >= 0) continue;
+      memmove(SIG(F, o), SIG(F, j), W * 8);
+      F->amp[o] = F->amp[j];
+      ++o;
+    }
+    F->K = o;
+  }
+  free(part); free(dd); free(zq);
+  return npairs;
+}
+
+/* A stabilizer circuit C (gate list, applied in order) with C G C^dag =
+ * <Z_0, .., Z_{n-1}> for the unsigned group G of a canonical matrix
+ * (Corollary: every stabilizer matrix maps to the basis form of Figure 2a):
+ * CNOTs make every X-block row's x part its pivot alone, S and CZ clear its
+ * z part, H turns it into Z at the pivot, and CNOTs reduce the Z-type rows
+ * to single Z's.  Returns the number of gates (3 ints each: op, a, b). */
+static int basis_circuit(const tab_t *src, int *gates) {
+  tab_t t; tab_copy(&t, src);
+  int n = t.n, W = t.W, ng = 0, k = xblock(&t);
+  uint64_t f[8];
+#define EMIT(o, a, b) do { gates[3 * ng] = (o); gates[3 * ng + 1] = (a); gates[3 * ng + 2] = (b); ++ng; \
+                           clifford_columns(&t, (o), (a), (b), f); } while (0)
+  int *piv = malloc(sizeof(int) * (n ? n : 1));
+  for (int l = 0; l < k; ++l) piv[l] = lowest_bit(RX(&t, l), W);
+  for (int l = 0; l < k; ++l)
+    for (int j = 0; j < n; ++j)
+      if (j != piv[l] && getbit(RX(&t, l), j)) EMIT(OP_CNOT, piv[l], j);
+  for (int l = 0; l < k; ++l) {
+    if (getbit(RZ(&t, l), piv[l])) EMIT(OP_S, piv[l], 0);
+    for (int j = 0; j < n; ++j)
+      if (j != piv[l] && getbit(RZ(&t, l), j)) EMIT(OP_CZ, piv[l], j);
+  }
+  for (int l = 0; l < k; ++l) EMIT(OP_H, piv[l], 0);
+  /* now every row is Z-type: reduce, then clear each row off its pivot */
+  oplog L = {0};
+  canonicalize(&t, &L);
+  free(L.op);
+  for (int i = 0; i < n; ++i) {
+    int q = lowest_bit(RZ(&t, i), W);
+    for (int j = 0; j < n; ++j)
+      if (j != q && getbit(RZ(&t, i), j)) EMIT(OP_CNOT, j, q);
+  }
+#undef EMIT
+  for (int i = 0; i < n; ++i) {
+    int bad = 0;
+    for (int w = 0; w < W; ++w) bad |= RX(&t, i)[w] != 0;
+    if (bad || __builtin_popcountll(RZ(&t, i)[lowest_bit(RZ(&t, i), W) >> 6]) != 1) {
+      fprintf(stderr, "oracle: basis circuit left a row that is not a single Z\n");
+      abort();
+    }
+  }
+  free(piv);
+  tab_free(&t);
+  return ng;
+}
+
+static void frame_rotate(frame_t *F, const int *gates, int ng, int inverse) {
+  if (!inverse) {
+    for (int g = 0; g < ng; ++g) frame_clifford(F, gates[3 * g], gates[3 * g + 1], gates[3 * g + 2]);
+  } else {
+    for (int g = ng - 1; g >= 0; --g) {
+      int op = gates[3 * g];
+      if (op == OP_S) op = OP_SDG;
+      else if (op == OP_SDG) op = OP_S;
+      frame_clifford(F, op, gates[3 * g + 1], gates[3 * g + 2]);
+    }
+  }
+}
+
+/* The extension of COALESCE to matrices without Z_k rows (section 4): find
+ * C mapping M to the basis form, ROTATE(F, C), COALESCE, and ROTATE every
+ * resulting frame by C^dag. */
+static size_t frame_coalesce_general(frame_t *F, mframe_t *M) {
+  const int n = F->n;
+  int *gates = malloc(sizeof(int) * 3 * (size_t)(4 * n * n + 4 * n + 8));
+  int ng = basis_circuit(&F->t, gates);
+  frame_rotate(F, gates, ng, 0);
+  mframe_t tmp = {0};
+  tmp.n = M->n; tmp.W = M->W;
+  size_t made = frame_coalesce(F, &tmp);
+  frame_rotate(F, gates, ng, 1);
+  for (size_t i = 0; i < tmp.nf; ++i) {
+    frame_rotate(tmp.fr[i], gates, ng, 1);
+    if (tmp.fr[i]->fragile) M->fragile = 1;
+    mf_push(M, tmp.fr[i]);
+  }
+  if (F->fragile) M->fragile = 1;
+  free(tmp.fr);
+  free(gates);
+  return made;
+}
+
+static void mf_coalesce_all(mframe_t *M) {
+  for (;;) {
+    size_t made = 0, nf0 = M->nf;
+    for (size_t i = 0; i < nf0; ++i)
+      made += M->general ? frame_coalesce_general(M->fr[i], M) : frame_coalesce(M->fr[i], M);
+    mf_merge_equal(M);
+    M->coalesced += made;
+    if (!made) break;
+  }
+}
+
+/* Sign of the product of the rows of `t` selected by mask c, as
+ * sign(prod_i in c (-1)^{sig_i} row_i) = sig.c ^ kappa(c): kappa from the
+ * Pauli products (Table 1) of the unsigned rows, applied left to right. */
+static int product_kappa(tab_t *t, const uint64_t *c, uint64_t *px, uint64_t *pz) {
+  int W = t->W, e = 0;
+  memset(px, 0, W * 8); memset(pz, 0, W * 8);
+  for (int i = 0; i < t->n; ++i) {
+    if (!getbit(c, i)) continue;
+    for (int q = 0; q < t->n; ++q)
+      e += pauli_g(getbit(px, q), getbit(pz, q), getbit(RX(t, i), q), getbit(RZ(t, i), q));
+    for (int w = 0; w < W; ++w) { px[w] ^= RX(t, i)[w]; pz[w] ^= RZ(t, i)[w]; }
+  }
+  e = ((e % 4) + 4) % 4;
+  if (e & 1) { fprintf(stderr, "oracle: non-Hermitian product\n"); abort(); }
+  return e >> 1;
+}
+
+/* Basis of the intersection of the unsigned groups of two canonical
+ * matrices: for each basis element t, the row masks cA[t], cB[t] and the
+ * constants kA[t], kB[t].  Returns the number of basis elements. */
+static int intersection(tab_t *A, tab_t *B, uint64_t *cA, uint64_t *cB, int *kA, int *kB) {
+  int n = A->n, W = A->W;
+  /* pivots of A (fully reduced: row i's pivot column) */
+  int *pa = malloc(sizeof(int) * n);
+  for (int i = 0; i < n; ++i) {
+    pa[i] = -1;
+    for (int col = 0; col < 2 * n && pa[i] < 0; ++col) if (colbit(A, i, col)) pa[i] = col;
+  }
+  /* residuals of B's rows against A, with the combination tracked */
+  uint64_t *rx = calloc((size_t)n * W, 8), *rz = calloc((size_t)n * W, 8), *cb = calloc((size_t)n * W, 8);
+  for (int j = 0; j < n; ++j) {
+    memcpy(rx + (size_t)j * W, RX(B, j), W * 8);
+    memcpy(rz + (size_t)j * W, RZ(B, j), W * 8);
+    for (int i = 0; i < n; ++i) {
+      int col = pa[i];
+      int bit = col < n ? getbit(rx + (size_t)j * W, col) : getbit(rz + (size_t)j * W, col - n);
+      if (bit)
+        for (int w = 0; w < W; ++w) { rx[(size_t)j * W + w] ^= RX(A, i)[w]; rz[(size_t)j * W + w] ^= RZ(A, i)[w]; }
+    }
+    setbit(cb + (size_t)j * W, j, 1);
+  }
+  /* null space of the residuals: eliminate, tracking combinations */
+  int r = 0;
+  for (int col = 0; col < 2 * n; ++col) {
+    int p = -1;
+    for (int j = r; j < n; ++j) {
+      int bit = col < n ? getbit(rx + (size_t)j * W, col) : getbit(rz + (size_t)j * W, col - n);
+      if (bit) { p = j; break; }
+    }
+    if (p < 0) continue;
+    for (int w = 0; w < W; ++w) {
+      uint64_t t;
+      t = rx[(size_t)p * W + w]; rx[(size_t)p * W + w] = rx[(size_t)r * W + w]; rx[(size_t)r * W + w] = t;
+      t = rz[(size_t)p * W + w]; rz[(size_t)p * W + w] = rz[(size_t)r * W + w]; rz[(size_t)r * W + w] = t;
+      t = cb[(size_t)p * W + w]; cb[(size_t)p * W + w] = cb[(size_t)r * W + w]; cb[(size_t)r * W + w] = t;
+    }
+    for (int j = 0; j < n; ++j) {
+      if (j == r) continue;
+      int bit = col < n ? getbit(rx + (size_t)j * W, col) : getbit(rz + (size_t)j * W, col - n);
+      if (bit)
+        for (int w = 0; w < W; ++w) {
+          rx[(size_t)j * W + w] ^= rx[(size_t)r * W + w];
+          rz[(size_t)j * W + w] ^= rz[(size_t)r * W + w];
+          cb[(size_t)j * W + w] ^= cb[(size_t)r * W + w];
+        }
+    }
+    ++r;
+  }
+  int nb = 0;
+  uint64_t gx[8], gz[8];
+  for (int j = r; j < n; ++j) {
+    /* combination cb[j] of B's rows lies in span(A) */
+    memcpy(cB + (size_t)nb * W, cb + (size_t)j * W, W * 8);
+    kB[nb] = product_kappa(B, cB + (size_t)nb * W, gx, gz);
+    memset(cA + (size_t)nb * W, 0, W * 8);
+    for (int i = 0; i < n; ++i) {
+      int col = pa[i];
+      if (col < n ? getbit(gx, col) : getbit(gz, col - n)) setbit(cA + (size_t)nb * W, i, 1);
+    }
+    uint64_t hx[8], hz[8];
+    kA[nb] = product_kappa(A, cA + (size_t)nb * W, hx, hz);
+    for (int w = 0; w < W; ++w)
+      if (hx[w] != gx[w] || hz[w] != gz[w]) { fprintf(stderr, "oracle: intersection element outside span\n"); abort(); }
+    ++nb;
+  }
+  free(pa); free(rx); free(rz); free(cb);
+  return nb;
+}
+
+/* Invariant 2 between two frames: every state of A is orthogonal to every
+ * state of B (frames with distinct matrices). */
+static int frames_orthogonal(frame_t *A, frame_t *B) {
+  int n = A->n, W = A->W;
+  uint64_t *cA = calloc((size_t)n * W, 8), *cB = calloc((size_t)n * W, 8);
+  int *kA = malloc(sizeof(int) * n), *kB = malloc(sizeof(int) * n);
+  int nb = intersection(&A->t, &B->t, cA, cB, kA, kB);
+  int ok = 1;
+  for (size_t i = 0; i < A->K && ok; ++i)
+    for (size_t j = 0; j < B->K && ok; ++j) {
+      int differ = 0;
+      for (int t = 0; t < nb && !differ; ++t)
+        differ = (parity_and(SIG(A, i), cA + (size_t)t * W, W) ^ kA[t]) !=
+                 (parity_and(SIG(B, j), cB + (size_t)t * W, W) ^ kB[t]);
+      if (!differ) ok = 0;
+    }
+  free(cA); free(cB); free(kA); free(kB);
+  return ok;
+}
+
+static int mf_orthogonal(mframe_t *M) {
+  for (size_t a = 0; a < M->nf; ++a)
+    for (size_t b = a + 1; b < M->nf; ++b)
+      if (!frames_orthogonal(M->fr[a], M->fr[b])) return 0;
+  return 1;
+}
+
+/* literal set of column q of a matrix: bit 0 I, 1 Z, 2 X, 3 Y present */
+static int literal_set(tab_t *t, int q) {
+  int s = 0;
+  for (int i = 0; i < t->n; ++i) s |= 1 << (2 * getbit(RX(t, i), q) + getbit(RZ(t, i), q));
+  return s;
+}
+
+static int column_differs(tab_t *a, tab_t *b, int q) {
+  for (int i = 0; i < a->n; ++i)
+    if (getbit(RX(a, i), q) != getbit(RX(b, i), q) || getbit(RZ(a, i), q) != getbit(RZ(b, i), q)) return 1;
+  return 0;
+}
+
+/* Orthogonalization (section 4): cofactor every frame on a pivot qubit and
+ * merge frames with equal matrices until one frame remains. */
+static void mf_orthogonalize(mframe_t *M) {
+  const cplx one = {1.0, 0.0};
+  M->ortho_runs++;
+  while (M->nf > 1) {
+    int p = -1;
+    for (int q = 0; q < M->n && p < 0; ++q) {
+      int s0 = literal_set(&M->fr[0]->t, q);
+      for (size_t i = 1; i < M->nf && p < 0; ++i) if (literal_set(&M->fr[i]->t, q) != s0) p = q;
+    }
+    for (int q = 0; q < M->n && p < 0; ++q)
+      for (size_t i = 1; i < M->nf && p < 0; ++i) if (column_differs(&M->fr[0]->t, &M->fr[i]->t, q)) p = q;
+    if (p < 0) break; /* equal matrices: merged below */
+    for (size_t i = 0; i < M->nf; ++i) frame_cofactor(M->fr[i], p, one, 0);
+    mf_merge_equal(M);
+  }
+  mf_merge_equal(M);
+}
+
+static int mf_measure(mframe_t *M, int q) {
+  const cplx one = {1.0, 0.0};
+  int W = M->W;
+  for (size_t i = 0; i < M->nf; ++i) frame_cofactor(M->fr[i], q, one, 0);
+  mf_merge_equal(M);
+  if (!mf_orthogonal(M)) mf_orthogonalize(M);
+  size_t tot = 0;
+  for (size_t i = 0; i < M->nf; ++i) tot += M->fr[i]->K;
+  double *v1 = malloc(sizeof(double) * (tot ? tot : 1)), *v0 = malloc(sizeof(double) * (tot ? tot : 1));
+  uint64_t rq[8];
+  size_t k = 0;
+  for (size_t i = 0; i < M->nf; ++i) {
+    frame_t *F = M->fr[i];
+    if (!zq_rows(&F->t, q, rq)) abort();
+    for (size_t j = 0; j < F->K; ++j, ++k) {
+      int x = parity_and(SIG(F, j), rq, W);
+      volatile double rr = F->amp[j].re * F->amp[j].re;
+      volatile double ii = F->amp[j].im * F->amp[j].im;
+      double m2 = rr + ii;
+      v1[k] = x ? m2 : 0.0;
+      v0[k] = x ? 0.0 : m2;
+    }
+  }
+  double p1 = tree_sum(v1, tot), p0 = tree_sum(v0, tot);
+  free(v1); free(v0);
+  double u = (double)(sm64(M->seed, M->nmeas) >> 11) * (1.0 / 9007199254740992.0);
+  M->nmeas++;
+  if (fabs(u - p1) < FRAGILE_COIN) M->fragile = 1;
+  int outcome = u < p1;
+  double s = 1.0 / sqrt(outcome ? p1 : p0);
+  for (size_t i = 0; i < M->nf; ++i) {
+    frame_t *F = M->fr[i];
+    zq_rows(&F->t, q, rq);
+    size_t o = 0;
+    for (size_t j = 0; j < F->K; ++j) {
+      if (parity_and(SIG(F, j), rq, W) != outcome) continue;
+      memmove(SIG(F, o), SIG(F, j), W * 8);
+      F->amp[o] = cscale(F->amp[j], s);
+      ++o;
+    }
+    F->K = o;
+  }
+  mf_merge_equal(M);
+  if (M->nout == M->outcap) { M->outcap = M->outcap ? 2 * M->outcap : 16; M->out = realloc(M->out, M->outcap); }
+  M->out[M->nout++] = (uint8_t)outcome;
+  return outcome;
+}
+
+mframe_t *omf_new(int n, const uint8_t *init_bits, uint64_t seed) {
+  frame_t *F = ofr_new(n, init_bits, seed);
+  if (!F) return NULL;
+  mframe_t *M = calloc(1, sizeof(mframe_t));
+  M->n = n; M->W = F->W; M->seed = seed;
+  mf_push(M, F);
+  return M;
+}
+
+void omf_free(mframe_t *M) {
+  if (!M) return;
+  for (size_t i = 0; i < M->nf; ++i) frame_destroy(M->fr[i]);
+  free(M->fr); free(M->out); free(M);
+}
+
+static int is_cofactoring(int op, int64_t num, int64_t den) {
+  int which;
+  if (op == OP_T || op == OP_TDG) return 1;
+  if (op == OP_PHASE) { if (den < 0) { num = -num; den = -den; } return !is_clifford_angle(num, den, &which); }
+  if (op == OP_CPHASE_D) { if (den < 0) { num = -num; den = -den; } return num % den != 0; }
+  return op == OP_TOF_D;
+}
+
+/* Apply one gate to a multiframe; returns the outcome of MEASURE, else 0;
+ * -1 on an invalid gate. */
+int omf_apply(mframe_t *M, int op, int q0, int q1, int q2, int64_t num, int64_t den) {
+  int n = M->n;
+  if (q0 < 0 || q0 >= n) return -1;
+  if (op == OP_MEASURE) return mf_measure(M, q0);
+  if (op == OP_TOF) {
+    if (q1 < 0 || q1 >= n || q2 < 0 || q2 >= n || q1 == q0 || q2 == q0 || q2 == q1) return -1;
+    int c1 = q0, c2 = q1, t = q2;
+    omf_apply(M, OP_H, t, 0, 0, 0, 1);
+    omf_apply(M, OP_CNOT, c2, t, 0, 0, 1); omf_apply(M, OP_TDG, t, 0, 0, 0, 1);
+    omf_apply(M, OP_CNOT, c1, t, 0, 0, 1); omf_apply(M, OP_T, t, 0, 0, 0, 1);
+    omf_apply(M, OP_CNOT, c2, t, 0, 0, 1); omf_apply(M, OP_TDG, t, 0, 0, 0, 1);
+    omf_apply(M, OP_CNOT, c1, t, 0, 0, 1); omf_apply(M, OP_T, c2, 0, 0, 0, 1); omf_apply(M, OP_T, t, 0, 0, 0, 1);
+    omf_apply(M, OP_H, t, 0, 0, 0, 1);
+    omf_apply(M, OP_CNOT, c1, c2, 0, 0, 1); omf_apply(M, OP_T, c1, 0, 0, 0, 1); omf_apply(M, OP_TDG, c2, 0, 0, 0, 1);
+    omf_apply(M, OP_CNOT, c1, c2, 0, 0, 1);
+    return 0;
+  }
+  if (op == OP_CPHASE) {
+    if (den == 0 || q1 < 0 || q1 >= n || q1 == q0) return -1;
+    omf_apply(M, OP_PHASE, q1, 0, 0, num, 2 * den);
+    omf_apply(M, OP_CNOT, q0, q1, 0, 0, 1);
+    omf_apply(M, OP_PHASE, q1, 0, 0, -num, 2 * den);
+    omf_apply(M, OP_CNOT, q0, q1, 0, 0, 1);
+    omf_apply(M, OP_PHASE, q0, 0, 0, num, 2 * den);
+    return 0;
+  }
+  for (size_t i = 0; i < M->nf; ++i)
+    if (ofr_apply(M->fr[i], op, q0, q1, q2, num, den) < 0) return -1;
+  for (size_t i = 0; i < M->nf; ++i) if (M->fr[i]->fragile) M->fragile = 1;
+  if (is_cofactoring(op, num, den)) mf_coalesce_all(M);
+  else mf_merge_equal(M);
+  return 0;
+}
+
+int omf_run(mframe_t *M, const int32_t *ops, const int32_t *q, const int64_t *num, const int64_t *den,
+            size_t ngates, uint64_t *sizes, uint64_t *nframes) {
+  for (size_t g = 0; g < ngates; ++g) {
+    size_t tot = 0;
+    for (size_t i = 0; i < M->nf; ++i) tot += M->fr[i]->K;
+    if (sizes) sizes[g] = tot;
+    if (nframes) nframes[g] = M->nf;
+    if (omf_apply(M, ops[g], q[3 * g], q[3 * g + 1], q[3 * g + 2], num[g], den[g]) < 0) return -1;
+  }
+  return 0;
+}
+
+size_t omf_nframes(mframe_t *M) { return M->nf; }
+size_t omf_frame_size(mframe_t *M, size_t i) { return i < M->nf ? M->fr[i]->K : 0; }
+size_t omf_read(mframe_t *M, size_t i, uint64_t *tableau, uint64_t *sigma, double *amp, size_t cap) {
+  if (i >= M->nf) return 0;
+  return ofr_read(M->fr[i], tableau, sigma, amp, cap);
+}
+int omf_fragile(mframe_t *M) { return M->fragile; }
+int omf_orthogonal(mframe_t *M) { return mf_orthogonal(M); }
+size_t omf_ortho_runs(mframe_t *M) { return M->ortho_runs; }
+size_t omf_outcomes(mframe_t *M, uint8_t *out, size_t cap) {
+  size_t m = M->nout < cap ? M->nout : cap;
+  if (out && m) memcpy(out, M->out, m);
+  return M->nout;
+}
+
+/* A multiframe of one frame given explicitly (canonical matrix, sorted
+ * distinct phase vectors, amplitudes): for pinning the frame operations. */
+mframe_t *omf_load(int n, const uint64_t *tableau, const uint64_t *sigma, const double *amp, size_t K,
+                   uint64_t seed) {
+  mframe_t *M = omf_new(n, NULL, seed);
+  if (!M) return NULL;
+  frame_t *F = M->fr[0];
+  int W = F->W;
+  for (int i = 0; i < n; ++i) {
+    memcpy(RX(&F->t, i), tableau + (size_t)i * 2 * W, W * 8);
+    memcpy(RZ(&F->t, i), tableau + (size_t)i * 2 * W + W, W * 8);
+  }
+  F->K = 0;
+  for (size_t j = 0; j < K; ++j) {
+    cplx a = {amp[2 * j], amp[2 * j + 1]};
+    frame_push(F, sigma + j * W, a);
+  }
+  frame_sort(F);
+  return M;
+}
+
+/* COALESCE on every frame and the merge of equal matrices, until no pair is
+ * left (the step run after every cofactoring gate); returns the pairs. */
+size_t omf_coalesce(mframe_t *M) {
+  size_t before = M->coalesced;
+  mf_coalesce_all(M);
+  return M->coalesced - before;
+}
+
+/* Invariant 2 check and, if it fails, the orthogonalization. */
+int omf_orthogonalize(mframe_t *M) {
+  if (mf_orthogonal(M)) return 0;
+  mf_orthogonalize(M);
+  return 1;
+}
+
+/* Append one explicit frame (canonical matrix, distinct phase vectors,
+ * amplitudes) to a multiframe; frames with equal matrices merge. */
+int omf_add_frame(mframe_t *M, const uint64_t *tableau, const uint64_t *sigma, const double *amp, size_t K) {
+  frame_t *F = frame_empty_like(M->fr[0]);
+  int W = F->W;
+  for (int i = 0; i < M->n; ++i) {
+    memcpy(RX(&F->t, i), tableau + (size_t)i * 2 * W, W * 8);
+    memcpy(RZ(&F->t, i), tableau + (size_t)i * 2 * W + W, W * 8);
+  }
+  for (size_t j = 0; j < K; ++j) {
+    cplx a = {amp[2 * j], amp[2 * j + 1]};
+    frame_push(F, sigma + j * W, a);
+  }
+  frame_sort(F);
+  mf_push(M, F);
+  mf_merge_equal(M);
+  return 0;
+}
+
+/* Choose the basic COALESCE (0: Z_k rows of the matrix as it is) or its
+ * extension through the basis circuit (1). */
+void omf_set_general(mframe_t *M, int general) { M->general = general; }

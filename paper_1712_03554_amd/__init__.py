@@ -130,7 +130,11 @@ def _ptr(a):
 class Engine:
     """A library context bound to one HIP device and stream."""
 
-    def __init__(self, device: int = 0, stream=None, budget_bytes: int = 0, torch_allocator: bool = True):
+    def __init__(self, device: int = 0, stream=None, budget_bytes: int = 0, torch_allocator: bool = True,
+                 refuse=None):
+        """refuse: optional predicate on a request's byte count; requests it
+        accepts are answered with NULL (device allocation failure), as an
+        allocator that has run out would."""
         self._L = load_library()
         self._keep = []
         stream_ptr = None
@@ -148,6 +152,8 @@ class Engine:
                 dev = device
 
                 def _alloc(nbytes, stream, user):
+                    if refuse is not None and refuse(int(nbytes)):
+                        return None
                     try:
                         return torch.cuda.caching_allocator_alloc(int(nbytes), dev, s)
                     except Exception:
@@ -334,7 +340,7 @@ class State:
         """(tableau[n, 2W] uint64, sigma[K, W] uint64, amp[K] complex128), canonical order."""
         K = ctypes.c_size_t()
         tab = np.zeros((self.n, 2 * self.W), dtype=np.uint64)
-        st = self._L.sf_read_frame(self._h, _ptr(tab), None, None, 0, ctypes.byref(K))
+        st = self._L.sf_read_frame(self._h, None, None, None, 0, ctypes.byref(K))
         if st not in (SF_OK, SF_E_BUFSIZE):
             self._check(st)
         k = K.value

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <new>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/sframe.h"
@@ -1072,7 +1073,7 @@ extern "C" sf_status sf_read_frame(sf_state* s, uint64_t* tableau, uint64_t* sig
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(&K, total.p, 8, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e == hipSuccess && tableau) {
+  if (e == hipSuccess && tableau && K <= cap) {
     std::vector<uint64_t> tab((size_t)n * 2 * W);
     e = hipMemcpy(tab.data(), (char*)s->ri.p + offsetof(ReadoutInfo, tab), tab.size() * 8, hipMemcpyDeviceToHost);
     if (e == hipSuccess) memcpy(tableau, tab.data(), tab.size() * 8);
@@ -1221,13 +1222,16 @@ struct RoundPlan {
 };
 
 // Plans the next round from the progress pr[] and advances it; false when no
-// frame has work left.  seedp[i] (optional) is where frame i's seed is read.
+// frame has work left or on an error (*err set; *bad = index of the state
+// that caused it, or -1).  seedp[i] (optional) is where frame i's seed is
+// read.  Nothing is queued before an error.
 static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap, const uint64_t* const* seedp,
-                       RoundPlan* rp, sf_status* err) {
+                       RoundPlan* rp, sf_status* err, int* bad = nullptr) {
   std::vector<int> act;
   std::vector<size_t> A(ns), B(ns), O(ns);
   std::vector<int> NS(ns), ML(ns), CL(ns);
   *err = SF_OK;
+  if (bad) *bad = -1;
   for (size_t i = 0; i < ns; ++i) {
     const sf_circuit* c = states[i]->c;
     if (pr[i].orig_done >= c->orig_end.size()) continue;
@@ -1235,6 +1239,7 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
     if (ML[i] && pr[i].nmeas + 1 > states[i]->meas_cap) {
       *err = fail(states[i]->ctx, SF_E_STATE, "state %zu: outcome buffer holds %zu measurements", i,
                   states[i]->meas_cap);
+      if (bad) *bad = (int)i;
       return false;
     }
     act.push_back((int)i);
@@ -1277,10 +1282,14 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
     if (NS[i] > s->c->max_segs || B[i] - A[i] > (size_t)s->c->rec_len) {
       *err = fail(s->ctx, SF_E_STATE, "state %d: range of %zu gates with %d segments exceeds its buffers", i,
                   B[i] - A[i], NS[i]);
+      if (bad) *bad = i;
       return false;
     }
     const bool use = split_form(s->c->n) || rp->wcount[words_of(s->c->n)] <= SF_SPLIT_WIDE_MAX;
-    if (use && (*err = ensure_split_buffers(s)) != SF_OK) return false;
+    if (use && (*err = ensure_split_buffers(s)) != SF_OK) {
+      if (bad) *bad = i;
+      return false;
+    }
     split_fields(s, &jb, NS[i], use);
     const int wi = words_of(s->c->n);
     rp->wlen[wi] = std::max(rp->wlen[wi], (int)(B[i] - A[i]));
@@ -1412,14 +1421,16 @@ static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs
 // scratch must be large enough.
 // staged: the descriptors go through pinned memory (the caller synchronises
 // the stream and releases it before the next batch).
+// *bad (optional) receives the index of the state that made planning fail
+// (nothing was queued then), or -1.
 static sf_status batch_round(sf_ctx* ctx, sf_state* const* states, size_t ns, BatchScratch* bs, int* active,
-                             int cap = 0, bool staged = false) {
+                             int cap = 0, bool staged = false, int* bad = nullptr) {
   std::vector<Progress> pr(ns);
   for (size_t i = 0; i < ns; ++i) pr[i] = progress_of(states[i]);
   RoundPlan rp;
   sf_status err;
   *active = 0;
-  if (!plan_round(states, ns, pr.data(), cap, nullptr, &rp, &err)) return err;
+  if (!plan_round(states, ns, pr.data(), cap, nullptr, &rp, &err, bad)) return err;
   *active = rp.na;
   if (staged) {
     const size_t bj = rp.na * sizeof(TrackJob), bd = rp.desc.size() * sizeof(ElemDesc);
@@ -1832,8 +1843,14 @@ struct ServeJob {
   std::vector<uint64_t> basis;
   uint64_t seed;
   sf_state* st;
-  int status;  // 0 queued, 1 resident, 2 done, 3 cancelled, 4 failed
+  int status;       // 0 queued, 1 resident, 2 done, 3 cancelled, 4 failed
+  uint32_t passed;  // ticks in which a later job was admitted ahead of it
 };
+
+// A queued job that does not fit yet may be passed by later jobs that do, for
+// at most this many ticks; after that nothing behind it is admitted until it
+// is (so a large job is not starved by a stream of small ones).
+#define SF_SERVE_MAX_PASS 16
 
 struct sf_server {
   sf_ctx* ctx;
@@ -1843,7 +1860,7 @@ struct sf_server {
   uint64_t next_id;
   std::vector<ServeJob*> queue;     // waiting, arrival order
   std::vector<ServeJob*> resident;  // admitted, running
-  std::vector<ServeJob*> all;
+  std::unordered_map<uint64_t, ServeJob*> jobs;  // every job not yet released
   BatchScratch bs;
   uint64_t ticks, admitted, rejected;
 };
@@ -1865,9 +1882,8 @@ extern "C" sf_status sf_serve_create(sf_ctx* ctx, uint64_t budget_bytes, uint32_
 }
 
 static ServeJob* find_job(sf_server* sv, uint64_t id) {
-  for (ServeJob* j : sv->all)
-    if (j->id == id) return j;
-  return nullptr;
+  auto it = sv->jobs.find(id);
+  return it == sv->jobs.end() ? nullptr : it->second;
 }
 
 extern "C" sf_status sf_serve_submit(sf_server* sv, const sf_circuit* c, const uint64_t* basis, uint64_t seed,
@@ -1889,38 +1905,80 @@ extern "C" sf_status sf_serve_submit(sf_server* sv, const sf_circuit* c, const u
   j->seed = seed;
   j->st = nullptr;
   j->status = 0;
+  j->passed = 0;
   sv->queue.push_back(j);
-  sv->all.push_back(j);
+  sv->jobs[j->id] = j;
   *job_id = j->id;
   return SF_OK;
+}
+
+// Admission: queued jobs in arrival order, each admitted when its projected
+// bytes fit the budget and a resident slot is free.  A job that does not fit
+// is passed over (later jobs may still be admitted) unless it has been passed
+// SF_SERVE_MAX_PASS times.  A job whose state cannot be allocated waits while
+// others are resident (they will free memory) and fails when none is.
+static void serve_admit(sf_server* sv) {
+  sf_ctx* ctx = sv->ctx;
+  std::vector<ServeJob*> waiting;
+  bool blocked = false;  // an old job is waiting: admit nothing behind it
+  bool passed = false;   // a job was admitted ahead of the oldest waiting one
+  ServeJob* first_passed = nullptr;
+  for (size_t qi = 0; qi < sv->queue.size(); ++qi) {
+    ServeJob* j = sv->queue[qi];
+    bool fits = !blocked && sv->resident.size() < sv->max_resident &&
+                !(sv->budget && sv->used + j->c->projected > sv->budget);
+    if (fits) {
+      sf_status rc = sf_state_init(ctx, j->c, j->basis.data(), j->seed, &j->st);
+      if ((rc == SF_E_OOM || rc == SF_E_TOO_LARGE) && !sv->resident.empty()) {
+        fits = false;
+      } else if (rc != SF_OK) {
+        j->st = nullptr;
+        j->status = 4;
+        continue;
+      }
+    }
+    if (!fits) {
+      waiting.push_back(j);
+      if (!first_passed) first_passed = j;
+      if (j->passed >= SF_SERVE_MAX_PASS) blocked = true;
+      continue;
+    }
+    j->status = 1;
+    sv->used += j->c->projected;
+    sv->admitted++;
+    sv->resident.push_back(j);
+    passed |= first_passed != nullptr;
+  }
+  if (passed) first_passed->passed++;
+  sv->queue.swap(waiting);
+}
+
+// A resident job whose round could not be planned (its buffers could not be
+// allocated, or it ran out of room): it fails, keeps its budget share until
+// released, and the others go on.
+static void serve_fail_resident(sf_server* sv, size_t idx) {
+  ServeJob* j = sv->resident[idx];
+  j->status = 4;
+  sv->resident.erase(sv->resident.begin() + (long)idx);
 }
 
 extern "C" sf_status sf_serve_tick(sf_server* sv, uint32_t* n_resident, uint32_t* n_queued) {
   if (!sv) return SF_E_INVALID;
   sf_ctx* ctx = sv->ctx;
-  // admission in arrival order
-  size_t qi = 0;
-  while (qi < sv->queue.size() && sv->resident.size() < sv->max_resident) {
-    ServeJob* j = sv->queue[qi];
-    if (sv->budget && sv->used + j->c->projected > sv->budget) break;
-    sf_status rc = sf_state_init(ctx, j->c, j->basis.data(), j->seed, &j->st);
-    // out of device memory: wait for resident jobs to free some; with none
-    // resident, waiting cannot help and the job fails
-    if ((rc == SF_E_OOM || rc == SF_E_TOO_LARGE) && !sv->resident.empty()) break;
-    if (rc != SF_OK) { j->status = 4; sv->queue.erase(sv->queue.begin() + qi); continue; }
-    j->status = 1;
-    sv->used += j->c->projected;
-    sv->admitted++;
-    sv->resident.push_back(j);
-    sv->queue.erase(sv->queue.begin() + qi);
-  }
-  if (!sv->resident.empty()) {
+  serve_admit(sv);
+  while (!sv->resident.empty()) {
     std::vector<sf_state*> sts;
     int maxseg = 1;
     for (ServeJob* j : sv->resident) { sts.push_back(j->st); maxseg = std::max(maxseg, j->c->max_segs); }
     sf_status rc = scratch_reserve(ctx, &sv->bs, sts.size(), maxseg);
-    int active = 0;
-    if (rc == SF_OK) rc = batch_round(ctx, sts.data(), sts.size(), &sv->bs, &active, sv->tick_segments);
+    if (rc != SF_OK) return rc;
+    int active = 0, bad = -1;
+    rc = batch_round(ctx, sts.data(), sts.size(), &sv->bs, &active, sv->tick_segments, false, &bad);
+    if (rc != SF_OK && bad >= 0) {
+      // nothing was queued: drop the offending job and plan again
+      serve_fail_resident(sv, (size_t)bad);
+      continue;
+    }
     hipError_t e = hipStreamSynchronize(ctx->stream);
     sv->bs.keep_jobs.clear();
     sv->bs.keep_desc.clear();
@@ -1935,6 +1993,7 @@ extern "C" sf_status sf_serve_tick(sf_server* sv, uint32_t* n_resident, uint32_t
       }
     }
     sv->resident.swap(still);
+    break;
   }
   sv->ticks++;
   if (n_resident) *n_resident = (uint32_t)sv->resident.size();
@@ -1964,8 +2023,7 @@ extern "C" sf_status sf_serve_release(sf_server* sv, uint64_t job_id) {
   }
   for (size_t i = 0; i < sv->queue.size(); ++i)
     if (sv->queue[i] == j) { sv->queue.erase(sv->queue.begin() + i); break; }
-  for (size_t i = 0; i < sv->all.size(); ++i)
-    if (sv->all[i] == j) { sv->all.erase(sv->all.begin() + i); break; }
+  sv->jobs.erase(j->id);
   delete j;
   return SF_OK;
 }
@@ -2003,9 +2061,9 @@ extern "C" sf_status sf_serve_stats(sf_server* sv, uint64_t* ticks, uint64_t* ad
 
 extern "C" sf_status sf_serve_destroy(sf_server* sv) {
   if (!sv) return SF_OK;
-  for (ServeJob* j : sv->all) {
-    if (j->st) sf_state_destroy(j->st);
-    delete j;
+  for (auto& kv : sv->jobs) {
+    if (kv.second->st) sf_state_destroy(kv.second->st);
+    delete kv.second;
   }
   scratch_free(sv->ctx, &sv->bs);
   delete sv;

@@ -62,3 +62,45 @@ def oracle_vs_dense(circ, seed: int = 0, every_gate: bool = True):
     assert f.outcomes() == outs
     assert not f.fragile
     return f
+
+
+def oracle_config4(job: int):
+    """The oracle's result for uneven circuit `job` (tableau, sigma, amplitudes,
+    outcomes, fragile flag); a top-level function so that a process pool can
+    run it."""
+    from paper_1712_03554_amd import workloads as wl
+    c = wl.config4(job)
+    f = OracleFrame(c.n, c.init_bits, wl.derive_seed(4, job))
+    f.run(c.array())
+    tab, sig, amp = f.read()
+    return tab, sig, amp, f.outcomes(), f.fragile
+
+
+def oracle_config2(job: int):
+    """As oracle_config4, for the n = 128 Clifford+T circuit `job`."""
+    from paper_1712_03554_amd import workloads as wl
+    c = wl.config2(job)
+    f = OracleFrame(c.n, c.init_bits, wl.derive_seed(2, job))
+    f.run(c.array())
+    tab, sig, amp = f.read()
+    return tab, sig, amp, f.outcomes(), f.fragile
+
+
+def oracle_pool(workers: int = 16):
+    """A process pool for oracle runs (spawned: no state of the parent's GPU
+    runtime is inherited), at most `workers` processes."""
+    import multiprocessing as mp
+    import os
+    from concurrent.futures import ProcessPoolExecutor
+    n = max(1, min(workers, os.cpu_count() or 1))
+    return ProcessPoolExecutor(max_workers=n, mp_context=mp.get_context("spawn"))
+
+
+def assert_frame_arrays_equal(sig_a, amp_a, sig_b, amp_b, what=""):
+    """As assert_frames_equal, on (K, W) word arrays without conversion to
+    integers (for frames of millions of elements)."""
+    assert sig_a.shape == sig_b.shape, f"{what}: {sig_a.shape[0]} vs {sig_b.shape[0]} elements"
+    assert np.array_equal(sig_a, sig_b), f"{what}: phase vectors differ"
+    err = np.abs(np.asarray(amp_a) - np.asarray(amp_b))
+    bound = AMP_RTOL * np.abs(amp_b) + AMP_ATOL
+    assert np.all(err <= bound), f"{what}: amplitude mismatch, worst {np.max(err / bound)} x bound"

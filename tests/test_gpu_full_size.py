@@ -6,9 +6,8 @@ the graph form), checked against the oracle (needs an MI355X).
   measurements (the headline step): every frame against the oracle.
 * 4096 Steane fault-injection trials: every trial against the oracle.
 * 1024 uneven random Clifford+T circuits (n in 16..256, up to 12 T): every
-  frame's norm and size bound; the oracle on all circuits of at most 72
-  qubits and on the two narrowest of each wider word count (the oracle's
-  per-gate elimination makes the 200-qubit circuits take seconds each).
+  frame against the oracle (run in a process pool while the GPU works), and
+  every frame's norm and size bound.
 * The large frame (Cuccaro adder, m = 12, on an equal superposition: 2^26
   elements): every qubit measured afterwards gives a consistent addition.
 
@@ -19,7 +18,8 @@ import pytest
 
 from oracle.frame import OracleFrame
 from paper_1712_03554_amd import workloads as wl
-from tests.oracle_helpers import assert_frames_equal, sigma_ints
+from tests.oracle_helpers import (assert_frame_arrays_equal, assert_frames_equal, oracle_config4, oracle_pool,
+                                  sigma_ints)
 
 pytestmark = pytest.mark.gpu
 
@@ -99,23 +99,25 @@ def test_steane_trials_full_batch(eng):
         _check_oracle(c, s, res)
 
 
+@pytest.mark.timeout(600)
 def test_uneven_batch_full_size(eng):
     circs = [wl.config4(j) for j in range(1024)]
     seeds = [wl.derive_seed(4, j) for j in range(1024)]
-    print("case 1024 uneven circuits, batched and graph", flush=True)
-    eager = _full_batch(eng, circs, seeds)
-    picked = {j for j, c in enumerate(circs) if c.n <= 72}
-    for words in (2, 3, 4):
-        wider = sorted((c.n, j) for j, c in enumerate(circs) if (c.n + 63) // 64 == words)
-        picked.update(j for _, j in wider[:2])
-    for j, (c, s, res) in enumerate(zip(circs, seeds, eager)):
-        (tab, sig, amp), outs, frag = res
-        n_t = sum(1 for g in c.gates if g[0] in (wl.T, wl.TDG))
-        assert 1 <= len(amp) <= 2 ** n_t, c.name
-        assert abs(float(np.sum(amp.real ** 2 + amp.imag ** 2)) - 1.0) <= 1e-12, c.name
-        assert not frag, c.name
-        if j in picked:
-            _check_oracle(c, s, res)
+    print("case 1024 uneven circuits, batched and graph; oracle in a process pool", flush=True)
+    with oracle_pool() as pool:
+        futs = [pool.submit(oracle_config4, j) for j in range(1024)]
+        eager = _full_batch(eng, circs, seeds)
+        for j, (c, res, fut) in enumerate(zip(circs, eager, futs)):
+            (tab, sig, amp), outs, frag = res
+            n_t = sum(1 for g in c.gates if g[0] in (wl.T, wl.TDG))
+            assert 1 <= len(amp) <= 2 ** n_t, c.name
+            assert abs(float(np.sum(amp.real ** 2 + amp.imag ** 2)) - 1.0) <= 1e-12, c.name
+            assert not frag, c.name
+            rtab, rsig, ramp, routs, rfrag = fut.result()
+            assert not rfrag, c.name
+            assert np.array_equal(tab, rtab), c.name
+            assert_frame_arrays_equal(sig, amp, rsig, ramp, what=c.name)
+            assert outs == routs, c.name
 
 
 @pytest.mark.parametrize("seed", [11, 12])
