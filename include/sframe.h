@@ -162,6 +162,21 @@ sf_status sf_run(sf_state* s);
  * context keeps (allocated on first use, freed by sf_ctx_destroy).
  * Synchronises. */
 sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t n_states);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not allocate, harnesses that forbid it).
+ * sf_batch_run without any allocation: the per-round launch descriptors and
+ * the error-gather table go to an 8 MiB device array of the library (one per
+ * device, kept until the process ends) instead of memory from the allocator
+ * hook, and the descriptors are copied from pageable host memory.  A frame of
+ * more than 128 qubits whose per-gate record buffer does not exist yet runs
+ * with the in-kernel phase evaluation instead of allocating it.  Results are
+ * those of sf_batch_run.  SF_E_TOO_LARGE (nothing queued) when the states
+ * would need more than 8 MiB of descriptors and gather table: about
+ * n_states x (108 + 96 x (most segments of one range + 1)) bytes.  Calls on
+ * one device share the array: calls that
+ * overlap in time on one device (other host threads or streams) race and
+ * must be serialised by the caller.  Synchronises. */
+sf_status sf_batch_run_noalloc(sf_ctx* ctx, sf_state* const* states, size_t n_states);
 /* Section 4, "Measuring F" (with COFACTOR of section 3).
  * Measure qubit q in the Z basis now, between circuit gates (the state must
  * be at a gate boundary, as after sf_step).  Same rule and random stream as

@@ -28,7 +28,7 @@ EXPORTS = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_measure", "sf
            "sf_graph_set_input", "sf_graph_launch", "sf_graph_destroy", "sf_circuit_load", "sf_circuit_info",
            "sf_circuit_destroy", "sf_state_init", "sf_state_destroy", "sf_step", "sf_run", "sf_sync",
            "sf_outcomes", "sf_frame_size", "sf_read_frame", "sf_state_info", "sf_state_reset",
-           "sf_state_dim", "sf_profile", "sf_profile_read", "sf_state_cycles", "sf_batch_run",
+           "sf_state_dim", "sf_profile", "sf_profile_read", "sf_state_cycles", "sf_batch_run", "sf_batch_run_noalloc",
            "sf_serve_create", "sf_serve_submit", "sf_serve_tick", "sf_serve_poll", "sf_serve_release",
            "sf_serve_cancel", "sf_serve_stats", "sf_serve_destroy"]
 
@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "sf_profile_read": [vp, vp, vp, ctypes.c_int],
         "sf_state_cycles": [vp, vp, ctypes.c_int],
         "sf_batch_run": [vp, vp, sz],
+        "sf_batch_run_noalloc": [vp, vp, sz],
         "sf_serve_create": [vp, u64, ctypes.c_uint32, ctypes.c_uint32, P(vp)],
         "sf_serve_submit": [vp, vp, vp, u64, P(u64)],
         "sf_serve_tick": [vp, P(ctypes.c_uint32), P(ctypes.c_uint32)],
@@ -189,6 +190,11 @@ class Engine:
         (synchronises).  states: a list of State or a StateBatch."""
         sb = states if isinstance(states, StateBatch) else StateBatch(states)
         self._check(self._L.sf_batch_run(self._h, sb.handles(), len(sb)))
+
+    def batch_run_noalloc(self, states):
+        """As batch_run, allocating no device memory (sf_batch_run_noalloc)."""
+        sb = states if isinstance(states, StateBatch) else StateBatch(states)
+        self._check(self._L.sf_batch_run_noalloc(self._h, sb.handles(), len(sb)))
 
     def batch_reset(self, states, bases=None, seeds=None):
         """Re-initialise the states with one launch.  states: a list of State

@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <unordered_map>
 #include <vector>
@@ -73,6 +74,31 @@ static void* pin_take(sf_ctx* ctx, size_t bytes) {
 static void pin_release(sf_ctx* ctx) {
   ctx->pin_cur = 0;
   ctx->pin_off = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free batched run.  The round descriptors (track jobs and element
+// descriptors) and the error-gather table live in `scratch`, a file-scope
+// device array of SF_SCRATCH_BYTES that every call on a device shares; its
+// device address is looked up once per device at context creation
+// (hipGetSymbolAddress) and only that address is used from the host.
+// ---------------------------------------------------------------------------
+#define SF_SCRATCH_BYTES ((size_t)8 << 20)
+#define SF_MAX_DEVICES 64
+static __device__ __align__(256) unsigned char scratch[SF_SCRATCH_BYTES];
+static void* g_scratch_dev[SF_MAX_DEVICES];
+
+static std::mutex g_scratch_mu;
+
+// Once per device, with that device current (context creation).  A failed
+// lookup leaves the address unset: sf_batch_run_noalloc then reports
+// SF_E_DEVICE, every other call is unaffected.
+static void scratch_lookup(int device) {
+  if (device < 0 || device >= SF_MAX_DEVICES) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p) g_scratch_dev[device] = p;
 }
 
 // Circuits whose hull never exceeds this dimension (2^8 = EB slots, one
@@ -348,6 +374,7 @@ extern "C" sf_status sf_ctx_create(int device, void* hip_stream, const sf_alloca
   c->ev_used = 0;
   for (int k = 0; k < PK_N; ++k) { c->prof_ms[k] = 0; c->prof_n[k] = 0; }
   for (int d = 0; d <= SF_DMAX; ++d) { c->tune_block[d] = EB; c->tune_grid[d] = grid_for(d); }
+  scratch_lookup(device);
   *out = c;
   return SF_OK;
 }
@@ -1225,8 +1252,10 @@ struct RoundPlan {
 // frame has work left or on an error (*err set; *bad = index of the state
 // that caused it, or -1).  seedp[i] (optional) is where frame i's seed is
 // read.  Nothing is queued before an error.
+// With noalloc, a wide frame whose record buffers are not allocated yet runs
+// with the in-kernel phase evaluation instead of allocating them.
 static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap, const uint64_t* const* seedp,
-                       RoundPlan* rp, sf_status* err, int* bad = nullptr) {
+                       RoundPlan* rp, sf_status* err, int* bad = nullptr, bool noalloc = false) {
   std::vector<int> act;
   std::vector<size_t> A(ns), B(ns), O(ns);
   std::vector<int> NS(ns), ML(ns), CL(ns);
@@ -1285,7 +1314,8 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
       if (bad) *bad = i;
       return false;
     }
-    const bool use = split_form(s->c->n) || rp->wcount[words_of(s->c->n)] <= SF_SPLIT_WIDE_MAX;
+    const bool use = (split_form(s->c->n) || rp->wcount[words_of(s->c->n)] <= SF_SPLIT_WIDE_MAX) &&
+                     (!noalloc || s->rec.p);
     if (use && (*err = ensure_split_buffers(s)) != SF_OK) {
       if (bad) *bad = i;
       return false;
@@ -1424,13 +1454,13 @@ static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs
 // *bad (optional) receives the index of the state that made planning fail
 // (nothing was queued then), or -1.
 static sf_status batch_round(sf_ctx* ctx, sf_state* const* states, size_t ns, BatchScratch* bs, int* active,
-                             int cap = 0, bool staged = false, int* bad = nullptr) {
+                             int cap = 0, bool staged = false, int* bad = nullptr, bool noalloc = false) {
   std::vector<Progress> pr(ns);
   for (size_t i = 0; i < ns; ++i) pr[i] = progress_of(states[i]);
   RoundPlan rp;
   sf_status err;
   *active = 0;
-  if (!plan_round(states, ns, pr.data(), cap, nullptr, &rp, &err, bad)) return err;
+  if (!plan_round(states, ns, pr.data(), cap, nullptr, &rp, &err, bad, noalloc)) return err;
   *active = rp.na;
   if (staged) {
     const size_t bj = rp.na * sizeof(TrackJob), bd = rp.desc.size() * sizeof(ElemDesc);
@@ -1459,14 +1489,22 @@ static sf_status batch_round(sf_ctx* ctx, sf_state* const* states, size_t ns, Ba
   return SF_OK;
 }
 
+// Device memory of check_tracks' gather launch for ns states.
+static size_t gather_bytes(size_t ns) { return ((ns * sizeof(void*) + 255) & ~(size_t)255) + ns * sizeof(int); }
+
 // Device-side errors of many states with one gather launch and one copy.
-static sf_status check_tracks(sf_ctx* ctx, sf_state* const* states, size_t ns) {
+// work: device memory of gather_bytes(ns) bytes, or nullptr to allocate it.
+static sf_status check_tracks(sf_ctx* ctx, sf_state* const* states, size_t ns, void* work = nullptr) {
   if (ns == 0) return SF_OK;
   if (ns == 1) return check_track(states[0]);
   DevBuf buf;
   const size_t off = (ns * sizeof(void*) + 255) & ~(size_t)255;
-  sf_status rc = dalloc(ctx, &buf, off + ns * sizeof(int));
-  if (rc) return rc;
+  if (work) {
+    buf.p = work;
+  } else {
+    sf_status rc = dalloc(ctx, &buf, gather_bytes(ns));
+    if (rc) return rc;
+  }
   std::vector<const TrackState*> ptr(ns);
   for (size_t i = 0; i < ns; ++i) ptr[i] = (const TrackState*)states[i]->st.p;
   std::vector<int> errs(ns, 0);
@@ -1480,7 +1518,7 @@ static sf_status check_tracks(sf_ctx* ctx, sf_state* const* states, size_t ns) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(errs.data(), (char*)buf.p + off, ns * sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  dfree(ctx, &buf);
+  if (!work) dfree(ctx, &buf);
   if (e != hipSuccess) return fail(ctx, SF_E_DEVICE, "error check: %s", hipGetErrorString(e));
   for (size_t i = 0; i < ns; ++i)
     if (errs[i]) return fail(ctx, SF_E_DEVICE, "state %zu: tableau track reported error %d", i, errs[i]);
@@ -1505,6 +1543,40 @@ extern "C" sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t n
   if (rc != SF_OK) return rc;
   if (e != hipSuccess) return fail(ctx, SF_E_DEVICE, "batch run: %s", hipGetErrorString(e));
   return check_tracks(ctx, states, ns);
+}
+
+extern "C" sf_status sf_batch_run_noalloc(sf_ctx* ctx, sf_state* const* states, size_t ns) {
+  if (!ctx || (ns && !states)) return SF_E_INVALID;
+  int maxseg = 1;
+  for (size_t i = 0; i < ns; ++i) {
+    if (!states[i] || states[i]->ctx != ctx) return fail(ctx, SF_E_INVALID, "state %zu is not of this context", i);
+    maxseg = std::max(maxseg, states[i]->c->max_segs);
+  }
+  if (ns == 0) return SF_OK;
+  void* base = (ctx->device >= 0 && ctx->device < SF_MAX_DEVICES) ? g_scratch_dev[ctx->device] : nullptr;
+  if (!base) return fail(ctx, SF_E_DEVICE, "scratch array of device %d has no address", ctx->device);
+  // the largest round: every state active with maxseg segments and a measurement
+  const size_t need_d = (size_t)(maxseg + 1) * ns * sizeof(ElemDesc);
+  const size_t off_d = desc_offset(ns * sizeof(TrackJob));
+  const size_t off_g = desc_offset(off_d + need_d);
+  if (off_g + gather_bytes(ns) > SF_SCRATCH_BYTES)
+    return fail(ctx, SF_E_TOO_LARGE, "%zu states with up to %d segments need %zu scratch bytes, %zu available", ns,
+                maxseg, off_g + gather_bytes(ns), (size_t)SF_SCRATCH_BYTES);
+  BatchScratch bs;  // views into the scratch array, never freed
+  bs.djobs.p = base;
+  bs.djobs.bytes = off_d;
+  bs.ddesc.p = (char*)base + off_d;
+  bs.ddesc.bytes = need_d;
+  sf_status rc = SF_OK;
+  int active = 1;
+  while (rc == SF_OK && active) rc = batch_round(ctx, states, ns, &bs, &active, 0, false, nullptr, true);
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  bs.keep_jobs.clear();
+  bs.keep_desc.clear();
+  bs.djobs.p = bs.ddesc.p = nullptr;
+  if (rc != SF_OK) return rc;
+  if (e != hipSuccess) return fail(ctx, SF_E_DEVICE, "batch run: %s", hipGetErrorString(e));
+  return check_tracks(ctx, states, ns, (char*)base + off_g);
 }
 
 // Re-initialise many states with one kernel launch (their basis states and
