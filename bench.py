@@ -2,10 +2,14 @@
 """Frame-element gate updates per second on one MI355X.
 
 Workload (default): the n=128 random Clifford+T circuits (2000 H/S/CNOT drawn
-uniformly, 16 T at uniform slots, then 16 Z measurements), three seeded
-circuits per step, run through the batched path (--path): one batched reset
-and one sf_batch_run over the three states per step, whose rounds launch the
-tableau tracks of all frames together and their element kernels together.  U
+uniformly, 16 T at uniform slots, then 16 Z measurements), 1024 seeded
+circuits per step (four tableau-track workgroups per compute unit: the track
+of one circuit is one wavefront walking its gates in order, so a step of few
+circuits leaves the device idle), run through the batched path (--path): one
+batched reset and one sf_batch_run over all states per step, whose rounds
+launch the tableau tracks of all frames together and their element kernels
+together.  The same circuits three at a time (the smallest batch) and one at
+a time (the plain path, on the leading circuits) are reported beside it.  U
 counts, for every gate applied, the frame size just before it; value = U /
 wall time of the timed steps, with states already resident in HBM.  The plain
 path (one state at a time), the graph replay, the many-frame workloads, the
@@ -96,7 +100,50 @@ def accounting(state, circ, seed, wl, sizes=None):
     return U, seg_dims
 
 
+def host_info():
+    """Host core count and CPU model (from /proc/cpuinfo)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def _workload_circuit(kind, idx):
+    from paper_1712_03554_amd import workloads as wl
+    if kind == "steane":
+        return wl.config3(idx), wl.derive_seed(3, idx)
+    if kind == "uneven":
+        return wl.config4(idx), wl.derive_seed(4, idx)
+    if kind == "cfg2":
+        return wl.config2(idx), wl.derive_seed(2, idx)
+    return wl.config5_job(idx), wl.derive_seed(5, idx) ^ 0x5E
+
+
+def _oracle_task(task):
+    """One circuit on the oracle in a pool worker: (U, seconds)."""
+    from oracle.frame import OracleFrame
+    kind, idx = task
+    c, seed = _workload_circuit(kind, idx)
+    f = OracleFrame(c.n, c.init_bits, seed)
+    t0 = time.perf_counter()
+    sizes = f.run(c.array())
+    return int(sizes.sum()), time.perf_counter() - t0
+
+
+def _noop(_):
+    return 0
+
+
 def cpu_baseline(circ, seed):
+    """The oracle on one full cfg2 circuit on one host thread (the headline
+    comparison), plus the many-frame and served workloads with one circuit
+    per task on a process pool over the host cores."""
     from oracle.frame import OracleFrame
     f = OracleFrame(circ.n, circ.init_bits, seed)
     arr = circ.array()
@@ -104,8 +151,39 @@ def cpu_baseline(circ, seed):
     sizes = f.run(arr)
     dt = time.perf_counter() - t0
     U = int(sizes.sum())
-    return {"value": U / dt, "unit": "frame-element gate updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{circ.name}: one full circuit ({len(arr)} gates, U={U}) on one host thread, {dt:.2f} s"}
+    host = host_info()
+    out = {"value": U / dt, "unit": "frame-element gate updates/s", "cores": 1, "kind": "oracle",
+           "sample": f"{circ.name}: one full circuit ({len(arr)} gates, U={U}) on one host thread, {dt:.2f} s",
+           "host": host, "workloads": []}
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_1712_03554_amd import workloads as wl
+    workers = max(1, min(16, host["nproc"] or 1))
+    serve_idx = []
+    for j in range(48):
+        c = wl.config5_job(j)
+        if not c.name.startswith("cfg5b"):
+            serve_idx.append(j)
+    legs = [("random Clifford+T, n=128 (the headline workload)", "cfg2", list(range(workers)),
+             f"the first {workers} of its circuits, one per core"),
+            ("Steane fault-injection trials", "steane", list(range(4096)), "all 4096 trials"),
+            ("uneven random Clifford+T", "uneven", list(range(128)),
+             "the first 128 of the 1024 circuits (n in 16..256)"),
+            ("served mix", "serve", serve_idx,
+             f"the {len(serve_idx)} AQFT and uneven-shaped requests of the 48-request stream (the Cuccaro "
+             "adders, 2^18..2^66 elements, take minutes to hours each on the oracle and are left out)")]
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as pool:
+        list(pool.map(_noop, range(4 * workers)))  # start every worker before timing
+        for name, kind, idx, sample in legs:
+            t0 = time.perf_counter()
+            res = list(pool.map(_oracle_task, [(kind, i) for i in idx], chunksize=max(1, len(idx) // (8 * workers))))
+            wall = time.perf_counter() - t0
+            Us = sum(r[0] for r in res)
+            out["workloads"].append({"workload": name, "value": Us / wall, "unit": "frame-element gate updates/s",
+                                     "cores": workers, "kind": "oracle", "U": Us, "wall_s": wall,
+                                     "cpu_s": sum(r[1] for r in res), "requests_per_s": len(idx) / wall,
+                                     "sample": sample})
+    return out
 
 
 def batched_extra(eng, wl, name, circs, seeds, plain_sample):
@@ -415,7 +493,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--jobs", type=int, default=3)
+    ap.add_argument("--jobs", type=int, default=1024,
+                    help="circuits per step (1024: four tableau-track workgroups per compute unit)")
+    ap.add_argument("--plain-jobs", type=int, default=3,
+                    help="leading circuits the plain form runs one at a time (a rate)")
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg2L"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--path", default="batched", choices=["graph", "batched", "plain"])
@@ -465,14 +546,19 @@ def main():
     states = [l.state(c.init_bits, s) for l, c, s in zip(loaded, circs, seeds)]
     bounds = [l.info()[0] for l in loaded]
 
-    U_total, seg_dims = 0, []
+    U_each, seg_dims = [], []
     for st, c, s in zip(states, circs, seeds):
         U, dims = accounting(st, c, s, wl)
-        U_total += U
+        U_each.append(U)
         seg_dims.append(dims)
+    U_total = sum(U_each)
+    n_plain = max(1, min(args.plain_jobs, len(states)))
+    U_plain = sum(U_each[:n_plain])
+    n_small = min(3, len(states))
+    U_small = sum(U_each[:n_small])
 
     def plain_step():
-        for st, c, s in zip(states, circs, seeds):
+        for st, c, s in list(zip(states, circs, seeds))[:n_plain]:
             st.reset(c.init_bits, s)
             st.run()
 
@@ -484,12 +570,18 @@ def main():
         eng.batch_reset(batch, bases, seeds)
         eng.batch_run(batch)
 
+    small = sf.StateBatch(states[:n_small])
+
+    def small_step():
+        eng.batch_reset(small, bases[:n_small], seeds[:n_small])
+        eng.batch_run(small)
+
     graph = None
 
     def graph_step():
         graph.launch()
 
-    def timed(fn):
+    def timed(fn, U):
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
@@ -497,15 +589,19 @@ def main():
         for _ in range(args.steps):
             fn()
         torch.cuda.synchronize()
-        return args.steps * U_total / (time.perf_counter() - t)
+        dt = (time.perf_counter() - t) / args.steps
+        return U / dt, dt * 1e3
 
     # the other forms, timed for the record
-    plain_value = timed(plain_step)
-    batched_value = timed(batched_step)
+    plain_value, plain_ms = timed(plain_step, U_plain)
+    small_value, small_ms = timed(small_step, U_small)
+    batched_value, batched_ms = timed(batched_step, U_total)
     graph = eng.batch_graph(states, [c.init_bits for c in circs], seeds)
-    graph_value = timed(graph_step)
+    graph_value, graph_ms = timed(graph_step, U_total)
 
     one_step = {"graph": graph_step, "batched": batched_step, "plain": plain_step}[args.path]
+    U_one = U_plain if args.path == "plain" else U_total
+    step_circs = circs[:n_plain] if args.path == "plain" else circs
     # untimed pass with every kernel kind timed: the breakdown per kind
     eng.profile(True)
     for _ in range(args.steps):
@@ -533,7 +629,7 @@ def main():
         for k, v in st.track_cycles().items():
             cyc[k] = cyc.get(k, 0) + v
     elapsed = t1 - t0
-    value = args.steps * U_total / elapsed
+    value = args.steps * U_one / elapsed
 
     # roofline of the dominant kernel (its launches timed in the timed region)
     seg_bytes_per_step = sum(32.0 * (1 << d) for dims in seg_dims for d in dims)
@@ -550,7 +646,7 @@ def main():
     else:
         # tableau track: one pass over the n rows per gate (4 n W 64-bit words)
         tr_ms, tr_n = prof["track"]
-        words_per_step = sum(len(c.gates) * 4 * c.n * ((c.n + 63) // 64) for c in circs)
+        words_per_step = sum(len(c.gates) * 4 * c.n * ((c.n + 63) // 64) for c in step_circs)
         ach = (words_per_step * args.steps / tr_n) / (tr_ms / 1e3 / tr_n) / 1e9
         wset = sorted({(c.n + 63) // 64 for c in circs})
         kname = ("sf_track_one<%d>" if args.path == "plain" else "sf_track_many<%d>") % wset[-1]
@@ -573,11 +669,18 @@ def main():
         "vs_baseline": None,
         "dtype": "c128",
         "data": "synthetic",
-        "config": {"workload": wname, "circuits_per_step": args.jobs, "path": args.path,
-                   "U_per_step": U_total, "frame_bound_log2": bounds},
+        "config": {"workload": wname, "circuits_per_step": len(step_circs), "path": args.path,
+                   "U_per_step": U_one, "frame_bound_log2_max": max(bounds),
+                   "seeds": "splitmix64 stream of master seed 20171210, config 2, circuits 0..%d" % (len(circs) - 1)},
         "plain_value": plain_value,
+        "plain_ms_per_step": plain_ms,
+        "plain_circuits": n_plain,
         "batched_value": batched_value,
+        "batched_ms_per_step": batched_ms,
         "graph_value": graph_value,
+        "graph_ms_per_step": graph_ms,
+        "three_circuit_batched_value": small_value,
+        "three_circuit_batched_ms_per_step": small_ms,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kinds.items()},
         "kernel_launches_per_step": {k: v[1] / args.steps for k, v in kinds.items()},
         "roofline": roof,

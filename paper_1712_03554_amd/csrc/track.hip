@@ -695,35 +695,55 @@ static __device__ __forceinline__ void point_vec(const uint64_t* base, const uin
 // the sign flips f (applied to every phase vector through s0 ^= f, s0 being
 // lane d's hull register) and keep the column-major copy in step.  Registers
 // only.
-static __device__ __forceinline__ void conj_regs(Regs& R, uint64_t (&hv)[W], int op, int a, int b, int n, int d) {
-  const int lane = lane_id();
-  const int wa = a >> 6, ba = a & 63, wb = b >> 6, bb = b & 63;
-  const bool two = op == DG_CNOT || op == DG_CZ;
-  uint64_t fm[W];
+// One gate kind per instantiation, so that the per-row work is straight-line
+// code (the gate is dispatched once, by a scalar branch, in conj_regs).
+template <int OP>
+static __device__ __forceinline__ void conj_rows(Regs& R, uint64_t (&fm)[W], int wa, int ba, int wb, int bb, int n) {
   for (int k = 0; k < W; ++k) {
-    const int xa = (int)((pick(R.x[k], wa) >> ba) & 1ull), za = (int)((pick(R.z[k], wa) >> ba) & 1ull);
-    const int xb = two ? (int)((pick(R.x[k], wb) >> bb) & 1ull) : 0;
-    const int zb = two ? (int)((pick(R.z[k], wb) >> bb) & 1ull) : 0;
-    int fl = 0, fxa = 0, fza = 0, fxb = 0, fzb = 0;
-    switch (op) {
-      case DG_H: fl = xa & za; fxa = fza = xa ^ za; break;
-      case DG_S: fl = xa & za; fza = xa; break;
-      case DG_SDG: fl = xa & (za ^ 1); fza = xa; break;
-      case DG_X: fl = za; break;
-      case DG_Z: fl = xa; break;
-      case DG_Y: fl = xa ^ za; break;
-      case DG_CNOT: fl = xa & zb & (xb ^ za ^ 1); fxb = xa; fza = zb; break;
-      case DG_CZ: fl = xa & xb & (za ^ zb); fza = xb; fzb = xa; break;
+    const uint64_t xwa = pick(R.x[k], wa), zwa = pick(R.z[k], wa);
+    const int xa = (int)((xwa >> ba) & 1ull), za = (int)((zwa >> ba) & 1ull);
+    int xb = 0, zb = 0;
+    if constexpr (OP == DG_CNOT || OP == DG_CZ) {
+      xb = (int)((pick(R.x[k], wb) >> bb) & 1ull);
+      zb = (int)((pick(R.z[k], wb) >> bb) & 1ull);
     }
-    for (int w = 0; w < W; ++w) {
-      R.x[k][w] ^= ((w == wa ? (uint64_t)fxa << ba : 0ull) | (w == wb ? (uint64_t)fxb << bb : 0ull));
-      R.z[k][w] ^= ((w == wa ? (uint64_t)fza << ba : 0ull) ^ (w == wb ? (uint64_t)fzb << bb : 0ull));
+    int fl = 0;
+    uint64_t mxa = 0, mza = 0, mxb = 0, mzb = 0;  // bits to toggle at a and b
+    if constexpr (OP == DG_H) { fl = xa & za; mxa = mza = (uint64_t)(xa ^ za) << ba; }
+    else if constexpr (OP == DG_S) { fl = xa & za; mza = (uint64_t)xa << ba; }
+    else if constexpr (OP == DG_SDG) { fl = xa & (za ^ 1); mza = (uint64_t)xa << ba; }
+    else if constexpr (OP == DG_X) { fl = za; }
+    else if constexpr (OP == DG_Z) { fl = xa; }
+    else if constexpr (OP == DG_Y) { fl = xa ^ za; }
+    else if constexpr (OP == DG_CNOT) { fl = xa & zb & (xb ^ za ^ 1); mxb = (uint64_t)xa << bb; mza = (uint64_t)zb << ba; }
+    else if constexpr (OP == DG_CZ) { fl = xa & xb & (za ^ zb); mza = (uint64_t)xb << ba; mzb = (uint64_t)xa << bb; }
+    if constexpr (OP == DG_H || OP == DG_S || OP == DG_SDG || OP == DG_CNOT || OP == DG_CZ) {
+      for (int w = 0; w < W; ++w) {
+        R.x[k][w] ^= (w == wa ? mxa : 0ull) | (w == wb ? mxb : 0ull);
+        R.z[k][w] ^= (w == wa ? mza : 0ull) ^ (w == wb ? mzb : 0ull);
+      }
     }
     // only H and CNOT move leads: the diagonal gates change z bits of rows
     // that have an x bit (whose lead is an x column), the Paulis no bits
-    if (op == DG_H || op == DG_CNOT)
-      R.ld[k] = (fxa | fza | fxb | fzb) ? row_lead_sel(R.x[k], R.z[k], n) : R.ld[k];
+    if constexpr (OP == DG_H || OP == DG_CNOT)
+      R.ld[k] = (mxa | mza | mxb) ? row_lead_sel(R.x[k], R.z[k], n) : R.ld[k];
     fm[k] = __ballot(fl);
+  }
+}
+
+static __device__ __forceinline__ void conj_regs(Regs& R, uint64_t (&hv)[W], int op, int a, int b, int n, int d) {
+  const int lane = lane_id();
+  const int wa = a >> 6, ba = a & 63, wb = b >> 6, bb = b & 63;
+  uint64_t fm[W];
+  switch (op) {
+    case DG_H: conj_rows<DG_H>(R, fm, wa, ba, wb, bb, n); break;
+    case DG_S: conj_rows<DG_S>(R, fm, wa, ba, wb, bb, n); break;
+    case DG_SDG: conj_rows<DG_SDG>(R, fm, wa, ba, wb, bb, n); break;
+    case DG_X: conj_rows<DG_X>(R, fm, wa, ba, wb, bb, n); break;
+    case DG_Z: conj_rows<DG_Z>(R, fm, wa, ba, wb, bb, n); break;
+    case DG_Y: conj_rows<DG_Y>(R, fm, wa, ba, wb, bb, n); break;
+    case DG_CNOT: conj_rows<DG_CNOT>(R, fm, wa, ba, wb, bb, n); break;
+    default: conj_rows<DG_CZ>(R, fm, wa, ba, wb, bb, n); break;
   }
   // column-major copy
   if (op == DG_H) {

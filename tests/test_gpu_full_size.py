@@ -3,7 +3,9 @@ benchmark times (one batched reset and one batched run of every frame, and
 the graph form), checked against the oracle (needs an MI355X).
 
 * 3 random Clifford+T circuits, n = 128, 2000 Cliffords + 16 T, 16
-  measurements (the headline step): every frame against the oracle.
+  measurements: every frame against the oracle; and 1024 of them in one
+  batch (the headline step as the benchmark times it): 16 against the
+  oracle, all against size-independent properties.
 * 4096 Steane fault-injection trials: every trial against the oracle.
 * 1024 uneven random Clifford+T circuits (n in 16..256, up to 12 T): every
   frame against the oracle (run in a process pool while the GPU works), and
@@ -18,8 +20,8 @@ import pytest
 
 from oracle.frame import OracleFrame
 from paper_1712_03554_amd import workloads as wl
-from tests.oracle_helpers import (assert_frame_arrays_equal, assert_frames_equal, oracle_config4, oracle_pool,
-                                  sigma_ints)
+from tests.oracle_helpers import (assert_frame_arrays_equal, assert_frames_equal, oracle_config2, oracle_config4,
+                                  oracle_pool, sigma_ints)
 
 pytestmark = pytest.mark.gpu
 
@@ -85,6 +87,34 @@ def test_random_clifford_t_n128_full_batch(eng):
     for c, s, res in zip(circs, seeds, eager):
         assert len(res[1]) == 16, c.name
         _check_oracle(c, s, res)
+
+
+@pytest.mark.timeout(600)
+def test_random_clifford_t_n128_device_filling_batch(eng):
+    """The headline step as the benchmark times it: 1024 circuits in one
+    batched run (and its graph form, equal bit for bit); 16 of them against
+    the oracle (in a process pool while the GPU works), every one against the
+    properties that hold at any size: 16 outcomes, norm 1, at most 2^16
+    elements, no fragile outcome."""
+    circs = [wl.config2(j) for j in range(1024)]
+    seeds = [wl.derive_seed(2, j) for j in range(1024)]
+    sample = list(range(0, 1024, 64))
+    print("case 1024 x n=128 Clifford+T circuits, batched and graph", flush=True)
+    with oracle_pool() as pool:
+        futs = {j: pool.submit(oracle_config2, j) for j in sample}
+        eager = _full_batch(eng, circs, seeds)
+        for j, (c, res) in enumerate(zip(circs, eager)):
+            (tab, sig, amp), outs, frag = res
+            assert len(outs) == 16 and not frag, c.name
+            assert 1 <= len(amp) <= 1 << 16, c.name
+            assert abs(float(np.sum(amp.real ** 2 + amp.imag ** 2)) - 1.0) <= 1e-12, c.name
+        for j in sample:
+            (tab, sig, amp), outs, frag = eager[j]
+            rtab, rsig, ramp, routs, rfrag = futs[j].result()
+            assert not rfrag, circs[j].name
+            assert np.array_equal(tab, rtab), circs[j].name
+            assert_frame_arrays_equal(sig, amp, rsig, ramp, what=circs[j].name)
+            assert outs == routs, circs[j].name
 
 
 def test_steane_trials_full_batch(eng):
