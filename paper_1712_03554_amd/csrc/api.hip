@@ -282,8 +282,14 @@ struct sf_circuit {
   struct Range {
     size_t o0, a, b, o;
     int ns, ml, cl;  // segments, ends in a measurement, has a Clifford gate
+    int dofs;        // its segments' hull dimensions at rdims[dofs..dofs + ns)
   };
   std::vector<Range> ranges;
+  // hull dimension on entry to every terminal gate (device index; -1 for the
+  // others), from the load-time dry run; per range, its segments' dimensions
+  // (they size the element launches; the hull dimension does not depend on
+  // measurement outcomes)
+  std::vector<int8_t> dterm, rdims;
   std::vector<int32_t> rstart;
 };
 
@@ -292,6 +298,7 @@ static bool is_cut(const sf_circuit* c, size_t e) {
 }
 
 static void build_range_table(sf_circuit* c);
+static void fill_range_dims(sf_circuit* c);
 
 struct sf_state {
   sf_ctx* ctx;
@@ -583,10 +590,13 @@ extern "C" sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n, const sf_gate* gat
   build_range_table(c);
   sf_status rc = dalloc(ctx, &c->dgates, sizeof(DGate) * std::max<size_t>(1, c->g.size()));
   if (rc != SF_OK) { delete c; return rc; }
-  // dry run of the tableau track: frame bound of the whole circuit
-  DevBuf dst;
+  // dry run of the tableau track: frame bound of the whole circuit, and the
+  // hull dimension on entry to every terminal gate (in the gate-info slot,
+  // which a dry run does not use otherwise)
+  DevBuf dst, dtr;
   rc = dalloc(ctx, &dst, sizeof(TrackState));
-  if (rc != SF_OK) { dfree(ctx, &c->dgates); delete c; return rc; }
+  if (rc == SF_OK) rc = dalloc(ctx, &dtr, 4 * std::max<size_t>(1, c->g.size()));
+  if (rc != SF_OK) { dfree(ctx, &dst); dfree(ctx, &c->dgates); delete c; return rc; }
   TrackState* h = (TrackState*)calloc(1, sizeof(TrackState));
   h->n = (int)n;
   h->W = (int)((n + 63) / 64);
@@ -595,6 +605,7 @@ extern "C" sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n, const sf_gate* gat
     h->cz[q * SF_WMAX + (q >> 6)] = 1ull << (q & 63);
   }
   hipError_t e = hipMemcpyAsync(dst.p, h, sizeof(TrackState), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(dtr.p, 0xff, dtr.bytes, ctx->stream);
   if (e == hipSuccess && !c->g.empty())
     e = hipMemcpyAsync(c->dgates.p, c->g.data(), sizeof(DGate) * c->g.size(), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) {
@@ -605,14 +616,19 @@ extern "C" sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n, const sf_gate* gat
     job.g0 = 0;
     job.g1 = (int)c->g.size();
     job.dry = 1;
+    job.ginfo = (int32_t*)dtr.p;
     launch_track_one(ctx->stream, job, words_of(n));
     e = hipGetLastError();
   }
+  std::vector<int32_t> dtrace(std::max<size_t>(1, c->g.size()), -1);
   if (e == hipSuccess) e = hipMemcpyAsync(h, dst.p, 64, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dtrace.data(), dtr.p, 4 * dtrace.size(), hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   int dmax = h->dmax, terr = h->error;
   free(h);
   dfree(ctx, &dst);
+  dfree(ctx, &dtr);
   if (e != hipSuccess) {
     dfree(ctx, &c->dgates);
     delete c;
@@ -629,6 +645,10 @@ extern "C" sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n, const sf_gate* gat
     return fail(ctx, SF_E_DEVICE, "tableau track reported internal error %d", terr);
   }
   c->dmax = dmax;
+  c->dterm.assign(c->g.size(), (int8_t)-1);
+  for (size_t i = 0; i < c->g.size(); ++i)
+    if (is_terminal(c->g[i].op)) c->dterm[i] = (int8_t)std::min(std::max(dtrace[i], -1), dmax);
+  fill_range_dims(c);
   uint64_t amp = (uint64_t)16 << dmax;
   c->projected = 2 * amp + sizeof(TrackState) + sizeof(ReadoutInfo) +
                  (uint64_t)c->max_segs * sizeof(SegProg) + (uint64_t)c->max_had * sizeof(GF2Q);
@@ -1206,12 +1226,43 @@ static void build_range_table(sf_circuit* c) {
   while (p.orig_done < c->orig_end.size()) {
     sf_circuit::Range r;
     r.o0 = p.orig_done;
+    r.dofs = -1;
     plan_range(c, p, &r.a, &r.b, &r.o, &r.ns, &r.ml, 0, &r.cl);
     if (r.b <= r.a && r.o <= r.o0) break;  // no progress: leave the rest to the walk
     c->rstart[r.a] = (int32_t)c->ranges.size();
     c->ranges.push_back(r);
     p.orig_done = r.o;
     p.dev_done = r.b;
+  }
+}
+
+// Per range, the hull dimension of each segment: a segment ending in a
+// terminal gate runs at the dimension on entry to it; an open segment at the
+// end of a range at the dimension on entry to the next terminal gate (its
+// continuation), or the circuit's bound.
+static void fill_range_dims(sf_circuit* c) {
+  c->rdims.clear();
+  const size_t G = c->g.size();
+  std::vector<int8_t> next(G + 1, (int8_t)c->dmax);
+  for (size_t i = G; i-- > 0;) next[i] = c->dterm[i] >= 0 ? c->dterm[i] : next[i + 1];
+  for (sf_circuit::Range& r : c->ranges) {
+    r.dofs = (int)c->rdims.size();
+    bool open = false;
+    int k = 0;
+    for (size_t i = r.a; i < r.b; ++i) {
+      if (is_terminal(c->g[i].op)) {
+        c->rdims.push_back(c->dterm[i] >= 0 ? c->dterm[i] : (int8_t)c->dmax);
+        open = false;
+        ++k;
+      } else {
+        open = true;
+      }
+    }
+    if (open) { c->rdims.push_back(next[r.b]); ++k; }
+    if (k != r.ns) {  // inconsistent: size by the bound
+      c->rdims.resize(r.dofs);
+      r.dofs = -1;
+    }
   }
 }
 
@@ -1246,6 +1297,9 @@ struct RoundPlan {
   int wlen[SF_WMAX + 1] = {0, 0, 0, 0, 0};    // per word count: longest range, most segments,
   int wseg[SF_WMAX + 1] = {0, 0, 0, 0, 0};    // phase-kernel chunks of the longest range
   int wchunk[SF_WMAX + 1] = {0, 0, 0, 0, 0};  // 0: no Clifford gate in the group's ranges
+  // per segment row k (and the measurement row kmax): launch shape from the
+  // largest hull dimension any frame has there
+  std::vector<int> kbx, kgx;
 };
 
 // Plans the next round from the progress pr[] and advances it; false when no
@@ -1352,6 +1406,30 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
   }
   elem_shape(states[act[0]]->ctx, dm, &rp->bx, &rp->gx);
   rp->msmall = dm <= SF_MSMALL_D;
+  // launch shapes per segment row from the frames' segment dimensions (any
+  // shape covers every slot: the element kernels stride over the grid)
+  {
+    std::vector<int> kd((size_t)rp->kmax + 1, 0);
+    for (int j = 0; j < na; ++j) {
+      const int i = act[j];
+      const sf_circuit* c = states[i]->c;
+      const int8_t* dims = nullptr;
+      if (cap == 0 && A[i] < c->rstart.size()) {
+        const int r = c->rstart[A[i]];
+        if (r >= 0 && c->ranges[(size_t)r].o0 == pr[i].orig_done && c->ranges[(size_t)r].dofs >= 0 &&
+            c->ranges[(size_t)r].ns == NS[i])
+          dims = c->rdims.data() + c->ranges[(size_t)r].dofs;
+      }
+      for (int k = 0; k < NS[i]; ++k) kd[(size_t)k] = std::max(kd[(size_t)k], dims ? (int)dims[k] : c->dmax);
+      if (ML[i] && NS[i] > 0) {
+        const int dl = dims ? std::min((int)dims[NS[i] - 1] + 1, c->dmax) : c->dmax;
+        kd[(size_t)rp->kmax] = std::max(kd[(size_t)rp->kmax], dl);
+      }
+    }
+    rp->kbx.assign((size_t)rp->kmax + 1, EB);
+    rp->kgx.assign((size_t)rp->kmax + 1, 1);
+    for (int k = 0; k <= rp->kmax; ++k) elem_shape(states[act[0]]->ctx, kd[(size_t)k], &rp->kbx[(size_t)k], &rp->kgx[(size_t)k]);
+  }
   const int kmax = rp->kmax;
   rp->desc.assign((size_t)(kmax + 1) * na, ElemDesc{});
   for (int k = 0; k <= kmax; ++k)
@@ -1407,6 +1485,14 @@ static void scratch_free(sf_ctx* ctx, BatchScratch* bs) {
   bs->keep_desc.clear();
 }
 
+// The measurement coin in a kernel of its own (once per frame) when the
+// filter launch has many blocks: each block of the fused filter kernel sums
+// the reduction's partials again, which costs more than a launch there.
+#define SF_COIN_APART_BLOCKS 2048
+static bool coin_apart(const RoundPlan& rp) {
+  return (size_t)rp.kgx[(size_t)rp.kmax] * (size_t)rp.na > SF_COIN_APART_BLOCKS;
+}
+
 // Kernel launches of one planned round, with its descriptors at djobs/ddesc.
 static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs, const ElemDesc* dd) {
   const int na = rp.na;
@@ -1431,17 +1517,28 @@ static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs
   }
   for (int k = 0; k < rp.kmax; ++k) {
     prof_begin(ctx, PK_SEG);
-    hipLaunchKernelGGL(sf_seg_batch, dim3(rp.gx, na), dim3(rp.bx), 0, ctx->stream, dd + (size_t)k * na);
+    hipLaunchKernelGGL(sf_seg_batch, dim3(rp.kgx[(size_t)k], na), dim3(rp.kbx[(size_t)k]), 0, ctx->stream,
+                       dd + (size_t)k * na);
     prof_end(ctx);
   }
   if (rp.anym) {
     const ElemDesc* dm = dd + (size_t)rp.kmax * na;
+    const int fx = rp.kgx[(size_t)rp.kmax], fb = rp.kbx[(size_t)rp.kmax];
     prof_begin(ctx, PK_MREDUCE);
     hipLaunchKernelGGL(sf_meas_reduce_batch, dim3(rp.gm, na), dim3(EB), 0, ctx->stream, dm);
     prof_end(ctx);
-    prof_begin(ctx, PK_MFILTER);
-    hipLaunchKernelGGL(sf_meas_filter_batch, dim3(rp.gx, na), dim3(rp.bx), 0, ctx->stream, dm);
-    prof_end(ctx);
+    if (coin_apart(rp)) {
+      prof_begin(ctx, PK_MFINAL);
+      hipLaunchKernelGGL(sf_meas_coin_batch, dim3(na), dim3(EB), 0, ctx->stream, dm);
+      prof_end(ctx);
+      prof_begin(ctx, PK_MFILTER);
+      hipLaunchKernelGGL(sf_meas_apply_batch, dim3(fx, na), dim3(fb), 0, ctx->stream, dm);
+      prof_end(ctx);
+    } else {
+      prof_begin(ctx, PK_MFILTER);
+      hipLaunchKernelGGL(sf_meas_filter_batch, dim3(fx, na), dim3(fb), 0, ctx->stream, dm);
+      prof_end(ctx);
+    }
   }
 }
 
@@ -1852,14 +1949,21 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
     for (int k = 0; k < rp.kmax && e == hipSuccess; ++k) {
       const ElemDesc* dk = dd + (size_t)k * na;
       void* args[] = {(void*)&dk};
-      e = add_kernel_node(g->graph, &last, (const void*)sf_seg_batch, dim3(rp.gx, na), dim3(rp.bx), args);
+      e = add_kernel_node(g->graph, &last, (const void*)sf_seg_batch, dim3(rp.kgx[(size_t)k], na),
+                          dim3(rp.kbx[(size_t)k]), args);
     }
     if (rp.anym && e == hipSuccess) {
       const ElemDesc* dm = dd + (size_t)rp.kmax * na;
       void* args[] = {(void*)&dm};
+      const dim3 fg(rp.kgx[(size_t)rp.kmax], na), fb(rp.kbx[(size_t)rp.kmax]);
       e = add_kernel_node(g->graph, &last, (const void*)sf_meas_reduce_batch, dim3(rp.gm, na), dim3(EB), args);
-      if (e == hipSuccess)
-        e = add_kernel_node(g->graph, &last, (const void*)sf_meas_filter_batch, dim3(rp.gx, na), dim3(rp.bx), args);
+      if (e == hipSuccess && coin_apart(rp)) {
+        e = add_kernel_node(g->graph, &last, (const void*)sf_meas_coin_batch, dim3(na), dim3(EB), args);
+        if (e == hipSuccess)
+          e = add_kernel_node(g->graph, &last, (const void*)sf_meas_apply_batch, fg, fb, args);
+      } else if (e == hipSuccess) {
+        e = add_kernel_node(g->graph, &last, (const void*)sf_meas_filter_batch, fg, fb, args);
+      }
     }
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);

@@ -417,6 +417,28 @@ extern "C" __global__ void __launch_bounds__(EB) sf_meas_filter_batch(const Elem
   meas_filter_body(e.prog, e.amp, e.amp_other, o, sc, BTID, BSTRIDE);
 }
 
+// The same in two kernels for launches of many frames: the coin once per
+// frame (one block each: the sums, outcome, p(1) and scale of
+// meas_coin_local, stored), then the filter reading outcome and scale back.
+// Same values as the fused kernel, without every filter block summing the
+// partials again.
+extern "C" __global__ void __launch_bounds__(EB) sf_meas_coin_batch(const ElemDesc* __restrict__ D) {
+  const ElemDesc& e = D[blockIdx.x];
+  if (!e.prog) return;
+  uint32_t o;
+  double sc;
+  meas_coin_local(e.prog, e.partials, e.G, e.seedp ? *e.seedp : e.seed, true, e.outcomes, e.pvals, e.scale,
+                  e.flags, &o, &sc);
+}
+
+extern "C" __global__ void __launch_bounds__(EB) sf_meas_apply_batch(const ElemDesc* __restrict__ D) {
+  const ElemDesc& e = D[blockIdx.y];
+  if (!e.prog) return;
+  const uint32_t o = e.outcomes[e.prog->meas_index];
+  const double sc = e.scale[0];
+  meas_filter_body(e.prog, e.amp, e.amp_other, o, sc, BTID, BSTRIDE);
+}
+
 // Frames of at most EB slots: every segment of a round, then its
 // measurement, in one block per frame (segments in order, a barrier between
 // them; each slot's arithmetic is that of the separate launches).

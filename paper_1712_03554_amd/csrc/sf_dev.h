@@ -104,7 +104,8 @@ struct TrackState {
 // per segment); a fit
 // kernel turns each segment's sums into its program's phase E.
 // ginfo[2 i] = segment of gate g0 + i, ginfo[2 i + 1] = index of its GF(2)
-// Hadamard term in had (or -1).  rec == nullptr: everything in the track
+// Hadamard term in had (or -1).  In a dry run (no records) ginfo, if set,
+// receives ginfo[i] = hull dimension on entry to terminal gate g0 + i.  rec == nullptr: everything in the track
 // kernel.
 struct TrackJob {
   TrackState* st;

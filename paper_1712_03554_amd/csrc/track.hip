@@ -1293,6 +1293,9 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
       continue;
     }
     TIC(6);
+    // the load-time dry run records the hull dimension on entry to every
+    // terminal gate (the sizes of the element launches)
+    if (job.dry && job.ginfo && lane == 0) *gmem(job.ginfo + gi) = d;
     // terminal gate of the segment: works on the LDS copy of the tableau
     regs_store(L, TB, n, true);
     hull_to_lds(L, HB, d);
@@ -2513,6 +2516,7 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
       continue;
     }
     TIC(6);
+    if (job.dry && job.ginfo && lane == 0) *gmem(job.ginfo + gi) = d;
     if (rec) {
       // the Clifford steps of the split form keep no b* basis or images
       build_beta(L, n);
