@@ -112,13 +112,21 @@ const char* sf_last_error(const sf_ctx* ctx);
  * rules: Eq. 2 Toffoli, Eq. 3 controlled phase, the T rule of the
  * technology-dependent decompositions); the frame bound follows COFACTOR
  * (section 3: a frame keeps or doubles its size).
- * Validate and load a circuit on n_qubits (1..256).  Qubit indices must be
+ * Validate and load a circuit on n_qubits (1..2048).  Qubit indices must be
  * < n_qubits and distinct within a gate; theta_den != 0 for phase gates.
  * Loading rewrites phase gates whose angle is a multiple of pi/2 into
  * I/S/Z/S-dagger, expands SF_CPHASE and SF_TOF, and runs the tableau track
  * once to bound the frame: every frame of the run has at most 2^bound
  * elements (the dimension of the affine hull of its phase vectors).
- * Returns SF_E_TOO_LARGE when the bound exceeds 29. */
+ * Returns SF_E_TOO_LARGE when the bound exceeds 29.
+ * Circuits on more than 256 qubits must be stabilizer circuits (Clifford
+ * gates, phase gates at multiples of pi/2, measurements; the
+ * random-stabilizer-circuit experiment of section 6), else SF_E_INVALID.
+ * Their frames keep one element (bound 0) with the stabilizer rows in device
+ * memory ("wide" states): they run through sf_step, sf_run, sf_measure and
+ * sf_batch_run (one workgroup per frame), are reset by sf_state_reset and
+ * read by the readout calls; sf_batch_run_noalloc, sf_batch_reset,
+ * sf_batch_graph and sf_serve_submit refuse them with SF_E_INVALID. */
 sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n_qubits, const sf_gate* gates, size_t n_gates,
                           sf_circuit** out);
 /* Not in the paper (admission).  Frame bound (log2) and the device bytes a

@@ -30,6 +30,8 @@
 enum { OP_H, OP_S, OP_SDG, OP_X, OP_Y, OP_Z, OP_CNOT, OP_CZ, OP_T, OP_TDG,
        OP_PHASE, OP_CPHASE, OP_TOF, OP_MEASURE, OP_CPHASE_D, OP_TOF_D };
 
+/* largest register: OW words of 64 qubits (fixed-size scratch vectors) */
+#define OW 32
 #define PRUNE_EPS 1e-12
 #define FRAGILE_AMP 1e-9
 #define FRAGILE_COIN 1e-12
@@ -240,7 +242,7 @@ static void bstar(const bmap_t *B, const uint64_t *sig, uint64_t *out) {
 static int amp_at(tab_t *t, const bmap_t *B, const uint64_t *sig, const uint64_t *bst,
                   const uint64_t *b, cplx *u) {
   int W = t->W, e = 0;
-  uint64_t v[8];
+  uint64_t v[OW];
   memcpy(v, bst, W * 8);
   for (int l = 0; l < B->k; ++l) {
     if (!getbit(b, B->piv[l])) continue;
@@ -360,7 +362,7 @@ static void clifford_columns(tab_t *t, int op, int a, int b, uint64_t *f) {
 
 /* Row b' of the gate matrix: U[b', b] for the (at most two) b with a non-zero
  * entry.  Returns the count. */
-static int gate_row(int op, int a, int c2, const uint64_t *bp, int W, uint64_t bs[2][8], cplx coef[2]) {
+static int gate_row(int op, int a, int c2, const uint64_t *bp, int W, uint64_t bs[2][OW], cplx coef[2]) {
   for (int j = 0; j < 2; ++j) memcpy(bs[j], bp, W * 8);
   int ba = getbit(bp, a);
   const double r2 = 0.70710678118654752440;
@@ -387,7 +389,7 @@ static void frame_clifford(frame_t *F, int op, int a, int b) {
   int W = F->W;
   tab_t old; tab_copy(&old, &F->t);
   bmap_t Bo; bmap_build(&Bo, &old);
-  uint64_t f[8];
+  uint64_t f[OW];
   clifford_columns(&F->t, op, a, b, f);
   oplog L = {0};
   canonicalize(&F->t, &L);
@@ -395,7 +397,7 @@ static void frame_clifford(frame_t *F, int op, int a, int b) {
   double scale = ldexp(1.0, 0);
   int dk = Bn.k - Bo.k; /* 2^{(k'-k)/2} */
   if (dk == 1) scale = sqrt(2.0); else if (dk == -1) scale = sqrt(0.5); else if (dk != 0) abort();
-  uint64_t so[8], sn[8], bo[8], bn[8], bs[2][8];
+  uint64_t so[OW], sn[OW], bo[OW], bn[OW], bs[2][OW];
   cplx coef[2];
   for (size_t j = 0; j < F->K; ++j) {
     memcpy(so, SIG(F, j), W * 8);
@@ -424,7 +426,7 @@ static void frame_clifford(frame_t *F, int op, int a, int b) {
 static int zq_rows(tab_t *t, int q, uint64_t *mask) {
   int W = t->W, k = xblock(t);
   for (int l = 0; l < k; ++l) if (getbit(RX(t, l), q)) return 0;
-  uint64_t tgt[8] = {0};
+  uint64_t tgt[OW] = {0};
   setbit(tgt, q, 1);
   memset(mask, 0, W * 8);
   for (int h = k; h < t->n; ++h) {
@@ -443,7 +445,7 @@ static int zq_rows(tab_t *t, int q, uint64_t *mask) {
  * Returns 1 if the frame was split. */
 static int frame_cofactor(frame_t *F, int q, cplx ph1, int apply_phase) {
   int W = F->W;
-  uint64_t rq[8];
+  uint64_t rq[OW];
   if (zq_rows(&F->t, q, rq)) {
     /* deterministic: qubit value of each element is the parity of its signs
      * on the rows whose product is Z_q. */
@@ -468,7 +470,7 @@ static int frame_cofactor(frame_t *F, int q, cplx ph1, int apply_phase) {
   size_t K = F->K;
   frame_reserve(F, 2 * K);
   const double r2 = 0.70710678118654752440;
-  uint64_t so[8], s1[8], sc[8], bo[8], bn[8];
+  uint64_t so[OW], s1[OW], sc[OW], bo[OW], bn[OW];
   for (size_t j = K; j-- > 0;) {
     memcpy(so, SIG(F, j), W * 8);
     cplx a = F->amp[j];
@@ -504,11 +506,11 @@ static void frame_pauli_masked(frame_t *F, int op, int a, const uint64_t *m1, co
   int W = F->W;
   if (op != OP_X && op != OP_Y && op != OP_Z) abort();
   tab_t t2; tab_copy(&t2, &F->t);
-  uint64_t f[8];
+  uint64_t f[OW];
   clifford_columns(&t2, op, a, 0, f);
   tab_free(&t2);
   bmap_t B; bmap_build(&B, &F->t);
-  uint64_t so[8], sn[8], bo[8], bn[8], bs[2][8];
+  uint64_t so[OW], sn[OW], bo[OW], bn[OW], bs[2][OW];
   cplx coef[2];
   for (size_t j = 0; j < F->K; ++j) {
     memcpy(so, SIG(F, j), W * 8);
@@ -543,7 +545,7 @@ static int frame_cphase_direct(frame_t *F, int c, int t, int64_t num, int64_t de
   const cplx one = {1.0, 0.0};
   frame_cofactor(F, c, one, 0);
   frame_cofactor(F, t, one, 0);
-  uint64_t rc[8], rt[8];
+  uint64_t rc[OW], rt[OW];
   if (!zq_rows(&F->t, c, rc) || !zq_rows(&F->t, t, rt)) abort();
   double th = M_PI * (double)num / (double)den;
   cplx ph = {cos(th), sin(th)};
@@ -558,7 +560,7 @@ static int frame_toffoli_direct(frame_t *F, int c1, int c2, int t) {
   const cplx one = {1.0, 0.0};
   frame_cofactor(F, c1, one, 0);
   frame_cofactor(F, c2, one, 0);
-  uint64_t r1[8], r2[8];
+  uint64_t r1[OW], r2[OW];
   if (!zq_rows(&F->t, c1, r1) || !zq_rows(&F->t, c2, r2)) abort();
   frame_pauli_masked(F, OP_X, t, r1, r2);
   return 0;
@@ -590,7 +592,7 @@ static int frame_measure(frame_t *F, int q) {
   int W = F->W;
   cplx one = {1, 0};
   frame_cofactor(F, q, one, 0);
-  uint64_t rq[8];
+  uint64_t rq[OW];
   if (!zq_rows(&F->t, q, rq)) abort();
   double *v1 = malloc(sizeof(double) * (F->K ? F->K : 1));
   double *v0 = malloc(sizeof(double) * (F->K ? F->K : 1));
@@ -626,7 +628,7 @@ static int frame_measure(frame_t *F, int q) {
 /* Exported C API (loaded by the Python wrapper in oracle/frame.py)           */
 /* ------------------------------------------------------------------------- */
 frame_t *ofr_new(int n, const uint8_t *init_bits, uint64_t seed) {
-  if (n < 1 || n > 512) return NULL;
+  if (n < 1 || n > 64 * OW) return NULL;
   frame_t *F = calloc(1, sizeof(frame_t));
   tab_init(&F->t, n);
   F->n = n; F->W = F->t.W; F->seed = seed;
@@ -761,7 +763,7 @@ int ofr_conjugate_row(int n, int op, int a, int b, uint64_t *x, uint64_t *z) {
   tab_t t; tab_init(&t, n > 1 ? n : 1);
   t.n = 1;
   RX(&t, 0)[0] = *x; RZ(&t, 0)[0] = *z;
-  uint64_t f[8];
+  uint64_t f[OW];
   clifford_columns(&t, op, a, b, f);
   *x = RX(&t, 0)[0]; *z = RZ(&t, 0)[0];
   t.n = n;
@@ -901,7 +903,7 @@ static void mf_merge_equal(mframe_t *M) {
  * new frames appended to M.  Returns the number of pairs coalesced. */
 static size_t frame_coalesce(frame_t *F, mframe_t *M) {
   const int n = F->n, W = F->W;
-  uint64_t zr[8] = {0};
+  uint64_t zr[OW] = {0};
   int *zq = malloc(sizeof(int) * (size_t)n);
   for (int i = 0; i < n; ++i) {
     int xany = 0, zc = 0;
@@ -914,7 +916,7 @@ static size_t frame_coalesce(frame_t *F, mframe_t *M) {
   int *dd = malloc(sizeof(int) * (K ? K : 1));
   for (size_t j = 0; j < K; ++j) part[j] = -1;
   size_t npairs = 0;
-  uint64_t diff[8];
+  uint64_t diff[OW];
   for (size_t r = 0; r < K; ++r) {
     if (part[r] >= 0) continue;
     long best = -1;
@@ -954,10 +956,10 @@ static size_t frame_coalesce(frame_t *F, mframe_t *M) {
     uint8_t *done = calloc(K ? K : 1, 1);
     for (size_t r = 0; r < K; ++r) {
       if (part[r] < 0 || done[r] || (size_t)part[r] < r) continue;
-      uint64_t cls[8];
+      uint64_t cls[OW];
       for (int w = 0; w < W; ++w) cls[w] = SIG(F, r)[w] ^ SIG(F, part[r])[w];
       const int dcls = dd[r];
-      int v[512] = {0}, m = 0;
+      int v[64 * OW] = {0}, m = 0;
       for (int i = 0; i < n; ++i) if (getbit(cls, i)) v[m++] = zq[i];
       /* v ascending */
       for (int a = 0; a < m; ++a)
@@ -1008,7 +1010,7 @@ static size_t frame_coalesce(frame_t *F, mframe_t *M) {
 static int basis_circuit(const tab_t *src, int *gates) {
   tab_t t; tab_copy(&t, src);
   int n = t.n, W = t.W, ng = 0, k = xblock(&t);
-  uint64_t f[8];
+  uint64_t f[OW];
 #define EMIT(o, a, b) do { gates[3 * ng] = (o); gates[3 * ng + 1] = (a); gates[3 * ng + 2] = (b); ++ng; \
                            clifford_columns(&t, (o), (a), (b), f); } while (0)
   int *piv = malloc(sizeof(int) * (n ? n : 1));
@@ -1161,7 +1163,7 @@ static int intersection(tab_t *A, tab_t *B, uint64_t *cA, uint64_t *cB, int *kA,
     ++r;
   }
   int nb = 0;
-  uint64_t gx[8], gz[8];
+  uint64_t gx[OW], gz[OW];
   for (int j = r; j < n; ++j) {
     /* combination cb[j] of B's rows lies in span(A) */
     memcpy(cB + (size_t)nb * W, cb + (size_t)j * W, W * 8);
@@ -1171,7 +1173,7 @@ static int intersection(tab_t *A, tab_t *B, uint64_t *cA, uint64_t *cB, int *kA,
       int col = pa[i];
       if (col < n ? getbit(gx, col) : getbit(gz, col - n)) setbit(cA + (size_t)nb * W, i, 1);
     }
-    uint64_t hx[8], hz[8];
+    uint64_t hx[OW], hz[OW];
     kA[nb] = product_kappa(A, cA + (size_t)nb * W, hx, hz);
     for (int w = 0; w < W; ++w)
       if (hx[w] != gx[w] || hz[w] != gz[w]) { fprintf(stderr, "oracle: intersection element outside span\n"); abort(); }
@@ -1250,7 +1252,7 @@ static int mf_measure(mframe_t *M, int q) {
   size_t tot = 0;
   for (size_t i = 0; i < M->nf; ++i) tot += M->fr[i]->K;
   double *v1 = malloc(sizeof(double) * (tot ? tot : 1)), *v0 = malloc(sizeof(double) * (tot ? tot : 1));
-  uint64_t rq[8];
+  uint64_t rq[OW];
   size_t k = 0;
   for (size_t i = 0; i < M->nf; ++i) {
     frame_t *F = M->fr[i];

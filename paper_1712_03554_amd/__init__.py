@@ -32,7 +32,8 @@ EXPORTS = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_measure", "sf
            "sf_serve_create", "sf_serve_submit", "sf_serve_tick", "sf_serve_poll", "sf_serve_release",
            "sf_serve_cancel", "sf_serve_stats", "sf_serve_destroy"]
 
-KERNEL_KINDS = ["track", "segment", "meas_reduce", "meas_coin", "meas_filter", "readout", "init", "phase", "fit"]
+KERNEL_KINDS = ["track", "segment", "meas_reduce", "meas_coin", "meas_filter", "readout", "init", "phase", "fit",
+                "wide"]
 
 
 class SFrameError(RuntimeError):
@@ -445,21 +446,24 @@ class StateBatch:
 
 def _basis_word_rows(bases, ns: int) -> np.ndarray:
     """Basis bits per state (lists, or an array of 0/1 of shape (states, n))
-    as 4 little-endian 64-bit words per state."""
+    as 4 little-endian 64-bit words per state (the batched calls' layout,
+    which covers 256 qubits; they refuse wider states themselves)."""
     bits = np.zeros((max(1, ns), 256), dtype=np.uint8)
     if isinstance(bases, np.ndarray):
-        bits[:bases.shape[0], :bases.shape[1]] = bases.astype(np.uint8) & 1
+        m = min(256, bases.shape[1])
+        bits[:bases.shape[0], :m] = bases[:, :m].astype(np.uint8) & 1
     else:
         for i, row in enumerate(bases):
             if row is not None and len(row):
-                bits[i, :len(row)] = np.asarray(row, dtype=np.uint8) & 1
+                r = np.asarray(row, dtype=np.uint8)[:256]
+                bits[i, :len(r)] = r & 1
     return np.ascontiguousarray(np.packbits(bits, axis=1, bitorder="little").view(np.uint64))
 
 
 def _basis_words(n: int, bits):
     words = np.zeros(4, dtype=np.uint64)
     if bits is not None:
-        for q, b in enumerate(bits):
+        for q, b in enumerate(bits[:256]):
             if int(b) & 1:
                 words[q >> 6] |= np.uint64(1 << (q & 63))
     return words

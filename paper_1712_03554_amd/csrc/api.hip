@@ -20,8 +20,9 @@
 #include "elem.hip"
 #include "sf_dev.h"
 #include "track.hip"
+#include "wide.hip"
 
-enum { PK_TRACK = 0, PK_SEG, PK_MREDUCE, PK_MFINAL, PK_MFILTER, PK_READOUT, PK_INIT, PK_PHASE, PK_FIT, PK_N };
+enum { PK_TRACK = 0, PK_SEG, PK_MREDUCE, PK_MFINAL, PK_MFILTER, PK_READOUT, PK_INIT, PK_PHASE, PK_FIT, PK_WIDE, PK_N };
 
 struct sf_ctx {
   int device;
@@ -264,6 +265,9 @@ struct DevBuf {
 struct sf_circuit {
   sf_ctx* ctx;
   uint32_t n;
+  // more than SF_NMAX qubits: a stabilizer circuit run by the wide-frame
+  // kernels (one element, rows in device memory), without ranges or segments
+  bool wide = false;
   std::vector<DGate> g;          // device gates (after rewriting)
   std::vector<size_t> orig_end;  // device index one past original gate i
   DevBuf dgates;
@@ -305,6 +309,7 @@ struct sf_state {
   const sf_circuit* c;
   DevBuf st, prog, had, amp[2], outcomes, pvals, scale, flags, partials, ri, count, adhoc;
   DevBuf rec, ginfo, segacc;  // split form of the tableau track
+  DevBuf wbasis;              // wide frames: basis words for (re)initialisation
   int cur;
   size_t orig_done, dev_done, nmeas;
   size_t meas_cap;  // capacity of outcomes / pvals (circuit measurements, grown by sf_measure)
@@ -454,7 +459,7 @@ extern "C" sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n, const sf_gate* gat
                                      sf_circuit** out) {
   if (!ctx || !out) return SF_E_INVALID;
   *out = nullptr;
-  if (n < 1 || n > SF_NMAX) return fail(ctx, SF_E_INVALID, "qubit count %u outside 1..%d", n, SF_NMAX);
+  if (n < 1 || n > SF_WIDE_NMAX) return fail(ctx, SF_E_INVALID, "qubit count %u outside 1..%d", n, SF_WIDE_NMAX);
   if (ng && !gates) return fail(ctx, SF_E_INVALID, "null gate list");
   sf_circuit* c = new (std::nothrow) sf_circuit();
   if (!c) return fail(ctx, SF_E_OOM, "host allocation failed");
@@ -554,6 +559,34 @@ extern "C" sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n, const sf_gate* gat
         return bad("unknown operation");
     }
     c->orig_end.push_back(c->g.size());
+  }
+  if (n > SF_NMAX) {
+    // wide frame: Clifford gates and measurements only
+    for (size_t i = 0; i < c->g.size(); ++i)
+      if (c->g[i].op >= DG_NCPHASE && c->g[i].op != DG_MEASURE) {
+        delete c;
+        return fail(ctx, SF_E_INVALID, "frames of more than %d qubits take stabilizer circuits only "
+                    "(device gate %zu is not Clifford)", SF_NMAX, i);
+      }
+    c->wide = true;
+    c->dmax = 0;
+    c->max_segs = 1;
+    c->max_had = 1;
+    c->rec_len = 1;
+    sf_status rc = dalloc(ctx, &c->dgates, sizeof(DGate) * std::max<size_t>(1, c->g.size()));
+    hipError_t e = hipSuccess;
+    if (rc == SF_OK && !c->g.empty())
+      e = hipMemcpyAsync(c->dgates.p, c->g.data(), sizeof(DGate) * c->g.size(), hipMemcpyHostToDevice, ctx->stream);
+    if (rc == SF_OK && e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (rc != SF_OK || e != hipSuccess) {
+      dfree(ctx, &c->dgates);
+      delete c;
+      return rc != SF_OK ? rc : fail(ctx, SF_E_DEVICE, "gate upload: %s", hipGetErrorString(e));
+    }
+    const size_t W = words_of(n);
+    c->projected = wide_layout((int)n).bytes + (4 * (size_t)n * W + W + 2) * 8 + 2 * c->n_meas * 9 + 64;
+    *out = c;
+    return SF_OK;
   }
   // range planning: ranges end after each measurement
   c->max_segs = 1;
@@ -679,12 +712,29 @@ static void state_free(sf_state* s) {
   sf_ctx* ctx = s->ctx;
   DevBuf* all[] = {&s->st, &s->prog, &s->had, &s->amp[0], &s->amp[1], &s->outcomes, &s->pvals,
                    &s->scale, &s->flags, &s->partials, &s->ri, &s->count, &s->adhoc,
-                   &s->rec, &s->ginfo, &s->segacc};
+                   &s->rec, &s->ginfo, &s->segacc, &s->wbasis};
   for (DevBuf* b : all) dfree(ctx, b);
 }
 
 static sf_status queue_init(sf_state* s, const uint64_t* basis, uint64_t seed) {
   sf_ctx* ctx = s->ctx;
+  if (s->c->wide) {
+    const int n = (int)s->c->n, W = words_of(s->c->n);
+    std::vector<uint64_t> b(W, 0);
+    if (basis)
+      for (int w = 0; w < W; ++w) b[w] = basis[w];
+    s->cur = 0;
+    s->orig_done = s->dev_done = s->nmeas = 0;
+    s->seed = seed;
+    HIPCHK(ctx, hipMemcpyAsync(s->wbasis.p, b.data(), W * 8, hipMemcpyHostToDevice, ctx->stream));
+    prof_begin(ctx, PK_INIT);
+    hipLaunchKernelGGL(sf_wide_init, dim3(1), dim3(WT), 0, ctx->stream, (unsigned char*)s->st.p, n,
+                       (const uint64_t*)s->wbasis.p, seed, (int*)s->flags.p);
+    prof_end(ctx);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return SF_OK;
+  }
   uint64_t b[4] = {0, 0, 0, 0};
   const int W = (int)((s->c->n + 63) / 64);
   if (basis)
@@ -708,6 +758,10 @@ extern "C" sf_status sf_state_reset(sf_state* s, const uint64_t* basis, uint64_t
 extern "C" sf_status sf_state_cycles(sf_state* s, uint64_t* cycles, int n) {
   if (!s || !cycles) return SF_E_INVALID;
   sf_ctx* ctx = s->ctx;
+  if (s->c->wide) {
+    for (int k = 0; k < n && k < 16; ++k) cycles[k] = 0;
+    return SF_OK;
+  }
   uint64_t c[16];
   HIPCHK(ctx, hipMemcpyAsync(c, (char*)s->st.p + offsetof(TrackState, cycles), sizeof c, hipMemcpyDeviceToHost,
                              ctx->stream));
@@ -719,6 +773,10 @@ extern "C" sf_status sf_state_cycles(sf_state* s, uint64_t* cycles, int n) {
 extern "C" sf_status sf_state_dim(sf_state* s, uint32_t* d) {
   if (!s || !d) return SF_E_INVALID;
   sf_ctx* ctx = s->ctx;
+  if (s->c->wide) {
+    *d = 0;
+    return SF_OK;
+  }
   int hdr[16];
   HIPCHK(ctx, hipMemcpyAsync(hdr, s->st.p, sizeof hdr, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -742,6 +800,30 @@ extern "C" sf_status sf_state_init(sf_ctx* ctx, const sf_circuit* c, const uint6
   s->meas_cap = std::max<size_t>(1, c->n_meas);
   s->graph_refs = 0;
   sf_status rc = SF_OK;
+  if (c->wide) {
+    const size_t W = words_of(c->n);
+    if ((rc = dalloc(ctx, &s->st, wide_layout((int)c->n).bytes)) ||
+        (rc = dalloc(ctx, &s->outcomes, std::max<size_t>(1, c->n_meas))) ||
+        (rc = dalloc(ctx, &s->pvals, 8 * std::max<size_t>(1, c->n_meas))) || (rc = dalloc(ctx, &s->flags, 8)) ||
+        (rc = dalloc(ctx, &s->ri, (4 * (size_t)c->n * W + W + 2) * 8)) || (rc = dalloc(ctx, &s->wbasis, W * 8))) {
+      state_free(s);
+      delete s;
+      return rc;
+    }
+    sf_status r2 = queue_init(s, basis, seed);
+    if (r2 == SF_OK) {
+      hipError_t e = hipMemsetAsync(s->outcomes.p, 0, std::max<size_t>(1, c->n_meas), ctx->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+      if (e != hipSuccess) r2 = fail(ctx, SF_E_DEVICE, "state init: %s", hipGetErrorString(e));
+    }
+    if (r2 != SF_OK) {
+      state_free(s);
+      delete s;
+      return r2;
+    }
+    *out = s;
+    return SF_OK;
+  }
   size_t ampb = (size_t)16 << c->dmax;
   if ((rc = dalloc(ctx, &s->st, sizeof(TrackState))) ||
       (rc = dalloc(ctx, &s->prog, sizeof(SegProg) * (size_t)c->max_segs)) ||
@@ -838,6 +920,23 @@ static sf_status run_chunk(sf_state* s, const DGate* dgates, const DGate* hg, si
     else { open = true; meas_last = false; }
   }
   if (open) ++nseg;
+  if (c->wide) {
+    WideJob job;
+    memset(&job, 0, sizeof job);
+    job.base = (unsigned char*)s->st.p;
+    job.gates = dgates;
+    job.g0 = (int)a;
+    job.g1 = (int)b;
+    job.outcomes = (uint8_t*)s->outcomes.p;
+    job.pvals = (double*)s->pvals.p;
+    job.flags = (int*)s->flags.p;
+    prof_begin(ctx, PK_WIDE);
+    hipLaunchKernelGGL(sf_wide_one, dim3(1), dim3(WT), 0, ctx->stream, job);
+    prof_end(ctx);
+    HIPCHK(ctx, hipGetLastError());
+    s->nmeas += nm;
+    return SF_OK;
+  }
   if (nseg > c->max_segs || b - a > (size_t)c->rec_len)
     return fail(ctx, SF_E_STATE, "range of %zu gates with %d segments exceeds the state's buffers", b - a, nseg);
   // one frame: the split form pays for every width
@@ -974,10 +1073,12 @@ extern "C" sf_status sf_measure(sf_state* s, uint32_t q, int* outcome) {
   g.op = DG_MEASURE;
   g.q0 = (int)q;
   HIPCHK(ctx, hipMemcpyAsync(s->adhoc.p, &g, sizeof g, hipMemcpyHostToDevice, ctx->stream));
+  hipError_t e = hipSuccess;
+  if (!c->wide) {
   // dry pass: this measurement, then the rest of the circuit
   DevBuf tmp;
   if ((rc = dalloc(ctx, &tmp, sizeof(TrackState)))) return rc;
-  hipError_t e = hipMemcpyAsync(tmp.p, s->st.p, sizeof(TrackState), hipMemcpyDeviceToDevice, ctx->stream);
+  e = hipMemcpyAsync(tmp.p, s->st.p, sizeof(TrackState), hipMemcpyDeviceToDevice, ctx->stream);
   for (int part = 0; part < 2 && e == hipSuccess; ++part) {
     TrackJob job;
     memset(&job, 0, sizeof job);
@@ -1001,6 +1102,7 @@ extern "C" sf_status sf_measure(sf_state* s, uint32_t q, int* outcome) {
     return fail(ctx, SF_E_TOO_LARGE, "after measuring qubit %u the rest of the circuit needs 2^%d elements, "
                 "the state holds 2^%d", q, dmax_after, c->dmax);
   if (terr) return fail(ctx, SF_E_DEVICE, "tableau track reported internal error %d", terr);
+  }
   // room for this outcome and for those of the circuit's remaining
   // measurements, whose indices it shifts by one
   size_t rem = 0;
@@ -1062,6 +1164,10 @@ extern "C" sf_status sf_outcomes(sf_state* s, uint8_t* out, size_t cap, size_t* 
 extern "C" sf_status sf_frame_size(sf_state* s, uint64_t* K) {
   if (!s || !K) return SF_E_INVALID;
   sf_ctx* ctx = s->ctx;
+  if (s->c->wide) {
+    *K = 1;
+    return check_track(s);
+  }
   HIPCHK(ctx, hipMemsetAsync(s->count.p, 0, 8, ctx->stream));
   hipLaunchKernelGGL(sf_count_kernel, dim3(grid_for(s->c->dmax)), dim3(EB), 0, ctx->stream,
                      (const TrackState*)s->st.p, (const double2*)s->amp[s->cur].p,
@@ -1092,6 +1198,24 @@ extern "C" sf_status sf_read_frame(sf_state* s, uint64_t* tableau, uint64_t* sig
   sf_ctx* ctx = s->ctx;
   sf_status rc = check_track(s);
   if (rc != SF_OK) return rc;
+  if (s->c->wide) {
+    const size_t n = s->c->n, W = words_of(s->c->n);
+    uint64_t* out = (uint64_t*)s->ri.p;
+    prof_begin(ctx, PK_READOUT);
+    hipLaunchKernelGGL(sf_wide_readout, dim3(1), dim3(WT), 0, ctx->stream, (const unsigned char*)s->st.p, out,
+                       out + n * 2 * W + W + 2);
+    prof_end(ctx);
+    HIPCHK(ctx, hipGetLastError());
+    std::vector<uint64_t> h(n * 2 * W + W + 2);
+    HIPCHK(ctx, hipMemcpyAsync(h.data(), out, h.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (K_out) *K_out = 1;
+    if (tableau && cap >= 1) memcpy(tableau, h.data(), n * 2 * W * 8);
+    if (cap < 1) return fail(ctx, SF_E_BUFSIZE, "frame has 1 element, buffer holds 0");
+    if (sigma) memcpy(sigma, h.data() + n * 2 * W, W * 8);
+    if (amp) memcpy(amp, h.data() + n * 2 * W + W, 16);
+    return SF_OK;
+  }
   hipLaunchKernelGGL(sf_readout_track, dim3(1), dim3(TL), 0, ctx->stream, (const TrackState*)s->st.p,
                      (const uint8_t*)s->outcomes.p, (ReadoutInfo*)s->ri.p);
   HIPCHK(ctx, hipGetLastError());
@@ -1622,14 +1746,75 @@ static sf_status check_tracks(sf_ctx* ctx, sf_state* const* states, size_t ns, v
   return SF_OK;
 }
 
-extern "C" sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t ns) {
-  if (!ctx || (ns && !states)) return SF_E_INVALID;
-  int maxseg = 1;
-  for (size_t i = 0; i < ns; ++i) {
-    if (!states[i] || states[i]->ctx != ctx) return fail(ctx, SF_E_INVALID, "state %zu is not of this context", i);
-    maxseg = std::max(maxseg, states[i]->c->max_segs);
+// Wide frames of a batch: the rest of each circuit, one workgroup per frame in
+// one launch.
+static sf_status run_wide_batch(sf_ctx* ctx, const std::vector<sf_state*>& ws, DevBuf* djobs) {
+  if (ws.empty()) return SF_OK;
+  std::vector<WideJob> jobs(ws.size());
+  std::vector<size_t> nm(ws.size(), 0);
+  for (size_t i = 0; i < ws.size(); ++i) {
+    sf_state* s = ws[i];
+    const sf_circuit* c = s->c;
+    for (size_t g = s->dev_done; g < c->g.size(); ++g) nm[i] += c->g[g].op == DG_MEASURE;
+    if (s->nmeas + nm[i] > s->meas_cap)
+      return fail(ctx, SF_E_STATE, "outcome buffer holds %zu measurements, %zu needed", s->meas_cap, s->nmeas + nm[i]);
+    WideJob& j = jobs[i];
+    memset(&j, 0, sizeof j);
+    j.base = (unsigned char*)s->st.p;
+    j.gates = (const DGate*)c->dgates.p;
+    j.g0 = (int)s->dev_done;
+    j.g1 = (int)c->g.size();
+    j.outcomes = (uint8_t*)s->outcomes.p;
+    j.pvals = (double*)s->pvals.p;
+    j.flags = (int*)s->flags.p;
   }
-  if (ns == 0) return SF_OK;
+  sf_status rc = dalloc(ctx, djobs, jobs.size() * sizeof(WideJob));
+  if (rc != SF_OK) return rc;
+  HIPCHK(ctx, hipMemcpyAsync(djobs->p, jobs.data(), jobs.size() * sizeof(WideJob), hipMemcpyHostToDevice, ctx->stream));
+  prof_begin(ctx, PK_WIDE);
+  hipLaunchKernelGGL(sf_wide_run, dim3((unsigned)jobs.size()), dim3(WT), 0, ctx->stream, (const WideJob*)djobs->p);
+  prof_end(ctx);
+  HIPCHK(ctx, hipGetLastError());
+  for (size_t i = 0; i < ws.size(); ++i) {
+    sf_state* s = ws[i];
+    s->nmeas += nm[i];
+    s->orig_done = s->c->orig_end.size();
+    s->dev_done = s->c->g.size();
+  }
+  return SF_OK;
+}
+
+static bool any_wide(sf_state* const* states, size_t ns) {
+  for (size_t i = 0; i < ns; ++i)
+    if (states[i] && states[i]->c->wide) return true;
+  return false;
+}
+
+extern "C" sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* all, size_t ns_all) {
+  if (!ctx || (ns_all && !all)) return SF_E_INVALID;
+  int maxseg = 1;
+  std::vector<sf_state*> reg, wsts;
+  for (size_t i = 0; i < ns_all; ++i) {
+    if (!all[i] || all[i]->ctx != ctx) return fail(ctx, SF_E_INVALID, "state %zu is not of this context", i);
+    (all[i]->c->wide ? wsts : reg).push_back(all[i]);
+    if (!all[i]->c->wide) maxseg = std::max(maxseg, all[i]->c->max_segs);
+  }
+  if (ns_all == 0) return SF_OK;
+  DevBuf wj;
+  sf_status wrc = run_wide_batch(ctx, wsts, &wj);
+  if (wrc != SF_OK) {
+    (void)hipStreamSynchronize(ctx->stream);
+    dfree(ctx, &wj);
+    return wrc;
+  }
+  if (reg.empty()) {
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    dfree(ctx, &wj);
+    if (e != hipSuccess) return fail(ctx, SF_E_DEVICE, "batch run: %s", hipGetErrorString(e));
+    return check_tracks(ctx, all, ns_all);
+  }
+  sf_state* const* states = reg.data();
+  const size_t ns = reg.size();
   BatchScratch bs;
   sf_status rc = scratch_reserve(ctx, &bs, ns, maxseg);
   int active = 1;
@@ -1637,13 +1822,16 @@ extern "C" sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t n
   hipError_t e = hipStreamSynchronize(ctx->stream);
   pin_release(ctx);
   scratch_free(ctx, &bs);
+  dfree(ctx, &wj);
   if (rc != SF_OK) return rc;
   if (e != hipSuccess) return fail(ctx, SF_E_DEVICE, "batch run: %s", hipGetErrorString(e));
-  return check_tracks(ctx, states, ns);
+  return check_tracks(ctx, all, ns_all);
 }
 
 extern "C" sf_status sf_batch_run_noalloc(sf_ctx* ctx, sf_state* const* states, size_t ns) {
   if (!ctx || (ns && !states)) return SF_E_INVALID;
+  if (any_wide(states, ns)) return fail(ctx, SF_E_INVALID, "frames of more than %d qubits run through sf_run, sf_step "
+                                        "and sf_batch_run", SF_NMAX);
   int maxseg = 1;
   for (size_t i = 0; i < ns; ++i) {
     if (!states[i] || states[i]->ctx != ctx) return fail(ctx, SF_E_INVALID, "state %zu is not of this context", i);
@@ -1682,6 +1870,8 @@ extern "C" sf_status sf_batch_reset(sf_ctx* ctx, sf_state* const* states, size_t
                                     const uint64_t* seeds) {
   if (!ctx || (ns && !states)) return SF_E_INVALID;
   if (ns == 0) return SF_OK;
+  if (any_wide(states, ns)) return fail(ctx, SF_E_INVALID, "frames of more than %d qubits are reset by sf_state_reset",
+                                        SF_NMAX);
   for (size_t i = 0; i < ns; ++i)
     if (!states[i] || states[i]->ctx != ctx) return fail(ctx, SF_E_INVALID, "state %zu is not of this context", i);
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -1847,6 +2037,8 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
   *out = nullptr;
   for (size_t i = 0; i < ns; ++i)
     if (!states[i] || states[i]->ctx != ctx) return fail(ctx, SF_E_INVALID, "state %zu is not of this context", i);
+  if (any_wide(states, ns)) return fail(ctx, SF_E_INVALID, "frames of more than %d qubits run through sf_run, sf_step "
+                                        "and sf_batch_run", SF_NMAX);
   {
     std::vector<sf_state*> srt(states, states + ns);
     std::sort(srt.begin(), srt.end());
@@ -2065,6 +2257,8 @@ static ServeJob* find_job(sf_server* sv, uint64_t id) {
 extern "C" sf_status sf_serve_submit(sf_server* sv, const sf_circuit* c, const uint64_t* basis, uint64_t seed,
                                      uint64_t* job_id) {
   if (!sv || !c || !job_id) return SF_E_INVALID;
+  if (c->wide) return fail(sv->ctx, SF_E_INVALID, "frames of more than %d qubits run through sf_run, sf_step and "
+                           "sf_batch_run", SF_NMAX);
   if (sv->budget && c->projected > sv->budget) {
     sv->rejected++;
     return fail(sv->ctx, SF_E_TOO_LARGE, "job needs %llu bytes, budget is %llu",

@@ -86,6 +86,17 @@ def oracle_config2(job: int):
     return tab, sig, amp, f.outcomes(), f.fragile
 
 
+def oracle_stabilizer(n: int, circuit_seed: int, beta: float, seed: int):
+    """Oracle frame (tableau, sigma, amp), outcomes and fragile flag of the
+    random stabilizer circuit of n qubits (for process pools)."""
+    from oracle.frame import OracleFrame
+    from paper_1712_03554_amd import workloads as wl
+    c = wl.stabilizer_circuit(n, circuit_seed, beta)
+    f = OracleFrame(c.n, c.init_bits, seed)
+    f.run(c.array())
+    return f.read(), f.outcomes(), f.fragile
+
+
 def oracle_pool(workers: int = 16):
     """A process pool for oracle runs (spawned: no state of the parent's GPU
     runtime is inherited), at most `workers` processes."""

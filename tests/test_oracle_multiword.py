@@ -12,8 +12,8 @@ the oracle itself:
   (conjugation by each Clifford gate; a random cofactor keeps the commutant
   of Z_q and adds Z_q), run here on plain 0/1 arrays;
 * a circuit on a few qubits gives the same frame when its qubits are spread
-  over a wide register across the 63/64, 127/128 and 191/192 word
-  boundaries: the wide tableau restricted to those qubits equals the narrow
+  over a wide register across the 63/64, 127/128, 191/192, 511/512 and
+  1023/1024 word boundaries (registers of up to 1100 qubits): the wide tableau restricted to those qubits equals the narrow
   one, the other rows are Z_q, the phase vectors agree on the matching rows,
   the outcomes and amplitudes agree, and the narrow frame read back out of
   the wide one expands to the narrow circuit's dense state vector;
@@ -131,7 +131,7 @@ def test_invariants_at_every_gate_wide(n, n_t):
     assert np.array_equal(tableau_bits(tab, n), _track(n, c.gates))
 
 
-@pytest.mark.parametrize("n", [130, 256])
+@pytest.mark.parametrize("n", [130, 256, 600])
 def test_tableau_matches_group_recursion_long_circuit(n):
     """Many gates on a wide register: the unsigned matrix equals the group
     recursion, checked at several points of the run."""
@@ -155,6 +155,8 @@ EMBEDDINGS = [
     (200, [1, 63, 64, 126, 127, 128, 191, 192]),
     (256, [0, 63, 64, 127, 128, 191, 192, 255]),
     (256, [60, 61, 62, 63, 64, 65, 66, 67]),
+    (700, [0, 255, 256, 511, 512, 513, 640, 699]),
+    (1100, [63, 64, 511, 512, 1023, 1024, 1025, 1099]),
 ]
 
 
