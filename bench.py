@@ -122,6 +122,8 @@ def _workload_circuit(kind, idx):
         return wl.config4(idx), wl.derive_seed(4, idx)
     if kind == "cfg2":
         return wl.config2(idx), wl.derive_seed(2, idx)
+    if kind == "stab512":
+        return wl.stabilizer_circuit(512, 9300 + 17 * 512 + idx % 4), idx
     return wl.config5_job(idx), wl.derive_seed(5, idx) ^ 0x5E
 
 
@@ -169,6 +171,8 @@ def cpu_baseline(circ, seed):
             ("Steane fault-injection trials", "steane", list(range(4096)), "all 4096 trials"),
             ("uneven random Clifford+T", "uneven", list(range(128)),
              "the first 128 of the 1024 circuits (n in 16..256)"),
+            ("stabilizer circuits n=512 (beta = 1, then every qubit measured)", "stab512",
+             list(range(workers)), f"{workers} circuits (4 distinct gate lists, one seed each), one per core"),
             ("served mix", "serve", serve_idx,
              f"the {len(serve_idx)} AQFT and uneven-shaped requests of the 48-request stream (the Cuccaro "
              "adders, 2^18..2^66 elements, take minutes to hours each on the oracle and are left out)")]
@@ -183,6 +187,58 @@ def cpu_baseline(circ, seed):
                                      "cores": workers, "kind": "oracle", "U": Us, "wall_s": wall,
                                      "cpu_s": sum(r[1] for r in res), "requests_per_s": len(idx) / wall,
                                      "sample": sample})
+    return out
+
+
+def clifford_only_wide(eng, wl, sizes=(512, 1024, 1500), frames=256, distinct=4, reps=2):
+    """The Clifford-only workload on frames of more than 256 qubits (rows in
+    device memory, one workgroup per frame): one circuit alone, and `frames`
+    circuits (`distinct` gate lists, one seed per frame) in one batched run.
+    U = gates applied (one element)."""
+    import torch
+    out = []
+    for n in sizes:
+        circs = [wl.stabilizer_circuit(n, 9300 + 17 * n + j) for j in range(distinct)]
+        loaded = [eng.load(c.n, c) for c in circs]
+        states = [loaded[j % distinct].state(circs[j % distinct].init_bits, j) for j in range(frames)]
+        G = sum(len(circs[j % distinct]) for j in range(frames))
+        st = states[0]
+        st.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st.reset(circs[0].init_bits, 0)
+            st.run()
+        torch.cuda.synchronize()
+        alone_s = (time.perf_counter() - t0) / reps
+
+        def reset_all():
+            for j, s in enumerate(states):
+                s.reset(circs[j % distinct].init_bits, j)
+
+        reset_all()
+        eng.batch_run(states)
+        torch.cuda.synchronize()
+        tot = 0.0
+        eng.profile(True, ["wide"])
+        for _ in range(reps):
+            reset_all()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            eng.batch_run(states)
+            torch.cuda.synchronize()
+            tot += time.perf_counter() - t0
+        kms, kn = eng.profile_read()["wide"]
+        eng.profile(False)
+        batch_s = tot / reps
+        out.append({"workload": f"stabilizer circuits n={n}, {len(circs[0])} gates incl. {n} measurements",
+                    "alone_ms_per_circuit": alone_s * 1e3, "alone_us_per_gate": alone_s / len(circs[0]) * 1e6,
+                    "alone_gates_per_s": len(circs[0]) / alone_s, "batched_frames": frames,
+                    "batched_ms": batch_s * 1e3, "batched_gates_per_s": G / batch_s,
+                    "kernel_ms_per_launch": kms / max(1, kn),
+                    "frame_sizes_after": sorted({s.frame_size() for s in states[:8]})})
+        for s in states:
+            s.close()
     return out
 
 
@@ -701,7 +757,7 @@ def main():
         line["direct_forms"] = direct_vs_decomposed(eng, wl)
         line["element_hbm_probe"] = hbm_probe(eng, wl)
         line["large_frame"] = large_frame(eng, wl)
-        line["clifford_only"] = clifford_only(eng, wl)
+        line["clifford_only"] = clifford_only(eng, wl) + clifford_only_wide(eng, wl)
     if args.serve_jobs > 0:
         line["serve"] = serve_bench(eng, sf, wl, args.serve_jobs, args.tick_segments, args.max_resident,
                                     int(args.serve_budget_gib * (1 << 30)))

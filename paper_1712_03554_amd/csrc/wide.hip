@@ -87,13 +87,16 @@ struct WideJob {
 
 struct WideLds {
   uint64_t sig[SF_WIDE_WMAX], bst[SF_WIDE_WMAX], s[SF_WIDE_WMAX];
-  uint64_t xlm[SF_WIDE_WMAX], zlm[SF_WIDE_WMAX];
+  // candidate columns of the repair and z bits of rows that left the X-block
+  // (bit b: x column b for b < 64 W, z column b - 64 W above)
+  uint64_t cand[2 * SF_WIDE_WMAX], zpend[SF_WIDE_WMAX];
   uint64_t px[WWAVES][SF_WIDE_WMAX], pz[WWAVES][SF_WIDE_WMAX];
   int pe[WWAVES];
+  int cnt[2 * SF_WIDE_NMAX];      // rows leading at each column (same bit index)
   int16_t lead[SF_WIDE_NMAX];
   int16_t list[SF_WIDE_NMAX];
   double2 amp;
-  int nlist, best, piv, kx, err, ue, tex;
+  int nlist, best, piv, pmin, kx, err, ue, tex;
 };
 
 namespace wide {
@@ -147,90 +150,192 @@ __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_dou
 
 struct Frame {
   int n, W;
+  int seg, rpw;   // lanes per row (power of two >= W) and rows per wavefront step
   uint64_t* rx;
   uint64_t* rz;
 };
 
-// Repair the form after the rows in the listed columns changed: repeatedly
-// take the smallest lead column that another row of its block also has (or
-// that two rows lead at), and multiply the lowest slot leading there into
-// every other such row.  Each step clears a column that no later step
-// touches, so at most 2n steps run.  Leaves L.kx = X-block size.
-__device__ void repair(WideLds& L, const Frame& F) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int n = F.n, W = F.W;
-  for (int guard = 0; guard <= 2 * n + 1; ++guard) {
-    for (int w = tid; w < W; w += WT) { L.xlm[w] = 0; L.zlm[w] = 0; }
-    if (tid == 0) { L.best = 0x7fffffff; L.kx = 0; }
-    __syncthreads();
-    int kl = 0;
-    for (int i = tid; i < n; i += WT) {
-      const int ld = L.lead[i];
-      if (ld < 0) { atomicOr(&L.err, 1 << E_FORM); continue; }
-      const int q = ld < n ? ld : ld - n;
-      const unsigned long long bit = 1ull << (q & 63);
-      const unsigned long long old = atomicOr((unsigned long long*)(ld < n ? &L.xlm[q >> 6] : &L.zlm[q >> 6]), bit);
-      if (old & bit) atomicMin(&L.best, ld);
-      kl += ld < n;
+// bit index of a lead column: x column q -> q, z column n + q -> 64 W + q
+__device__ __forceinline__ int cbit(const Frame F, int col) { return col < F.n ? col : 64 * F.W + (col - F.n); }
+
+// A row's lead changes (by its owning thread): lead counts, X-block size and
+// the candidate set follow.
+__device__ __forceinline__ void set_lead(WideLds& L, const Frame F, int i, int nl) {
+  const int old = L.lead[i];
+  if (old == nl) return;
+  if (old >= 0) atomicSub(&L.cnt[cbit(F, old)], 1);
+  if (nl >= 0) {
+    const int b = cbit(F, nl);
+    atomicAdd(&L.cnt[b], 1);
+    atomicOr((unsigned long long*)&L.cand[b >> 6], 1ull << (b & 63));
+  }
+  const int dx = (nl >= 0 && nl < F.n) - (old >= 0 && old < F.n);
+  if (dx) atomicAdd(&L.kx, dx);
+  L.lead[i] = (int16_t)nl;
+}
+
+// Add to the candidates the bits of v (word w of the candidate index) that
+// are lead columns.
+__device__ __forceinline__ void add_lead_bits(WideLds& L, int w, uint64_t v) {
+  uint64_t keep = 0;
+  while (v) {
+    const int b = __builtin_ctzll(v);
+    v &= v - 1;
+    if (L.cnt[64 * w + b] > 0) keep |= 1ull << b;
+  }
+  if (keep) atomicOr((unsigned long long*)&L.cand[w], keep);
+}
+
+// Full scan of one row's lead (one thread).
+__device__ int row_lead_scan(const Frame F, int i) {
+  const uint64_t* X = F.rx + (size_t)i * F.W;
+  const uint64_t* Z = F.rz + (size_t)i * F.W;
+  for (int w = 0; w < F.W; ++w)
+    if (X[w]) return 64 * w + __builtin_ctzll(X[w]);
+  for (int w = 0; w < F.W; ++w)
+    if (Z[w]) return F.n + 64 * w + __builtin_ctzll(Z[w]);
+  return -1;
+}
+
+// Multiply row m into every row of L.list[0..nlist) except m (lanes over
+// words, rows in aligned lane segments): signs into sigma, leads and the
+// candidates follow; rows that leave the X-block put their z bits in zpend.
+__device__ void absorb(WideLds& L, const Frame F, int m) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n = F.n, W = F.W, seg = F.seg, rpw = F.rpw;
+  const int r = lane / seg, w = lane % seg, l0 = r * seg;
+  const uint64_t smask = (seg == 64 ? ~0ull : ((1ull << seg) - 1)) << l0;
+  const uint64_t xm = w < W ? F.rx[(size_t)m * W + w] : 0ull;
+  const uint64_t zm = w < W ? F.rz[(size_t)m * W + w] : 0ull;
+  const int sm = bitof(L.sig, m);
+  const int nh = L.nlist;
+  // KP row groups per step, their words loaded up front
+  constexpr int KP = 4;
+  const int stride = WWAVES * rpw;
+  for (int j0 = wv * rpw; j0 < nh; j0 += KP * stride) {
+    uint64_t xs[KP], zs[KP];
+#pragma unroll
+    for (int t = 0; t < KP; ++t) {
+      const int j = j0 + t * stride + r;
+      const int i = j < nh ? L.list[j] : m;
+      const bool ok = j < nh && i != m && w < W;
+      xs[t] = ok ? F.rx[(size_t)i * W + w] : 0ull;
+      zs[t] = ok ? F.rz[(size_t)i * W + w] : 0ull;
     }
-    kl = wave_sum(kl);
-    if (lane == 0) atomicAdd(&L.kx, kl);
-    __syncthreads();
-    for (int i = tid; i < n; i += WT) {
-      const int ld = L.lead[i];
-      int cand = 0x7fffffff;
-      if (ld >= 0 && ld < n) {
-        const uint64_t* X = F.rx + (size_t)i * W;
-        for (int w = 0; w < W; ++w) {
-          uint64_t m = X[w] & L.xlm[w];
-          if (w == (ld >> 6)) m &= ~(1ull << (ld & 63));
-          if (m) { cand = 64 * w + __builtin_ctzll(m); break; }
-        }
-      } else if (ld >= n) {
-        const int q = ld - n;
-        const uint64_t* Z = F.rz + (size_t)i * W;
-        for (int w = 0; w < W; ++w) {
-          uint64_t m = Z[w] & L.zlm[w];
-          if (w == (q >> 6)) m &= ~(1ull << (q & 63));
-          if (m) { cand = n + 64 * w + __builtin_ctzll(m); break; }
-        }
+#pragma unroll
+    for (int t = 0; t < KP; ++t) {
+      const int j = j0 + t * stride + r;
+      const int i = j < nh ? L.list[j] : m;
+      const bool act = j < nh && i != m;
+      const bool ok = act && w < W;
+      const int old = L.lead[i];
+      const uint64_t x = xs[t], z = zs[t];
+      int e = ok ? gword(x, z, xm, zm) : 0;
+      for (int o = seg >> 1; o > 0; o >>= 1) e += __shfl_xor(e, o);
+      const uint64_t nx = x ^ xm, nz = z ^ zm;
+      if (ok) { F.rx[(size_t)i * W + w] = nx; F.rz[(size_t)i * W + w] = nz; }
+      const uint64_t xb = __ballot(ok && nx != 0ull) & smask;
+      const uint64_t zb = __ballot(ok && nz != 0ull) & smask;
+      const int myc = xb ? (nx ? __builtin_ctzll(nx) : 64) : (nz ? __builtin_ctzll(nz) : 64);
+      const int src = xb ? __builtin_ctzll(xb) : zb ? __builtin_ctzll(zb) : lane;
+      const int c = __shfl(myc, src);
+      const bool toz = act && old < n && xb == 0ull;
+      if (ok && toz && nz) atomicOr((unsigned long long*)&L.zpend[w], nz);
+      if (act && lane == l0) {
+        const int nl = xb ? 64 * (src - l0) + c : zb ? n + 64 * (src - l0) + c : -1;
+        set_lead(L, F, i, nl);
+        if (sm ^ ((e & 3) >> 1)) atomicXor((unsigned long long*)&L.sig[i >> 6], 1ull << (i & 63));
       }
-      if (cand != 0x7fffffff) atomicMin(&L.best, cand);
+    }
+  }
+}
+
+// Rows with a bit at column col (z columns: Z-block rows only, unless all)
+// into L.list; L.piv = lowest slot leading at col, L.pmin = lowest slot in
+// the list.
+__device__ void collect(WideLds& L, const Frame F, int col, bool all) {
+  const int tid = threadIdx.x, n = F.n, W = F.W;
+  if (tid == 0) { L.nlist = 0; L.piv = 0x7fffffff; L.pmin = 0x7fffffff; }
+  __syncthreads();
+  const bool xcol = col < n;
+  const int q = xcol ? col : col - n;
+  const uint64_t* base = (xcol ? F.rx : F.rz) + (q >> 6);
+  constexpr int KR = 4;
+  for (int c0 = 0; c0 < n; c0 += KR * WT) {
+    uint64_t wv[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int i = c0 + tid + WT * k;
+      wv[k] = i < n ? base[(size_t)i * W] : 0ull;
+    }
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int i = c0 + tid + WT * k;
+      if (i >= n) break;
+      const int ld = L.lead[i];
+      if (((wv[k] >> (q & 63)) & 1ull) && (xcol || all || ld >= n)) {
+        L.list[atomicAdd(&L.nlist, 1)] = (int16_t)i;
+        atomicMin(&L.pmin, i);
+        if (ld == col) atomicMin(&L.piv, i);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// After row m was multiplied into the rows with a bit at an x column (xcol)
+// or into Z-block rows with a bit at a z column: the changed rows gained m's
+// bits, so the lead columns among them are candidates -- for an x column only
+// m's x bits count (the changed rows stay in the X-block, whose z bits are
+// free) plus the z bits of rows that left the X-block.
+__device__ void add_row_candidates(WideLds& L, const Frame F, int m, bool xcol) {
+  const int tid = threadIdx.x, W = F.W;
+  __syncthreads();
+  if (tid < W) {
+    const uint64_t v = xcol ? F.rx[(size_t)m * W + tid] : 0ull;
+    if (v) add_lead_bits(L, tid, v);
+  } else if (tid < 2 * W) {
+    const uint64_t v = (xcol ? 0ull : F.rz[(size_t)m * W + tid - W]) | L.zpend[tid - W];
+    if (v) add_lead_bits(L, tid, v);
+  }
+  __syncthreads();
+  if (tid < W) L.zpend[tid] = 0ull;
+}
+
+// Repair the form: take the smallest candidate column that rows lead at; if
+// another row of its block has a bit there, multiply the lowest slot leading
+// there into every such row.  New bits appear only at larger columns, so the
+// candidates are taken in increasing order and each column is handled once.
+__device__ void repair(WideLds& L, const Frame F) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int W = F.W;
+  for (int guard = 0; guard <= 2 * F.n + 2; ++guard) {
+    __syncthreads();
+    if (tid < 64) {
+      // lowest candidate bit that is a lead column (others are dropped)
+      int pick = 0x7fffffff;
+      for (;;) {
+        const uint64_t v = lane < 2 * W ? L.cand[lane] : 0ull;
+        const uint64_t nzw = __ballot(v != 0ull);
+        if (!nzw) break;
+        const int w0 = __builtin_ctzll(nzw);
+        const uint64_t vw = L.cand[w0];
+        const int b = 64 * w0 + __builtin_ctzll(vw);
+        if (lane == 0) L.cand[w0] = vw & (vw - 1);
+        __builtin_amdgcn_wave_barrier();
+        if (L.cnt[b] > 0) { pick = b; break; }
+      }
+      if (lane == 0) L.best = pick;
     }
     __syncthreads();
-    const int col = L.best;
-    if (col == 0x7fffffff || L.err) return;
-    if (tid == 0) L.piv = 0x7fffffff;
-    __syncthreads();
-    for (int i = tid; i < n; i += WT)
-      if (L.lead[i] == col) atomicMin(&L.piv, i);
-    __syncthreads();
+    const int b = L.best;
+    if (b == 0x7fffffff || L.err) return;
+    const int col = b < 64 * W ? b : F.n + (b - 64 * W);
+    collect(L, F, col, false);
     const int m = L.piv;
-    const bool xcol = col < n;
-    const int cq = xcol ? col : col - n;
-    const uint64_t* Xm = F.rx + (size_t)m * W;
-    const uint64_t* Zm = F.rz + (size_t)m * W;
-    const int sm = bitof(L.sig, m);
-    for (int i0 = 0; i0 < n; i0 += WT) {
-      const int i = i0 + tid;
-      int fl = 0;
-      if (i < n && i != m) {
-        uint64_t* X = F.rx + (size_t)i * W;
-        uint64_t* Z = F.rz + (size_t)i * W;
-        const int ld = L.lead[i];
-        const bool hit = xcol ? ((X[cq >> 6] >> (cq & 63)) & 1ull)
-                              : (ld >= n && ((Z[cq >> 6] >> (cq & 63)) & 1ull));
-        if (hit) {
-          const int c = rowsign(X, Z, Xm, Zm, W);
-          for (int w = 0; w < W; ++w) { X[w] ^= Xm[w]; Z[w] ^= Zm[w]; }
-          L.lead[i] = (int16_t)row_lead(X, Z, W, n);
-          fl = sm ^ c;
-        }
-      }
-      const uint64_t fm = __ballot(fl);
-      if (lane == 0 && i0 + 64 * wv < n) L.sig[(i0 >> 6) + wv] ^= fm;
-    }
-    __syncthreads();
+    if (L.nlist <= 1 || m == 0x7fffffff) continue;
+    absorb(L, F, m);
+    add_row_candidates(L, F, m, col < F.n);
   }
   if (tid == 0) atomicOr(&L.err, 1 << E_FORM);
   __syncthreads();
@@ -238,10 +343,8 @@ __device__ void repair(WideLds& L, const Frame& F) {
 
 // Amplitude of psi(M, sigma) at L.s relative to b*: the X-block rows whose
 // x-leads are set in s multiply to P with P |b*> ~ |s>.  Sets L.bst = b* =
-// s ^ x(P) and L.ue = e with psi(s) = 2^{-k/2} i^e; checks that b* meets the
-// Z-block signs (z_h . b* = sigma_h), which holds exactly when s lies in the
-// support.
-__device__ void walk(WideLds& L, const Frame& F) {
+// s ^ x(P) and L.ue = e with psi(s) = 2^{-k/2} i^e.
+__device__ void walk(WideLds& L, const Frame F) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int n = F.n, W = F.W;
   if (tid == 0) L.nlist = 0;
@@ -288,33 +391,61 @@ __device__ void walk(WideLds& L, const Frame& F) {
     }
   }
   __syncthreads();
-  for (int i = tid; i < n; i += WT) {
-    const int ld = L.lead[i];
-    if (ld < n) continue;
-    const uint64_t* Z = F.rz + (size_t)i * W;
-    uint64_t acc = 0;
-    for (int w = 0; w < W; ++w) acc ^= Z[w] & L.bst[w];
-    if ((__popcll(acc) & 1) != bitof(L.sig, i)) atomicOr(&L.err, 1 << E_SUPPORT);
+}
+
+// b* against the form and the signs: zero at every x-lead (by construction)
+// and z_h . b* = sigma_h on every Z-block row h, which holds exactly when the
+// walk's string lay in the support.  Rows in lane segments.
+__device__ void check_support(WideLds& L, const Frame F) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n = F.n, W = F.W, seg = F.seg, rpw = F.rpw;
+  const int r = lane / seg, w = lane % seg, l0 = r * seg;
+  const uint64_t smask = (seg == 64 ? ~0ull : ((1ull << seg) - 1)) << l0;
+  for (int i0 = wv * rpw; i0 < n; i0 += WWAVES * rpw) {
+    const int i = i0 + r;
+    const bool zrow = i < n && L.lead[i] >= n;
+    const uint64_t z = zrow && w < W ? F.rz[(size_t)i * W + w] : 0ull;
+    const int par = __popcll(__ballot(__popcll(z & (w < W ? L.bst[w] : 0ull)) & 1) & smask) & 1;
+    if (zrow && lane == l0 && par != bitof(L.sig, i)) atomicOr(&L.err, 1 << E_SUPPORT);
   }
   __syncthreads();
 }
 
 // Table 2 on the columns of the gate's qubits: row i's bits at a (and b)
-// change, its sign flip goes into sigma and its lead is recomputed.
-__device__ void conjugate(WideLds& L, const Frame& F, int op, int a, int b) {
+// change and its sign flip goes into sigma.  Its lead follows from the old
+// one unless the old lead sat on a changed column (then the row is scanned);
+// the changed columns and every new lead become repair candidates.
+__device__ void conjugate(WideLds& L, const Frame F, int op, int a, int b) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int n = F.n, W = F.W;
   const int wa = a >> 6, wb = b >> 6;
   const uint64_t ma = 1ull << (a & 63), mb = 1ull << (b & 63);
   const bool two = op == DG_CNOT || op == DG_CZ;
-  for (int i0 = 0; i0 < n; i0 += WT) {
+  // rows i = tid + WT k in chunks of KR per thread, the gate's words of a
+  // chunk loaded up front
+  constexpr int KR = 4;
+  for (int c0 = 0; c0 < n; c0 += KR * WT) {
+  uint64_t pXa[KR], pZa[KR], pXb[KR], pZb[KR];
+#pragma unroll
+  for (int k = 0; k < KR; ++k) {
+    const int i = c0 + tid + WT * k;
+    const bool ok = i < n;
+    pXa[k] = ok ? F.rx[(size_t)i * W + wa] : 0ull;
+    pZa[k] = ok ? F.rz[(size_t)i * W + wa] : 0ull;
+    pXb[k] = ok && two ? F.rx[(size_t)i * W + wb] : 0ull;
+    pZb[k] = ok && two ? F.rz[(size_t)i * W + wb] : 0ull;
+  }
+#pragma unroll
+  for (int k = 0; k < KR; ++k) {
+    const int i0 = c0 + WT * k;
+    if (i0 >= n) break;
     const int i = i0 + tid;
     int flip = 0;
     if (i < n) {
       uint64_t* X = F.rx + (size_t)i * W;
       uint64_t* Z = F.rz + (size_t)i * W;
-      const uint64_t Xa = X[wa], Za = Z[wa];
-      const uint64_t Xb = two ? X[wb] : 0ull, Zb = two ? Z[wb] : 0ull;
+      const uint64_t Xa = pXa[k], Za = pZa[k];
+      const uint64_t Xb = pXb[k], Zb = pZb[k];
       const int xa = (Xa & ma) != 0, za = (Za & ma) != 0;
       const int xb = (Xb & mb) != 0, zb = (Zb & mb) != 0;
       uint64_t tXa = 0, tZa = 0, tXb = 0, tZb = 0;   // bits to toggle in words a, b
@@ -344,17 +475,53 @@ __device__ void conjugate(WideLds& L, const Frame& F, int op, int a, int b) {
           if (tXa | tZa) { X[wa] = Xa ^ tXa; Z[wa] = Za ^ tZa; }
           if (tXb | tZb) { X[wb] = Xb ^ tXb; Z[wb] = Zb ^ tZb; }
         }
-        L.lead[i] = (int16_t)row_lead(X, Z, W, n);
+        const int old = L.lead[i];
+        const int nxa = xa ^ (tXa != 0), nxb = two ? (xb ^ (tXb != 0)) : 0;
+        const int nza = za ^ (tZa != 0), nzb = two ? (zb ^ (tZb != 0)) : 0;
+        int nl;
+        if (old == a || old == n + a || (two && (old == b || old == n + b))) {
+          nl = row_lead_scan(F, i);
+          if (old < n && (nl < 0 || nl >= n))
+            for (int w = 0; w < W; ++w)
+              if (Z[w]) atomicOr((unsigned long long*)&L.zpend[w], Z[w]);
+        } else if (old < n) {
+          nl = old;
+          if (nxa && a < nl) nl = a;
+          if (nxb && b < nl) nl = b;
+        } else {
+          int xl = 0x7fffffff;
+          if (nxa) xl = a;
+          if (nxb && b < xl) xl = b;
+          if (xl != 0x7fffffff) {
+            nl = xl;
+          } else {
+            nl = old;
+            if (nza && n + a < nl) nl = n + a;
+            if (nzb && n + b < nl) nl = n + b;
+          }
+        }
+        set_lead(L, F, i, nl);
       }
     }
     const uint64_t fm = __ballot(flip);
     if (lane == 0 && i0 + 64 * wv < n) L.sig[(i0 >> 6) + wv] ^= fm;
   }
+  }
+  if (tid < (two ? 4 : 2)) {
+    const int col = tid == 0 ? a : tid == 1 ? n + a : tid == 2 ? b : n + b;
+    const int bb = cbit(F, col);
+    atomicOr((unsigned long long*)&L.cand[bb >> 6], 1ull << (bb & 63));
+  }
+  __syncthreads();
+  if (tid < W) {
+    add_lead_bits(L, W + tid, L.zpend[tid]);
+    L.zpend[tid] = 0ull;
+  }
   __syncthreads();
 }
 
 // One Clifford gate with its phase factor.
-__device__ void clifford(WideLds& L, const Frame& F, int op, int a, int b) {
+__device__ void clifford(WideLds& L, const Frame F, int op, int a, int b) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int n = F.n, W = F.W;
   const double r2 = 0.70710678118654752440;
@@ -380,16 +547,17 @@ __device__ void clifford(WideLds& L, const Frame& F, int op, int a, int b) {
       if (lane == 0 && single) L.tex = (2 * (bitof(L.sig, l) ^ par) + za) & 3;
     }
     __syncthreads();
-    // A[c] = 2^{k/2} psi(b* with bit a = c); one of them is b* itself (1)
-    int are[2], aim[2];
+    // A[c] = 2^{k/2} psi(b* with bit a = c): A[ba] = 1 (b* itself), A[ba ^ 1] = t
     const int te = L.tex;
     const int tre = te < 0 ? 0 : (te == 0 ? 1 : te == 2 ? -1 : 0);
     const int tim = te < 0 ? 0 : (te == 1 ? 1 : te == 3 ? -1 : 0);
-    are[ba] = 1; aim[ba] = 0;
-    are[ba ^ 1] = tre; aim[ba ^ 1] = tim;
     // <c|H psi> = r2 (A[0] + (-1)^c A[1]); take c with a nonzero value
-    int sre = are[0] + are[1], sim = aim[0] + aim[1], c = 0;
-    if (sre == 0 && sim == 0) { sre = are[0] - are[1]; sim = aim[0] - aim[1]; c = 1; }
+    int sre = 1 + tre, sim = tim, c = 0;
+    if (sre == 0 && sim == 0) {
+      sre = ba ? tre - 1 : 1 - tre;
+      sim = ba ? tim : -tim;
+      c = 1;
+    }
     beta = make_double2(__dmul_rn(r2, (double)sre), __dmul_rn(r2, (double)sim));
     for (int w = tid; w < W; w += WT) {
       uint64_t v = L.bst[w];
@@ -415,10 +583,15 @@ __device__ void clifford(WideLds& L, const Frame& F, int op, int a, int b) {
     }
   }
   __syncthreads();
-  conjugate(L, F, op, a, b);
   // S, S-dagger and CZ change z bits of X-block rows only, and Paulis change
   // signs only: the form holds.  H and CNOT can break it.
-  if (op == DG_H || op == DG_CNOT) repair(L, F);
+  if (op == DG_H || op == DG_CNOT) {
+    conjugate(L, F, op, a, b);
+    repair(L, F);
+  } else {
+    conjugate(L, F, op, a, b);
+    if (tid < 2 * W) L.cand[tid] = 0ull;
+  }
   walk(L, F);
   if (tid == 0) {
     const int dk = L.kx - k0;
@@ -440,21 +613,20 @@ __device__ __forceinline__ uint64_t splitmix(uint64_t state, uint64_t index) {
 }
 
 // Z measurement of qubit q with the seeded coin of measurement index mi.
-__device__ void measure(WideLds& L, const Frame& F, const WideJob& J, int q, int mi, uint64_t seed) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+__device__ void measure(WideLds& L, const Frame F, const WideJob& J, int q, int mi, uint64_t seed) {
+  const int tid = threadIdx.x, lane = tid & 63;
   const int n = F.n, W = F.W;
   const double r2 = 0.70710678118654752440;
   const double u = (double)(splitmix(seed, (uint64_t)mi) >> 11) * (1.0 / 9007199254740992.0);
-  if (tid == 0) { L.piv = 0x7fffffff; L.best = -1; }
-  __syncthreads();
-  for (int i = tid; i < n; i += WT) {
-    if ((F.rx[(size_t)i * W + (q >> 6)] >> (q & 63)) & 1ull) atomicMin(&L.piv, i);
-    if (L.lead[i] == n + q) L.best = i;
-  }
-  __syncthreads();
-  const int p = L.piv;
+  collect(L, F, q, true);
+  const int p = L.pmin;
   if (p == 0x7fffffff) {
-    // Z_q is a Z-block row; its sign is the outcome
+    // Z_q is the Z-block row leading at z column q; its sign is the outcome
+    if (tid == 0) L.best = -1;
+    __syncthreads();
+    for (int i = tid; i < n; i += WT)
+      if (L.lead[i] == n + q) L.best = i;
+    __syncthreads();
     const int h = L.best;
     if (tid == 0) {
       if (h < 0) {
@@ -500,36 +672,16 @@ __device__ void measure(WideLds& L, const Frame& F, const WideJob& J, int q, int
   const int ae = o == x0 ? 0 : L.tex;   // old amplitude at the child's string, 2^{-k/2} i^ae
   for (int w = tid; w < W; w += WT) L.s[w] = L.bst[w] ^ (o == x0 ? 0ull : F.rx[(size_t)p * W + w]);
   __syncthreads();
-  // other rows with an x bit at q absorb row p
-  {
-    const uint64_t* Xp = F.rx + (size_t)p * W;
-    const uint64_t* Zp = F.rz + (size_t)p * W;
-    const int sp = bitof(L.sig, p);
-    for (int i0 = 0; i0 < n; i0 += WT) {
-      const int i = i0 + tid;
-      int fl = 0;
-      if (i < n && i != p) {
-        uint64_t* X = F.rx + (size_t)i * W;
-        uint64_t* Z = F.rz + (size_t)i * W;
-        if ((X[q >> 6] >> (q & 63)) & 1ull) {
-          const int c = rowsign(X, Z, Xp, Zp, W);
-          for (int w = 0; w < W; ++w) { X[w] ^= Xp[w]; Z[w] ^= Zp[w]; }
-          L.lead[i] = (int16_t)row_lead(X, Z, W, n);
-          fl = sp ^ c;
-        }
-      }
-      const uint64_t fm = __ballot(fl);
-      if (lane == 0 && i0 + 64 * wv < n) L.sig[(i0 >> 6) + wv] ^= fm;
-    }
-  }
-  __syncthreads();
+  // the other rows with an x bit at q absorb row p
+  absorb(L, F, p);
+  add_row_candidates(L, F, p, true);
   // row p becomes (-1)^o Z_q
   for (int w = tid; w < W; w += WT) {
     F.rx[(size_t)p * W + w] = 0ull;
     F.rz[(size_t)p * W + w] = w == (q >> 6) ? (1ull << (q & 63)) : 0ull;
   }
   if (tid == 0) {
-    L.lead[p] = (int16_t)(n + q);
+    set_lead(L, F, p, n + q);
     const uint64_t m = 1ull << (p & 63);
     L.sig[p >> 6] = o ? (L.sig[p >> 6] | m) : (L.sig[p >> 6] & ~m);
   }
@@ -560,20 +712,31 @@ __device__ void wide_body(WideLds& L, const WideJob& J) {
   wide::Frame F;
   F.n = n;
   F.W = W;
+  F.seg = 1;
+  while (F.seg < W) F.seg <<= 1;
+  F.rpw = 64 / F.seg;
   F.rx = (uint64_t*)(J.base + o.rx);
   F.rz = (uint64_t*)(J.base + o.rz);
   const uint64_t* gsig = (const uint64_t*)(J.base + o.sig);
   const uint64_t* gbst = (const uint64_t*)(J.base + o.bst);
   int32_t* glead = (int32_t*)(J.base + o.lead);
-  for (int w = tid; w < W; w += WT) { L.sig[w] = gsig[w]; L.bst[w] = gbst[w]; }
-  for (int i = tid; i < n; i += WT) L.lead[i] = (int16_t)glead[i];
+  for (int w = tid; w < W; w += WT) { L.sig[w] = gsig[w]; L.bst[w] = gbst[w]; L.zpend[w] = 0ull; }
+  for (int w = tid; w < 2 * W; w += WT) L.cand[w] = 0ull;
+  for (int c = tid; c < 128 * W; c += WT) L.cnt[c] = 0;
   if (tid == 0) {
     L.amp = H->amp;
-    L.kx = H->k;
+    L.kx = 0;
     L.err = H->error;
   }
   const uint64_t seed = H->seed;
   int nm = H->nmeas;
+  __syncthreads();
+  for (int i = tid; i < n; i += WT) {
+    const int ld = glead[i];
+    L.lead[i] = (int16_t)ld;
+    if (ld >= 0 && ld < 2 * n) atomicAdd(&L.cnt[wide::cbit(F, ld)], 1);
+    if (ld >= 0 && ld < n) atomicAdd(&L.kx, 1);
+  }
   __syncthreads();
   for (int gi = J.g0; gi < J.g1; ++gi) {
     if (L.err) break;
@@ -597,6 +760,7 @@ __device__ void wide_body(WideLds& L, const WideJob& J) {
     }
   }
   __syncthreads();
+  if (J.g1 > J.g0 && !L.err) wide::check_support(L, F);
   uint64_t* sig = (uint64_t*)(J.base + o.sig);
   uint64_t* bst = (uint64_t*)(J.base + o.bst);
   for (int w = tid; w < W; w += WT) { sig[w] = L.sig[w]; bst[w] = L.bst[w]; }

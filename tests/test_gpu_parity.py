@@ -186,7 +186,13 @@ def test_invalid_circuits_rejected(eng):
     with pytest.raises(sf.SFrameError):
         eng.load(0, wl.Circuit(1))
     with pytest.raises(sf.SFrameError):
-        eng.load(257, wl.Circuit(1))
+        eng.load(2049, wl.Circuit(1))
+    # more than 256 qubits: stabilizer circuits only
+    c = wl.Circuit(257)
+    c.t(3)
+    with pytest.raises(sf.SFrameError) as ei:
+        eng.load(257, c)
+    assert ei.value.status == sf.SF_E_INVALID
 
 
 def test_too_large_frame_rejected(eng):
