@@ -230,6 +230,19 @@ sf_status sf_graph_destroy(sf_graph* g);
  * launch.  Allocates 16 * 2^d_hi bytes of scratch while it runs.
  * Synchronises. */
 sf_status sf_autotune(sf_ctx* ctx, int d_lo, int d_hi, int* blocks, int* grids, float* ms);
+/* Not in the paper (tuning).
+ * The context's launch tuning, so that a caller can keep it across
+ * processes: the elementwise kernels' shape per hull dimension d
+ * (SF_TUNE_DIMS entries, d = 0..30: threads per block and blocks) and the
+ * number of phase-kernel wavefronts a batched launch aims for (each walks a
+ * chunk of consecutive gates; default 65536).  sf_tuning_get copies it out
+ * (any pointer may be NULL).  sf_tuning_set installs it: blocks and grids
+ * both NULL keeps the shapes; a block other than 64, 128 or 256, a grid
+ * outside 1..2^24 or phase_waves < 1 returns SF_E_INVALID and changes
+ * nothing.  Results never depend on these values. */
+#define SF_TUNE_DIMS 31
+sf_status sf_tuning_get(const sf_ctx* ctx, int* blocks, int* grids, int* phase_waves);
+sf_status sf_tuning_set(sf_ctx* ctx, const int* blocks, const int* grids, int phase_waves);
 /* Not in the paper.  Wait for queued work; reports device-side failures of
  * the queued steps. */
 sf_status sf_sync(sf_state* s);

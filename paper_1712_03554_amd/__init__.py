@@ -24,7 +24,8 @@ SF_OK, SF_E_INVALID, SF_E_OOM, SF_E_DEVICE, SF_E_TOO_LARGE, SF_E_STATE, SF_E_BUF
 STATUS_NAMES = ["SF_OK", "SF_E_INVALID", "SF_E_OOM", "SF_E_DEVICE", "SF_E_TOO_LARGE", "SF_E_STATE",
                 "SF_E_BUFSIZE", "SF_E_CANCELLED"]
 
-EXPORTS = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_measure", "sf_batch_graph", "sf_autotune", "sf_batch_reset",
+EXPORTS = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_measure", "sf_batch_graph", "sf_autotune",
+           "sf_tuning_get", "sf_tuning_set", "sf_batch_reset",
            "sf_graph_set_input", "sf_graph_launch", "sf_graph_destroy", "sf_circuit_load", "sf_circuit_info",
            "sf_circuit_destroy", "sf_state_init", "sf_state_destroy", "sf_step", "sf_run", "sf_sync",
            "sf_outcomes", "sf_frame_size", "sf_read_frame", "sf_state_info", "sf_state_reset",
@@ -79,6 +80,8 @@ def load_library(path: str = LIB_PATH):
         "sf_graph_launch": [vp],
         "sf_graph_destroy": [vp],
         "sf_autotune": [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp],
+        "sf_tuning_get": [vp, vp, vp, P(ctypes.c_int)],
+        "sf_tuning_set": [vp, vp, vp, ctypes.c_int],
         "sf_batch_reset": [vp, vp, sz, vp, vp],
         "sf_sync": [vp],
         "sf_outcomes": [vp, vp, sz, P(sz)],
@@ -139,6 +142,7 @@ class Engine:
         allocator that has run out would."""
         self._L = load_library()
         self._keep = []
+        self.device = device
         stream_ptr = None
         alloc_ptr = None
         try:
@@ -214,13 +218,70 @@ class Engine:
         """Record a whole batched run of these states (see sf_batch_graph)."""
         return Graph(self, states, bases, seeds)
 
-    def autotune(self, d_lo: int = 12, d_hi: int = 24) -> dict:
-        """Pick launch shapes of the elementwise frame kernels; {d: (block, grid, ms)}."""
+    TUNE_DIMS = 31
+
+    def tuning(self) -> dict:
+        """The context's launch tuning: {"blocks": [...], "grids": [...] (per
+        hull dimension d = 0..30), "phase_waves": int}."""
+        b = np.zeros(self.TUNE_DIMS, dtype=np.int32)
+        g = np.zeros(self.TUNE_DIMS, dtype=np.int32)
+        pw = ctypes.c_int()
+        self._check(self._L.sf_tuning_get(self._h, _ptr(b), _ptr(g), ctypes.byref(pw)))
+        return {"blocks": b.tolist(), "grids": g.tolist(), "phase_waves": int(pw.value)}
+
+    def set_tuning(self, tun: dict):
+        """Install a tuning as returned by tuning() (shapes optional)."""
+        pw = int(tun.get("phase_waves", self.tuning()["phase_waves"]))
+        if tun.get("blocks") is None:
+            self._check(self._L.sf_tuning_set(self._h, None, None, pw))
+            return
+        b = np.ascontiguousarray(tun["blocks"], dtype=np.int32)
+        g = np.ascontiguousarray(tun["grids"], dtype=np.int32)
+        if b.shape != (self.TUNE_DIMS,) or g.shape != (self.TUNE_DIMS,):
+            raise ValueError(f"tuning tables need {self.TUNE_DIMS} entries")
+        self._check(self._L.sf_tuning_set(self._h, _ptr(b), _ptr(g), pw))
+
+    def _device_tag(self) -> str:
+        import torch
+        p = torch.cuda.get_device_properties(self.device)
+        return f"{p.name}|{getattr(p, 'gcnArchName', '')}|{p.multi_processor_count}"
+
+    def save_tuning(self, path: str):
+        """Write the tuning with the device it was made on (JSON)."""
+        import json
+        rec = dict(self.tuning(), device=self._device_tag())
+        with open(path, "w") as fh:
+            json.dump(rec, fh)
+
+    def load_tuning(self, path: str) -> bool:
+        """Install a saved tuning if it was made on this kind of device;
+        returns whether it was installed."""
+        import json
+        try:
+            with open(path) as fh:
+                rec = json.load(fh)
+        except (OSError, ValueError):
+            return False
+        if rec.get("device") != self._device_tag():
+            return False
+        self.set_tuning(rec)
+        return True
+
+    def autotune(self, d_lo: int = 12, d_hi: int = 24, cache: str = None) -> dict:
+        """Pick launch shapes of the elementwise frame kernels; {d: (block, grid, ms)}.
+        With cache: a tuning saved there for this kind of device is installed
+        instead (the result then holds (block, grid, None)); otherwise the
+        tuner runs and its result is saved there."""
+        if cache and self.load_tuning(cache):
+            t = self.tuning()
+            return {d: (t["blocks"][d], t["grids"][d], None) for d in range(d_lo, d_hi + 1)}
         k = d_hi - d_lo + 1
         b = np.zeros(k, dtype=np.int32)
         g = np.zeros(k, dtype=np.int32)
         t = np.zeros(k, dtype=np.float32)
         self._check(self._L.sf_autotune(self._h, d_lo, d_hi, _ptr(b), _ptr(g), _ptr(t)))
+        if cache:
+            self.save_tuning(cache)
         return {d_lo + i: (int(b[i]), int(g[i]), float(t[i])) for i in range(k)}
 
     def profile(self, enable: bool, kinds=None):

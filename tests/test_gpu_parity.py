@@ -735,3 +735,49 @@ def test_small_frames_same_alone_and_in_mixed_rounds(eng):
             assert st.outcomes() == oa, (with_big, c.name)
         for st in states:
             st.close()
+
+
+def test_tuning_roundtrip_and_results_independent_of_it(eng, tmp_path):
+    """The launch tuning can be read, changed, saved and loaded; invalid
+    values are refused without change; batched results are bit-identical
+    under very different tunings (one gate per phase wavefront, small and
+    large element-kernel grids)."""
+    import paper_1712_03554_amd as sf
+    t0 = eng.tuning()
+    assert len(t0["blocks"]) == 31 and t0["phase_waves"] >= 1
+    circs = [wl.config2(j) for j in range(3)] + [wl.config3(t) for t in range(5)]
+    seeds = [wl.derive_seed(2, j) for j in range(3)] + [wl.derive_seed(3, t) for t in range(5)]
+    results = []
+    for tun in (t0, {"blocks": [64] * 31, "grids": [1] * 31, "phase_waves": 1},
+                {"blocks": [256] * 31, "grids": [4096] * 31, "phase_waves": 1 << 20}):
+        eng.set_tuning(tun)
+        assert eng.tuning()["phase_waves"] == tun["phase_waves"]
+        sts = [eng.load(c.n, c).state(c.init_bits, s) for c, s in zip(circs, seeds)]
+        eng.batch_run(sts)
+        results.append([(st.read_frame(), st.outcomes()) for st in sts])
+        for st in sts:
+            st.close()
+    for other in results[1:]:
+        for (a, oa), (b, ob) in zip(results[0], other):
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+            assert np.array_equal(a[2].view(np.uint64), b[2].view(np.uint64)) and oa == ob
+    # refused without change
+    eng.set_tuning(t0)
+    for bad in ({"blocks": [96] * 31, "grids": [1] * 31, "phase_waves": 8},
+                {"blocks": [64] * 31, "grids": [0] * 31, "phase_waves": 8}, {"phase_waves": 0}):
+        with pytest.raises(sf.SFrameError) as e:
+            eng.set_tuning(bad)
+        assert e.value.status == sf.SF_E_INVALID
+        assert eng.tuning() == t0
+    # saved and loaded (a file from another kind of device is ignored)
+    path = str(tmp_path / "tuning.json")
+    eng.set_tuning({"blocks": [128] * 31, "grids": [7] * 31, "phase_waves": 123})
+    eng.save_tuning(path)
+    eng.set_tuning(t0)
+    assert eng.load_tuning(path) and eng.tuning()["phase_waves"] == 123 and eng.tuning()["grids"] == [7] * 31
+    import json
+    rec = json.load(open(path))
+    rec["device"] = "another device"
+    json.dump(rec, open(path, "w"))
+    eng.set_tuning(t0)
+    assert not eng.load_tuning(path) and eng.tuning() == t0
