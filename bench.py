@@ -383,7 +383,9 @@ def large_frame(eng, wl, m=12, reps=2):
            "track_ms": prof["track"][0] / reps,
            "element_roofline": {"bound": "hbm", "kernel": "sf_seg_kernel", "achieved": gbs,
                                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-                                "bytes_per_circuit": seg_bytes}}
+                                "bytes_per_circuit": seg_bytes,
+                                "live_fraction": sum(Ks) / max(1.0, sum(float(1 << d) for d in dims)),
+                                "bytes_per_live_element": seg_bytes / max(1, sum(Ks))}}
     st.close()
     return out
 
@@ -602,11 +604,13 @@ def main():
     states = [l.state(c.init_bits, s) for l, c, s in zip(loaded, circs, seeds)]
     bounds = [l.info()[0] for l in loaded]
 
-    U_each, seg_dims = [], []
+    U_each, seg_dims, seg_sizes = [], [], []
     for st, c, s in zip(states, circs, seeds):
-        U, dims = accounting(st, c, s, wl)
+        Ks = []
+        U, dims = accounting(st, c, s, wl, sizes=Ks)
         U_each.append(U)
         seg_dims.append(dims)
+        seg_sizes.append(Ks)
     U_total = sum(U_each)
     n_plain = max(1, min(args.plain_jobs, len(states)))
     U_plain = sum(U_each[:n_plain])
@@ -689,6 +693,10 @@ def main():
 
     # roofline of the dominant kernel (its launches timed in the timed region)
     seg_bytes_per_step = sum(32.0 * (1 << d) for dims in seg_dims for d in dims)
+    # how full the hulls are: elements on entry to the segment launches over
+    # the slots those launches stream
+    live_elems = sum(k for ks in seg_sizes for k in ks)
+    live_frac = live_elems / max(1.0, sum(float(1 << d) for dims in seg_dims for d in dims))
     seg_ms, seg_n = (prof if dom == "segment" else prof_all)["segment"]
     seg_ach = (seg_bytes_per_step * args.steps / max(seg_n, 1)) / (seg_ms / 1e3 / max(seg_n, 1)) / 1e9 \
         if seg_n else 0.0
@@ -696,7 +704,9 @@ def main():
                  "achieved": seg_ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": seg_ach / PEAK_HBM_GBS,
                  "traffic": measured_traffic("sf_seg_kernel" if args.path == "plain" else "sf_seg_batch",
                                              args.workload),
-                 "note": "32 B per slot (read + write of 16 B) over 2^d slots per segment launch"}
+                 "live_fraction": live_frac, "bytes_per_live_element": seg_bytes_per_step / max(1, live_elems),
+                 "note": "32 B per slot (read + write of 16 B) over 2^d slots per segment launch; "
+                         "live_fraction = frame elements / hull slots over those launches"}
     if dom == "segment":
         roof = dict(elem_roof)
     else:
