@@ -5,7 +5,7 @@
 //
 // The rows do not fit one workgroup's LDS (n = 1024 takes 256 KiB), so they
 // stay in device memory (L2-resident while a frame runs) and one workgroup of
-// four wavefronts works on a frame, one row per thread and pass.  Per frame
+// eight wavefronts works on a frame, one row per thread and pass.  Per frame
 // the workgroup keeps in LDS: sigma, b* (the smallest basis string of the
 // support of psi(M, sigma)), every row's lead and the masks of the repair.
 //
@@ -42,7 +42,7 @@
 
 #define SF_WIDE_NMAX 2048
 #define SF_WIDE_WMAX (SF_WIDE_NMAX / 64)
-#define WT 256               // threads per frame
+#define WT 512               // threads per frame (eight wavefronts)
 #define WWAVES (WT / 64)
 
 // Per-frame header; rows and vectors follow it in the same allocation.  The
