@@ -64,6 +64,27 @@ def measured_traffic(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
+def rec_stride(n):
+    """Bytes of one per-gate record of the split tableau track: the rows (x
+    and z words of n slots), the hull (31 vectors of W words) and its
+    dimension, rounded to 256 bytes."""
+    W = (n + 63) // 64
+    b = n * 2 * W * 8 + 31 * W * 8 + 8
+    return (b + 255) & ~255
+
+
+def clifford_gate_count(circ, wl):
+    """Device Clifford gates of a circuit (phase gates at multiples of pi/2
+    other than the identity included)."""
+    k = 0
+    for op, q0, q1, q2, num, den in circ.gates:
+        if op in (wl.H, wl.S, wl.SDG, wl.X, wl.Y, wl.Z, wl.CNOT, wl.CZ):
+            k += 1
+        elif op == wl.PHASE and (2 * num) % den == 0 and ((2 * num) // den) % 4 != 0:
+            k += 1
+    return k
+
+
 def terminal_indices(circ, wl):
     """Indices of the gates that end a segment: non-Clifford phase gates and
     measurements (T, T-dagger, PHASE with an angle off the pi/2 grid, MEASURE)."""
@@ -670,7 +691,14 @@ def main():
     prof_all = eng.profile_read()
     eng.profile(False)
     kinds = {k: v for k, v in prof_all.items() if v[1] > 0}
-    dom = max(kinds, key=lambda k: kinds[k][0])
+    # the dominant kernel on the step's critical path: when the batched
+    # forms overlap rounds (circuits with a range cut every 1024 gates), the
+    # phase kernel of a round runs beside the next round's tracks, so the
+    # chain of tracks is on the critical path and the phase launches only
+    # partly; their summed time then overstates their share
+    overlapped = args.path != "plain" and any(len(c.gates) > 1024 for c in step_circs)
+    crit = {k: v for k, v in kinds.items() if not (overlapped and k == "phase")}
+    dom = max(crit, key=lambda k: crit[k][0])
     # timed region: HIP events around the dominant kernel's launches only
     for _ in range(args.warmup):
         one_step()
@@ -707,21 +735,35 @@ def main():
                  "live_fraction": live_frac, "bytes_per_live_element": seg_bytes_per_step / max(1, live_elems),
                  "note": "32 B per slot (read + write of 16 B) over 2^d slots per segment launch; "
                          "live_fraction = frame elements / hull slots over those launches"}
-    if dom == "segment":
-        roof = dict(elem_roof)
-    else:
-        # tableau track: one pass over the n rows per gate (4 n W 64-bit words)
-        tr_ms, tr_n = prof["track"]
-        words_per_step = sum(len(c.gates) * 4 * c.n * ((c.n + 63) // 64) for c in step_circs)
-        ach = (words_per_step * args.steps / tr_n) / (tr_ms / 1e3 / tr_n) / 1e9
-        wset = sorted({(c.n + 63) // 64 for c in circs})
-        kname = ("sf_track_one<%d>" if args.path == "plain" else "sf_track_many<%d>") % wset[-1]
-        roof = {"bound": "alu", "kernel": kname, "avg_launch_us": tr_ms / tr_n * 1e3,
-                "achieved": ach, "peak": PEAK_WORD_GOPS,
-                "unit": "G 64-bit word-ops/s", "frac": ach / PEAK_WORD_GOPS,
-                "traffic": measured_traffic(kname, args.workload),
-                "note": "one wavefront per circuit walks the gates; bound by the dependent LDS/VALU latency of "
-                        "that wavefront, not by throughput"}
+    def kind_ms(kind):
+        """(ms, launches) of a kernel kind: from the timed region for the
+        dominant kind, else from the untimed pass over the same steps."""
+        return (prof if dom == kind else prof_all).get(kind, (0.0, 0))
+
+    wset = sorted({(c.n + 63) // 64 for c in circs})
+    # tableau track: one pass over the n rows per gate (4 n W 64-bit words)
+    tr_ms, tr_n = kind_ms("track")
+    words_per_step = sum(len(c.gates) * 4 * c.n * ((c.n + 63) // 64) for c in step_circs)
+    ach = (words_per_step * args.steps / tr_n) / (tr_ms / 1e3 / tr_n) / 1e9 if tr_n else 0.0
+    kname = ("sf_track_one<%d>" if args.path == "plain" else "sf_track_many<%d>") % wset[-1]
+    track_roof = {"bound": "alu", "kernel": kname, "avg_launch_us": tr_ms / tr_n * 1e3 if tr_n else None,
+                  "achieved": ach, "peak": PEAK_WORD_GOPS,
+                  "unit": "G 64-bit word-ops/s", "frac": ach / PEAK_WORD_GOPS,
+                  "traffic": measured_traffic(kname, args.workload),
+                  "note": "one wavefront per circuit walks the gates; bound by the dependent LDS/VALU latency "
+                          "of that wavefront, not by throughput"}
+    # phase kernel: reads one record (the state after the gate) per Clifford
+    # gate of a frame in split form (n <= 128)
+    ph_ms, ph_n = kind_ms("phase")
+    ph_bytes = sum(clifford_gate_count(c, wl) * rec_stride(c.n) for c in step_circs if c.n <= 128)
+    ph_ach = (ph_bytes * args.steps / ph_n) / (ph_ms / 1e3 / ph_n) / 1e9 if ph_n else 0.0
+    pname = ("sf_phase_one<%d>" if args.path == "plain" else "sf_phase_many<%d>") % min(2, wset[-1])
+    phase_roof = {"bound": "hbm", "kernel": pname, "avg_launch_us": ph_ms / ph_n * 1e3 if ph_n else None,
+                  "achieved": ph_ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ph_ach / PEAK_HBM_GBS,
+                  "traffic": measured_traffic(pname, args.workload),
+                  "note": "one record (rows and hull after the gate) read per Clifford gate; runs beside the "
+                          "next round's tracks, so its launches share the SIMDs with them"}
+    roof = dict({"segment": elem_roof, "phase": phase_roof}.get(dom, track_roof))
     line = {
         "metric": "frame-element gate updates/s",
         "value": value,
@@ -736,6 +778,7 @@ def main():
         "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": wname, "circuits_per_step": len(step_circs), "path": args.path,
+                   "rounds_overlapped": overlapped,
                    "U_per_step": U_one, "frame_bound_log2_max": max(bounds),
                    "seeds": "splitmix64 stream of master seed 20171210, config 2, circuits 0..%d" % (len(circs) - 1)},
         "plain_value": plain_value,
@@ -750,6 +793,8 @@ def main():
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kinds.items()},
         "kernel_launches_per_step": {k: v[1] / args.steps for k, v in kinds.items()},
         "roofline": roof,
+        "track_roofline": track_roof,
+        "phase_roofline": phase_roof,
         "element_roofline": elem_roof,
         "track_cycles_last_step": cyc,
         "autotune": {str(d): {"block": b, "grid": g, "ms": round(t, 4)} for d, (b, g, t) in tuned.items()},

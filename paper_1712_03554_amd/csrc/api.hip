@@ -45,6 +45,12 @@ struct sf_ctx {
   // phase-kernel wavefronts per launch to aim for (each walks a chunk of
   // consecutive gates of one frame's range)
   int phase_waves;
+  // second stream of sf_batch_run: the tableau tracks of round r + 1 run on
+  // it while the phase and element kernels of round r run on `stream`
+  // (default priority, non-blocking); nullptr: one stream only
+  hipStream_t side = nullptr;
+  hipEvent_t ev_track = nullptr, ev_meas = nullptr, ev_join = nullptr, ev_elem[2] = {nullptr, nullptr};
+  hipStream_t prof_stream = nullptr;
   // pinned host chunks that stage batched-round descriptors for async copies;
   // reused after the stream has been synchronised
   std::vector<std::pair<char*, size_t>> pin;
@@ -182,8 +188,9 @@ static void elem_shape(const sf_ctx* ctx, int d, int* block, int* grid) {
   *grid = ctx->tune_grid[d];
 }
 
-static void prof_begin(sf_ctx* ctx, int kind) {
+static void prof_begin(sf_ctx* ctx, int kind, hipStream_t on = nullptr) {
   ctx->prof_open = 0;
+  ctx->prof_stream = on ? on : ctx->stream;
   if (!ctx->prof || !((ctx->prof >> kind) & 1)) return;
   size_t i = ctx->ev_used;
   if (2 * i + 2 > ctx->ev.size()) {
@@ -194,13 +201,13 @@ static void prof_begin(sf_ctx* ctx, int kind) {
     ctx->ev_kind.push_back(kind);
   }
   ctx->ev_kind[i] = kind;
-  (void)hipEventRecord(ctx->ev[2 * i], ctx->stream);
+  (void)hipEventRecord(ctx->ev[2 * i], ctx->prof_stream);
   ctx->prof_open = 1;
 }
 
 static void prof_end(sf_ctx* ctx) {
   if (!ctx->prof_open) return;
-  (void)hipEventRecord(ctx->ev[2 * ctx->ev_used + 1], ctx->stream);
+  (void)hipEventRecord(ctx->ev[2 * ctx->ev_used + 1], ctx->prof_stream);
   ctx->ev_used++;
   ctx->prof_open = 0;
 }
@@ -317,6 +324,9 @@ struct sf_state {
   DevBuf st, prog, had, amp[2], outcomes, pvals, scale, flags, partials, ri, count, adhoc;
   DevBuf rec, ginfo, segacc;  // split form of the tableau track
   DevBuf wbasis;              // wide frames: basis words for (re)initialisation
+  // second set of the per-range buffers, for the odd rounds of an
+  // overlapped sf_batch_run (allocated on first use)
+  DevBuf prog2, had2, rec2, ginfo2, segacc2;
   int cur;
   size_t orig_done, dev_done, nmeas;
   size_t meas_cap;  // capacity of outcomes / pvals (circuit measurements, grown by sf_measure)
@@ -394,6 +404,20 @@ extern "C" sf_status sf_ctx_create(int device, void* hip_stream, const sf_alloca
   for (int k = 0; k < PK_N; ++k) { c->prof_ms[k] = 0; c->prof_n[k] = 0; }
   for (int d = 0; d <= SF_DMAX; ++d) { c->tune_block[d] = EB; c->tune_grid[d] = grid_for(d); }
   c->phase_waves = SF_PHASE_WAVES;
+  {
+    hipStream_t side = nullptr;
+    bool ok = hipStreamCreateWithFlags(&side, hipStreamNonBlocking) == hipSuccess;
+    hipEvent_t* evs[5] = {&c->ev_track, &c->ev_meas, &c->ev_join, &c->ev_elem[0], &c->ev_elem[1]};
+    for (hipEvent_t* e : evs) ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+    if (ok) {
+      c->side = side;
+    } else {
+      for (hipEvent_t* e : evs)
+        if (*e) { (void)hipEventDestroy(*e); *e = nullptr; }
+      if (side) (void)hipStreamDestroy(side);
+      (void)hipGetLastError();
+    }
+  }
   scratch_lookup(device);
   *out = c;
   return SF_OK;
@@ -404,6 +428,12 @@ extern "C" sf_status sf_ctx_destroy(sf_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   for (auto& ch : ctx->pin) (void)hipHostFree(ch.first);
+  if (ctx->side) {
+    (void)hipStreamSynchronize(ctx->side);
+    hipEvent_t evs[5] = {ctx->ev_track, ctx->ev_meas, ctx->ev_join, ctx->ev_elem[0], ctx->ev_elem[1]};
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(ctx->side);
+  }
   delete ctx;
   return SF_OK;
 }
@@ -720,7 +750,8 @@ static void state_free(sf_state* s) {
   sf_ctx* ctx = s->ctx;
   DevBuf* all[] = {&s->st, &s->prog, &s->had, &s->amp[0], &s->amp[1], &s->outcomes, &s->pvals,
                    &s->scale, &s->flags, &s->partials, &s->ri, &s->count, &s->adhoc,
-                   &s->rec, &s->ginfo, &s->segacc, &s->wbasis};
+                   &s->rec, &s->ginfo, &s->segacc, &s->wbasis, &s->prog2, &s->had2, &s->rec2, &s->ginfo2,
+                   &s->segacc2};
   for (DevBuf* b : all) dfree(ctx, b);
 }
 
@@ -881,31 +912,52 @@ extern "C" sf_status sf_state_destroy(sf_state* s) {
 // Record, gate-info and segment-sum buffers of a wide frame, allocated when a
 // launch first runs it in split form (frames of up to 128 qubits get them at
 // init).
-static sf_status ensure_split_buffers(sf_state* s) {
-  if (s->rec.p) return SF_OK;
+// par: which of the two buffer sets (the second serves the odd rounds of an
+// overlapped batched run); on: the stream that initialises the gate info.
+static DevBuf& rec_buf(sf_state* s, int par) { return par ? s->rec2 : s->rec; }
+static DevBuf& ginfo_buf(sf_state* s, int par) { return par ? s->ginfo2 : s->ginfo; }
+static DevBuf& segacc_buf(sf_state* s, int par) { return par ? s->segacc2 : s->segacc; }
+static const DevBuf& prog_buf(const sf_state* s, int par) { return par ? s->prog2 : s->prog; }
+static const DevBuf& had_buf(const sf_state* s, int par) { return par ? s->had2 : s->had; }
+
+static sf_status ensure_split_buffers(sf_state* s, int par = 0, hipStream_t on = nullptr) {
+  DevBuf &rec = rec_buf(s, par), &ginfo = ginfo_buf(s, par), &segacc = segacc_buf(s, par);
+  if (rec.p) return SF_OK;
   sf_ctx* ctx = s->ctx;
   const sf_circuit* c = s->c;
   sf_status rc;
-  if ((rc = dalloc(ctx, &s->rec, (size_t)(c->rec_len + 1) * rec_stride_of(c->n))) ||
-      (rc = dalloc(ctx, &s->ginfo, (size_t)c->rec_len * 8)) ||
-      (rc = dalloc(ctx, &s->segacc, (size_t)c->max_segs * pe_of(c->dmax) * 4))) {
-    dfree(ctx, &s->rec);
-    dfree(ctx, &s->ginfo);
-    dfree(ctx, &s->segacc);
+  if ((rc = dalloc(ctx, &rec, (size_t)(c->rec_len + 1) * rec_stride_of(c->n))) ||
+      (rc = dalloc(ctx, &ginfo, (size_t)c->rec_len * 8)) ||
+      (rc = dalloc(ctx, &segacc, (size_t)c->max_segs * pe_of(c->dmax) * 4))) {
+    dfree(ctx, &rec);
+    dfree(ctx, &ginfo);
+    dfree(ctx, &segacc);
     return rc;
   }
-  HIPCHK(ctx, hipMemsetAsync(s->ginfo.p, 0xff, s->ginfo.bytes, ctx->stream));
+  HIPCHK(ctx, hipMemsetAsync(ginfo.p, 0xff, ginfo.bytes, on ? on : ctx->stream));
+  return SF_OK;
+}
+
+// Programs and Hadamard terms of the second set.
+static sf_status ensure_second_set(sf_state* s) {
+  if (s->prog2.p) return SF_OK;
+  sf_status rc;
+  if ((rc = dalloc(s->ctx, &s->prog2, s->prog.bytes)) || (rc = dalloc(s->ctx, &s->had2, s->had.bytes))) {
+    dfree(s->ctx, &s->prog2);
+    dfree(s->ctx, &s->had2);
+    return rc;
+  }
   return SF_OK;
 }
 
 // The split-form buffers of a state in a track job (use: this launch runs the
 // frame in split form).
-static void split_fields(const sf_state* s, TrackJob* job, int nseg, bool use = true) {
+static void split_fields(sf_state* s, TrackJob* job, int nseg, bool use = true, int par = 0) {
   job->nseg = nseg;
-  if (!use || !s->rec.p || job->dry) return;
-  job->rec = (uint8_t*)s->rec.p;
-  job->ginfo = (int32_t*)s->ginfo.p;
-  job->segacc = (uint32_t*)s->segacc.p;
+  if (!use || !rec_buf(s, par).p || job->dry) return;
+  job->rec = (uint8_t*)rec_buf(s, par).p;
+  job->ginfo = (int32_t*)ginfo_buf(s, par).p;
+  job->segacc = (uint32_t*)segacc_buf(s, par).p;
   job->rec_stride = rec_stride_of(s->c->n);
   job->pe = pe_of(s->c->dmax);
   job->pchunk = 1;
@@ -1398,11 +1450,11 @@ static void fill_range_dims(sf_circuit* c) {
   }
 }
 
-static ElemDesc elem_desc(const sf_state* s, int cur, const SegProg* prog, const uint64_t* seedp) {
+static ElemDesc elem_desc(const sf_state* s, int cur, const SegProg* prog, const uint64_t* seedp, int par = 0) {
   ElemDesc e;
   memset(&e, 0, sizeof e);
   e.prog = prog;
-  e.had = (const GF2Q*)s->had.p;
+  e.had = (const GF2Q*)had_buf(s, par).p;
   e.amp = (double2*)s->amp[cur].p;
   e.amp_other = (double2*)s->amp[cur ^ 1].p;
   e.partials = (double2*)s->partials.p;
@@ -1441,7 +1493,8 @@ struct RoundPlan {
 // With noalloc, a wide frame whose record buffers are not allocated yet runs
 // with the in-kernel phase evaluation instead of allocating them.
 static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap, const uint64_t* const* seedp,
-                       RoundPlan* rp, sf_status* err, int* bad = nullptr, bool noalloc = false) {
+                       RoundPlan* rp, sf_status* err, int* bad = nullptr, bool noalloc = false, int par = 0,
+                       hipStream_t on = nullptr) {
   std::vector<int> act;
   std::vector<size_t> A(ns), B(ns), O(ns);
   std::vector<int> NS(ns), ML(ns), CL(ns);
@@ -1491,8 +1544,8 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
     jb.gates = (const DGate*)s->c->dgates.p;
     jb.g0 = (int)A[i];
     jb.g1 = (int)B[i];
-    jb.prog = (SegProg*)s->prog.p;
-    jb.had = (GF2Q*)s->had.p;
+    jb.prog = (SegProg*)prog_buf(s, par).p;
+    jb.had = (GF2Q*)had_buf(s, par).p;
     jb.outcomes = (const uint8_t*)s->outcomes.p;
     if (NS[i] > s->c->max_segs || B[i] - A[i] > (size_t)s->c->rec_len) {
       *err = fail(s->ctx, SF_E_STATE, "state %d: range of %zu gates with %d segments exceeds its buffers", i,
@@ -1502,11 +1555,11 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
     }
     const bool use = (split_form(s->c->n) || rp->wcount[words_of(s->c->n)] <= SF_SPLIT_WIDE_MAX) &&
                      (!noalloc || s->rec.p);
-    if (use && (*err = ensure_split_buffers(s)) != SF_OK) {
+    if (use && (*err = ensure_split_buffers(s, par, on)) != SF_OK) {
       if (bad) *bad = i;
       return false;
     }
-    split_fields(s, &jb, NS[i], use);
+    split_fields(s, &jb, NS[i], use, par);
     const int wi = words_of(s->c->n);
     rp->wlen[wi] = std::max(rp->wlen[wi], (int)(B[i] - A[i]));
     rp->wseg[wi] = std::max(rp->wseg[wi], NS[i]);
@@ -1568,12 +1621,12 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
     for (int j = 0; j < na; ++j) {
       const int i = act[j];
       sf_state* s = states[i];
-      const SegProg* base = (const SegProg*)s->prog.p;
+      const SegProg* base = (const SegProg*)prog_buf(s, par).p;
       const SegProg* p = nullptr;
       if (k < kmax) p = k < NS[i] ? base + k : nullptr;
       else p = ML[i] ? base + (NS[i] - 1) : nullptr;  // measurement descriptors
       // (an idle entry only needs its null program, which assign left)
-      if (p) rp->desc[(size_t)k * na + j] = elem_desc(s, pr[i].cur, p, seedp ? seedp[i] : nullptr);
+      if (p) rp->desc[(size_t)k * na + j] = elem_desc(s, pr[i].cur, p, seedp ? seedp[i] : nullptr, par);
     }
   for (int j = 0; j < na; ++j) {
     const int i = act[j];
@@ -1718,6 +1771,74 @@ static sf_status batch_round(sf_ctx* ctx, sf_state* const* states, size_t ns, Ba
   return SF_OK;
 }
 
+// One round of an overlapped batched run (round index r, buffer set r & 1):
+// the descriptors and the tableau tracks go to the side stream, the phase,
+// fit, segment and measurement kernels to the context's stream after the
+// tracks.  The tracks of the next round can then run while this round's
+// other kernels do: a track reads the previous round's measurement outcomes
+// (it waits for them when that round measured) and writes the per-range
+// buffers of its set (it waits until the round two back, the last one that
+// used them, has finished on the context's stream).
+static sf_status batch_round_ov(sf_ctx* ctx, sf_state* const* states, size_t ns, BatchScratch* bsets, int* active,
+                                int round, bool* prev_meas) {
+  const int par = round & 1;
+  hipStream_t T = ctx->side, E = ctx->stream;
+  std::vector<Progress> pr(ns);
+  for (size_t i = 0; i < ns; ++i) pr[i] = progress_of(states[i]);
+  RoundPlan rp;
+  sf_status err;
+  *active = 0;
+  if (!plan_round(states, ns, pr.data(), 0, nullptr, &rp, &err, nullptr, false, par, T)) return err;
+  *active = rp.na;
+  BatchScratch* bs = &bsets[par];
+  if (round >= 2) HIPCHK(ctx, hipStreamWaitEvent(T, ctx->ev_elem[par], 0));
+  if (*prev_meas) HIPCHK(ctx, hipStreamWaitEvent(T, ctx->ev_meas, 0));
+  const size_t bj = rp.na * sizeof(TrackJob), bd = rp.desc.size() * sizeof(ElemDesc);
+  const size_t offd = desc_offset(bj);
+  const TrackJob* djobs;
+  const ElemDesc* dd;
+  char* h = offd + bd <= bs->djobs.bytes ? (char*)pin_take(ctx, offd + bd) : nullptr;
+  if (h) {
+    memcpy(h, rp.jobs.data(), bj);
+    memcpy(h + offd, rp.desc.data(), bd);
+    HIPCHK(ctx, hipMemcpyAsync(bs->djobs.p, h, offd + bd, hipMemcpyHostToDevice, T));
+    djobs = (const TrackJob*)bs->djobs.p;
+    dd = (const ElemDesc*)((char*)bs->djobs.p + offd);
+  } else {
+    bs->keep_jobs.push_back(std::move(rp.jobs));
+    bs->keep_desc.push_back(std::move(rp.desc));
+    HIPCHK(ctx, hipMemcpyAsync(bs->djobs.p, bs->keep_jobs.back().data(), bj, hipMemcpyHostToDevice, T));
+    HIPCHK(ctx, hipMemcpyAsync(bs->ddesc.p, bs->keep_desc.back().data(), bd, hipMemcpyHostToDevice, T));
+    djobs = (const TrackJob*)bs->djobs.p;
+    dd = (const ElemDesc*)bs->ddesc.p;
+  }
+  int off = 0;
+  for (int w = 1; w <= SF_WMAX; ++w) {
+    if (!rp.wcount[w]) continue;
+    prof_begin(ctx, PK_TRACK, T);
+    launch_track_many(T, djobs + off, rp.wcount[w], w);
+    prof_end(ctx);
+    off += rp.wcount[w];
+  }
+  HIPCHK(ctx, hipEventRecord(ctx->ev_track, T));
+  HIPCHK(ctx, hipStreamWaitEvent(E, ctx->ev_track, 0));
+  RoundPlan el = rp;          // the element part of launch_round, without the tracks
+  for (int w = 0; w <= SF_WMAX; ++w) el.wcount[w] = 0;
+  off = 0;
+  for (int w = 1; w <= SF_WMAX; ++w) {
+    if (!rp.wcount[w]) continue;
+    launch_phase_many(ctx, djobs + off, rp.wcount[w], w, rp.wchunk[w], rp.wseg[w]);
+    off += rp.wcount[w];
+  }
+  launch_round(ctx, el, djobs, dd);
+  HIPCHK(ctx, hipGetLastError());
+  if (rp.anym) HIPCHK(ctx, hipEventRecord(ctx->ev_meas, E));
+  HIPCHK(ctx, hipEventRecord(ctx->ev_elem[par], E));
+  *prev_meas = rp.anym;
+  for (size_t i = 0; i < ns; ++i) set_progress(states[i], pr[i]);
+  return SF_OK;
+}
+
 // Device memory of check_tracks' gather launch for ns states.
 static size_t gather_bytes(size_t ns) { return ((ns * sizeof(void*) + 255) & ~(size_t)255) + ns * sizeof(int); }
 
@@ -1823,13 +1944,38 @@ extern "C" sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* all, size_t ns_a
   }
   sf_state* const* states = reg.data();
   const size_t ns = reg.size();
-  BatchScratch bs;
-  sf_status rc = scratch_reserve(ctx, &bs, ns, maxseg);
+  BatchScratch bs[2];
+  sf_status rc = scratch_reserve(ctx, &bs[0], ns, maxseg);
   int active = 1;
-  while (rc == SF_OK && active) rc = batch_round(ctx, states, ns, &bs, &active, 0, true);
+  // overlap pays only when a round's tracks can run beside the previous
+  // round's other kernels: when some circuit has a range that ends without
+  // a measurement (a cut every SF_RANGE_MAX gates); rounds that end in
+  // measurements wait for the coin anyway
+  bool overlap = false;
+  for (size_t i = 0; i < ns && !overlap; ++i) overlap = !states[i]->c->cuts.empty();
+  if (ctx->side && overlap) {
+    // overlapped rounds: both buffer sets exist before the first launch, and
+    // the side stream starts after the work already queued on the context's
+    for (size_t i = 0; i < ns && rc == SF_OK; ++i) rc = ensure_second_set(states[i]);
+    if (rc == SF_OK) rc = scratch_reserve(ctx, &bs[1], ns, maxseg);
+    if (rc == SF_OK && hipEventRecord(ctx->ev_join, ctx->stream) == hipSuccess &&
+        hipStreamWaitEvent(ctx->side, ctx->ev_join, 0) == hipSuccess) {
+      bool prev_meas = false;
+      for (int r = 0; rc == SF_OK && active; ++r) rc = batch_round_ov(ctx, states, ns, bs, &active, r, &prev_meas);
+    } else if (rc == SF_OK) {
+      rc = fail(ctx, SF_E_DEVICE, "batch run: stream join failed");
+    }
+    // whatever was queued on the side stream finishes before the context's
+    if (hipEventRecord(ctx->ev_join, ctx->side) == hipSuccess)
+      (void)hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0);
+    (void)hipStreamSynchronize(ctx->side);
+  } else {
+    while (rc == SF_OK && active) rc = batch_round(ctx, states, ns, &bs[0], &active, 0, true);
+  }
   hipError_t e = hipStreamSynchronize(ctx->stream);
   pin_release(ctx);
-  scratch_free(ctx, &bs);
+  scratch_free(ctx, &bs[0]);
+  scratch_free(ctx, &bs[1]);
   dfree(ctx, &wj);
   if (rc != SF_OK) return rc;
   if (e != hipSuccess) return fail(ctx, SF_E_DEVICE, "batch run: %s", hipGetErrorString(e));
@@ -2046,8 +2192,17 @@ struct sf_graph {
   hipGraphExec_t exec = nullptr;
 };
 
-static hipError_t add_kernel_node(hipGraph_t g, hipGraphNode_t* last, const void* func, dim3 grid, dim3 block,
-                                  void** args) {
+// A kernel node after the given nodes (null entries and repeats skipped).
+static hipError_t add_node_after(hipGraph_t g, hipGraphNode_t* node, std::initializer_list<hipGraphNode_t> after,
+                                 const void* func, dim3 grid, dim3 block, void** args) {
+  hipGraphNode_t deps[4];
+  size_t nd = 0;
+  for (hipGraphNode_t a : after) {
+    if (!a) continue;
+    bool seen = false;
+    for (size_t t = 0; t < nd; ++t) seen |= deps[t] == a;
+    if (!seen && nd < 4) deps[nd++] = a;
+  }
   hipKernelNodeParams p;
   memset(&p, 0, sizeof p);
   p.func = const_cast<void*>(func);
@@ -2056,10 +2211,7 @@ static hipError_t add_kernel_node(hipGraph_t g, hipGraphNode_t* last, const void
   p.sharedMemBytes = 0;
   p.kernelParams = args;
   p.extra = nullptr;
-  hipGraphNode_t node;
-  hipError_t e = hipGraphAddKernelNode(&node, g, *last ? last : nullptr, *last ? 1 : 0, &p);
-  if (e == hipSuccess) *last = node;
-  return e;
+  return hipGraphAddKernelNode(node, g, nd ? deps : nullptr, nd, &p);
 }
 
 static void graph_free(sf_graph* g) {
@@ -2102,11 +2254,15 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
   std::vector<Progress> pr(ns, Progress{0, 0, 0, 0});
   std::vector<const uint64_t*> seedp(ns);
   for (size_t i = 0; i < ns; ++i) seedp[i] = (const uint64_t*)g->dparams.p + 8 * i + 4;
+  // rounds alternate between the two per-range buffer sets, so that the
+  // tracks of a round need not wait for the previous round's element kernels
+  for (size_t i = 0; i < ns; ++i)
+    if ((rc = ensure_second_set(states[i]))) { graph_free(g); delete g; return rc; }
   std::vector<RoundPlan> rounds;
   for (;;) {
     RoundPlan rp;
     sf_status err;
-    if (!plan_round(states, ns, pr.data(), 0, seedp.data(), &rp, &err)) {
+    if (!plan_round(states, ns, pr.data(), 0, seedp.data(), &rp, &err, nullptr, false, (int)(rounds.size() & 1))) {
       if (err != SF_OK) { graph_free(g); delete g; return err; }
       break;
     }
@@ -2142,29 +2298,57 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
   hipError_t e = hipMemcpyAsync(g->ddesc.p, host.data(), total, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e == hipSuccess) e = hipGraphCreate(&g->graph, 0);
-  hipGraphNode_t last = nullptr;
+  // dependencies as in the overlapped sf_batch_run: the tracks of round r
+  // follow the tracks of round r - 1, the element work of round r - 2 (the
+  // last user of their buffer set) and the measurement of round r - 1 (its
+  // outcomes); the phase, fit, segment and measurement kernels of round r
+  // follow the tracks of round r and the element work of round r - 1
   char* base = (char*)g->ddesc.p;
+  hipGraphNode_t init = nullptr, track_last = nullptr, elem_last = nullptr, meas_prev = nullptr;
+  std::vector<hipGraphNode_t> elem_end(rounds.size(), nullptr);
   if (e == hipSuccess && ns) {
     const InitDesc* di = (const InitDesc*)(base + off_init);
     void* args[] = {(void*)&di};
-    e = add_kernel_node(g->graph, &last, (const void*)sf_init_batch, dim3((unsigned)ns), dim3(EB), args);
+    e = add_node_after(g->graph, &init, {}, (const void*)sf_init_batch, dim3((unsigned)ns), dim3(EB), args);
+    track_last = elem_last = init;
   }
   for (size_t r = 0; r < rounds.size() && e == hipSuccess; ++r) {
     const RoundPlan& rp = rounds[r];
     const int na = rp.na;
     const TrackJob* dj = (const TrackJob*)(base + off_j[r]);
     const ElemDesc* dd = (const ElemDesc*)(base + off_d[r]);
+    const hipGraphNode_t reuse = r >= 2 ? elem_end[r - 2] : nullptr;
     int off = 0;
     for (int w = 1; w <= SF_WMAX && e == hipSuccess; ++w) {
       if (!rp.wcount[w]) continue;
       const TrackJob* djw = dj + off;
       void* args[] = {(void*)&djw};
-      e = add_kernel_node(g->graph, &last, track_many_fn(w), dim3(rp.wcount[w]), dim3(TL), args);
-      if (e == hipSuccess && rp.wchunk[w] > 0) {
-        e = add_kernel_node(g->graph, &last, phase_many_fn(w), dim3(rp.wchunk[w], rp.wcount[w]), dim3(TL), args);
+      hipGraphNode_t nd = nullptr;
+      e = add_node_after(g->graph, &nd, {track_last, reuse, meas_prev}, track_many_fn(w), dim3(rp.wcount[w]),
+                         dim3(TL), args);
+      if (e == hipSuccess) track_last = nd;
+      off += rp.wcount[w];
+    }
+    // element chain of this round
+    hipGraphNode_t prev = elem_last;
+    bool first = true;
+    auto chain = [&](const void* func, dim3 grid, dim3 block, void** args) {
+      hipGraphNode_t nd = nullptr;
+      if (first)
+        e = add_node_after(g->graph, &nd, {prev, track_last}, func, grid, block, args);
+      else
+        e = add_node_after(g->graph, &nd, {prev}, func, grid, block, args);
+      if (e == hipSuccess) { prev = nd; first = false; }
+    };
+    off = 0;
+    for (int w = 1; w <= SF_WMAX && e == hipSuccess; ++w) {
+      if (!rp.wcount[w]) continue;
+      const TrackJob* djw = dj + off;
+      void* args[] = {(void*)&djw};
+      if (rp.wchunk[w] > 0) {
+        chain(phase_many_fn(w), dim3(rp.wchunk[w], rp.wcount[w]), dim3(TL), args);
         if (e == hipSuccess && rp.wseg[w] > 0)
-          e = add_kernel_node(g->graph, &last, (const void*)sf_fit_many, dim3(rp.wseg[w], rp.wcount[w]), dim3(TL),
-                              args);
+          chain((const void*)sf_fit_many, dim3(rp.wseg[w], rp.wcount[w]), dim3(TL), args);
       }
       off += rp.wcount[w];
     }
@@ -2173,29 +2357,34 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
         const ElemDesc* d0 = dd;
         int kmax = rp.kmax, nna = na, meas = rp.anym ? 1 : 0;
         void* args[] = {(void*)&d0, (void*)&kmax, (void*)&nna, (void*)&meas};
-        e = add_kernel_node(g->graph, &last, (const void*)sf_elem_small_batch, dim3(na), dim3(EB), args);
+        chain((const void*)sf_elem_small_batch, dim3(na), dim3(EB), args);
       }
-      continue;
-    }
-    for (int k = 0; k < rp.kmax && e == hipSuccess; ++k) {
-      const ElemDesc* dk = dd + (size_t)k * na;
-      void* args[] = {(void*)&dk};
-      e = add_kernel_node(g->graph, &last, (const void*)sf_seg_batch, dim3(rp.kgx[(size_t)k], na),
-                          dim3(rp.kbx[(size_t)k]), args);
-    }
-    if (rp.anym && e == hipSuccess) {
-      const ElemDesc* dm = dd + (size_t)rp.kmax * na;
-      void* args[] = {(void*)&dm};
-      const dim3 fg(rp.kgx[(size_t)rp.kmax], na), fb(rp.kbx[(size_t)rp.kmax]);
-      e = add_kernel_node(g->graph, &last, (const void*)sf_meas_reduce_batch, dim3(rp.gm, na), dim3(EB), args);
-      if (e == hipSuccess && coin_apart(rp)) {
-        e = add_kernel_node(g->graph, &last, (const void*)sf_meas_coin_batch, dim3(na), dim3(EB), args);
-        if (e == hipSuccess)
-          e = add_kernel_node(g->graph, &last, (const void*)sf_meas_apply_batch, fg, fb, args);
-      } else if (e == hipSuccess) {
-        e = add_kernel_node(g->graph, &last, (const void*)sf_meas_filter_batch, fg, fb, args);
+    } else {
+      for (int k = 0; k < rp.kmax && e == hipSuccess; ++k) {
+        const ElemDesc* dk = dd + (size_t)k * na;
+        void* args[] = {(void*)&dk};
+        chain((const void*)sf_seg_batch, dim3(rp.kgx[(size_t)k], na), dim3(rp.kbx[(size_t)k]), args);
+      }
+      if (rp.anym && e == hipSuccess) {
+        const ElemDesc* dm = dd + (size_t)rp.kmax * na;
+        void* args[] = {(void*)&dm};
+        const dim3 fg(rp.kgx[(size_t)rp.kmax], na), fb(rp.kbx[(size_t)rp.kmax]);
+        chain((const void*)sf_meas_reduce_batch, dim3(rp.gm, na), dim3(EB), args);
+        if (e == hipSuccess && coin_apart(rp)) {
+          chain((const void*)sf_meas_coin_batch, dim3(na), dim3(EB), args);
+          if (e == hipSuccess) chain((const void*)sf_meas_apply_batch, fg, fb, args);
+        } else if (e == hipSuccess) {
+          chain((const void*)sf_meas_filter_batch, fg, fb, args);
+        }
       }
     }
+    if (first && e == hipSuccess) {
+      // no element work this round: the round ends with its tracks
+      prev = track_last;
+    }
+    elem_last = prev;
+    elem_end[r] = prev;
+    meas_prev = rp.anym ? prev : nullptr;
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) {
