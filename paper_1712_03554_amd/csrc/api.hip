@@ -114,6 +114,21 @@ static void scratch_lookup(int device) {
 // Circuits whose hull never exceeds this dimension (2^8 = EB slots, one
 // reduction block) measure with one fused kernel per measurement.
 #define SF_MSMALL_D 8
+// Flattened batched element launches: slots per thread, and at most this many
+// blocks of EB threads per frame (a larger frame's threads stride over it).
+#ifndef SF_BATCH_EPT
+#define SF_BATCH_EPT 4
+#endif
+#define SF_BATCH_BLOCKS_MAX 8192
+
+// blocks of a frame whose hull dimension is at most d in a flattened launch
+static uint32_t batch_blocks(int d, uint64_t cap) {
+  if (d < 0) d = 0;
+  if (d > SF_DMAX) d = SF_DMAX;
+  const uint64_t per = (uint64_t)EB * SF_BATCH_EPT;
+  const uint64_t nb = ((1ull << d) + per - 1) / per;
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(nb, cap));
+}
 
 static int grid_for(int d) {
   uint64_t blocks = ((1ull << d) + EB - 1) / EB;
@@ -1474,17 +1489,28 @@ static ElemDesc elem_desc(const sf_state* s, int cur, const SegProg* prog, const
 struct RoundPlan {
   std::vector<TrackJob> jobs;
   std::vector<ElemDesc> desc;
-  int na = 0, kmax = 0, gx = 1, bx = EB, gm = 1;
+  int na = 0, kmax = 0;
   bool anym = false;
   bool msmall = false;  // every frame's hull stays within SF_MSMALL_D: fused measurement kernel
   int wcount[SF_WMAX + 1] = {0, 0, 0, 0, 0};  // frames per word count (jobs are ordered by it)
   int wlen[SF_WMAX + 1] = {0, 0, 0, 0, 0};    // per word count: longest range, most segments,
   int wseg[SF_WMAX + 1] = {0, 0, 0, 0, 0};    // phase-kernel chunks of the longest range
   int wchunk[SF_WMAX + 1] = {0, 0, 0, 0, 0};  // 0: no Clifford gate in the group's ranges
-  // per segment row k (and the measurement row kmax): launch shape from the
-  // largest hull dimension any frame has there
-  std::vector<int> kbx, kgx;
+  // block starts of the flattened element launches: rows 0..kmax-1 the
+  // segments, row kmax the measurement reductions, row kmax+1 the
+  // measurement filters; na + 1 entries per row (the last is the row's grid)
+  std::vector<uint32_t> bst;
+  // the bytes copied to the device: desc, then bst at offset bst_off
+  size_t bst_off = 0;
+  std::vector<char> dbytes;
 };
+
+static unsigned row_blocks(const RoundPlan& rp, int r) { return rp.bst[(size_t)r * (rp.na + 1) + rp.na]; }
+
+// row r's block starts in the device copy whose descriptors are at dd
+static const uint32_t* row_starts(const RoundPlan& rp, const ElemDesc* dd, int r) {
+  return (const uint32_t*)((const char*)dd + rp.bst_off) + (size_t)r * (rp.na + 1);
+}
 
 // Plans the next round from the progress pr[] and advances it; false when no
 // frame has work left or on an error (*err set; *bad = index of the state
@@ -1532,7 +1558,6 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
   rp->na = na;
   rp->jobs.assign(na, TrackJob{});
   rp->kmax = 0;
-  rp->gx = rp->gm = 1;
   rp->anym = false;
   int dm = 0;
   for (int j = 0; j < na; ++j) {
@@ -1565,7 +1590,6 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
     rp->wseg[wi] = std::max(rp->wseg[wi], NS[i]);
     rp->kmax = std::max(rp->kmax, NS[i]);
     dm = std::max(dm, s->c->dmax);
-    rp->gm = std::max(rp->gm, s->G);
     rp->anym |= ML[i] != 0;
   }
   // phase-kernel chunk per word count: the group's gates over SF_PHASE_WAVES
@@ -1589,12 +1613,17 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
     for (int j = 0; j < na; ++j)
       if (rp->jobs[j].rec) rp->jobs[j].pchunk = kw[jw[j]];
   }
-  elem_shape(states[act[0]]->ctx, dm, &rp->bx, &rp->gx);
   rp->msmall = dm <= SF_MSMALL_D;
-  // launch shapes per segment row from the frames' segment dimensions (any
-  // shape covers every slot: the element kernels stride over the grid)
+  // flattened element launches: in row k (segment k; then the measurements'
+  // reduction row and filter row) frame j takes its own number of blocks,
+  // from the bound on its hull dimension there, so small frames beside a
+  // large one start no idle blocks.  Row r holds na + 1 block starts.
   {
-    std::vector<int> kd((size_t)rp->kmax + 1, 0);
+    const int R = rp->kmax + 2;
+    const size_t stride = (size_t)na + 1;
+    rp->bst.assign((size_t)R * stride, 0);
+    // every row's total stays a valid grid size
+    const uint64_t bcap = std::min<uint64_t>(SF_BATCH_BLOCKS_MAX, (uint64_t)INT32_MAX / (uint64_t)na);
     for (int j = 0; j < na; ++j) {
       const int i = act[j];
       const sf_circuit* c = states[i]->c;
@@ -1605,15 +1634,17 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
             c->ranges[(size_t)r].ns == NS[i])
           dims = c->rdims.data() + c->ranges[(size_t)r].dofs;
       }
-      for (int k = 0; k < NS[i]; ++k) kd[(size_t)k] = std::max(kd[(size_t)k], dims ? (int)dims[k] : c->dmax);
+      for (int k = 0; k < NS[i]; ++k)
+        rp->bst[(size_t)k * stride + j + 1] = batch_blocks(dims ? (int)dims[k] : c->dmax, bcap);
       if (ML[i] && NS[i] > 0) {
         const int dl = dims ? std::min((int)dims[NS[i] - 1] + 1, c->dmax) : c->dmax;
-        kd[(size_t)rp->kmax] = std::max(kd[(size_t)rp->kmax], dl);
+        const uint64_t live = ((1ull << dl) + EB - 1) / EB;  // reduction blocks that meet a slot
+        rp->bst[(size_t)rp->kmax * stride + j + 1] = (uint32_t)std::min<uint64_t>(live, (uint64_t)states[i]->G);
+        rp->bst[(size_t)(rp->kmax + 1) * stride + j + 1] = batch_blocks(dl, bcap);
       }
     }
-    rp->kbx.assign((size_t)rp->kmax + 1, EB);
-    rp->kgx.assign((size_t)rp->kmax + 1, 1);
-    for (int k = 0; k <= rp->kmax; ++k) elem_shape(states[act[0]]->ctx, kd[(size_t)k], &rp->kbx[(size_t)k], &rp->kgx[(size_t)k]);
+    for (int r = 0; r < R; ++r)
+      for (int j = 0; j < na; ++j) rp->bst[(size_t)r * stride + j + 1] += rp->bst[(size_t)r * stride + j];
   }
   const int kmax = rp->kmax;
   rp->desc.assign((size_t)(kmax + 1) * na, ElemDesc{});
@@ -1628,6 +1659,10 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
       // (an idle entry only needs its null program, which assign left)
       if (p) rp->desc[(size_t)k * na + j] = elem_desc(s, pr[i].cur, p, seedp ? seedp[i] : nullptr, par);
     }
+  rp->bst_off = (rp->desc.size() * sizeof(ElemDesc) + 255) & ~(size_t)255;
+  rp->dbytes.assign(rp->bst_off + rp->bst.size() * sizeof(uint32_t), 0);
+  memcpy(rp->dbytes.data(), rp->desc.data(), rp->desc.size() * sizeof(ElemDesc));
+  memcpy(rp->dbytes.data() + rp->bst_off, rp->bst.data(), rp->bst.size() * sizeof(uint32_t));
   for (int j = 0; j < na; ++j) {
     const int i = act[j];
     pr[i].dev_done = B[i];
@@ -1642,14 +1677,21 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
 struct BatchScratch {
   DevBuf djobs, ddesc;
   std::vector<std::vector<TrackJob>> keep_jobs;
-  std::vector<std::vector<ElemDesc>> keep_desc;
+  std::vector<std::vector<char>> keep_desc;
 };
 
 // jobs then (at a 256-byte boundary) descriptors: one copy per round
 static size_t desc_offset(size_t job_bytes) { return (job_bytes + 255) & ~(size_t)255; }
 
+// device bytes of a round's descriptors and block starts (RoundPlan::dbytes)
+// for ns frames of at most maxseg segments
+static size_t desc_capacity(size_t ns, int maxseg) {
+  ns = std::max<size_t>(1, ns);
+  return desc_offset((size_t)(maxseg + 1) * ns * sizeof(ElemDesc)) + (size_t)(maxseg + 2) * (ns + 1) * sizeof(uint32_t);
+}
+
 static sf_status scratch_reserve(sf_ctx* ctx, BatchScratch* bs, size_t ns, int maxseg) {
-  size_t need_d = (size_t)(maxseg + 1) * std::max<size_t>(1, ns) * sizeof(ElemDesc);
+  size_t need_d = desc_capacity(ns, maxseg);
   size_t need_j = desc_offset(std::max<size_t>(1, ns) * sizeof(TrackJob)) + need_d;
   sf_status rc;
   if (bs->djobs.bytes < need_j) {
@@ -1674,9 +1716,7 @@ static void scratch_free(sf_ctx* ctx, BatchScratch* bs) {
 // filter launch has many blocks: each block of the fused filter kernel sums
 // the reduction's partials again, which costs more than a launch there.
 #define SF_COIN_APART_BLOCKS 2048
-static bool coin_apart(const RoundPlan& rp) {
-  return (size_t)rp.kgx[(size_t)rp.kmax] * (size_t)rp.na > SF_COIN_APART_BLOCKS;
-}
+static bool coin_apart(const RoundPlan& rp) { return row_blocks(rp, rp.kmax + 1) > SF_COIN_APART_BLOCKS; }
 
 // Kernel launches of one planned round, with its descriptors at djobs/ddesc.
 static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs, const ElemDesc* dd) {
@@ -1701,27 +1741,30 @@ static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs
     return;
   }
   for (int k = 0; k < rp.kmax; ++k) {
+    if (!row_blocks(rp, k)) continue;
     prof_begin(ctx, PK_SEG);
-    hipLaunchKernelGGL(sf_seg_batch, dim3(rp.kgx[(size_t)k], na), dim3(rp.kbx[(size_t)k]), 0, ctx->stream,
-                       dd + (size_t)k * na);
+    hipLaunchKernelGGL(sf_seg_batch, dim3(row_blocks(rp, k)), dim3(EB), 0, ctx->stream, dd + (size_t)k * na,
+                       row_starts(rp, dd, k), na);
     prof_end(ctx);
   }
   if (rp.anym) {
     const ElemDesc* dm = dd + (size_t)rp.kmax * na;
-    const int fx = rp.kgx[(size_t)rp.kmax], fb = rp.kbx[(size_t)rp.kmax];
+    const uint32_t* rb = row_starts(rp, dd, rp.kmax);
+    const uint32_t* fb = row_starts(rp, dd, rp.kmax + 1);
+    const dim3 rg(row_blocks(rp, rp.kmax)), fg(row_blocks(rp, rp.kmax + 1));
     prof_begin(ctx, PK_MREDUCE);
-    hipLaunchKernelGGL(sf_meas_reduce_batch, dim3(rp.gm, na), dim3(EB), 0, ctx->stream, dm);
+    hipLaunchKernelGGL(sf_meas_reduce_batch, rg, dim3(EB), 0, ctx->stream, dm, rb, na);
     prof_end(ctx);
     if (coin_apart(rp)) {
       prof_begin(ctx, PK_MFINAL);
       hipLaunchKernelGGL(sf_meas_coin_batch, dim3(na), dim3(EB), 0, ctx->stream, dm);
       prof_end(ctx);
       prof_begin(ctx, PK_MFILTER);
-      hipLaunchKernelGGL(sf_meas_apply_batch, dim3(fx, na), dim3(fb), 0, ctx->stream, dm);
+      hipLaunchKernelGGL(sf_meas_apply_batch, fg, dim3(EB), 0, ctx->stream, dm, fb, na);
       prof_end(ctx);
     } else {
       prof_begin(ctx, PK_MFILTER);
-      hipLaunchKernelGGL(sf_meas_filter_batch, dim3(fx, na), dim3(fb), 0, ctx->stream, dm);
+      hipLaunchKernelGGL(sf_meas_filter_batch, fg, dim3(EB), 0, ctx->stream, dm, fb, na);
       prof_end(ctx);
     }
   }
@@ -1745,12 +1788,12 @@ static sf_status batch_round(sf_ctx* ctx, sf_state* const* states, size_t ns, Ba
   if (!plan_round(states, ns, pr.data(), cap, nullptr, &rp, &err, bad, noalloc)) return err;
   *active = rp.na;
   if (staged) {
-    const size_t bj = rp.na * sizeof(TrackJob), bd = rp.desc.size() * sizeof(ElemDesc);
+    const size_t bj = rp.na * sizeof(TrackJob), bd = rp.dbytes.size();
     const size_t offd = desc_offset(bj);
     char* h = offd + bd <= bs->djobs.bytes ? (char*)pin_take(ctx, offd + bd) : nullptr;
     if (h) {
       memcpy(h, rp.jobs.data(), bj);
-      memcpy(h + offd, rp.desc.data(), bd);
+      memcpy(h + offd, rp.dbytes.data(), bd);
       HIPCHK(ctx, hipMemcpyAsync(bs->djobs.p, h, offd + bd, hipMemcpyHostToDevice, ctx->stream));
       launch_round(ctx, rp, (const TrackJob*)bs->djobs.p, (const ElemDesc*)((char*)bs->djobs.p + offd));
       HIPCHK(ctx, hipGetLastError());
@@ -1758,13 +1801,12 @@ static sf_status batch_round(sf_ctx* ctx, sf_state* const* states, size_t ns, Ba
       return SF_OK;
     }
   }
-  const size_t ndesc = rp.desc.size();
+  const size_t ndesc = rp.dbytes.size();
   bs->keep_jobs.push_back(std::move(rp.jobs));
-  bs->keep_desc.push_back(std::move(rp.desc));
+  bs->keep_desc.push_back(std::move(rp.dbytes));
   HIPCHK(ctx, hipMemcpyAsync(bs->djobs.p, bs->keep_jobs.back().data(), rp.na * sizeof(TrackJob),
                              hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(ctx, hipMemcpyAsync(bs->ddesc.p, bs->keep_desc.back().data(), ndesc * sizeof(ElemDesc),
-                             hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(bs->ddesc.p, bs->keep_desc.back().data(), ndesc, hipMemcpyHostToDevice, ctx->stream));
   launch_round(ctx, rp, (const TrackJob*)bs->djobs.p, (const ElemDesc*)bs->ddesc.p);
   HIPCHK(ctx, hipGetLastError());
   for (size_t i = 0; i < ns; ++i) set_progress(states[i], pr[i]);
@@ -1793,20 +1835,20 @@ static sf_status batch_round_ov(sf_ctx* ctx, sf_state* const* states, size_t ns,
   BatchScratch* bs = &bsets[par];
   if (round >= 2) HIPCHK(ctx, hipStreamWaitEvent(T, ctx->ev_elem[par], 0));
   if (*prev_meas) HIPCHK(ctx, hipStreamWaitEvent(T, ctx->ev_meas, 0));
-  const size_t bj = rp.na * sizeof(TrackJob), bd = rp.desc.size() * sizeof(ElemDesc);
+  const size_t bj = rp.na * sizeof(TrackJob), bd = rp.dbytes.size();
   const size_t offd = desc_offset(bj);
   const TrackJob* djobs;
   const ElemDesc* dd;
   char* h = offd + bd <= bs->djobs.bytes ? (char*)pin_take(ctx, offd + bd) : nullptr;
   if (h) {
     memcpy(h, rp.jobs.data(), bj);
-    memcpy(h + offd, rp.desc.data(), bd);
+    memcpy(h + offd, rp.dbytes.data(), bd);
     HIPCHK(ctx, hipMemcpyAsync(bs->djobs.p, h, offd + bd, hipMemcpyHostToDevice, T));
     djobs = (const TrackJob*)bs->djobs.p;
     dd = (const ElemDesc*)((char*)bs->djobs.p + offd);
   } else {
     bs->keep_jobs.push_back(std::move(rp.jobs));
-    bs->keep_desc.push_back(std::move(rp.desc));
+    bs->keep_desc.push_back(std::move(rp.dbytes));
     HIPCHK(ctx, hipMemcpyAsync(bs->djobs.p, bs->keep_jobs.back().data(), bj, hipMemcpyHostToDevice, T));
     HIPCHK(ctx, hipMemcpyAsync(bs->ddesc.p, bs->keep_desc.back().data(), bd, hipMemcpyHostToDevice, T));
     djobs = (const TrackJob*)bs->djobs.p;
@@ -1995,7 +2037,7 @@ extern "C" sf_status sf_batch_run_noalloc(sf_ctx* ctx, sf_state* const* states, 
   void* base = (ctx->device >= 0 && ctx->device < SF_MAX_DEVICES) ? g_scratch_dev[ctx->device] : nullptr;
   if (!base) return fail(ctx, SF_E_DEVICE, "scratch array of device %d has no address", ctx->device);
   // the largest round: every state active with maxseg segments and a measurement
-  const size_t need_d = (size_t)(maxseg + 1) * ns * sizeof(ElemDesc);
+  const size_t need_d = desc_capacity(ns, maxseg);
   const size_t off_d = desc_offset(ns * sizeof(TrackJob));
   const size_t off_g = desc_offset(off_d + need_d);
   if (off_g + gather_bytes(ns) > SF_SCRATCH_BYTES)
@@ -2277,7 +2319,7 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
     off_j[r] = total;
     total += al(rounds[r].jobs.size() * sizeof(TrackJob));
     off_d[r] = total;
-    total += al(rounds[r].desc.size() * sizeof(ElemDesc));
+    total += al(rounds[r].dbytes.size());
   }
   if ((rc = dalloc(ctx, &g->ddesc, total))) { graph_free(g); delete g; return rc; }
   std::vector<char> host(total, 0);
@@ -2293,7 +2335,7 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
   }
   for (size_t r = 0; r < rounds.size(); ++r) {
     memcpy(host.data() + off_j[r], rounds[r].jobs.data(), rounds[r].jobs.size() * sizeof(TrackJob));
-    memcpy(host.data() + off_d[r], rounds[r].desc.data(), rounds[r].desc.size() * sizeof(ElemDesc));
+    memcpy(host.data() + off_d[r], rounds[r].dbytes.data(), rounds[r].dbytes.size());
   }
   hipError_t e = hipMemcpyAsync(g->ddesc.p, host.data(), total, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -2360,21 +2402,28 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
         chain((const void*)sf_elem_small_batch, dim3(na), dim3(EB), args);
       }
     } else {
+      int nna = na;
       for (int k = 0; k < rp.kmax && e == hipSuccess; ++k) {
+        if (!row_blocks(rp, k)) continue;
         const ElemDesc* dk = dd + (size_t)k * na;
-        void* args[] = {(void*)&dk};
-        chain((const void*)sf_seg_batch, dim3(rp.kgx[(size_t)k], na), dim3(rp.kbx[(size_t)k]), args);
+        const uint32_t* bk = row_starts(rp, dd, k);
+        void* args[] = {(void*)&dk, (void*)&bk, (void*)&nna};
+        chain((const void*)sf_seg_batch, dim3(row_blocks(rp, k)), dim3(EB), args);
       }
       if (rp.anym && e == hipSuccess) {
         const ElemDesc* dm = dd + (size_t)rp.kmax * na;
-        void* args[] = {(void*)&dm};
-        const dim3 fg(rp.kgx[(size_t)rp.kmax], na), fb(rp.kbx[(size_t)rp.kmax]);
-        chain((const void*)sf_meas_reduce_batch, dim3(rp.gm, na), dim3(EB), args);
+        const uint32_t* rb = row_starts(rp, dd, rp.kmax);
+        const uint32_t* fb = row_starts(rp, dd, rp.kmax + 1);
+        void* rargs[] = {(void*)&dm, (void*)&rb, (void*)&nna};
+        void* cargs[] = {(void*)&dm};
+        void* fargs[] = {(void*)&dm, (void*)&fb, (void*)&nna};
+        const dim3 fg(row_blocks(rp, rp.kmax + 1));
+        chain((const void*)sf_meas_reduce_batch, dim3(row_blocks(rp, rp.kmax)), dim3(EB), rargs);
         if (e == hipSuccess && coin_apart(rp)) {
-          chain((const void*)sf_meas_coin_batch, dim3(na), dim3(EB), args);
-          if (e == hipSuccess) chain((const void*)sf_meas_apply_batch, fg, fb, args);
+          chain((const void*)sf_meas_coin_batch, dim3(na), dim3(EB), cargs);
+          if (e == hipSuccess) chain((const void*)sf_meas_apply_batch, fg, dim3(EB), fargs);
         } else if (e == hipSuccess) {
-          chain((const void*)sf_meas_filter_batch, fg, fb, args);
+          chain((const void*)sf_meas_filter_batch, fg, dim3(EB), fargs);
         }
       }
     }

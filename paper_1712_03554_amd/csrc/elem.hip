@@ -238,9 +238,13 @@ __device__ __forceinline__ void meas_coin_local(const SegProg* __restrict__ sp, 
   __shared__ uint32_t s_o;
   __shared__ double s_sc;
   const int nt = blockDim.x;
+  // partials of blocks beyond the slots are +0.0, which leaves a sum of
+  // non-negative terms unchanged: they are neither read nor required
+  const uint64_t live = ((1ull << sp->d_out) + EB - 1) / EB;
+  const int Gl = live < (uint64_t)G ? (int)live : G;
   for (int t = threadIdx.x; t < EB; t += nt) {
     double p0 = 0.0, p1 = 0.0;
-    for (int i = t; i < G; i += EB) {
+    for (int i = t; i < Gl; i += EB) {
       p0 = __dadd_rn(p0, partials[i].x);
       p1 = __dadd_rn(p1, partials[i].y);
     }
@@ -389,32 +393,67 @@ sf_meas_filter(const SegProg* __restrict__ sp, const double2* __restrict__ parti
 }
 
 // ---------------------------------------------------------------------------
-// Batched forms: blockIdx.y selects the frame (ElemDesc), blockIdx.x and the
-// block's threads stride over that frame's slots.
+// Batched forms, flattened: the grid is the concatenation of every frame's
+// blocks.  B[j] is the first block of descriptor j (B[0] = 0, B[na] = the
+// grid); a descriptor without blocks is idle.  A block finds its frame by a
+// binary search over B (uniform across the block) and strides over that
+// frame's slots with the frame's own block count, so each frame launches
+// only the blocks its hull needs.
 // ---------------------------------------------------------------------------
-#define BTID ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x)
-#define BSTRIDE ((uint64_t)gridDim.x * blockDim.x)
+struct BatchPos {
+  int j;            // descriptor
+  uint64_t tid;     // thread index within the frame's blocks
+  uint64_t stride;  // threads of the frame's blocks
+  uint32_t blk;     // block index within the frame's blocks
+};
 
-extern "C" __global__ void __launch_bounds__(EB) sf_seg_batch(const ElemDesc* __restrict__ D) {
-  const ElemDesc& e = D[blockIdx.y];
+__device__ __forceinline__ BatchPos batch_pos(const uint32_t* __restrict__ B, int na) {
+  const uint32_t b = blockIdx.x;
+  int lo = 0, hi = na;  // B[lo] <= b < B[hi] (B[na] is the grid)
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (B[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  BatchPos p;
+  p.j = lo;
+  const uint32_t b0 = B[lo];
+  const uint32_t nb = B[lo + 1] - b0;
+  p.blk = b - b0;
+  p.tid = (uint64_t)p.blk * blockDim.x + threadIdx.x;
+  p.stride = (uint64_t)nb * blockDim.x;
+  return p;
+}
+
+extern "C" __global__ void __launch_bounds__(EB)
+sf_seg_batch(const ElemDesc* __restrict__ D, const uint32_t* __restrict__ B, int na) {
+  const BatchPos p = batch_pos(B, na);
+  const ElemDesc& e = D[p.j];
   if (!e.prog) return;
-  seg_body(e.prog, e.had, e.amp, BTID, BSTRIDE);
+  seg_body(e.prog, e.had, e.amp, p.tid, p.stride);
 }
 
-extern "C" __global__ void __launch_bounds__(EB) sf_meas_reduce_batch(const ElemDesc* __restrict__ D) {
-  const ElemDesc& e = D[blockIdx.y];
-  if (!e.prog || (int)blockIdx.x >= e.G) return;
-  meas_reduce_body(e.prog, e.amp, e.partials, blockIdx.x, e.G);
+// Reduction blocks of a frame: partial b of its fixed shape G; only blocks
+// that meet a slot are launched (the others' partials are zero, and the coin
+// reads no partial beyond them).
+extern "C" __global__ void __launch_bounds__(EB)
+sf_meas_reduce_batch(const ElemDesc* __restrict__ D, const uint32_t* __restrict__ B, int na) {
+  const BatchPos p = batch_pos(B, na);
+  const ElemDesc& e = D[p.j];
+  if (!e.prog || (int)p.blk >= e.G) return;
+  meas_reduce_body(e.prog, e.amp, e.partials, (int)p.blk, e.G);
 }
 
-extern "C" __global__ void __launch_bounds__(EB) sf_meas_filter_batch(const ElemDesc* __restrict__ D) {
-  const ElemDesc& e = D[blockIdx.y];
+extern "C" __global__ void __launch_bounds__(EB)
+sf_meas_filter_batch(const ElemDesc* __restrict__ D, const uint32_t* __restrict__ B, int na) {
+  const BatchPos p = batch_pos(B, na);
+  const ElemDesc& e = D[p.j];
   if (!e.prog) return;
   uint32_t o;
   double sc;
-  meas_coin_local(e.prog, e.partials, e.G, e.seedp ? *e.seedp : e.seed, blockIdx.x == 0, e.outcomes, e.pvals,
+  meas_coin_local(e.prog, e.partials, e.G, e.seedp ? *e.seedp : e.seed, p.blk == 0, e.outcomes, e.pvals,
                   e.scale, e.flags, &o, &sc);
-  meas_filter_body(e.prog, e.amp, e.amp_other, o, sc, BTID, BSTRIDE);
+  meas_filter_body(e.prog, e.amp, e.amp_other, o, sc, p.tid, p.stride);
 }
 
 // The same in two kernels for launches of many frames: the coin once per
@@ -431,12 +470,14 @@ extern "C" __global__ void __launch_bounds__(EB) sf_meas_coin_batch(const ElemDe
                   e.flags, &o, &sc);
 }
 
-extern "C" __global__ void __launch_bounds__(EB) sf_meas_apply_batch(const ElemDesc* __restrict__ D) {
-  const ElemDesc& e = D[blockIdx.y];
+extern "C" __global__ void __launch_bounds__(EB)
+sf_meas_apply_batch(const ElemDesc* __restrict__ D, const uint32_t* __restrict__ B, int na) {
+  const BatchPos p = batch_pos(B, na);
+  const ElemDesc& e = D[p.j];
   if (!e.prog) return;
   const uint32_t o = e.outcomes[e.prog->meas_index];
   const double sc = e.scale[0];
-  meas_filter_body(e.prog, e.amp, e.amp_other, o, sc, BTID, BSTRIDE);
+  meas_filter_body(e.prog, e.amp, e.amp_other, o, sc, p.tid, p.stride);
 }
 
 // Frames of at most EB slots: every segment of a round, then its
