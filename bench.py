@@ -100,9 +100,10 @@ def terminal_indices(circ, wl):
     return out
 
 
-def accounting(state, circ, seed, wl, sizes=None):
+def accounting(state, circ, seed, wl, sizes=None, meas=None):
     """Untimed pass: U (sum over gates of |F| before the gate) and the hull
-    dimension on entry to every segment launch (and, into sizes, |F| there)."""
+    dimension on entry to every segment launch (and, into sizes, |F| there;
+    into meas, (d before, d after) of every measurement)."""
     state.reset(circ.init_bits, seed)
     terms = terminal_indices(circ, wl)
     U, K, d, pos = 0, 1, 0, 0
@@ -116,7 +117,9 @@ def accounting(state, circ, seed, wl, sizes=None):
         k = state.step(t + 1 - pos)
         assert k == t + 1 - pos, (k, t, pos)
         K = state.frame_size()
-        d = state.dim()
+        d_before, d = d, state.dim()
+        if meas is not None and circ.gates[t][0] == wl.MEASURE:
+            meas.append((d_before, d))
         pos = t + 1
     return U, seg_dims
 
@@ -625,10 +628,11 @@ def main():
     states = [l.state(c.init_bits, s) for l, c, s in zip(loaded, circs, seeds)]
     bounds = [l.info()[0] for l in loaded]
 
-    U_each, seg_dims, seg_sizes = [], [], []
+    U_each, seg_dims, seg_sizes, meas_dims = [], [], [], []
     for st, c, s in zip(states, circs, seeds):
-        Ks = []
-        U, dims = accounting(st, c, s, wl, sizes=Ks)
+        Ks, Ms = [], []
+        U, dims = accounting(st, c, s, wl, sizes=Ks, meas=Ms)
+        meas_dims.append(Ms)
         U_each.append(U)
         seg_dims.append(dims)
         seg_sizes.append(Ks)
@@ -763,7 +767,29 @@ def main():
                   "traffic": measured_traffic(pname, args.workload),
                   "note": "one record (rows and hull after the gate) read per Clifford gate; runs beside the "
                           "next round's tracks, so its launches share the SIMDs with them"}
-    roof = dict({"segment": elem_roof, "phase": phase_roof}.get(dom, track_roof))
+    # measurements: the reduction reads the 2^d slots before (16 B each); the
+    # filter reads the kept 2^d' slots and writes them (32 B each)
+    step_meas = meas_dims[:n_plain] if args.path == "plain" else meas_dims
+    red_bytes = sum(16.0 * (1 << a) for ms in step_meas for a, _ in ms)
+    fil_bytes = sum(32.0 * (1 << b) for ms in step_meas for _, b in ms)
+
+    def hbm_roof(kind, kname, nbytes, note):
+        ms_, n_ = kind_ms(kind)
+        a = (nbytes * args.steps / n_) / (ms_ / 1e3 / n_) / 1e9 if n_ else 0.0
+        return {"bound": "hbm", "kernel": kname, "avg_launch_us": ms_ / n_ * 1e3 if n_ else None,
+                "achieved": a, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": a / PEAK_HBM_GBS,
+                "traffic": measured_traffic(kname, args.workload), "bytes_per_step": nbytes, "note": note}
+
+    batched_names = args.path != "plain"
+    meas_roof = {
+        "reduce": hbm_roof("meas_reduce", "sf_meas_reduce_batch" if batched_names else "sf_meas_reduce",
+                           red_bytes, "16 B read per hull slot before the measurement"),
+        "filter": hbm_roof("meas_filter", "sf_meas_filter_batch" if batched_names else "sf_meas_filter",
+                           fil_bytes, "32 B (read + write) per kept slot; the fused form also sums the "
+                                      "reduction partials in every block"),
+    }
+    roof = dict({"segment": elem_roof, "phase": phase_roof, "meas_reduce": meas_roof["reduce"],
+                 "meas_filter": meas_roof["filter"]}.get(dom, track_roof))
     line = {
         "metric": "frame-element gate updates/s",
         "value": value,
@@ -796,6 +822,7 @@ def main():
         "track_roofline": track_roof,
         "phase_roofline": phase_roof,
         "element_roofline": elem_roof,
+        "measurement_rooflines": meas_roof,
         "track_cycles_last_step": cyc,
         "autotune": {str(d): {"block": b, "grid": g, "ms": round(t, 4)} for d, (b, g, t) in tuned.items()},
     }

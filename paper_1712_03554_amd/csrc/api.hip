@@ -850,7 +850,7 @@ extern "C" sf_status sf_state_init(sf_ctx* ctx, const sf_circuit* c, const uint6
   s->cur = 0;
   s->orig_done = s->dev_done = s->nmeas = 0;
   s->seed = seed;
-  s->G = grid_for(c->dmax) > 1024 ? 1024 : grid_for(c->dmax);
+  s->G = red_grid(c->dmax);  // partials of the largest reduction shape
   s->meas_cap = std::max<size_t>(1, c->n_meas);
   s->graph_refs = 0;
   sf_status rc = SF_OK;
@@ -1067,7 +1067,7 @@ static sf_status run_chunk(sf_state* s, const DGate* dgates, const DGate* hg, si
                        (double2*)s->partials.p);
     prof_end(ctx);
     prof_begin(ctx, PK_MFILTER);
-    hipLaunchKernelGGL(sf_meas_filter, dim3(grid), dim3(eb), 0, ctx->stream, sp, (const double2*)s->partials.p, s->G,
+    hipLaunchKernelGGL(sf_meas_filter, dim3(grid), dim3(eb), 0, ctx->stream, sp, (const double2*)s->partials.p,
                        s->seed, (uint8_t*)s->outcomes.p, (double*)s->pvals.p, (double*)s->scale.p,
                        (int*)s->flags.p, (const double2*)s->amp[s->cur].p, (double2*)s->amp[s->cur ^ 1].p);
     prof_end(ctx);
@@ -1638,8 +1638,7 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
         rp->bst[(size_t)k * stride + j + 1] = batch_blocks(dims ? (int)dims[k] : c->dmax, bcap);
       if (ML[i] && NS[i] > 0) {
         const int dl = dims ? std::min((int)dims[NS[i] - 1] + 1, c->dmax) : c->dmax;
-        const uint64_t live = ((1ull << dl) + EB - 1) / EB;  // reduction blocks that meet a slot
-        rp->bst[(size_t)rp->kmax * stride + j + 1] = (uint32_t)std::min<uint64_t>(live, (uint64_t)states[i]->G);
+        rp->bst[(size_t)rp->kmax * stride + j + 1] = (uint32_t)red_grid(dl);
         rp->bst[(size_t)(rp->kmax + 1) * stride + j + 1] = batch_blocks(dl, bcap);
       }
     }

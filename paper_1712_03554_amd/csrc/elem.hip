@@ -189,31 +189,68 @@ __device__ __forceinline__ void seg_body(const SegProg* __restrict__ sp, const G
   }
 }
 
+// Reduction shape of a measurement over 2^d slots: red_grid(d) blocks of EB
+// threads, about SF_RED_EPT slots per thread (at most SF_RED_GMAX blocks).
+// A function of d alone, so every path (one frame, batched, graph) adds the
+// same terms in the same order.
+#define SF_RED_EPT 8
+#define SF_RED_GMAX 1024
+__host__ __device__ __forceinline__ int red_grid(int d) {
+  const uint64_t per = (uint64_t)EB * SF_RED_EPT;
+  const uint64_t g = ((1ull << d) + per - 1) / per;
+  return g > SF_RED_GMAX ? SF_RED_GMAX : (int)g;
+}
+
+__device__ __forceinline__ void meas_acc(double2 a, uint64_t Y, uint32_t c0, uint32_t r, double& p0, double& p1) {
+  const double v = norm2(a);
+  if ((c0 ^ (uint32_t)__popc(r & (uint32_t)Y)) & 1u) p1 = __dadd_rn(p1, v);
+  else p0 = __dadd_rn(p0, v);
+}
+
 // Measurement: block partial sums of |a|^2 split by the qubit value; block b
-// of G covers slots b*EB + t, stepping by G*EB (a fixed reduction shape).
+// of G = red_grid(d) covers slots b*EB + t, stepping by G*EB, in that order,
+// then a pairwise tree over the block's threads (s[t] += s[t + h] for
+// h = EB/2 .. 1; the levels within one wavefront by lane shuffles, which add
+// the same pairs).  Blocks b >= G write nothing.
 __device__ __forceinline__ void meas_reduce_body(const SegProg* __restrict__ sp, const double2* __restrict__ amp,
-                                                 double2* __restrict__ partials, int block, int G) {
+                                                 double2* __restrict__ partials, int block) {
   __shared__ double s0[EB], s1[EB];
-  const uint64_t N = 1ull << sp->d_out;
+  const int d = sp->d_out;
+  const int G = red_grid(d);
+  if (block >= G) return;
+  const uint64_t N = 1ull << d;
   const uint32_t c0 = sp->m_c0, r = sp->m_r;
   const uint64_t stride = (uint64_t)G * EB;
   double p0 = 0.0, p1 = 0.0;
-  for (uint64_t Y = (uint64_t)block * EB + threadIdx.x; Y < N; Y += stride) {
-    double v = norm2(amp[Y]);
-    if ((c0 ^ (uint32_t)__popc(r & (uint32_t)Y)) & 1u) p1 = __dadd_rn(p1, v);
-    else p0 = __dadd_rn(p0, v);
+  uint64_t Y = (uint64_t)block * EB + threadIdx.x;
+  // four loads in flight, added in slot order
+  for (; Y + 3 * stride < N; Y += 4 * stride) {
+    const double2 a0 = amp[Y], a1 = amp[Y + stride], a2 = amp[Y + 2 * stride], a3 = amp[Y + 3 * stride];
+    meas_acc(a0, Y, c0, r, p0, p1);
+    meas_acc(a1, Y + stride, c0, r, p0, p1);
+    meas_acc(a2, Y + 2 * stride, c0, r, p0, p1);
+    meas_acc(a3, Y + 3 * stride, c0, r, p0, p1);
   }
+  for (; Y < N; Y += stride) meas_acc(amp[Y], Y, c0, r, p0, p1);
   s0[threadIdx.x] = p0;
   s1[threadIdx.x] = p1;
   __syncthreads();
-  for (int h = EB / 2; h > 0; h >>= 1) {
+  for (int h = EB / 2; h >= 64; h >>= 1) {
     if (threadIdx.x < h) {
       s0[threadIdx.x] = __dadd_rn(s0[threadIdx.x], s0[threadIdx.x + h]);
       s1[threadIdx.x] = __dadd_rn(s1[threadIdx.x], s1[threadIdx.x + h]);
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) partials[block] = make_double2(s0[0], s1[0]);
+  if (threadIdx.x < 64) {
+    double v0 = s0[threadIdx.x], v1 = s1[threadIdx.x];
+    for (int h = 32; h > 0; h >>= 1) {
+      const double u0 = __shfl_down(v0, h, 64), u1 = __shfl_down(v1, h, 64);
+      v0 = __dadd_rn(v0, u0);
+      v1 = __dadd_rn(v1, u1);
+    }
+    if (threadIdx.x == 0) partials[block] = make_double2(v0, v1);
+  }
 }
 
 __device__ __forceinline__ uint64_t splitmix64_at(uint64_t state, uint64_t index) {
@@ -231,20 +268,17 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t state, uint64_t index
 // the scale.  Every block computes the same values; the writer block stores
 // them.  One launch less per measurement than a separate coin kernel.
 __device__ __forceinline__ void meas_coin_local(const SegProg* __restrict__ sp, const double2* __restrict__ partials,
-                                                int G, uint64_t seed, bool writer, uint8_t* __restrict__ outcomes,
+                                                uint64_t seed, bool writer, uint8_t* __restrict__ outcomes,
                                                 double* __restrict__ pvals, double* __restrict__ scale,
                                                 int* __restrict__ flags, uint32_t* o_out, double* sc_out) {
   __shared__ double v0[EB], v1[EB];
   __shared__ uint32_t s_o;
   __shared__ double s_sc;
   const int nt = blockDim.x;
-  // partials of blocks beyond the slots are +0.0, which leaves a sum of
-  // non-negative terms unchanged: they are neither read nor required
-  const uint64_t live = ((1ull << sp->d_out) + EB - 1) / EB;
-  const int Gl = live < (uint64_t)G ? (int)live : G;
+  const int G = red_grid(sp->d_out);
   for (int t = threadIdx.x; t < EB; t += nt) {
     double p0 = 0.0, p1 = 0.0;
-    for (int i = t; i < Gl; i += EB) {
+    for (int i = t; i < G; i += EB) {
       p0 = __dadd_rn(p0, partials[i].x);
       p1 = __dadd_rn(p1, partials[i].y);
     }
@@ -379,16 +413,16 @@ sf_seg_kernel(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all, 
 
 extern "C" __global__ void __launch_bounds__(EB)
 sf_meas_reduce(const SegProg* __restrict__ sp, const double2* __restrict__ amp, double2* __restrict__ partials) {
-  meas_reduce_body(sp, amp, partials, blockIdx.x, gridDim.x);
+  meas_reduce_body(sp, amp, partials, blockIdx.x);
 }
 
 extern "C" __global__ void __launch_bounds__(EB)
-sf_meas_filter(const SegProg* __restrict__ sp, const double2* __restrict__ partials, int G, uint64_t seed,
+sf_meas_filter(const SegProg* __restrict__ sp, const double2* __restrict__ partials, uint64_t seed,
                uint8_t* __restrict__ outcomes, double* __restrict__ pvals, double* __restrict__ scale,
                int* __restrict__ flags, const double2* __restrict__ src, double2* __restrict__ dst) {
   uint32_t o;
   double sc;
-  meas_coin_local(sp, partials, G, seed, blockIdx.x == 0, outcomes, pvals, scale, flags, &o, &sc);
+  meas_coin_local(sp, partials, seed, blockIdx.x == 0, outcomes, pvals, scale, flags, &o, &sc);
   meas_filter_body(sp, src, dst, o, sc, TID, STRIDE);
 }
 
@@ -433,15 +467,14 @@ sf_seg_batch(const ElemDesc* __restrict__ D, const uint32_t* __restrict__ B, int
   seg_body(e.prog, e.had, e.amp, p.tid, p.stride);
 }
 
-// Reduction blocks of a frame: partial b of its fixed shape G; only blocks
-// that meet a slot are launched (the others' partials are zero, and the coin
-// reads no partial beyond them).
+// Reduction blocks of a frame: partial b of the shape red_grid(d) (the host
+// launches red_grid of its bound on d; blocks beyond the actual shape exit).
 extern "C" __global__ void __launch_bounds__(EB)
 sf_meas_reduce_batch(const ElemDesc* __restrict__ D, const uint32_t* __restrict__ B, int na) {
   const BatchPos p = batch_pos(B, na);
   const ElemDesc& e = D[p.j];
-  if (!e.prog || (int)p.blk >= e.G) return;
-  meas_reduce_body(e.prog, e.amp, e.partials, (int)p.blk, e.G);
+  if (!e.prog) return;
+  meas_reduce_body(e.prog, e.amp, e.partials, (int)p.blk);
 }
 
 extern "C" __global__ void __launch_bounds__(EB)
@@ -451,7 +484,7 @@ sf_meas_filter_batch(const ElemDesc* __restrict__ D, const uint32_t* __restrict_
   if (!e.prog) return;
   uint32_t o;
   double sc;
-  meas_coin_local(e.prog, e.partials, e.G, e.seedp ? *e.seedp : e.seed, p.blk == 0, e.outcomes, e.pvals,
+  meas_coin_local(e.prog, e.partials, e.seedp ? *e.seedp : e.seed, p.blk == 0, e.outcomes, e.pvals,
                   e.scale, e.flags, &o, &sc);
   meas_filter_body(e.prog, e.amp, e.amp_other, o, sc, p.tid, p.stride);
 }
@@ -466,7 +499,7 @@ extern "C" __global__ void __launch_bounds__(EB) sf_meas_coin_batch(const ElemDe
   if (!e.prog) return;
   uint32_t o;
   double sc;
-  meas_coin_local(e.prog, e.partials, e.G, e.seedp ? *e.seedp : e.seed, true, e.outcomes, e.pvals, e.scale,
+  meas_coin_local(e.prog, e.partials, e.seedp ? *e.seedp : e.seed, true, e.outcomes, e.pvals, e.scale,
                   e.flags, &o, &sc);
 }
 
