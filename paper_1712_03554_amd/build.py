@@ -10,6 +10,10 @@ OUT = os.path.join(HERE, "libsframe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+         # every floating-point operation rounded on its own (no fused
+         # multiply-add contraction): the same expression gives the same bits
+         # in every kernel it is inlined into
+         "-ffp-contract=off",
          # keep packed fp32 instructions out of the generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

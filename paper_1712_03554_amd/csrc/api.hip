@@ -323,6 +323,9 @@ struct sf_circuit {
   // (they size the element launches; the hull dimension does not depend on
   // measurement outcomes)
   std::vector<int8_t> dterm, rdims;
+  // per gate: a measurement whose cofactor adds a hull coordinate (its
+  // segment pass is folded into the measurement kernels)
+  std::vector<uint8_t> mgrow;
   std::vector<int32_t> rstart;
 };
 
@@ -732,8 +735,13 @@ extern "C" sf_status sf_circuit_load(sf_ctx* ctx, uint32_t n, const sf_gate* gat
   }
   c->dmax = dmax;
   c->dterm.assign(c->g.size(), (int8_t)-1);
-  for (size_t i = 0; i < c->g.size(); ++i)
-    if (is_terminal(c->g[i].op)) c->dterm[i] = (int8_t)std::min(std::max(dtrace[i], -1), dmax);
+  c->mgrow.assign(c->g.size(), 0);
+  for (size_t i = 0; i < c->g.size(); ++i) {
+    if (!is_terminal(c->g[i].op)) continue;
+    const int v = dtrace[i];
+    c->dterm[i] = (int8_t)std::min(std::max(v < 0 ? -1 : (v & 0xff), -1), dmax);
+    c->mgrow[i] = v >= 0 && (v & SF_DTRACE_GROW) && c->g[i].op == DG_MEASURE;
+  }
   fill_range_dims(c);
   uint64_t amp = (uint64_t)16 << dmax;
   c->projected = 2 * amp + sizeof(TrackState) + sizeof(ReadoutInfo) +
@@ -978,6 +986,12 @@ static void split_fields(sf_state* s, TrackJob* job, int nseg, bool use = true, 
   job->pchunk = 1;
 }
 
+// The device range ending before gate b ends in a measurement whose segment
+// pass is folded into the measurement kernels (no launch needed for it).
+static bool folded_meas(const sf_circuit* c, size_t b) {
+  return b > 0 && b - 1 < c->mgrow.size() && c->mgrow[b - 1];
+}
+
 static sf_status run_chunk(sf_state* s, const DGate* dgates, const DGate* hg, size_t a, size_t b) {
   sf_ctx* ctx = s->ctx;
   const sf_circuit* c = s->c;
@@ -1054,7 +1068,8 @@ static sf_status run_chunk(sf_state* s, const DGate* dgates, const DGate* hg, si
     HIPCHK(ctx, hipGetLastError());
     return SF_OK;
   }
-  for (int k = 0; k < nseg; ++k) {
+  const int kseg = (meas_last && dgates == (const DGate*)c->dgates.p && folded_meas(c, b)) ? nseg - 1 : nseg;
+  for (int k = 0; k < kseg; ++k) {
     prof_begin(ctx, PK_SEG);
     hipLaunchKernelGGL(sf_seg_kernel, dim3(grid), dim3(eb), 0, ctx->stream, prog + k, (const GF2Q*)s->had.p,
                        (double2*)s->amp[s->cur].p);
@@ -1063,11 +1078,12 @@ static sf_status run_chunk(sf_state* s, const DGate* dgates, const DGate* hg, si
   if (meas_last) {
     const SegProg* sp = prog + (nseg - 1);
     prof_begin(ctx, PK_MREDUCE);
-    hipLaunchKernelGGL(sf_meas_reduce, dim3(s->G), dim3(EB), 0, ctx->stream, sp, (const double2*)s->amp[s->cur].p,
-                       (double2*)s->partials.p);
+    hipLaunchKernelGGL(sf_meas_reduce, dim3(s->G), dim3(EB), 0, ctx->stream, sp, (const GF2Q*)s->had.p,
+                       (const double2*)s->amp[s->cur].p, (double2*)s->partials.p);
     prof_end(ctx);
     prof_begin(ctx, PK_MFILTER);
-    hipLaunchKernelGGL(sf_meas_filter, dim3(grid), dim3(eb), 0, ctx->stream, sp, (const double2*)s->partials.p,
+    hipLaunchKernelGGL(sf_meas_filter, dim3(grid), dim3(eb), 0, ctx->stream, sp, (const GF2Q*)s->had.p,
+                       (const double2*)s->partials.p,
                        s->seed, (uint8_t*)s->outcomes.p, (double*)s->pvals.p, (double*)s->scale.p,
                        (int*)s->flags.p, (const double2*)s->amp[s->cur].p, (double2*)s->amp[s->cur ^ 1].p);
     prof_end(ctx);
@@ -1634,7 +1650,8 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
             c->ranges[(size_t)r].ns == NS[i])
           dims = c->rdims.data() + c->ranges[(size_t)r].dofs;
       }
-      for (int k = 0; k < NS[i]; ++k)
+      const int kseg = (ML[i] && folded_meas(c, B[i])) ? NS[i] - 1 : NS[i];
+      for (int k = 0; k < kseg; ++k)
         rp->bst[(size_t)k * stride + j + 1] = batch_blocks(dims ? (int)dims[k] : c->dmax, bcap);
       if (ML[i] && NS[i] > 0) {
         const int dl = dims ? std::min((int)dims[NS[i] - 1] + 1, c->dmax) : c->dmax;

@@ -99,11 +99,22 @@ __device__ __forceinline__ uint32_t insert_zero(uint64_t r, int j) {
   return (uint32_t)(lo | ((r >> j) << (j + 1)));
 }
 
+// A measurement of a qubit outside the Z block (section 4: cofactor on it,
+// then keep one branch) whose cofactor adds a hull coordinate: the segment
+// pass that would store both children is not run.  The measurement kernels
+// compute the value that pass would have stored at a slot from the parent
+// element instead (grow_child: the same operations, so the same bits), which
+// saves the write and re-read of the 2^(d+1) child slots.
+__device__ __forceinline__ bool grow_meas(const SegProg* __restrict__ sp) {
+  return sp->is_meas && sp->kind == SEG_GROW;
+}
+
 // ---------------------------------------------------------------------------
 // Segment: Clifford phases, then the terminal step of the segment
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void seg_body(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all,
                                          double2* __restrict__ amp, uint64_t tid, uint64_t stride) {
+  if (grow_meas(sp)) return;  // folded into the measurement kernels
   const int kind = sp->kind;
   const int d = sp->d;
   const GF2Q* had = had_all + sp->had_off;
@@ -189,6 +200,17 @@ __device__ __forceinline__ void seg_body(const SegProg* __restrict__ sp, const G
   }
 }
 
+// The value the SEG_GROW pass stores at slot Yc < 2^(d+1): child 0 of parent
+// Yc below 2^d, child 1 of parent Yc - 2^d above.
+__device__ __forceinline__ double2 grow_child(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all,
+                                              const double2* __restrict__ amp, uint64_t Yc) {
+  const uint64_t N = 1ull << sp->d;
+  const uint32_t Y = (uint32_t)(Yc & (N - 1));
+  const double2 a = rot8(amp[Y], seg_phase(sp, had_all + sp->had_off, Y));
+  if (Yc < N) return prune(child(a, &sp->B0, Y));
+  return prune(cmul(child(a, &sp->B1, Y), sp->ph_re, sp->ph_im));
+}
+
 // Reduction shape of a measurement over 2^d slots: red_grid(d) blocks of EB
 // threads, about SF_RED_EPT slots per thread (at most SF_RED_GMAX blocks).
 // A function of d alone, so every path (one frame, batched, graph) adds the
@@ -212,8 +234,9 @@ __device__ __forceinline__ void meas_acc(double2 a, uint64_t Y, uint32_t c0, uin
 // then a pairwise tree over the block's threads (s[t] += s[t + h] for
 // h = EB/2 .. 1; the levels within one wavefront by lane shuffles, which add
 // the same pairs).  Blocks b >= G write nothing.
-__device__ __forceinline__ void meas_reduce_body(const SegProg* __restrict__ sp, const double2* __restrict__ amp,
-                                                 double2* __restrict__ partials, int block) {
+__device__ __forceinline__ void meas_reduce_body(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all,
+                                                 const double2* __restrict__ amp, double2* __restrict__ partials,
+                                                 int block) {
   __shared__ double s0[EB], s1[EB];
   const int d = sp->d_out;
   const int G = red_grid(d);
@@ -223,6 +246,9 @@ __device__ __forceinline__ void meas_reduce_body(const SegProg* __restrict__ sp,
   const uint64_t stride = (uint64_t)G * EB;
   double p0 = 0.0, p1 = 0.0;
   uint64_t Y = (uint64_t)block * EB + threadIdx.x;
+  if (grow_meas(sp)) {
+    for (; Y < N; Y += stride) meas_acc(grow_child(sp, had_all, amp, Y), Y, c0, r, p0, p1);
+  }
   // four loads in flight, added in slot order
   for (; Y + 3 * stride < N; Y += 4 * stride) {
     const double2 a0 = amp[Y], a1 = amp[Y + stride], a2 = amp[Y + 2 * stride], a3 = amp[Y + 3 * stride];
@@ -315,16 +341,17 @@ __device__ __forceinline__ void meas_coin_local(const SegProg* __restrict__ sp, 
 }
 
 // Keep the elements consistent with the outcome and renormalise (new buffer).
-__device__ __forceinline__ void meas_filter_body(const SegProg* __restrict__ sp, const double2* __restrict__ src,
-                                                 double2* __restrict__ dst, uint32_t o, double s, uint64_t tid,
-                                                 uint64_t stride) {
+__device__ __forceinline__ void meas_filter_body(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all,
+                                                 const double2* __restrict__ src, double2* __restrict__ dst,
+                                                 uint32_t o, double s, uint64_t tid, uint64_t stride) {
   const uint32_t c0 = sp->m_c0, r = sp->m_r;
   const int j0 = sp->m_j0;
   const int dout = sp->d_out;
+  const bool gm = grow_meas(sp);
   if (r == 0) {
     const uint64_t N = 1ull << dout;
     for (uint64_t Y = tid; Y < N; Y += stride) {
-      double2 a = src[Y];
+      double2 a = gm ? grow_child(sp, had_all, src, Y) : src[Y];
       dst[Y] = make_double2(__dmul_rn(a.x, s), __dmul_rn(a.y, s));
     }
   } else {
@@ -332,7 +359,8 @@ __device__ __forceinline__ void meas_filter_body(const SegProg* __restrict__ sp,
     for (uint64_t Yp = tid; Yp < N; Yp += stride) {
       uint32_t rest = insert_zero(Yp, j0);
       uint32_t bit = (o ^ c0 ^ (uint32_t)__popc(r & rest)) & 1u;
-      double2 a = src[rest | (bit << j0)];
+      const uint32_t Y = rest | (bit << j0);
+      double2 a = gm ? grow_child(sp, had_all, src, Y) : src[Y];
       dst[Yp] = make_double2(__dmul_rn(a.x, s), __dmul_rn(a.y, s));
     }
   }
@@ -343,8 +371,8 @@ __device__ __forceinline__ void meas_filter_body(const SegProg* __restrict__ sp,
 // one block.  The sums equal those of the three-kernel form: the single
 // block's tree gives the only non-zero partial, and the final pass adds only
 // +0.0 to it (exact for a non-negative sum).
-__device__ __forceinline__ void meas_small_body(const SegProg* __restrict__ sp, const double2* __restrict__ src,
-                                                double2* __restrict__ dst, uint64_t seed,
+__device__ __forceinline__ void meas_small_body(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all,
+                                                const double2* __restrict__ src, double2* __restrict__ dst, uint64_t seed,
                                                 uint8_t* __restrict__ outcomes, double* __restrict__ pvals,
                                                 double* __restrict__ scale, int* __restrict__ flags) {
   __shared__ double s0[EB], s1[EB];
@@ -352,12 +380,10 @@ __device__ __forceinline__ void meas_small_body(const SegProg* __restrict__ sp, 
   __shared__ uint32_t s_out;
   const uint64_t N = 1ull << sp->d_out;
   const uint32_t c0 = sp->m_c0, r = sp->m_r;
+  const bool gm = grow_meas(sp);
   double p0 = 0.0, p1 = 0.0;
-  for (uint64_t Y = threadIdx.x; Y < N; Y += EB) {
-    double v = norm2(src[Y]);
-    if ((c0 ^ (uint32_t)__popc(r & (uint32_t)Y)) & 1u) p1 = __dadd_rn(p1, v);
-    else p0 = __dadd_rn(p0, v);
-  }
+  for (uint64_t Y = threadIdx.x; Y < N; Y += EB)
+    meas_acc(gm ? grow_child(sp, had_all, src, Y) : src[Y], Y, c0, r, p0, p1);
   s0[threadIdx.x] = p0;
   s1[threadIdx.x] = p1;
   __syncthreads();
@@ -389,7 +415,7 @@ __device__ __forceinline__ void meas_small_body(const SegProg* __restrict__ sp, 
   const int dout = sp->d_out;
   if (r == 0) {
     for (uint64_t Y = threadIdx.x; Y < N; Y += EB) {
-      double2 a = src[Y];
+      double2 a = gm ? grow_child(sp, had_all, src, Y) : src[Y];
       dst[Y] = make_double2(__dmul_rn(a.x, sc), __dmul_rn(a.y, sc));
     }
   } else {
@@ -397,7 +423,8 @@ __device__ __forceinline__ void meas_small_body(const SegProg* __restrict__ sp, 
     for (uint64_t Yp = threadIdx.x; Yp < Nh; Yp += EB) {
       uint32_t rest = insert_zero(Yp, j0);
       uint32_t bit = (o ^ c0 ^ (uint32_t)__popc(r & rest)) & 1u;
-      double2 a = src[rest | (bit << j0)];
+      const uint32_t Y = rest | (bit << j0);
+      double2 a = gm ? grow_child(sp, had_all, src, Y) : src[Y];
       dst[Yp] = make_double2(__dmul_rn(a.x, sc), __dmul_rn(a.y, sc));
     }
   }
@@ -412,18 +439,20 @@ sf_seg_kernel(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all, 
 }
 
 extern "C" __global__ void __launch_bounds__(EB)
-sf_meas_reduce(const SegProg* __restrict__ sp, const double2* __restrict__ amp, double2* __restrict__ partials) {
-  meas_reduce_body(sp, amp, partials, blockIdx.x);
+sf_meas_reduce(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all, const double2* __restrict__ amp,
+               double2* __restrict__ partials) {
+  meas_reduce_body(sp, had_all, amp, partials, blockIdx.x);
 }
 
 extern "C" __global__ void __launch_bounds__(EB)
-sf_meas_filter(const SegProg* __restrict__ sp, const double2* __restrict__ partials, uint64_t seed,
+sf_meas_filter(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all,
+               const double2* __restrict__ partials, uint64_t seed,
                uint8_t* __restrict__ outcomes, double* __restrict__ pvals, double* __restrict__ scale,
                int* __restrict__ flags, const double2* __restrict__ src, double2* __restrict__ dst) {
   uint32_t o;
   double sc;
   meas_coin_local(sp, partials, seed, blockIdx.x == 0, outcomes, pvals, scale, flags, &o, &sc);
-  meas_filter_body(sp, src, dst, o, sc, TID, STRIDE);
+  meas_filter_body(sp, had_all, src, dst, o, sc, TID, STRIDE);
 }
 
 // ---------------------------------------------------------------------------
@@ -474,7 +503,7 @@ sf_meas_reduce_batch(const ElemDesc* __restrict__ D, const uint32_t* __restrict_
   const BatchPos p = batch_pos(B, na);
   const ElemDesc& e = D[p.j];
   if (!e.prog) return;
-  meas_reduce_body(e.prog, e.amp, e.partials, (int)p.blk);
+  meas_reduce_body(e.prog, e.had, e.amp, e.partials, (int)p.blk);
 }
 
 extern "C" __global__ void __launch_bounds__(EB)
@@ -486,7 +515,7 @@ sf_meas_filter_batch(const ElemDesc* __restrict__ D, const uint32_t* __restrict_
   double sc;
   meas_coin_local(e.prog, e.partials, e.seedp ? *e.seedp : e.seed, p.blk == 0, e.outcomes, e.pvals,
                   e.scale, e.flags, &o, &sc);
-  meas_filter_body(e.prog, e.amp, e.amp_other, o, sc, p.tid, p.stride);
+  meas_filter_body(e.prog, e.had, e.amp, e.amp_other, o, sc, p.tid, p.stride);
 }
 
 // The same in two kernels for launches of many frames: the coin once per
@@ -510,7 +539,7 @@ sf_meas_apply_batch(const ElemDesc* __restrict__ D, const uint32_t* __restrict__
   if (!e.prog) return;
   const uint32_t o = e.outcomes[e.prog->meas_index];
   const double sc = e.scale[0];
-  meas_filter_body(e.prog, e.amp, e.amp_other, o, sc, p.tid, p.stride);
+  meas_filter_body(e.prog, e.had, e.amp, e.amp_other, o, sc, p.tid, p.stride);
 }
 
 // Frames of at most EB slots: every segment of a round, then its
@@ -525,7 +554,7 @@ sf_elem_small(const SegProg* __restrict__ prog, int nseg, const GF2Q* __restrict
     seg_body(prog + k, had_all, amp, threadIdx.x, EB);
     __syncthreads();
   }
-  if (meas) meas_small_body(prog + (nseg - 1), amp, amp_other, seed, outcomes, pvals, scale, flags);
+  if (meas) meas_small_body(prog + (nseg - 1), had_all, amp, amp_other, seed, outcomes, pvals, scale, flags);
 }
 
 // batched form: block j = frame j; rows k < kmax of D are the segments (row
@@ -541,7 +570,8 @@ sf_elem_small_batch(const ElemDesc* __restrict__ D, int kmax, int na, int meas) 
   if (!meas) return;
   const ElemDesc& e = D[(size_t)kmax * na + j];
   if (!e.prog) return;
-  meas_small_body(e.prog, e.amp, e.amp_other, e.seedp ? *e.seedp : e.seed, e.outcomes, e.pvals, e.scale, e.flags);
+  meas_small_body(e.prog, e.had, e.amp, e.amp_other, e.seedp ? *e.seedp : e.seed, e.outcomes, e.pvals, e.scale,
+                  e.flags);
 }
 
 // Number of non-zero amplitudes (frame size |F|).

@@ -127,6 +127,9 @@ struct TrackJob {
 
 // longest gate range of one split-form track launch (bounds the records)
 #define SF_RANGE_MAX 1024
+// dry-run trace of a terminal gate: the hull dimension on entry, or'ed with
+// this flag for a measurement whose cofactor adds a hull coordinate
+#define SF_DTRACE_GROW 0x100
 
 enum { TRK_OK = 0, TRK_E_DIM = 1, TRK_E_INTERNAL = 2, TRK_E_SEGS = 3 };
 

@@ -1474,6 +1474,11 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
         sp->kind = kind; sp->d_out = d;
         if (!is_meas) { sp->ph_re = gt.c; sp->ph_im = gt.s; }
       }
+      // the dry run marks measurements whose cofactor grows the hull (their
+      // segment pass is folded into the measurement kernels; the kind does
+      // not depend on outcomes)
+      if (job.dry && job.ginfo && lane == 0 && is_meas && kind == SEG_GROW)
+        *gmem(job.ginfo + gi) = d_entry | SF_DTRACE_GROW;
       if (is_meas) {
         uint32_t c0, r;
         det_functional(L, q, n, d, &c0, &r, &err);
@@ -1487,7 +1492,6 @@ static __device__ void track_body(LL& L, const TrackJob& job) {
     if (d > SF_DMAX - 1) err = TRK_E_DIM;
     err = wave_max(err);
     errw = err;
-    (void)d_entry;
     __syncthreads();
     regs_load(L, TB, n);
     hull_to_regs(L, HB, d);
@@ -2688,6 +2692,11 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
         sp->kind = kind; sp->d_out = d;
         if (!is_meas) { sp->ph_re = gt.c; sp->ph_im = gt.s; }
       }
+      // the dry run marks measurements whose cofactor grows the hull (their
+      // segment pass is folded into the measurement kernels; the kind does
+      // not depend on outcomes)
+      if (job.dry && job.ginfo && lane == 0 && is_meas && kind == SEG_GROW)
+        *gmem(job.ginfo + gi) = d_entry | SF_DTRACE_GROW;
       if (is_meas) {
         uint32_t c0, r;
         det_functional(L, q, n, d, &c0, &r, &err);
@@ -2700,7 +2709,6 @@ static __device__ void track_body(Lds& L, const TrackJob& job) {
     if (d > dmax) dmax = d;
     if (d > SF_DMAX - 1) err = TRK_E_DIM;
     err = wave_max(err);
-    (void)d_entry;
     __syncthreads();
     if (rec) {
       rec_write(job, gi + 1, L, n, d);
