@@ -185,7 +185,17 @@ static void launch_track_one(hipStream_t st, const TrackJob& job, int W) {
 // Split form: the phase kernels of a track launch (len = longest range,
 // nseg = most segments among the jobs).
 static void launch_phase_one(sf_ctx* ctx, const TrackJob& job, int W);
-static void launch_phase_many(sf_ctx* ctx, const TrackJob* jobs, int count, int W, int nchunk, int nseg);
+static void launch_phase_many(sf_ctx* ctx, const TrackJob* jobs, int count, int W, int nchunk, int nseg,
+                              size_t pad = 0);
+
+// Phase-kernel launches that run beside the next round's tableau tracks take
+// this much extra (unused) LDS per workgroup: fewer phase wavefronts per
+// compute unit leave the tracks, which are on the critical path there, more
+// of its issue slots and LDS bandwidth.  Alone, the phase kernel runs at its
+// full occupancy.
+#ifndef SF_PHASE_PAD_BESIDE
+#define SF_PHASE_PAD_BESIDE 6144
+#endif
 
 static void launch_track_many(hipStream_t st, const TrackJob* jobs, int count, int W) {
   switch (W) {
@@ -269,14 +279,16 @@ static void launch_phase_one(sf_ctx* ctx, const TrackJob& job, int W) {
   }
 }
 
-static void launch_phase_many(sf_ctx* ctx, const TrackJob* jobs, int count, int W, int nchunk, int nseg) {
+static void launch_phase_many(sf_ctx* ctx, const TrackJob* jobs, int count, int W, int nchunk, int nseg,
+                              size_t pad) {
   if (count <= 0 || nchunk <= 0) return;
   prof_begin(ctx, PK_PHASE);
+  const unsigned sh = (unsigned)pad;
   switch (W) {
-    case 1: hipLaunchKernelGGL(sf_phase_many<1>, dim3(nchunk, count), dim3(TL), 0, ctx->stream, jobs); break;
-    case 2: hipLaunchKernelGGL(sf_phase_many<2>, dim3(nchunk, count), dim3(TL), 0, ctx->stream, jobs); break;
-    case 3: hipLaunchKernelGGL(sf_phase_many<3>, dim3(nchunk, count), dim3(TL), 0, ctx->stream, jobs); break;
-    default: hipLaunchKernelGGL(sf_phase_many<4>, dim3(nchunk, count), dim3(TL), 0, ctx->stream, jobs); break;
+    case 1: hipLaunchKernelGGL(sf_phase_many<1>, dim3(nchunk, count), dim3(TL), sh, ctx->stream, jobs); break;
+    case 2: hipLaunchKernelGGL(sf_phase_many<2>, dim3(nchunk, count), dim3(TL), sh, ctx->stream, jobs); break;
+    case 3: hipLaunchKernelGGL(sf_phase_many<3>, dim3(nchunk, count), dim3(TL), sh, ctx->stream, jobs); break;
+    default: hipLaunchKernelGGL(sf_phase_many<4>, dim3(nchunk, count), dim3(TL), sh, ctx->stream, jobs); break;
   }
   prof_end(ctx);
   if (nseg > 0) {
@@ -1883,9 +1895,12 @@ static sf_status batch_round_ov(sf_ctx* ctx, sf_state* const* states, size_t ns,
   RoundPlan el = rp;          // the element part of launch_round, without the tracks
   for (int w = 0; w <= SF_WMAX; ++w) el.wcount[w] = 0;
   off = 0;
+  // without a measurement in this round the next round's tracks need not
+  // wait for it: they run beside this round's phase kernels
+  const size_t pad = rp.anym ? 0 : SF_PHASE_PAD_BESIDE;
   for (int w = 1; w <= SF_WMAX; ++w) {
     if (!rp.wcount[w]) continue;
-    launch_phase_many(ctx, djobs + off, rp.wcount[w], w, rp.wchunk[w], rp.wseg[w]);
+    launch_phase_many(ctx, djobs + off, rp.wcount[w], w, rp.wchunk[w], rp.wseg[w], pad);
     off += rp.wcount[w];
   }
   launch_round(ctx, el, djobs, dd);
@@ -2252,7 +2267,7 @@ struct sf_graph {
 
 // A kernel node after the given nodes (null entries and repeats skipped).
 static hipError_t add_node_after(hipGraph_t g, hipGraphNode_t* node, std::initializer_list<hipGraphNode_t> after,
-                                 const void* func, dim3 grid, dim3 block, void** args) {
+                                 const void* func, dim3 grid, dim3 block, void** args, size_t shmem = 0) {
   hipGraphNode_t deps[4];
   size_t nd = 0;
   for (hipGraphNode_t a : after) {
@@ -2266,7 +2281,7 @@ static hipError_t add_node_after(hipGraph_t g, hipGraphNode_t* node, std::initia
   p.func = const_cast<void*>(func);
   p.gridDim = grid;
   p.blockDim = block;
-  p.sharedMemBytes = 0;
+  p.sharedMemBytes = (unsigned)shmem;
   p.kernelParams = args;
   p.extra = nullptr;
   return hipGraphAddKernelNode(node, g, nd ? deps : nullptr, nd, &p);
@@ -2390,12 +2405,12 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
     // element chain of this round
     hipGraphNode_t prev = elem_last;
     bool first = true;
-    auto chain = [&](const void* func, dim3 grid, dim3 block, void** args) {
+    auto chain = [&](const void* func, dim3 grid, dim3 block, void** args, size_t shmem = 0) {
       hipGraphNode_t nd = nullptr;
       if (first)
-        e = add_node_after(g->graph, &nd, {prev, track_last}, func, grid, block, args);
+        e = add_node_after(g->graph, &nd, {prev, track_last}, func, grid, block, args, shmem);
       else
-        e = add_node_after(g->graph, &nd, {prev}, func, grid, block, args);
+        e = add_node_after(g->graph, &nd, {prev}, func, grid, block, args, shmem);
       if (e == hipSuccess) { prev = nd; first = false; }
     };
     off = 0;
@@ -2404,7 +2419,8 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
       const TrackJob* djw = dj + off;
       void* args[] = {(void*)&djw};
       if (rp.wchunk[w] > 0) {
-        chain(phase_many_fn(w), dim3(rp.wchunk[w], rp.wcount[w]), dim3(TL), args);
+        chain(phase_many_fn(w), dim3(rp.wchunk[w], rp.wcount[w]), dim3(TL), args,
+              rp.anym ? 0 : SF_PHASE_PAD_BESIDE);
         if (e == hipSuccess && rp.wseg[w] > 0)
           chain((const void*)sf_fit_many, dim3(rp.wseg[w], rp.wcount[w]), dim3(TL), args);
       }

@@ -25,6 +25,7 @@
 // fit kernel sums each segment's factors and fits its quadratic form.  Wider
 // frames (TrkL) do all of it in the track kernel.
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 
 #include "sf_dev.h"
 
@@ -33,11 +34,14 @@
 // LDS of one tableau-track workgroup.  NM row slots of WM words in the
 // row-indexed arrays (rows, column copy, pre-gate rows, b* basis, indexes);
 // the hull and sample arrays are sized for the largest frames.
+//
+// The fields up to (not including) cx are all the phase kernel uses: it
+// allocates only that prefix (phase_lds_bytes), which lets more of its
+// wavefronts share a compute unit.
 template <int NM, int WM>
 struct LdsT {
   static constexpr int RN = NM, RW = WM;
   uint64_t rx[NM * WM], rz[NM * WM];
-  uint64_t cx[NM * WM], cz[NM * WM];   // column q: slots with an x (z) bit at q
   uint64_t ox[NM * WM], oz[NM * WM];
   uint64_t beta[NM * WM];
   uint64_t s0[SF_WMAX], V[SF_DMAX][SF_WMAX], u[SF_WMAX];
@@ -45,17 +49,24 @@ struct LdsT {
   uint64_t hbO[SF_DMAX + 2][SF_WMAX], hbN[SF_DMAX + 2][SF_WMAX];
   uint64_t oxpm[SF_WMAX];
   uint64_t zsm[SF_WMAX];           // slot mask of Z-block slots
-  uint64_t rmask[SF_WMAX], cmask[SF_WMAX], fmask[SF_WMAX];
-  uint64_t dq[SF_WMAX];
+  uint64_t tc[16];                // per-phase shader clocks
   uint32_t Ys[SF_PMAX];
-  uint8_t acc[SF_PMAX], t0[SF_PMAX], t1[SF_PMAX];
+  int misc[8];                    // [0] X-block size, [1] last lead stamp
   int16_t lead[NM], xpiv[NM], zpiv[NM], oxpiv[NM];
   uint8_t ow[NM];
+  uint8_t t0[SF_PMAX];
+  // -- track kernel only from here --
+  uint64_t cx[NM * WM], cz[NM * WM];   // column q: slots with an x (z) bit at q
+  uint64_t rmask[SF_WMAX], cmask[SF_WMAX], fmask[SF_WMAX];
+  uint64_t dq[SF_WMAX];
+  uint8_t acc[SF_PMAX], t1[SF_PMAX];
   uint32_t ech[SF_DMAX];          // scratch for span tests
   uint32_t lst[2 * NM];           // lead stamps of the elimination passes
-  int misc[8];                    // [0] X-block size, [1] last lead stamp
-  uint64_t tc[16];                // per-phase shader clocks
 };
+
+// LDS bytes of the phase kernel: the prefix of LdsT before the track-only fields
+template <class LT>
+constexpr size_t phase_lds_bytes() { return offsetof(LT, cx); }
 
 typedef LdsT<SF_NMAX, SF_WMAX> Lds;
 
@@ -2869,7 +2880,9 @@ __global__ void __launch_bounds__(TL) sf_track_many(const TrackJob* __restrict__
 template <int W>
 __device__ __forceinline__ void phase_w(const TrackJob& job, int c) {
   if constexpr (W <= 2) {
-    __shared__ typename Trk<W>::LL L;
+    typedef typename Trk<W>::LL LT;
+    __shared__ __align__(16) unsigned char raw[phase_lds_bytes<LT>()];
+    LT& L = *reinterpret_cast<LT*>(raw);
     Trk<W>::phase_body(L, job, c);
   } else {
     __shared__ Lds L;
