@@ -102,9 +102,9 @@ __device__ __forceinline__ uint32_t insert_zero(uint64_t r, int j) {
 // A measurement of a qubit outside the Z block (section 4: cofactor on it,
 // then keep one branch) whose cofactor adds a hull coordinate: the segment
 // pass that would store both children is not run.  The measurement kernels
-// compute the value that pass would have stored at a slot from the parent
-// element instead (grow_child: the same operations, so the same bits), which
-// saves the write and re-read of the 2^(d+1) child slots.
+// compute a child from its parent element when they need it (grow_children:
+// the operations of the SEG_GROW pass), which saves the write and re-read of
+// the 2^(d+1) child slots.
 __device__ __forceinline__ bool grow_meas(const SegProg* __restrict__ sp) {
   return sp->is_meas && sp->kind == SEG_GROW;
 }
@@ -200,13 +200,21 @@ __device__ __forceinline__ void seg_body(const SegProg* __restrict__ sp, const G
   }
 }
 
-// The value the SEG_GROW pass stores at slot Yc < 2^(d+1): child 0 of parent
-// Yc below 2^d, child 1 of parent Yc - 2^d above.
-__device__ __forceinline__ double2 grow_child(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all,
-                                              const double2* __restrict__ amp, uint64_t Yc) {
+// The two children the SEG_GROW pass would store for parent element a at
+// slot Y < 2^d: child 0 at slot Y, child 1 at slot Y + 2^d.
+__device__ __forceinline__ void grow_children(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all,
+                                              double2 a, uint32_t Y, double2* c0, double2* c1) {
+  a = rot8(a, seg_phase(sp, had_all + sp->had_off, Y));
+  *c0 = prune(child(a, &sp->B0, Y));
+  *c1 = prune(cmul(child(a, &sp->B1, Y), sp->ph_re, sp->ph_im));
+}
+
+// ... and the one at child slot Yc < 2^(d+1) (parent element a = amp[Yc mod 2^d])
+__device__ __forceinline__ double2 grow_child_of(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all,
+                                                 double2 a, uint64_t Yc) {
   const uint64_t N = 1ull << sp->d;
   const uint32_t Y = (uint32_t)(Yc & (N - 1));
-  const double2 a = rot8(amp[Y], seg_phase(sp, had_all + sp->had_off, Y));
+  a = rot8(a, seg_phase(sp, had_all + sp->had_off, Y));
   if (Yc < N) return prune(child(a, &sp->B0, Y));
   return prune(cmul(child(a, &sp->B1, Y), sp->ph_re, sp->ph_im));
 }
@@ -229,6 +237,35 @@ __device__ __forceinline__ void meas_acc(double2 a, uint64_t Y, uint32_t c0, uin
   else p0 = __dadd_rn(p0, v);
 }
 
+// A growing measurement's per-thread sums: thread t of block b takes the
+// parents Y = b*EB + t + m*G*EB < 2^d in turn and adds child 0 (slot Y), then
+// child 1 (slot Y + 2^d), each parent read once (four loads in flight).
+__device__ __forceinline__ void grow_meas_acc(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all,
+                                              const double2* __restrict__ amp, int block, int G, double& p0,
+                                              double& p1) {
+  const uint64_t N = 1ull << sp->d;
+  const uint32_t c0 = sp->m_c0, r = sp->m_r;
+  const uint64_t stride = (uint64_t)G * EB;
+  uint64_t Y = (uint64_t)block * EB + threadIdx.x;
+  for (; Y + 3 * stride < N; Y += 4 * stride) {
+    double2 a[4];
+    for (int m = 0; m < 4; ++m) a[m] = amp[Y + m * stride];
+    for (int m = 0; m < 4; ++m) {
+      const uint64_t Ym = Y + m * stride;
+      double2 ch0, ch1;
+      grow_children(sp, had_all, a[m], (uint32_t)Ym, &ch0, &ch1);
+      meas_acc(ch0, Ym, c0, r, p0, p1);
+      meas_acc(ch1, Ym + N, c0, r, p0, p1);
+    }
+  }
+  for (; Y < N; Y += stride) {
+    double2 ch0, ch1;
+    grow_children(sp, had_all, amp[Y], (uint32_t)Y, &ch0, &ch1);
+    meas_acc(ch0, Y, c0, r, p0, p1);
+    meas_acc(ch1, Y + N, c0, r, p0, p1);
+  }
+}
+
 // Measurement: block partial sums of |a|^2 split by the qubit value; block b
 // of G = red_grid(d) covers slots b*EB + t, stepping by G*EB, in that order,
 // then a pairwise tree over the block's threads (s[t] += s[t + h] for
@@ -247,7 +284,8 @@ __device__ __forceinline__ void meas_reduce_body(const SegProg* __restrict__ sp,
   double p0 = 0.0, p1 = 0.0;
   uint64_t Y = (uint64_t)block * EB + threadIdx.x;
   if (grow_meas(sp)) {
-    for (; Y < N; Y += stride) meas_acc(grow_child(sp, had_all, amp, Y), Y, c0, r, p0, p1);
+    grow_meas_acc(sp, had_all, amp, block, G, p0, p1);
+    Y = N;
   }
   // four loads in flight, added in slot order
   for (; Y + 3 * stride < N; Y += 4 * stride) {
@@ -347,11 +385,37 @@ __device__ __forceinline__ void meas_filter_body(const SegProg* __restrict__ sp,
   const uint32_t c0 = sp->m_c0, r = sp->m_r;
   const int j0 = sp->m_j0;
   const int dout = sp->d_out;
-  const bool gm = grow_meas(sp);
+  if (grow_meas(sp)) {
+    // kept slot Yp holds child slot Y (below): computed from its parent,
+    // four parent loads in flight
+    const uint64_t Np = 1ull << sp->d;
+    const uint64_t N = r ? (1ull << (dout - 1)) : (1ull << dout);
+    for (uint64_t Y0 = tid; Y0 < N; Y0 += 4 * stride) {
+      uint32_t Ys[4];
+      double2 a[4];
+      for (int m = 0; m < 4; ++m) {
+        const uint64_t Yp = Y0 + m * stride;
+        uint32_t Y = (uint32_t)Yp;
+        if (r) {
+          const uint32_t rest = insert_zero(Yp, j0);
+          Y = rest | (((o ^ c0 ^ (uint32_t)__popc(r & rest)) & 1u) << j0);
+        }
+        Ys[m] = Y;
+        a[m] = Yp < N ? src[Y & (Np - 1)] : make_double2(0.0, 0.0);
+      }
+      for (int m = 0; m < 4; ++m) {
+        const uint64_t Yp = Y0 + m * stride;
+        if (Yp >= N) break;
+        const double2 v = grow_child_of(sp, had_all, a[m], Ys[m]);
+        dst[Yp] = make_double2(__dmul_rn(v.x, s), __dmul_rn(v.y, s));
+      }
+    }
+    return;
+  }
   if (r == 0) {
     const uint64_t N = 1ull << dout;
     for (uint64_t Y = tid; Y < N; Y += stride) {
-      double2 a = gm ? grow_child(sp, had_all, src, Y) : src[Y];
+      double2 a = src[Y];
       dst[Y] = make_double2(__dmul_rn(a.x, s), __dmul_rn(a.y, s));
     }
   } else {
@@ -359,8 +423,7 @@ __device__ __forceinline__ void meas_filter_body(const SegProg* __restrict__ sp,
     for (uint64_t Yp = tid; Yp < N; Yp += stride) {
       uint32_t rest = insert_zero(Yp, j0);
       uint32_t bit = (o ^ c0 ^ (uint32_t)__popc(r & rest)) & 1u;
-      const uint32_t Y = rest | (bit << j0);
-      double2 a = gm ? grow_child(sp, had_all, src, Y) : src[Y];
+      double2 a = src[rest | (bit << j0)];
       dst[Yp] = make_double2(__dmul_rn(a.x, s), __dmul_rn(a.y, s));
     }
   }
@@ -382,8 +445,9 @@ __device__ __forceinline__ void meas_small_body(const SegProg* __restrict__ sp, 
   const uint32_t c0 = sp->m_c0, r = sp->m_r;
   const bool gm = grow_meas(sp);
   double p0 = 0.0, p1 = 0.0;
-  for (uint64_t Y = threadIdx.x; Y < N; Y += EB)
-    meas_acc(gm ? grow_child(sp, had_all, src, Y) : src[Y], Y, c0, r, p0, p1);
+  if (gm) grow_meas_acc(sp, had_all, src, 0, 1, p0, p1);  // the one-block shape of the reduction
+  else
+    for (uint64_t Y = threadIdx.x; Y < N; Y += EB) meas_acc(src[Y], Y, c0, r, p0, p1);
   s0[threadIdx.x] = p0;
   s1[threadIdx.x] = p1;
   __syncthreads();
@@ -413,9 +477,10 @@ __device__ __forceinline__ void meas_small_body(const SegProg* __restrict__ sp, 
   const double sc = s_scale;
   const int j0 = sp->m_j0;
   const int dout = sp->d_out;
+  const uint64_t Np = gm ? (1ull << sp->d) : N;
   if (r == 0) {
     for (uint64_t Y = threadIdx.x; Y < N; Y += EB) {
-      double2 a = gm ? grow_child(sp, had_all, src, Y) : src[Y];
+      double2 a = gm ? grow_child_of(sp, had_all, src[Y & (Np - 1)], Y) : src[Y];
       dst[Y] = make_double2(__dmul_rn(a.x, sc), __dmul_rn(a.y, sc));
     }
   } else {
@@ -424,7 +489,7 @@ __device__ __forceinline__ void meas_small_body(const SegProg* __restrict__ sp, 
       uint32_t rest = insert_zero(Yp, j0);
       uint32_t bit = (o ^ c0 ^ (uint32_t)__popc(r & rest)) & 1u;
       const uint32_t Y = rest | (bit << j0);
-      double2 a = gm ? grow_child(sp, had_all, src, Y) : src[Y];
+      double2 a = gm ? grow_child_of(sp, had_all, src[Y & (Np - 1)], Y) : src[Y];
       dst[Yp] = make_double2(__dmul_rn(a.x, sc), __dmul_rn(a.y, sc));
     }
   }
