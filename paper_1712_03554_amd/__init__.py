@@ -203,8 +203,9 @@ class Engine:
 
     def batch_reset(self, states, bases=None, seeds=None):
         """Re-initialise the states with one launch.  states: a list of State
-        or a StateBatch; bases: basis bit lists, or an array of shape
-        (states, qubits) of 0/1; seeds: integers."""
+        or a StateBatch; bases: basis bit lists, an array of shape
+        (states, qubits) of 0/1, or the words of pack_bases; seeds: integers
+        (or a uint64 array)."""
         sb = states if isinstance(states, StateBatch) else StateBatch(states)
         ns = len(sb)
         b = None if bases is None else _basis_word_rows(bases, ns)
@@ -505,10 +506,25 @@ class StateBatch:
         return ctypes.cast(self._arr, ctypes.c_void_p)
 
 
-def _basis_word_rows(bases, ns: int) -> np.ndarray:
+class BasisWords(np.ndarray):
+    """Basis bits packed as the batched calls' words (pack_bases)."""
+
+
+def pack_bases(bases, ns: int = None) -> BasisWords:
     """Basis bits per state (lists, or an array of 0/1 of shape (states, n))
-    as 4 little-endian 64-bit words per state (the batched calls' layout,
-    which covers 256 qubits; they refuse wider states themselves)."""
+    as the batched calls' words: 4 little-endian 64-bit words per state
+    (covering 256 qubits; those calls refuse wider states themselves).  The
+    result can be passed as `bases` to batch_reset, which then uses it as is."""
+    return _basis_word_rows(bases, len(bases) if ns is None else ns).view(BasisWords)
+
+
+def _basis_word_rows(bases, ns: int) -> np.ndarray:
+    """Basis bits per state (lists, an array of 0/1 of shape (states, n), or
+    the words of pack_bases) as 4 little-endian 64-bit words per state."""
+    if isinstance(bases, BasisWords):
+        if bases.shape[0] < ns:
+            raise ValueError(f"packed bases for {bases.shape[0]} states, {ns} given")
+        return np.ascontiguousarray(bases.view(np.ndarray))
     bits = np.zeros((max(1, ns), 256), dtype=np.uint8)
     if isinstance(bases, np.ndarray):
         m = min(256, bases.shape[1])

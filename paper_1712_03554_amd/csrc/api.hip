@@ -1512,8 +1512,9 @@ static ElemDesc elem_desc(const sf_state* s, int cur, const SegProg* prog, const
 }
 
 // One batched round: the track job of every frame with work left and the
-// element descriptors of its segments (row k of desc = segment k of every
-// frame; row kmax = the measurement of frames whose range ends in one).
+// element descriptors (one per frame: its programs, buffers and the number
+// of its segments this round, and its measurement's program if the range
+// ends in one).
 struct RoundPlan {
   std::vector<TrackJob> jobs;
   std::vector<ElemDesc> desc;
@@ -1674,19 +1675,16 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
     for (int r = 0; r < R; ++r)
       for (int j = 0; j < na; ++j) rp->bst[(size_t)r * stride + j + 1] += rp->bst[(size_t)r * stride + j];
   }
-  const int kmax = rp->kmax;
-  rp->desc.assign((size_t)(kmax + 1) * na, ElemDesc{});
-  for (int k = 0; k <= kmax; ++k)
-    for (int j = 0; j < na; ++j) {
-      const int i = act[j];
-      sf_state* s = states[i];
-      const SegProg* base = (const SegProg*)prog_buf(s, par).p;
-      const SegProg* p = nullptr;
-      if (k < kmax) p = k < NS[i] ? base + k : nullptr;
-      else p = ML[i] ? base + (NS[i] - 1) : nullptr;  // measurement descriptors
-      // (an idle entry only needs its null program, which assign left)
-      if (p) rp->desc[(size_t)k * na + j] = elem_desc(s, pr[i].cur, p, seedp ? seedp[i] : nullptr, par);
-    }
+  // one descriptor per frame, shared by every launch of the round
+  rp->desc.resize((size_t)na);
+  for (int j = 0; j < na; ++j) {
+    const int i = act[j];
+    sf_state* s = states[i];
+    ElemDesc& e = rp->desc[(size_t)j];
+    e = elem_desc(s, pr[i].cur, (const SegProg*)prog_buf(s, par).p, seedp ? seedp[i] : nullptr, par);
+    e.nseg = NS[i];
+    e.mk = (ML[i] && NS[i] > 0) ? NS[i] - 1 : -1;
+  }
   rp->bst_off = (rp->desc.size() * sizeof(ElemDesc) + 255) & ~(size_t)255;
   rp->dbytes.assign(rp->bst_off + rp->bst.size() * sizeof(uint32_t), 0);
   memcpy(rp->dbytes.data(), rp->desc.data(), rp->desc.size() * sizeof(ElemDesc));
@@ -1715,7 +1713,7 @@ static size_t desc_offset(size_t job_bytes) { return (job_bytes + 255) & ~(size_
 // for ns frames of at most maxseg segments
 static size_t desc_capacity(size_t ns, int maxseg) {
   ns = std::max<size_t>(1, ns);
-  return desc_offset((size_t)(maxseg + 1) * ns * sizeof(ElemDesc)) + (size_t)(maxseg + 2) * (ns + 1) * sizeof(uint32_t);
+  return desc_offset(ns * sizeof(ElemDesc)) + (size_t)(maxseg + 2) * (ns + 1) * sizeof(uint32_t);
 }
 
 static sf_status scratch_reserve(sf_ctx* ctx, BatchScratch* bs, size_t ns, int maxseg) {
@@ -1771,12 +1769,12 @@ static void launch_round(sf_ctx* ctx, const RoundPlan& rp, const TrackJob* djobs
   for (int k = 0; k < rp.kmax; ++k) {
     if (!row_blocks(rp, k)) continue;
     prof_begin(ctx, PK_SEG);
-    hipLaunchKernelGGL(sf_seg_batch, dim3(row_blocks(rp, k)), dim3(EB), 0, ctx->stream, dd + (size_t)k * na,
-                       row_starts(rp, dd, k), na);
+    hipLaunchKernelGGL(sf_seg_batch, dim3(row_blocks(rp, k)), dim3(EB), 0, ctx->stream, dd, row_starts(rp, dd, k),
+                       na, k);
     prof_end(ctx);
   }
   if (rp.anym) {
-    const ElemDesc* dm = dd + (size_t)rp.kmax * na;
+    const ElemDesc* dm = dd;
     const uint32_t* rb = row_starts(rp, dd, rp.kmax);
     const uint32_t* fb = row_starts(rp, dd, rp.kmax + 1);
     const dim3 rg(row_blocks(rp, rp.kmax)), fg(row_blocks(rp, rp.kmax + 1));
@@ -2437,13 +2435,14 @@ extern "C" sf_status sf_batch_graph(sf_ctx* ctx, sf_state* const* states, size_t
       int nna = na;
       for (int k = 0; k < rp.kmax && e == hipSuccess; ++k) {
         if (!row_blocks(rp, k)) continue;
-        const ElemDesc* dk = dd + (size_t)k * na;
+        const ElemDesc* dk = dd;
         const uint32_t* bk = row_starts(rp, dd, k);
-        void* args[] = {(void*)&dk, (void*)&bk, (void*)&nna};
+        int kk = k;
+        void* args[] = {(void*)&dk, (void*)&bk, (void*)&nna, (void*)&kk};
         chain((const void*)sf_seg_batch, dim3(row_blocks(rp, k)), dim3(EB), args);
       }
       if (rp.anym && e == hipSuccess) {
-        const ElemDesc* dm = dd + (size_t)rp.kmax * na;
+        const ElemDesc* dm = dd;
         const uint32_t* rb = row_starts(rp, dd, rp.kmax);
         const uint32_t* fb = row_starts(rp, dd, rp.kmax + 1);
         void* rargs[] = {(void*)&dm, (void*)&rb, (void*)&nna};

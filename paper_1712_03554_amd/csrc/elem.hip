@@ -522,8 +522,10 @@ sf_meas_filter(const SegProg* __restrict__ sp, const GF2Q* __restrict__ had_all,
 
 // ---------------------------------------------------------------------------
 // Batched forms, flattened: the grid is the concatenation of every frame's
-// blocks.  B[j] is the first block of descriptor j (B[0] = 0, B[na] = the
-// grid); a descriptor without blocks is idle.  A block finds its frame by a
+// blocks.  B[j] is the first block of frame j's descriptor (B[0] = 0, B[na] =
+// the grid); a frame without blocks in a launch is idle there.  A segment
+// launch takes its row k (the program at prog + k), the measurement
+// launches the frame's measurement program (prog + mk).  A block finds its frame by a
 // binary search over B (uniform across the block) and strides over that
 // frame's slots with the frame's own block count, so each frame launches
 // only the blocks its hull needs.
@@ -554,11 +556,11 @@ __device__ __forceinline__ BatchPos batch_pos(const uint32_t* __restrict__ B, in
 }
 
 extern "C" __global__ void __launch_bounds__(EB)
-sf_seg_batch(const ElemDesc* __restrict__ D, const uint32_t* __restrict__ B, int na) {
+sf_seg_batch(const ElemDesc* __restrict__ D, const uint32_t* __restrict__ B, int na, int k) {
   const BatchPos p = batch_pos(B, na);
   const ElemDesc& e = D[p.j];
-  if (!e.prog) return;
-  seg_body(e.prog, e.had, e.amp, p.tid, p.stride);
+  if (k >= e.nseg) return;
+  seg_body(e.prog + k, e.had, e.amp, p.tid, p.stride);
 }
 
 // Reduction blocks of a frame: partial b of the shape red_grid(d) (the host
@@ -567,20 +569,21 @@ extern "C" __global__ void __launch_bounds__(EB)
 sf_meas_reduce_batch(const ElemDesc* __restrict__ D, const uint32_t* __restrict__ B, int na) {
   const BatchPos p = batch_pos(B, na);
   const ElemDesc& e = D[p.j];
-  if (!e.prog) return;
-  meas_reduce_body(e.prog, e.had, e.amp, e.partials, (int)p.blk);
+  if (e.mk < 0) return;
+  meas_reduce_body(e.prog + e.mk, e.had, e.amp, e.partials, (int)p.blk);
 }
 
 extern "C" __global__ void __launch_bounds__(EB)
 sf_meas_filter_batch(const ElemDesc* __restrict__ D, const uint32_t* __restrict__ B, int na) {
   const BatchPos p = batch_pos(B, na);
   const ElemDesc& e = D[p.j];
-  if (!e.prog) return;
+  if (e.mk < 0) return;
+  const SegProg* sp = e.prog + e.mk;
   uint32_t o;
   double sc;
-  meas_coin_local(e.prog, e.partials, e.seedp ? *e.seedp : e.seed, p.blk == 0, e.outcomes, e.pvals,
+  meas_coin_local(sp, e.partials, e.seedp ? *e.seedp : e.seed, p.blk == 0, e.outcomes, e.pvals,
                   e.scale, e.flags, &o, &sc);
-  meas_filter_body(e.prog, e.had, e.amp, e.amp_other, o, sc, p.tid, p.stride);
+  meas_filter_body(sp, e.had, e.amp, e.amp_other, o, sc, p.tid, p.stride);
 }
 
 // The same in two kernels for launches of many frames: the coin once per
@@ -590,10 +593,10 @@ sf_meas_filter_batch(const ElemDesc* __restrict__ D, const uint32_t* __restrict_
 // partials again.
 extern "C" __global__ void __launch_bounds__(EB) sf_meas_coin_batch(const ElemDesc* __restrict__ D) {
   const ElemDesc& e = D[blockIdx.x];
-  if (!e.prog) return;
+  if (e.mk < 0) return;
   uint32_t o;
   double sc;
-  meas_coin_local(e.prog, e.partials, e.seedp ? *e.seedp : e.seed, true, e.outcomes, e.pvals, e.scale,
+  meas_coin_local(e.prog + e.mk, e.partials, e.seedp ? *e.seedp : e.seed, true, e.outcomes, e.pvals, e.scale,
                   e.flags, &o, &sc);
 }
 
@@ -601,10 +604,11 @@ extern "C" __global__ void __launch_bounds__(EB)
 sf_meas_apply_batch(const ElemDesc* __restrict__ D, const uint32_t* __restrict__ B, int na) {
   const BatchPos p = batch_pos(B, na);
   const ElemDesc& e = D[p.j];
-  if (!e.prog) return;
-  const uint32_t o = e.outcomes[e.prog->meas_index];
+  if (e.mk < 0) return;
+  const SegProg* sp = e.prog + e.mk;
+  const uint32_t o = e.outcomes[sp->meas_index];
   const double sc = e.scale[0];
-  meas_filter_body(e.prog, e.had, e.amp, e.amp_other, o, sc, p.tid, p.stride);
+  meas_filter_body(sp, e.had, e.amp, e.amp_other, o, sc, p.tid, p.stride);
 }
 
 // Frames of at most EB slots: every segment of a round, then its
@@ -622,20 +626,20 @@ sf_elem_small(const SegProg* __restrict__ prog, int nseg, const GF2Q* __restrict
   if (meas) meas_small_body(prog + (nseg - 1), had_all, amp, amp_other, seed, outcomes, pvals, scale, flags);
 }
 
-// batched form: block j = frame j; rows k < kmax of D are the segments (row
-// k, column j), row kmax the measurements
+// batched form: block j = frame j (descriptor j): its segments k < nseg in
+// order, then its measurement if it has one
 extern "C" __global__ void __launch_bounds__(EB)
 sf_elem_small_batch(const ElemDesc* __restrict__ D, int kmax, int na, int meas) {
   const int j = blockIdx.x;
   for (int k = 0; k < kmax; ++k) {
-    const ElemDesc& e = D[(size_t)k * na + j];
-    if (e.prog) seg_body(e.prog, e.had, e.amp, threadIdx.x, EB);
+    const ElemDesc& e = D[j];
+    if (k < e.nseg) seg_body(e.prog + k, e.had, e.amp, threadIdx.x, EB);
     __syncthreads();
   }
   if (!meas) return;
-  const ElemDesc& e = D[(size_t)kmax * na + j];
-  if (!e.prog) return;
-  meas_small_body(e.prog, e.had, e.amp, e.amp_other, e.seedp ? *e.seedp : e.seed, e.outcomes, e.pvals, e.scale,
+  const ElemDesc& e = D[j];
+  if (e.mk < 0) return;
+  meas_small_body(e.prog + e.mk, e.had, e.amp, e.amp_other, e.seedp ? *e.seedp : e.seed, e.outcomes, e.pvals, e.scale,
                   e.flags);
 }
 

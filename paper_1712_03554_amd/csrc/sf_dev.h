@@ -145,9 +145,10 @@ struct ReadoutInfo {
   uint64_t tab[SF_NMAX * 2 * SF_WMAX];
 };
 
-// One frame's element-kernel arguments in a batched launch.
+// One frame's element-kernel arguments in a batched round (one per frame,
+// shared by every launch of the round).
 struct ElemDesc {
-  const SegProg* prog;     // program of this launch's segment (nullptr: idle)
+  const SegProg* prog;     // the round's segment programs: segment k at prog + k
   const GF2Q* had;
   double2* amp;            // current amplitude buffer
   double2* amp_other;      // measurement filter target
@@ -158,7 +159,10 @@ struct ElemDesc {
   int* flags;
   uint64_t seed;
   const uint64_t* seedp;   // if set, the seed is read here (graph replays)
-  int32_t G, pad;
+  int32_t G;
+  int32_t nseg;            // segments of the frame's range this round
+  int32_t mk;              // the measurement's program (prog + mk), or -1: none
+  int32_t pad;
 };
 
 // Initialisation of one frame in a batched launch: basis words and seed are

@@ -87,3 +87,22 @@ def test_basis_word_packing():
         one[q] = 1
         w = _basis_word_rows([one], 1)[0]
         assert int(w[q >> 6]) == 1 << (q & 63) and int(w.sum()) == 1 << (q & 63)
+
+
+def test_packed_bases_pass_through():
+    """pack_bases gives the same words, and batch calls take them as they are
+    (a plain uint64 array of 0/1 bits is still read as bits)."""
+    import numpy as np
+    from paper_1712_03554_amd import BasisWords, _basis_word_rows, pack_bases
+    rng = np.random.default_rng(8)
+    rows = [rng.integers(0, 2, size=130).tolist() for _ in range(5)]
+    w = pack_bases(rows)
+    assert isinstance(w, BasisWords) and w.shape == (5, 4) and w.dtype == np.uint64
+    assert np.array_equal(w, _basis_word_rows(rows, 5))
+    again = _basis_word_rows(w, 5)
+    assert type(again) is np.ndarray and np.array_equal(again, w)
+    bits4 = np.array([[1, 0, 1, 1]] * 5, dtype=np.uint64)
+    assert [int(x) for x in _basis_word_rows(bits4, 5)[0]] == [0b1101, 0, 0, 0]
+    import pytest
+    with pytest.raises(ValueError):
+        _basis_word_rows(w, 6)
