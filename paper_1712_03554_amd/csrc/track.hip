@@ -1043,6 +1043,128 @@ static __device__ __forceinline__ void rec_put(LL& L, const RecRegs& R, int d) {
   __syncthreads();
 }
 
+// The phase kernel's view of the current state carried in registers from
+// gate to gate: each lane's row leads (row slots lane and 64 + lane), the
+// pivot rows of its columns (xpiv at columns lane and 64 + lane), the
+// X-block size, and the image of its hull vector (lane 0: s0, lane j: V[j-1]).
+struct PhRegs {
+  int ld[W], xp[W];
+  int k;
+  uint64_t hb[SF_WMAX];
+};
+
+// Pre-gate view for the basis-amplitude walk, written from registers: the
+// X-block rows by pivot column (ox, oz, ow), the pivot map (oxpiv, oxpm), the
+// hull (os0, oV) and its images (hbO).  No LDS is read.
+static __device__ __forceinline__ void ph_save_old(LL& L, const RecRegs& cur, const PhRegs& pr, int n, int d) {
+  const int lane = lane_id();
+  for (int k = 0; k < W; ++k) {
+    const int i = 64 * k + lane;
+    const int ld = pr.ld[k];
+    if (i < n && ld >= 0 && ld < n) {
+      int c = 0;
+      for (int w = 0; w < W; ++w) {
+        L.ox[ld * LL::RW + w] = cur.x[k][w];
+        L.oz[ld * LL::RW + w] = cur.z[k][w];
+        c += __popcll(cur.x[k][w] & cur.z[k][w]);
+      }
+      L.ow[ld] = (uint8_t)(c & 3);
+    }
+    L.oxpiv[i] = i < n ? (int16_t)pr.xp[k] : (int16_t)-1;
+  }
+  if (lane <= d) {
+    for (int w = 0; w < SF_WMAX; ++w) {
+      const uint64_t v = w < W ? cur.h[w] : 0ull;
+      if (lane == 0) L.os0[w] = v;
+      else L.oV[lane - 1][w] = v;
+      L.hbO[lane][w] = pr.hb[w];
+    }
+  }
+  for (int k = 0; k < SF_WMAX; ++k) {
+    const uint64_t m = k < W ? __ballot(64 * k + lane < n && pr.xp[k] >= 0) : 0ull;
+    if (lane == 0) L.oxpm[k] = m;
+  }
+}
+
+// The new state's rows into LDS (the b* basis gathers other lanes' rows).
+static __device__ __forceinline__ void ph_put_rows(LL& L, const RecRegs& R) {
+  const int lane = lane_id();
+  for (int k = 0; k < W; ++k) {
+    const int i = 64 * k + lane;
+    for (int w = 0; w < W; ++w) {
+      L.rx[i * LL::RW + w] = R.x[k][w];
+      L.rz[i * LL::RW + w] = R.z[k][w];
+    }
+  }
+}
+
+// Row leads from the registers, the pivot map by scatter (X-block leads),
+// the Z-block slot mask and the X-block size; then each lane's columns'
+// pivot rows gathered back.  (rebuild_index without re-reading the rows.)
+static __device__ __forceinline__ void ph_index(LL& L, const RecRegs& R, PhRegs& pr, int n) {
+  const int lane = lane_id();
+  for (int k = 0; k < W; ++k) L.xpiv[64 * k + lane] = -1;
+  __syncthreads();
+  int kx = 0;
+  for (int k = 0; k < W; ++k) {
+    const int i = 64 * k + lane;
+    const int ld = i < n ? row_lead_sel(R.x[k], R.z[k], n) : -1;
+    pr.ld[k] = ld;
+    if (ld >= 0 && ld < n) L.xpiv[ld] = (int16_t)i;
+    kx += __popcll(__ballot(ld >= 0 && ld < n));
+    const uint64_t bz = __ballot(ld >= n);
+    if (lane == 0) L.zsm[k] = bz;
+  }
+  if (lane == 0) for (int k = W; k < SF_WMAX; ++k) L.zsm[k] = 0;
+  pr.k = kx;
+  __syncthreads();
+  for (int k = 0; k < W; ++k) pr.xp[k] = L.xpiv[64 * k + lane];
+}
+
+// b* basis rows of the lane's Z-block rows (build_beta with the leads in
+// registers).
+static __device__ __forceinline__ void ph_beta(LL& L, const PhRegs& pr, int n) {
+  const int lane = lane_id();
+  for (int k = 0; k < W; ++k) {
+    const int h = 64 * k + lane;
+    if (h >= n) continue;
+    uint64_t b[W];
+    for (int w = 0; w < W; ++w) b[w] = 0;
+    const int ld = pr.ld[k];
+    if (ld >= n) {
+      const int q = ld - n;
+      b[q >> 6] ^= 1ull << (q & 63);
+      const int l = L.xpiv[q];
+      if (l >= 0)
+        for (int w = 0; w < W; ++w) b[w] ^= L.rx[l * LL::RW + w];
+    }
+    for (int w = 0; w < W; ++w) L.beta[h * LL::RW + w] = b[w];
+  }
+  __syncthreads();
+}
+
+// Images of the hull vectors (lane j's vector from the record registers)
+// into hbN and the lane's register copy.
+static __device__ __forceinline__ void ph_images(LL& L, const RecRegs& R, PhRegs& pr, int d) {
+  const int lane = lane_id();
+  uint64_t out[SF_WMAX] = {0, 0, 0, 0};
+  if (lane <= d) {
+    bimage(L, R.h, out);
+    for (int w = 0; w < SF_WMAX; ++w) L.hbN[lane][w] = out[w];
+  }
+  for (int w = 0; w < SF_WMAX; ++w) pr.hb[w] = out[w];
+  __syncthreads();
+}
+
+// The whole new-state view from one record (chunk start, after a terminal
+// step, after a non-diagonal gate).
+static __device__ __forceinline__ void ph_load(LL& L, const RecRegs& R, PhRegs& pr, int n, int d) {
+  ph_put_rows(L, R);
+  ph_index(L, R, pr, n);
+  ph_beta(L, pr, n);
+  ph_images(L, R, pr, d);
+}
+
 // segment s starts: its sums start at zero
 static __device__ __forceinline__ void seg_clear(const TrackJob& job, int s, int d) {
   if (s >= job.nseg) return;
@@ -1098,11 +1220,10 @@ static __device__ void phase_body(LL& L, const TrackJob& job, int c) {
     if (lane == 0) st->error = TRK_E_INTERNAL;
     return;
   }
-  rec_put(L, pf, d);
+  RecRegs cur = pf;   // the state before the next gate
+  PhRegs pr;
+  ph_load(L, cur, pr, n, d);
   rec_fetch(job, i0 + 1, n, pf);
-  rebuild_index(L, n);
-  build_beta(L, n);
-  hull_images(L, L.hbN, d, false);
   build_points(L, d);
   // gate i and its info, fetched one gate ahead like the records
   DGate gnext = load_gate(job.gates + job.g0 + i0);
@@ -1126,10 +1247,8 @@ static __device__ void phase_body(LL& L, const TrackJob& job, int c) {
       if (i + 1 < i1) {
         if (dn < 0 || dn >= SF_DMAX) { err = TRK_E_INTERNAL; break; }
         d = dn;
-        rec_put(L, nx, d);
-        rebuild_index(L, n);
-        build_beta(L, n);
-        hull_images(L, L.hbN, d, false);
+        cur = nx;
+        ph_load(L, cur, pr, n, d);
         build_points(L, d);
       }
       continue;
@@ -1151,16 +1270,15 @@ static __device__ void phase_body(LL& L, const TrackJob& job, int c) {
         const int mu = op == DG_S ? ba : op == DG_SDG ? 3 * ba : op == DG_Z ? 2 * ba : 2 * (ba & bb);
         __hip_atomic_fetch_add(gmem(&acc[p]), (uint32_t)(mu & 3), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      if (i + 1 < i1) rec_put(L, nx, d);
+      // (the index, b* basis and images stay; the rows and signs change)
+      cur = nx;
       continue;
     }
-    save_old(L, n, d);
-    const int kold = L.misc[0];
-    rec_put(L, nx, d);
-    rebuild_index(L, n);
-    build_beta(L, n);
-    hull_images(L, L.hbN, d, false);
-    const int knew = L.misc[0];
+    ph_save_old(L, cur, pr, n, d);
+    const int kold = pr.k;
+    cur = nx;
+    ph_load(L, cur, pr, n, d);
+    const int knew = pr.k;
     const int dk = knew - kold;
     const bool hsplit = op == DG_H && dk == 0;
     for (int p = lane; p < P; p += TL) {
