@@ -416,7 +416,7 @@ def large_frame(eng, wl, m=12, reps=2):
 
 def clifford_only(eng, wl, sizes=(128, 256), batch=8, reps=3):
     """The paper's Clifford-only workload (random stabilizer circuits, n log2 n
-    H/S/CNOT gates, then every qubit measured) at the sizes this build
+    H/S/CNOT gates, then every qubit measured) at the sizes the library
     supports: one circuit at a time and `batch` circuits per batched run.  The
     frame keeps one element, so U = gates applied."""
     import torch
@@ -597,7 +597,7 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=128.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np

@@ -60,7 +60,7 @@ def load_library(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise ImportError(f"libsframe.so not built ({path}); run __graft_entry__.build()")
+        raise ImportError(f"libsframe.so not built ({path}); build it with paper_1712_03554_amd/build.py")
     L = ctypes.CDLL(path)
     vp, u64, sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_size_t
     P = ctypes.POINTER
