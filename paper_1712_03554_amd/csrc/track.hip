@@ -1025,24 +1025,6 @@ static __device__ __forceinline__ void rec_fetch(const TrackJob& job, int r, int
   R.d = *gmem((const int32_t*)(job.rec + (size_t)r * job.rec_stride + ((size_t)n * 2 * W + (SF_DMAX + 1) * W) * 8));
 }
 
-static __device__ __forceinline__ void rec_put(LL& L, const RecRegs& R, int d) {
-  const int lane = lane_id();
-  for (int k = 0; k < W; ++k) {
-    const int i = 64 * k + lane;
-    for (int w = 0; w < W; ++w) {
-      L.rx[i * LL::RW + w] = R.x[k][w];
-      L.rz[i * LL::RW + w] = R.z[k][w];
-    }
-  }
-  if (lane <= d)
-    for (int w = 0; w < SF_WMAX; ++w) {
-      const uint64_t v = w < W ? R.h[w] : 0ull;
-      if (lane == 0) L.s0[w] = v;
-      else L.V[lane - 1][w] = v;
-    }
-  __syncthreads();
-}
-
 // The phase kernel's view of the current state carried in registers from
 // gate to gate: each lane's row leads (row slots lane and 64 + lane), the
 // pivot rows of its columns (xpiv at columns lane and 64 + lane), the
@@ -1196,13 +1178,14 @@ static __device__ __forceinline__ bool clifford_gate_rec(LL& L, Regs& R, uint64_
 // Phase factors of the Clifford gates g0 + i, i in [c k, (c + 1) k) with
 // k = pchunk, of a split-form range at the fitting points (the evaluation of
 // the five-step procedure from the states before and after each gate), added
-// into their segments' sums.  The wavefront rebuilds the pivot index, b* basis
+// into their segments' sums.  The wavefront builds the pivot index, b* basis
 // and hull images from the record before its first gate and then carries
-// them: a non-diagonal gate saves them as its pre-gate view and rebuilds from
+// them, with the record itself, in registers (PhRegs, RecRegs): a
+// non-diagonal gate writes them out as its pre-gate view and rebuilds from
 // the record after it; a diagonal gate changes only z bits of X-block rows
 // and X-block signs, which leave the index, the b* basis and the images as
-// they are, so only the rows and hull are reloaded; after a terminal step
-// everything is rebuilt.
+// they are, so only the register copy of the record changes; after a
+// terminal step everything is rebuilt.
 static __device__ void phase_body(LL& L, const TrackJob& job, int c) {
   const int lane = lane_id();
   const int len = job.g1 - job.g0;
