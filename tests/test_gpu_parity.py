@@ -781,3 +781,40 @@ def test_tuning_roundtrip_and_results_independent_of_it(eng, tmp_path):
     json.dump(rec, open(path, "w"))
     eng.set_tuning(t0)
     assert not eng.load_tuning(path) and eng.tuning() == t0
+
+
+def test_batch_mixes_large_and_small_hulls(eng):
+    """Frames whose hulls differ by many orders of magnitude in one batch (a
+    superposed Cuccaro adder growing to 2^16 slots beside 13-qubit trials and
+    8-qubit circuits): each frame's blocks in the flattened element launches
+    and each measurement's reduction shape are its own, so the eager batched
+    run and the graph replay give every frame's result alone, bit for bit."""
+    circs = [wl.cuccaro_adder(7, name="cuccaro-m7"), wl.config1(0), wl.config3(3), wl.config3(11),
+             _mixed_circuit(41, 12), wl.qft(11, [1, 0] * 5 + [1], name="qft-11"), wl.config1(5)]
+    seeds = list(range(900, 900 + len(circs)))
+    alone = [_run_alone(eng, c, s) for c, s in zip(circs, seeds)]
+    loaded = [eng.load(c.n, c) for c in circs]
+    assert max(l.info()[0] for l in loaded) >= 14
+    states = [l.state(c.init_bits, s) for l, c, s in zip(loaded, circs, seeds)]
+    eng.batch_run(states)
+    for c, st, ((ta, sa, aa), oa) in zip(circs, states, alone):
+        tb, sb, ab = st.read_frame()
+        assert np.array_equal(ta, tb) and np.array_equal(sa, sb), c.name
+        assert np.array_equal(aa.view(np.uint64), ab.view(np.uint64)), c.name
+        assert st.outcomes() == oa, c.name
+    g = eng.batch_graph(states, [c.init_bits for c in circs], seeds)
+    for _ in range(2):
+        g.launch()
+        for c, st, ((ta, sa, aa), oa) in zip(circs, states, alone):
+            tb, sb, ab = st.read_frame()
+            assert np.array_equal(sa, sb) and np.array_equal(aa.view(np.uint64), ab.view(np.uint64)), c.name
+            assert st.outcomes() == oa, c.name
+    g.close()
+    # the reference values of the small frames are the oracle's
+    for c, s, ((ta, sa, aa), oa) in list(zip(circs, seeds, alone))[1:5]:
+        ref = OracleFrame(c.n, c.init_bits, s)
+        ref.run(c.array())
+        rtab, rsig, ramp = ref.read()
+        assert np.array_equal(ta, rtab), c.name
+        assert_frames_equal(sigma_ints(sa), aa, sigma_ints(rsig), ramp, what=c.name)
+        assert oa == ref.outcomes(), c.name
