@@ -180,7 +180,7 @@ sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t n_states);
  * with the in-kernel phase evaluation instead of allocating it.  Results are
  * those of sf_batch_run.  SF_E_TOO_LARGE (nothing queued) when the states
  * would need more than 8 MiB of descriptors and gather table: about
- * n_states x (108 + 96 x (most segments of one range + 1)) bytes.  Calls on
+ * n_states x (212 + 4 x (most segments of one range + 2)) bytes.  Calls on
  * one device share the array: calls that
  * overlap in time on one device (other host threads or streams) race and
  * must be serialised by the caller.  Synchronises. */
