@@ -165,10 +165,13 @@ sf_status sf_run(sf_state* s);
  * Run every remaining gate of n_states states (all of this context) as one
  * batch: per round, the tableau tracks of all frames share one launch (one
  * wavefront each) and the element kernels of all frames share one launch per
- * segment.  Results are identical to running each state alone.  The
- * per-round launch descriptors are staged through pinned host memory that the
- * context keeps (allocated on first use, freed by sf_ctx_destroy).
- * Synchronises. */
+ * segment.  Results are identical to running each state alone.  When some
+ * circuit has ranges that end without a measurement, the tracks of the next
+ * round run on a second stream that the context keeps, beside the current
+ * round's other kernels (the context's stream waits for that stream before
+ * the call returns).  The per-round launch descriptors are staged through
+ * pinned host memory that the context keeps (allocated on first use, freed
+ * by sf_ctx_destroy).  Synchronises. */
 sf_status sf_batch_run(sf_ctx* ctx, sf_state* const* states, size_t n_states);
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops that must not allocate, harnesses that forbid it).
