@@ -791,9 +791,10 @@ def main():
     meas_roof = {
         "reduce": hbm_roof("meas_reduce", "sf_meas_reduce_batch" if batched_names else "sf_meas_reduce",
                            red_bytes, "16 B read per hull slot before the measurement"),
-        "filter": hbm_roof("meas_filter", "sf_meas_filter_batch" if batched_names else "sf_meas_filter",
-                           fil_bytes, "32 B (read + write) per kept slot; the fused form also sums the "
-                                      "reduction partials in every block"),
+        "filter": hbm_roof("meas_filter", "sf_meas_apply_batch" if batched_names else "sf_meas_filter",
+                           fil_bytes, "32 B (read + write) per kept slot; launches of many blocks draw the coin "
+                                      "in a kernel of their own and filter with sf_meas_apply_batch, the others "
+                                      "with sf_meas_filter_batch, whose blocks also sum the reduction partials"),
     }
     roof = dict({"segment": elem_roof, "phase": phase_roof, "meas_reduce": meas_roof["reduce"],
                  "meas_filter": meas_roof["filter"]}.get(dom, track_roof))
