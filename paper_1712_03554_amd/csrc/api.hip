@@ -1672,8 +1672,17 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
         rp->bst[(size_t)(rp->kmax + 1) * stride + j + 1] = batch_blocks(dl, bcap);
       }
     }
-    for (int r = 0; r < R; ++r)
-      for (int j = 0; j < na; ++j) rp->bst[(size_t)r * stride + j + 1] += rp->bst[(size_t)r * stride + j];
+    for (int r = 0; r < R; ++r) {
+      uint64_t sum = 0;
+      for (int j = 0; j < na; ++j) {
+        sum += rp->bst[(size_t)r * stride + j + 1];
+        if (sum > (uint64_t)INT32_MAX) {
+          *err = fail(states[act[0]]->ctx, SF_E_TOO_LARGE, "%d frames need more than 2^31 blocks in one launch", na);
+          return false;
+        }
+        rp->bst[(size_t)r * stride + j + 1] = (uint32_t)sum;
+      }
+    }
   }
   // one descriptor per frame, shared by every launch of the round
   rp->desc.resize((size_t)na);
