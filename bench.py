@@ -842,6 +842,11 @@ def main():
                           [wl.derive_seed(3, t) for t in range(4096)], 256),
             batched_extra(eng, wl, "uneven random Clifford+T, 1024 circuits, n in 16..256", c4,
                           [wl.derive_seed(4, j) for j in range(1024)], 16),
+            # the large-frame variant of the headline workload: 24 T gates,
+            # frames of up to 2^21 elements (64 circuits per step)
+            batched_extra(eng, wl, "random Clifford+T, n=128, 2000 H/S/CNOT + 24 T, measure 16 qubits, "
+                          "64 circuits", [wl.config2(j, n_t=24) for j in range(64)],
+                          [wl.derive_seed(22, j) for j in range(64)], 2),
         ]
     if not args.no_extra:
         line["direct_forms"] = direct_vs_decomposed(eng, wl)
