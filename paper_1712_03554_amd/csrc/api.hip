@@ -114,18 +114,23 @@ static void scratch_lookup(int device) {
 // Circuits whose hull never exceeds this dimension (2^8 = EB slots, one
 // reduction block) measure with one fused kernel per measurement.
 #define SF_MSMALL_D 8
-// Flattened batched element launches: slots per thread, and at most this many
-// blocks of EB threads per frame (a larger frame's threads stride over it).
-#ifndef SF_BATCH_EPT
-#define SF_BATCH_EPT 4
+// Flattened batched element launches: slots per thread (segment launches and
+// measurement filters, measured best apart), and at most this many blocks of
+// EB threads per frame (a larger frame's threads stride over it).
+#ifndef SF_BATCH_EPT_SEG
+#define SF_BATCH_EPT_SEG 2
+#endif
+#ifndef SF_BATCH_EPT_FILTER
+#define SF_BATCH_EPT_FILTER 8
 #endif
 #define SF_BATCH_BLOCKS_MAX 8192
 
 // blocks of a frame whose hull dimension is at most d in a flattened launch
-static uint32_t batch_blocks(int d, uint64_t cap) {
+// with ept slots per thread
+static uint32_t batch_blocks(int d, uint64_t cap, int ept) {
   if (d < 0) d = 0;
   if (d > SF_DMAX) d = SF_DMAX;
-  const uint64_t per = (uint64_t)EB * SF_BATCH_EPT;
+  const uint64_t per = (uint64_t)EB * (uint64_t)ept;
   const uint64_t nb = ((1ull << d) + per - 1) / per;
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(nb, cap));
 }
@@ -1665,11 +1670,11 @@ static bool plan_round(sf_state* const* states, size_t ns, Progress* pr, int cap
       }
       const int kseg = (ML[i] && folded_meas(c, B[i])) ? NS[i] - 1 : NS[i];
       for (int k = 0; k < kseg; ++k)
-        rp->bst[(size_t)k * stride + j + 1] = batch_blocks(dims ? (int)dims[k] : c->dmax, bcap);
+        rp->bst[(size_t)k * stride + j + 1] = batch_blocks(dims ? (int)dims[k] : c->dmax, bcap, SF_BATCH_EPT_SEG);
       if (ML[i] && NS[i] > 0) {
         const int dl = dims ? std::min((int)dims[NS[i] - 1] + 1, c->dmax) : c->dmax;
         rp->bst[(size_t)rp->kmax * stride + j + 1] = (uint32_t)red_grid(dl);
-        rp->bst[(size_t)(rp->kmax + 1) * stride + j + 1] = batch_blocks(dl, bcap);
+        rp->bst[(size_t)(rp->kmax + 1) * stride + j + 1] = batch_blocks(dl, bcap, SF_BATCH_EPT_FILTER);
       }
     }
     for (int r = 0; r < R; ++r) {
