@@ -18,7 +18,8 @@ from . import workloads
 from .workloads import GATE_DTYPE
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsframe.so")
+# SFRAME_LIB names another build of the library (the host-sanitized one)
+LIB_PATH = os.environ.get("SFRAME_LIB") or os.path.join(_HERE, "libsframe.so")
 
 SF_OK, SF_E_INVALID, SF_E_OOM, SF_E_DEVICE, SF_E_TOO_LARGE, SF_E_STATE, SF_E_BUFSIZE, SF_E_CANCELLED = range(8)
 STATUS_NAMES = ["SF_OK", "SF_E_INVALID", "SF_E_OOM", "SF_E_DEVICE", "SF_E_TOO_LARGE", "SF_E_STATE",
