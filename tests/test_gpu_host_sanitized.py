@@ -57,7 +57,7 @@ def test_child_loads_the_sanitized_build(ubsan_lib):
 
 
 def test_host_paths_under_ubsan(ubsan_lib):
-    sel = [f"tests/test_gpu_parity.py", "tests/test_gpu_failures.py", "tests/test_gpu_wide.py",
+    sel = ["tests/test_gpu_parity.py", "tests/test_gpu_failures.py", "tests/test_gpu_wide.py",
            "tests/test_zz_no_alloc.py", "-k", " or ".join(PARITY + WIDE + ["allocat", "buffer_too_small", "noalloc"])]
     cmd = [sys.executable, "-u", "-m", "pytest", "-x", "-q", "-m", "gpu", "-p", "no:cacheprovider",
            "--timeout", "240", "--timeout-method", "thread"] + sel
