@@ -106,3 +106,35 @@ def test_packed_bases_pass_through():
     import pytest
     with pytest.raises(ValueError):
         _basis_word_rows(w, 6)
+
+
+def test_sanitized_build_keeps_sanitizers_on_the_host():
+    """The UBSan build's flags put every sanitizer option behind -Xarch_host
+    (device code is never sanitized), make reports fatal, and link the
+    shared runtime with a run path to it."""
+    from paper_1712_03554_amd import build as lib_build
+    fl = lib_build.UBSAN_FLAGS
+    for i, f in enumerate(fl):
+        if f.startswith("-fsanitize") or f.startswith("-fno-sanitize"):
+            assert i > 0 and fl[i - 1] == "-Xarch_host", f
+    assert "-fsanitize=undefined" in fl and "-fno-sanitize-recover=undefined" in fl
+    assert "-shared-libsan" in fl and any(f.startswith("-Wl,-rpath,") for f in fl)
+    assert lib_build.UBSAN_OUT != lib_build.OUT
+
+
+def test_library_path_override():
+    """SFRAME_LIB selects the library file the binding loads (checked in a
+    child process, so this one keeps its binding as it is)."""
+    import subprocess
+    import sys
+    code = ("import paper_1712_03554_amd as sf\n"
+            "print(sf.LIB_PATH)\n"
+            "try:\n    sf.load_library()\nexcept ImportError:\n    print('ImportError')\n")
+    env = dict(os.environ, SFRAME_LIB="/nonexistent/libsframe_other.so")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-1000:]
+    assert r.stdout.split() == ["/nonexistent/libsframe_other.so", "ImportError"]
+    env.pop("SFRAME_LIB")
+    r = subprocess.run([sys.executable, "-c", "import paper_1712_03554_amd as sf; print(sf.LIB_PATH)"], cwd=ROOT,
+                       env=env, capture_output=True, text=True, timeout=120)
+    assert r.stdout.strip() == os.path.join(ROOT, "paper_1712_03554_amd", "libsframe.so")
