@@ -91,7 +91,7 @@ def _check_frame(f, n, k, clifford_only, what):
     return K
 
 
-@settings(max_examples=300, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@settings(max_examples=300, deadline=None, derandomize=True, suppress_health_check=[HealthCheck.too_slow])
 @given(circuits())
 def test_frame_invariants_after_every_gate(case):
     n, bits, gates, seed = case
