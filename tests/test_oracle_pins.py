@@ -507,3 +507,38 @@ def test_qft_direct_matches_closed_form(n):
         yr = int(format(y, f"0{n}b")[::-1], 2)
         ref[y] = np.exp(2j * np.pi * X * yr / (1 << n)) / np.sqrt(1 << n)
     assert np.allclose(psi, ref, atol=1e-11)
+
+
+def test_splitmix64_known_answers():
+    """The measurement generator is SplitMix64 (Steele, Lea & Flood 2014):
+    started from state 0, the reference implementation's first outputs are
+    e220a8397b1dcdaf, 6e789e6aa1b965f4, 06c45d188009454f."""
+    assert [wl.splitmix64(0, i) for i in range(3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                                      0x06C45D188009454F]
+    assert wl.measurement_uniform(0, 0) == (0xE220A8397B1DCDAF >> 11) * 2.0 ** -53
+
+
+def test_oracle_coin_is_u_below_p1():
+    """Measurement outcome 1 exactly when u < p(1), u from the 53 high bits of
+    output k of the state's generator (k counts its measurements): |+>
+    measured again and again (p(1) = 1/2 each time), and H T H |0> measured
+    once (p(1) = (1 - cos(pi/4)) / 2) for 64 seeds."""
+    for seed in (0, 1, 7, 20171210, 2**63 + 5):
+        f = OracleFrame(1, [0], seed)
+        for _ in range(12):
+            f.apply(wl.H, 0)
+            f.apply(wl.MEASURE, 0)
+        want = [int(wl.measurement_uniform(seed, k) < 0.5) for k in range(12)]
+        assert f.outcomes() == want, seed
+    p1 = (1.0 - np.cos(np.pi / 4)) / 2.0
+    ones = 0
+    for seed in range(64):
+        u = wl.measurement_uniform(seed, 0)
+        if abs(u - p1) < 1e-12:
+            continue
+        f = OracleFrame(1, [0], seed)
+        for g in ((wl.H, 0), (wl.T, 0), (wl.H, 0), (wl.MEASURE, 0)):
+            f.apply(*g)
+        assert f.outcomes() == [int(u < p1)], seed
+        ones += f.outcomes()[0]
+    assert 0 < ones < 32
