@@ -138,3 +138,22 @@ def test_library_path_override():
     r = subprocess.run([sys.executable, "-c", "import paper_1712_03554_amd as sf; print(sf.LIB_PATH)"], cwd=ROOT,
                        env=env, capture_output=True, text=True, timeout=120)
     assert r.stdout.strip() == os.path.join(ROOT, "paper_1712_03554_amd", "libsframe.so")
+
+
+def test_every_declaration_names_its_passage():
+    """Each exported call's comment (its own, or the one it shares with the
+    calls declared right after it) names the passage of the paper it follows
+    (section, definition, equation, example, table, figure, theorem,
+    observation, invariant), or says it is not in the paper, or (the
+    allocation-free entry point) names the callers it is for."""
+    text = open(HEADER).read()
+    cite = re.compile(r"sections? \d|definition \d|eqs?\. ?\d|example \d|table \d|figure \d|theorem \d|"
+                      r"observation \d|invariant \d|not in the paper|cannot allocate", re.I)
+    prev, last, seen = 0, "", []
+    for m in re.finditer(r"^(?:sf_status|const char\*)\s+(sf_\w+)\(", text, re.M):
+        comments = re.findall(r"/\*.*?\*/", text[prev:m.start()], re.S)
+        last = comments[-1] if comments else last
+        assert cite.search(last), f"{m.group(1)}: no passage named"
+        seen.append(m.group(1))
+        prev = m.end()
+    assert sorted(seen) == _declared()
