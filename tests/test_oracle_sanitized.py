@@ -1,7 +1,9 @@
 """The frame oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
 (gcc, host code only) and run on circuits of one to four packed words per
-row: no sanitizer report, and the same frame size and outcomes as the
-oracle library the other tests load."""
+row, and its multiframe simulation (basic COALESCE and COALESCE through the
+basis circuit, merging, orthogonalization before measurements) on mixed
+circuits and superposed Cuccaro adders: no sanitizer report, and the same
+frame sizes and outcomes as the oracle library the other tests load."""
 import os
 import shutil
 import subprocess
@@ -9,7 +11,7 @@ import subprocess
 import numpy as np
 import pytest
 
-from oracle.frame import OracleFrame
+from oracle.frame import OracleFrame, OracleMultiframe
 from paper_1712_03554_amd import workloads as wl
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -65,3 +67,36 @@ def test_oracle_clean_under_sanitizers(sanitized, idx):
     assert int(got["K"]) == ref.size
     assert abs(float(got["norm"]) - 1.0) <= 1e-12
     assert [int(v) for v in got["outcomes"].split()] == ref.outcomes()
+
+
+def _multi_circuits():
+    from tests.test_oracle_multiframe import _random_mix
+    out = [_random_mix(seed, 3 + seed % 3, 40) for seed in range(4)]
+    for m, direct in ((3, False), (4, False), (3, True)):
+        c = wl.cuccaro_adder(m, direct=direct)
+        for q in range(c.n):
+            c.measure(q)
+        out.append(c)
+    return out
+
+
+@pytest.mark.parametrize("general", [False, True])
+@pytest.mark.parametrize("idx", range(7))
+def test_multiframe_oracle_clean_under_sanitizers(sanitized, idx, general):
+    c = _multi_circuits()[idx]
+    seed = 31 + idx
+    text = f"{c.n} {seed}\n" + " ".join(str(b) for b in c.init_bits) + f"\n{len(c.gates)}\n"
+    text += "".join(" ".join(str(int(v)) for v in g) + "\n" for g in c.gates)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([sanitized, "general" if general else "multi"], input=text, capture_output=True, text=True,
+                       env=env, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr, r.stderr[-2000:]
+    got = {k: v for k, _, v in (line.partition(" ") for line in r.stdout.strip().splitlines())}
+    ref = OracleMultiframe(c.n, c.init_bits, seed)
+    ref.set_general(general)
+    ref.run(c.array())
+    assert int(got["K"]) == ref.size and int(got["frames"]) == ref.nframes
+    assert abs(float(got["norm"]) - 1.0) <= 1e-12
+    assert [int(v) for v in got["outcomes"].split()] == ref.outcomes()
+    assert int(got["orthogonal"]) == int(ref.orthogonal())
