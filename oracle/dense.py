@@ -192,11 +192,6 @@ class TableauTrack:
         else:
             raise ValueError(op)
 
-    def is_random(self, q) -> bool:
-        zq = np.zeros(2 * self.n, dtype=np.uint8)
-        zq[self.n + q] = 1
-        return any(symplectic(r, zq, self.n) for r in self.rows)
-
     def cofactor(self, q):
         n = self.n
         zq = np.zeros(2 * n, dtype=np.uint8)

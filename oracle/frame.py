@@ -121,13 +121,6 @@ class OracleFrame:
         return tab, sig[:K], (amp[0::2] + 1j * amp[1::2])[:K]
 
 
-def run_circuit(circ, seed: int = 0):
-    """Run a workloads.Circuit; returns (frame, sizes-before-each-gate)."""
-    f = OracleFrame(circ.n, circ.init_bits, seed)
-    sizes = f.run(circ.array())
-    return f, sizes
-
-
 def _load_mf():
     L = _load()
     if getattr(L, "_mf_ready", False):
