@@ -103,3 +103,27 @@ def test_segment_u_count_matches_gate_by_gate_sizes(make):
     assert sizes == [int(ref[s]) for s in starts]
     assert len(seg_dims) == len(ends) and seg_dims[0] == 0
     assert len(meas) == sum(1 for g in c.gates if g[0] == wl.MEASURE)
+
+
+def _bench(*args):
+    import subprocess
+    import sys
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], cwd=ROOT, capture_output=True,
+                          text=True, timeout=300)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = _bench("--gpus", "2")
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
+
+
+def test_bench_fails_loudly_without_a_device():
+    """No HIP device: the benchmark stops with the library's device error
+    instead of measuring anything else."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a HIP device is present")
+    r = _bench("--no-cpu", "--no-extra", "--serve-jobs", "0", "--steps", "1", "--warmup", "0")
+    assert r.returncode != 0
+    assert "SF_E_DEVICE" in r.stderr and '"value"' not in r.stdout
