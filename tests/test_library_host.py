@@ -157,3 +157,35 @@ def test_every_declaration_names_its_passage():
         seen.append(m.group(1))
         prev = m.end()
     assert sorted(seen) == _declared()
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """A C99 (pedantic) and a C++ program that include the header and take
+    the address of every declared call compile warning-free, and the C one links against
+    the built library (every declaration has its definition)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None or shutil.which("g++") is None:
+        pytest.skip("no gcc")
+    names = _declared()
+    body = "#include \"sframe.h\"\n#include <stdio.h>\ntypedef void (*fn_t)(void);\nint main(void) {\n"
+    body += "  fn_t fns[] = {\n" + "".join(f"    (fn_t)&{n},\n" for n in names)
+    body += "  };\n  printf(\"%d\\n\", (int)(sizeof fns / sizeof fns[0]));\n  return 0;\n}\n"
+    src = tmp_path / "use.c"
+    src.write_text(body)
+    inc = os.path.join(ROOT, "include")
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                        "-I", inc, "-c", str(src), "-o", str(tmp_path / "use.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    srcpp = tmp_path / "use.cpp"
+    srcpp.write_text(body.replace("(fn_t)&", "(fn_t)&::"))
+    r = subprocess.run(["g++", "-std=c++11", "-Wall", "-Wextra", "-Werror", "-I", inc, "-c", str(srcpp),
+                        "-o", str(tmp_path / "usepp.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    if not os.path.exists(sf.LIB_PATH):
+        pytest.skip("library not built")
+    libdir = os.path.dirname(sf.LIB_PATH)
+    r = subprocess.run(["gcc", str(tmp_path / "use.o"), "-o", str(tmp_path / "use"), sf.LIB_PATH,
+                        "-Wl,--unresolved-symbols=ignore-in-shared-libs", "-Wl,-rpath," + libdir],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
